@@ -1,0 +1,208 @@
+/*
+ * ms.h — C ABI of the MI355X batched rigid-body step library (libms).
+ *
+ * The library advances many independent rigid-body environments ("envs") by one or more
+ * fixed time steps with a single fused HIP kernel on one GPU.  The capability follows the
+ * GPU-parallel, heterogeneous simulation of ManiSkill3 (arXiv 2410.00425): every parallel env
+ * is its own scene with its own object count and articulation (Sec. III-A, "heterogeneous
+ * simulation"), state stays resident on the GPU (Sec. III-B), envs can be reset in part
+ * (App. D, partial resets), and the solver runs a fixed number of position / velocity
+ * iterations (App. E, Setup: 120 Hz, 4 position and 0 velocity iterations).  The paper does not
+ * state the contact and solver equations; the step model this library implements is fixed
+ * by the oracle's documented reading (sequential-impulse TGS/PGS with speculative contacts,
+ * pyramid friction, revolute joints with a soft PD drive).
+ *
+ * Conventions: SI units, z up, quaternions (w, x, y, z), angular velocity in the world frame.
+ * Body and joint indices inside descriptors are env-local.  All device pointers are
+ * caller-owned (usually torch tensors) and must stay valid until the stream reaches the call.
+ * Every call is stream-ordered and non-blocking unless stated otherwise; none synchronises
+ * the device.  Argument and validation failures return a code synchronously and enqueue
+ * nothing; the thread-local message is available from ms_last_error().
+ * A batch is not thread-safe; distinct batches may be used from distinct threads.
+ */
+#ifndef MS_H
+#define MS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MS_OK = 0,
+    MS_E_INVALID_ARG = 1,  /* null pointer, bad size, bad index, bad descriptor */
+    MS_E_NO_WORKSPACE = 2, /* workspace smaller than ms_query_batch_bytes() */
+    MS_E_BUDGET = 3,       /* request exceeds the server's HBM budget */
+    MS_E_DEVICE = 4,       /* a HIP runtime call failed */
+    MS_E_CAPACITY = 5,     /* an env exceeds a kernel capacity (bodies, joints, LDS) */
+    MS_E_STATE = 6         /* call not valid in the object's current state */
+} ms_status;
+
+enum { MS_SPHERE = 0, MS_CAPSULE = 1, MS_BOX = 2 };
+enum { MS_BODY_STATIC = 1 };            /* zero inverse mass and inertia; never integrated */
+enum { MS_SOLVER_TGS = 0, MS_SOLVER_PGS = 1 };
+
+/* Per-env status bits written by the step (status[E], int32). */
+enum {
+    MS_STATUS_NONFINITE = 1,       /* a NaN/Inf appeared: the env keeps its pre-step state and is frozen */
+    MS_STATUS_CONTACT_OVERFLOW = 2,/* more contact points than the env's capacity: the first ones in
+                                      canonical pair order were kept */
+    MS_STATUS_COLOR_OVERFLOW = 4   /* more than 64 colours: extra blocks were solved serially */
+};
+#define MS_STATUS_FROZEN_MASK 1
+
+/* Limits of the fused kernel. */
+#define MS_MAX_BODIES_PER_ENV 64
+#define MS_MAX_JOINTS_PER_ENV 64
+
+/* One rigid body.  Shape dims: sphere (r, -, -); capsule (r, half_len, -) with its axis along
+ * body-local z and half_len = half the cylinder length; box (hx, hy, hz) half-extents.
+ * mass > 0 gives the mass; otherwise mass = density * volume.  The centre of mass is the shape
+ * centre and the principal axes are the shape axes.  88 bytes, no padding. */
+typedef struct {
+    int32_t shape;
+    int32_t flags;
+    float dims[3];
+    float mass;
+    float density;
+    float friction;
+    float restitution;
+    float pos[3];
+    float quat[4];
+    float linvel[3];
+    float angvel[3];
+} ms_body_desc;
+
+/* One revolute joint about the z axis of its joint frame.  parent = -1 attaches the child to
+ * the static world.  frame_* = (px, py, pz, qw, qx, qy, qz) in the body's local frame (the world
+ * frame for parent = -1).  kp (N m / rad) and kd (N m s / rad) define the PD position drive
+ * toward `target` (rad); kp = kd = 0 disables the drive.  76 bytes, no padding. */
+typedef struct {
+    int32_t parent;
+    int32_t child;
+    float frame_parent[7];
+    float frame_child[7];
+    float kp;
+    float kd;
+    float target;
+} ms_joint_desc;
+
+/* A batch of envs in compressed form: env e owns bodies [env_body_off[e], env_body_off[e+1]) and
+ * joints [env_joint_off[e], env_joint_off[e+1]).  Host memory, copied during create. */
+typedef struct {
+    int32_t n_envs;
+    const int32_t* env_body_off;   /* [n_envs + 1] */
+    const ms_body_desc* bodies;    /* [env_body_off[n_envs]] */
+    const int32_t* env_joint_off;  /* [n_envs + 1] */
+    const ms_joint_desc* joints;   /* [env_joint_off[n_envs]] */
+} ms_scene_desc;
+
+/* Step parameters.  One step advances dt; TGS runs pos_iters substeps of one iteration each,
+ * PGS runs one substep of pos_iters iterations; vel_iters velocity-only sweeps follow.  The
+ * ground is the half-space z <= plane_z when plane_enabled != 0.  max_contacts_per_env <= 0
+ * selects the default 8 * n_bodies + 16.  debug_export != 0 makes the step also write the last
+ * step's pair list, contact points and colours (read with ms_get_contacts). */
+typedef struct {
+    float dt;
+    int32_t pos_iters;
+    int32_t vel_iters;
+    int32_t solver;
+    float gravity[3];
+    float plane_z;
+    int32_t plane_enabled;
+    float plane_friction;
+    float plane_restitution;
+    float contact_offset;
+    float baumgarte;
+    float max_depen_vel;
+    float joint_baumgarte;
+    float bounce_threshold;
+    float lin_damping;
+    float ang_damping;
+    int32_t max_contacts_per_env;
+    int32_t debug_export;
+    int32_t joint_iters;
+} ms_sim_params;
+
+/* Caller-owned device buffers in structure-of-arrays form over all B bodies of the batch:
+ * pos[3][B], quat[4][B], linvel[3][B], angvel[3][B] (float32, component-major) and status[E]. */
+typedef struct {
+    float* pos;
+    float* quat;
+    float* linvel;
+    float* angvel;
+    int32_t* status;
+} ms_state_view;
+
+/* Execution plan knobs.  lanes_per_env = 0 lets the library pick (autotuned or heuristic);
+ * otherwise 1, 2, 4, 8, 16, 32 or 64 lanes of a 64-wide wavefront serve one env.  pack != 0
+ * sorts envs by size class before tiling (heterogeneous batches). */
+typedef struct {
+    int32_t lanes_per_env;
+    int32_t pack;
+    int32_t max_resident_groups; /* 0 = the device's resident capacity */
+} ms_plan;
+
+typedef struct ms_batch ms_batch;
+
+/* Device workspace bytes needed by a batch (state, parameters, joints, targets, tiles, debug).
+ * Host-only, never touches the device. */
+ms_status ms_query_batch_bytes(const ms_sim_params* params, const ms_scene_desc* scene,
+                               const ms_plan* plan, size_t* bytes);
+
+/* Validate the scene, lay out the workspace (caller-owned device memory of at least
+ * ms_query_batch_bytes() bytes, 256-byte aligned) and upload the initial state on `hip_stream`
+ * (NULL = the default stream).  The initial state is kept for ms_reset_envs(src = NULL).
+ * Reconfiguration is a destroy + create. */
+ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scene,
+                          const ms_plan* plan, void* dev_workspace, size_t ws_bytes,
+                          void* hip_stream, ms_batch** out);
+
+/* Advance every env by n_steps steps (n_steps >= 1) in one fused launch.  dev_targets holds one
+ * drive target per joint of the batch (float32 [total joints], device) and replaces the
+ * descriptor targets for this and later calls; NULL keeps the current ones.  Envs with a frozen
+ * status are skipped. */
+ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* hip_stream);
+
+/* Write state for the listed envs (int32 device array of n_ids env ids, each in [0, E)) and
+ * clear their status.  src = NULL restores the initial state; otherwise src holds full-batch
+ * SoA arrays (same shape as ms_state_view) from which the listed envs' bodies are copied. */
+ms_status ms_reset_envs(ms_batch* b, const int32_t* dev_env_ids, int32_t n_ids,
+                        const ms_state_view* src, void* hip_stream);
+
+/* Copy the current state (all envs) into caller-owned device buffers. */
+ms_status ms_get_state(ms_batch* b, const ms_state_view* dst, void* hip_stream);
+
+/* Body and joint offsets of the batch (host arrays of n_envs + 1 entries each), and totals. */
+ms_status ms_get_layout(ms_batch* b, int32_t* host_env_body_off, int32_t* host_env_joint_off);
+ms_status ms_get_sizes(ms_batch* b, int32_t* n_envs, int32_t* n_bodies, int32_t* n_joints);
+
+/* Contact export of the last step (requires debug_export).  Synchronises `hip_stream`.
+ * For every env, the candidate pairs in canonical order are written to pairs[] as
+ * int32 records {env, a, b, n_points, decision}; the plane is body 0xFFFF.  points[] receives
+ * float records {px, py, pz, nx, ny, nz, s, lambda_n, lambda_t1, lambda_t2} for every kept
+ * point, pair by pair, and colour[] the colour of each manifold with points.  *n_pairs and
+ * *n_points receive the totals; buffers may be NULL to query the counts. */
+ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, float* host_points,
+                          int32_t points_cap, int32_t* n_pairs, int32_t* n_points, void* hip_stream);
+
+ms_status ms_destroy_batch(ms_batch* b);
+
+/* Fused step over several batches in one launch: the env tiles of every batch are concatenated
+ * into one work list (the serving path).  targets[i] as in ms_step for batch i. */
+ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches,
+                       int32_t n_steps, void* hip_stream);
+
+/* Thread-local message of the last non-OK status returned on this thread. */
+const char* ms_last_error(void);
+
+/* Library version string. */
+const char* ms_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MS_H */

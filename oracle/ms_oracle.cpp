@@ -1,0 +1,1514 @@
+// ms_oracle.cpp — plain, slow CPU reference of the batched rigid-body step.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's CPU-baseline
+// leg load this library.  It shares no code, header or constant table with the GPU library and
+// exists to decide what the GPU step must compute.
+//
+// What it computes.  ManiSkill3 (arXiv 2410.00425) advances thousands of independent,
+// heterogeneous scenes with GPU rigid-body simulation (Sec. III-A), tuned by solver position /
+// velocity iteration counts (App. E, Setup) and PD joint drives (App. B, Controller).  The paper
+// states no contact or solver equations, so this file implements one documented step model,
+// each phase named after the published method it restates:
+//   S0 frozen step-start quantities; S1 exact AABBs; S2 all-pairs broadphase with filters;
+//   S3 narrowphase for sphere / capsule / box / plane pairs (closest points after Ericson,
+//      "Real-Time Collision Detection" 5.1.9; separating axes after Gottschalk's OBB test;
+//      Sutherland-Hodgman clipping) with a <= 4 point manifold reduction;
+//   S4 contact rows (tangent basis after Duff et al. 2017, "Building an Orthonormal Basis,
+//      Revisited"); S5 greedy colouring that fixes the Gauss-Seidel order;
+//   S6 TGS substeps (sequential impulses with clamped accumulated impulses, warm start across
+//      substeps, speculative contacts, Baumgarte bias; patch friction at the manifold centroid
+//      with a torsional row; revolute point + 2 angular rows with a per-step Baumgarte rate and
+//      extra joint-only passes; PD drive as a soft row after Catto, "Soft Constraints", GDC
+//      2011); symplectic Euler on offsets from the step-start pose;
+//   S7 velocity iterations and a restitution pass; S8 write-back with a non-finite guard.
+// Templated on float and double.  Built with -ffp-contract=off: no fused multiply-add anywhere.
+// Parity pins live in the CPU test suite (closed forms, invariants, brute force).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace orc {
+
+// ----------------------------------------------------------------------------- interface types
+// Byte layout of the descriptor records handed over by the input generators (88 / 76 bytes).
+struct BodyDesc {
+    int32_t shape, flags;
+    float dims[3];
+    float mass, density, friction, restitution;
+    float pos[3], quat[4], linvel[3], angvel[3];
+};
+struct JointDesc {
+    int32_t parent, child;
+    float frame_parent[7], frame_child[7];
+    float kp, kd, target;
+};
+struct Params {
+    float dt;
+    int32_t pos_iters, vel_iters, solver;
+    float gravity[3];
+    float plane_z;
+    int32_t plane_enabled;
+    float plane_friction, plane_restitution;
+    float contact_offset, baumgarte, max_depen_vel, joint_baumgarte, bounce_threshold;
+    float lin_damping, ang_damping;
+    int32_t max_contacts_per_env;
+    int32_t debug_export;
+    int32_t joint_iters;
+};
+static_assert(sizeof(BodyDesc) == 88, "body record layout");
+static_assert(sizeof(JointDesc) == 76, "joint record layout");
+
+enum { SPHERE = 0, CAPSULE = 1, BOX = 2 };
+enum { STATIC = 1 };
+enum { ST_NONFINITE = 1, ST_CONTACT_OVERFLOW = 2, ST_COLOR_OVERFLOW = 4 };
+constexpr int PLANE_ID = 0xFFFF;
+constexpr int MAX_COLORS = 64;
+
+// ----------------------------------------------------------------------------- small math
+template <class T> struct V3 { T x, y, z; };
+template <class T> inline V3<T> mk(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <class T> inline V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T> inline V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T> inline V3<T> operator-(V3<T> a) { return {-a.x, -a.y, -a.z}; }
+template <class T> inline V3<T> operator*(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class T> inline T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> inline V3<T> cross(V3<T> a, V3<T> b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class T> inline T len(V3<T> a) { return std::sqrt(dot(a, a)); }
+template <class T> inline V3<T> comp(V3<T> a, int i) { (void)a; return i == 0 ? mk<T>(1, 0, 0) : (i == 1 ? mk<T>(0, 1, 0) : mk<T>(0, 0, 1)); }
+template <class T> inline T get(V3<T> a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+template <class T> inline void set(V3<T>& a, int i, T v) { if (i == 0) a.x = v; else if (i == 1) a.y = v; else a.z = v; }
+
+template <class T> struct Q { T w, x, y, z; };
+template <class T> inline Q<T> qmul(Q<T> a, Q<T> b) {
+    return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z,
+            a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+            a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x,
+            a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+template <class T> inline Q<T> qconj(Q<T> a) { return {a.w, -a.x, -a.y, -a.z}; }
+template <class T> inline Q<T> qnormalize(Q<T> a) {
+    T n = std::sqrt(a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z);
+    T inv = T(1) / n;
+    return {a.w * inv, a.x * inv, a.y * inv, a.z * inv};
+}
+
+// Row-major 3x3.  Rotation matrix of a unit quaternion, written term by term (the AABB of S1
+// depends on these exact operations so that both implementations get identical bits).
+template <class T> struct M3 { T m[3][3]; };
+template <class T> inline M3<T> rotm(Q<T> q) {
+    T xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+    T xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+    T wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+    M3<T> r;
+    r.m[0][0] = T(1) - T(2) * (yy + zz); r.m[0][1] = T(2) * (xy - wz);        r.m[0][2] = T(2) * (xz + wy);
+    r.m[1][0] = T(2) * (xy + wz);        r.m[1][1] = T(1) - T(2) * (xx + zz); r.m[1][2] = T(2) * (yz - wx);
+    r.m[2][0] = T(2) * (xz - wy);        r.m[2][1] = T(2) * (yz + wx);        r.m[2][2] = T(1) - T(2) * (xx + yy);
+    return r;
+}
+template <class T> inline V3<T> mul(const M3<T>& a, V3<T> v) {
+    return {a.m[0][0] * v.x + a.m[0][1] * v.y + a.m[0][2] * v.z,
+            a.m[1][0] * v.x + a.m[1][1] * v.y + a.m[1][2] * v.z,
+            a.m[2][0] * v.x + a.m[2][1] * v.y + a.m[2][2] * v.z};
+}
+template <class T> inline V3<T> mulT(const M3<T>& a, V3<T> v) {
+    return {a.m[0][0] * v.x + a.m[1][0] * v.y + a.m[2][0] * v.z,
+            a.m[0][1] * v.x + a.m[1][1] * v.y + a.m[2][1] * v.z,
+            a.m[0][2] * v.x + a.m[1][2] * v.y + a.m[2][2] * v.z};
+}
+template <class T> inline V3<T> col(const M3<T>& a, int j) { return {a.m[0][j], a.m[1][j], a.m[2][j]}; }
+template <class T> inline V3<T> rotate(Q<T> q, V3<T> v) { return mul(rotm(q), v); }
+
+// Symmetric world inverse inertia R diag(d) R^T.
+template <class T> inline M3<T> world_inv_inertia(Q<T> q, V3<T> d) {
+    M3<T> r = rotm(q), o;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            o.m[i][j] = r.m[i][0] * d.x * r.m[j][0] + r.m[i][1] * d.y * r.m[j][1] + r.m[i][2] * d.z * r.m[j][2];
+    return o;
+}
+
+// ----------------------------------------------------------------------------- mass properties
+// Uniform density; COM at the shape centre.  Box: m/12 (b^2+c^2, ...) with full sides.  Sphere:
+// 2/5 m r^2.  Capsule = cylinder (length L, radius r) + two hemispheres, each hemisphere moved
+// from its own centre of mass (3r/8 from its flat face) to the capsule centre (parallel axes).
+template <class T> inline T shape_volume(int shape, const T* d) {
+    const T pi = T(3.14159265358979323846);
+    if (shape == SPHERE) return T(4) / T(3) * pi * d[0] * d[0] * d[0];
+    if (shape == CAPSULE) {
+        T L = T(2) * d[1];
+        return pi * d[0] * d[0] * L + T(4) / T(3) * pi * d[0] * d[0] * d[0];
+    }
+    return T(8) * d[0] * d[1] * d[2];
+}
+template <class T> inline V3<T> shape_inertia(int shape, const T* d, T mass) {
+    if (shape == SPHERE) { T i = T(2) / T(5) * mass * d[0] * d[0]; return {i, i, i}; }
+    if (shape == BOX) {
+        T a = T(2) * d[0], b = T(2) * d[1], c = T(2) * d[2];
+        return {mass / T(12) * (b * b + c * c), mass / T(12) * (a * a + c * c), mass / T(12) * (a * a + b * b)};
+    }
+    const T pi = T(3.14159265358979323846);
+    T r = d[0], L = T(2) * d[1];
+    T vc = pi * r * r * L, vs = T(4) / T(3) * pi * r * r * r;
+    T rho = mass / (vc + vs);
+    T mc = rho * vc, ms = rho * vs;
+    T izz = mc * r * r / T(2) + ms * T(2) * r * r / T(5);
+    T ixx = mc * (L * L / T(12) + r * r / T(4)) + ms * (T(2) * r * r / T(5) + L * L / T(4) + T(3) * L * r / T(8));
+    return {ixx, ixx, izz};
+}
+
+// ----------------------------------------------------------------------------- scene storage
+template <class T> struct Body {
+    int shape = 0, flags = 0;
+    T dims[3] = {0, 0, 0};
+    T invm = 0;
+    V3<T> invI{0, 0, 0};  // body-frame principal inverse inertia
+    T mu = 0, e = 0;
+    V3<T> x{0, 0, 0};
+    Q<T> q{1, 0, 0, 0};
+    V3<T> v{0, 0, 0}, w{0, 0, 0};
+    bool dyn() const { return !(flags & STATIC); }
+};
+template <class T> struct Joint {
+    int parent, child;
+    V3<T> aA, aB;  // anchors in body frames
+    Q<T> QA, QB;   // joint-frame rotations in body frames
+    T kp, kd, target;
+};
+
+struct PairRec { int32_t env, a, b, npts, decision, kind; double margin, lt1, lt2, ltw, mu, rt; };
+struct PointRec { int32_t env, pair; double p[3], n[3], s, ln; };
+struct BlockRec { int32_t env, kind, index, colour; };
+// Per-env counters for the work model: candidate pairs per shape pair, points, manifolds, joints,
+// colours, dynamic bodies, static bodies.
+enum { CNT_PAIRS_TESTED = 0, CNT_CAND = 1, CNT_POINTS = 2, CNT_MANIFOLDS = 3, CNT_COLOURS = 4,
+       CNT_DYN = 5, CNT_STATIC = 6, CNT_JOINTS = 7, CNT_KIND0 = 8, N_CNT = 8 + 12 };
+
+// ----------------------------------------------------------------------------- narrowphase
+template <class T> struct Pt { V3<T> p, n; T s; };
+template <class T> struct Out {
+    Pt<T> pt[16];
+    int n = 0;
+    int decision = 0;
+    double margin = 1e30;  // distance of this pair's discrete decisions to their thresholds
+    void note(double m) { m = std::fabs(m); if (m < margin) margin = m; }
+};
+
+template <class T> struct Shape {
+    int type;
+    V3<T> c;
+    M3<T> R;
+    T d[3];
+    // capsule segment end points
+    V3<T> p0() const { return c - d[1] * col(R, 2); }
+    V3<T> p1() const { return c + d[1] * col(R, 2); }
+};
+
+// Witness midpoint record: pa on A's surface, pb on B's surface, n from A to B.
+template <class T> inline void emit(Out<T>& o, V3<T> pa, V3<T> pb, V3<T> n, T s, T delta) {
+    o.note(double(s) - double(delta));
+    if (s < delta && o.n < 16) { o.pt[o.n++] = Pt<T>{T(0.5) * (pa + pb), n, s}; }
+}
+
+// Closest points of segments P(s) = p1 + s d1 and Q(t) = p2 + t d2, s, t in [0, 1]
+// (the clamped-parameter method of Ericson, RTCD 5.1.9, restated).
+template <class T> inline void seg_seg(V3<T> p1, V3<T> q1, V3<T> p2, V3<T> q2, T& s, T& t) {
+    V3<T> d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
+    T a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+    const T eps = T(1e-12);
+    auto clamp01 = [](T v) { return v < T(0) ? T(0) : (v > T(1) ? T(1) : v); };
+    if (a <= eps && e <= eps) { s = 0; t = 0; return; }
+    if (a <= eps) { s = 0; t = clamp01(f / e); return; }
+    T c = dot(d1, r);
+    if (e <= eps) { t = 0; s = clamp01(-c / a); return; }
+    T b = dot(d1, d2);
+    T denom = a * e - b * b;
+    s = denom != T(0) ? clamp01((b * f - c * e) / denom) : T(0);
+    t = (b * s + f) / e;
+    if (t < T(0)) { t = 0; s = clamp01(-c / a); }
+    else if (t > T(1)) { t = 1; s = clamp01((b - c) / a); }
+}
+template <class T> inline T closest_on_seg(V3<T> p0, V3<T> p1, V3<T> x) {
+    V3<T> d = p1 - p0;
+    T dd = dot(d, d);
+    if (dd <= T(1e-12)) return T(0);
+    T t = dot(x - p0, d) / dd;
+    return t < T(0) ? T(0) : (t > T(1) ? T(1) : t);
+}
+
+// N4: two spheres; n from A to B (+z when the centres coincide).
+template <class T> inline void sphere_sphere(Out<T>& o, V3<T> ca, T ra, V3<T> cb, T rb, T delta) {
+    V3<T> d = cb - ca;
+    T dist = len(d);
+    V3<T> n = dist < T(1e-9) ? mk<T>(0, 0, 1) : (T(1) / dist) * d;
+    T s = dist - ra - rb;
+    emit(o, ca + ra * n, cb - rb * n, n, s, delta);
+}
+
+// Plane (always A, normal +z) against a sphere of centre c.
+template <class T> inline void plane_sphere(Out<T>& o, T pz, V3<T> c, T r, T delta) {
+    V3<T> n = mk<T>(0, 0, 1);
+    T s = c.z - pz - r;
+    emit(o, mk<T>(c.x, c.y, pz), c - r * n, n, s, delta);
+}
+
+// N2: box corners below plane_z + delta, in corner index order (bit k of the index = + side).
+template <class T> inline void plane_box(Out<T>& o, T pz, const Shape<T>& b, T delta) {
+    for (int k = 0; k < 8; ++k) {
+        V3<T> l = mk<T>((k & 1) ? b.d[0] : -b.d[0], (k & 2) ? b.d[1] : -b.d[1], (k & 4) ? b.d[2] : -b.d[2]);
+        V3<T> c = b.c + mul(b.R, l);
+        T s = c.z - pz;
+        emit(o, mk<T>(c.x, c.y, pz), c, mk<T>(0, 0, 1), s, delta);
+    }
+}
+
+// N7: box vs sphere, n from the box to the sphere.
+template <class T> inline void box_sphere(Out<T>& o, const Shape<T>& bx, V3<T> c, T r, T delta) {
+    V3<T> l = mulT(bx.R, c - bx.c);
+    V3<T> q = l;
+    for (int i = 0; i < 3; ++i) {
+        T v = get(l, i), h = bx.d[i];
+        set(q, i, v < -h ? -h : (v > h ? h : v));
+    }
+    V3<T> dl = l - q;
+    T d2 = dot(dl, dl);
+    if (d2 > T(0)) {
+        o.decision = 0;
+        T dist = std::sqrt(d2);
+        V3<T> n = mul(bx.R, (T(1) / dist) * dl);
+        emit(o, bx.c + mul(bx.R, q), c - r * n, n, dist - r, delta);
+        o.note(double(dist));
+    } else {
+        // centre inside: least-penetration face (lowest axis on ties)
+        int best = 0;
+        T bd = bx.d[0] - std::fabs(l.x);
+        for (int i = 1; i < 3; ++i) {
+            T di = bx.d[i] - std::fabs(get(l, i));
+            if (di < bd) { o.note(double(bd) - double(di)); bd = di; best = i; }
+            else o.note(double(di) - double(bd));
+        }
+        T sg = get(l, best) >= T(0) ? T(1) : T(-1);
+        V3<T> nl = mk<T>(0, 0, 0);
+        set(nl, best, sg);
+        V3<T> n = mul(bx.R, nl);
+        V3<T> face = l;
+        set(face, best, sg * bx.d[best]);
+        o.decision = 1 + best;
+        emit(o, bx.c + mul(bx.R, face), c - r * n, n, -bd - r, delta);
+    }
+}
+
+// Shapes' support half-width along unit axis L.
+template <class T> inline T box_extent(const Shape<T>& b, V3<T> L) {
+    return (b.d[0] * std::fabs(dot(col(b.R, 0), L)) + b.d[1] * std::fabs(dot(col(b.R, 1), L))) +
+           b.d[2] * std::fabs(dot(col(b.R, 2), L));
+}
+template <class T> inline T tie_tol(T s, T hmin) { return T(0.05) * std::fabs(s) + T(0.01) * hmin; }
+
+// Clip the parameter interval [t0, t1] of segment p0 + t (p1 - p0) to the slab |(x - c).a| <= h.
+template <class T> inline void clip_slab(V3<T> p0, V3<T> p1, V3<T> c, V3<T> a, T h, T& t0, T& t1) {
+    T u0 = dot(p0 - c, a), du = dot(p1 - p0, a);
+    if (std::fabs(du) < T(1e-12)) {
+        if (u0 > h || u0 < -h) { t0 = T(1); t1 = T(0); }
+        return;
+    }
+    T ta = (-h - u0) / du, tb = (h - u0) / du;
+    if (ta > tb) std::swap(ta, tb);
+    if (ta > t0) t0 = ta;
+    if (tb < t1) t1 = tb;
+}
+
+// N8: box vs capsule, n from the box to the capsule.  Separating axes: the 3 box face normals,
+// then axis x box edge for the 3 edge directions.  Face axes are preferred; an edge axis wins
+// only when its separation exceeds the best face's by more than the tie tolerance.
+template <class T> inline void box_capsule(Out<T>& o, const Shape<T>& bx, const Shape<T>& cp, T delta) {
+    V3<T> P0 = cp.p0(), P1 = cp.p1(), u = col(cp.R, 2);
+    T rc = cp.d[0], hl = cp.d[1];
+    V3<T> dc = cp.c - bx.c;
+    T sep[6];
+    V3<T> ax[6];
+    bool valid[6];
+    for (int i = 0; i < 3; ++i) {
+        V3<T> L = col(bx.R, i);
+        if (dot(L, dc) < T(0)) L = -L;
+        ax[i] = L; valid[i] = true;
+        sep[i] = dot(dc, L) - hl * std::fabs(dot(u, L)) - bx.d[i] - rc;
+    }
+    for (int i = 0; i < 3; ++i) {
+        V3<T> L = cross(u, col(bx.R, i));
+        T l = len(L);
+        valid[3 + i] = l >= T(1e-6);
+        if (!valid[3 + i]) { sep[3 + i] = T(-1e30); ax[3 + i] = mk<T>(0, 0, 0); continue; }
+        L = (T(1) / l) * L;
+        if (dot(L, dc) < T(0)) L = -L;
+        ax[3 + i] = L;
+        sep[3 + i] = dot(dc, L) - hl * std::fabs(dot(u, L)) - box_extent(bx, L) - rc;
+    }
+    T hmin = std::min(std::min(bx.d[0], bx.d[1]), std::min(bx.d[2], rc));
+    int bf = 0;
+    for (int i = 1; i < 3; ++i) { o.note(double(sep[i]) - double(sep[bf])); if (sep[i] > sep[bf]) bf = i; }
+    int be = -1;
+    for (int i = 3; i < 6; ++i)
+        if (valid[i]) { if (be >= 0) o.note(double(sep[i]) - double(sep[be])); if (be < 0 || sep[i] > sep[be]) be = i; }
+    int best = bf;
+    if (be >= 0) {
+        T thr = sep[bf] + tie_tol(sep[bf], hmin);
+        o.note(double(sep[be]) - double(thr));
+        if (sep[be] > thr) best = be;
+    }
+    T smax = sep[0];
+    for (int i = 1; i < 6; ++i) if (valid[i] && sep[i] > smax) smax = sep[i];
+    o.note(double(smax) - double(delta));
+    o.decision = best;
+    if (smax >= delta) return;
+    if (best < 3) {
+        int i = best;
+        V3<T> nr = ax[i];
+        int j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+        T t0 = 0, t1 = 1;
+        clip_slab(P0, P1, bx.c, col(bx.R, j1), bx.d[j1], t0, t1);
+        clip_slab(P0, P1, bx.c, col(bx.R, j2), bx.d[j2], t0, t1);
+        o.note(double(t1) - double(t0));
+        if (t0 <= t1) {
+            T ts[2] = {t0, t1};
+            int np = t1 > t0 ? 2 : 1;
+            for (int k = 0; k < np; ++k) {
+                V3<T> C = P0 + ts[k] * (P1 - P0);
+                T above = dot(C - bx.c, nr) - bx.d[i];
+                emit(o, C - above * nr, C - rc * nr, nr, above - rc, delta);
+            }
+        } else {
+            // Segment outside the face's prism: nearest of the face's 4 boundary edges.
+            o.decision = 6 + i;
+            T bestd = T(1e30);
+            V3<T> bs{0, 0, 0}, be2{0, 0, 0};
+            V3<T> fc = bx.c + bx.d[i] * nr;
+            for (int k = 0; k < 4; ++k) {
+                int along = (k < 2) ? j1 : j2, other = (k < 2) ? j2 : j1;
+                T sg = (k & 1) ? T(1) : T(-1);
+                V3<T> ec = fc + (sg * bx.d[other]) * col(bx.R, other);
+                V3<T> e0 = ec - bx.d[along] * col(bx.R, along), e1 = ec + bx.d[along] * col(bx.R, along);
+                T s, t;
+                seg_seg(P0, P1, e0, e1, s, t);
+                V3<T> cs = P0 + s * (P1 - P0), ce = e0 + t * (e1 - e0);
+                V3<T> dd = cs - ce;
+                T d2 = dot(dd, dd);
+                if (k > 0) o.note(double(d2) - double(bestd));
+                if (d2 < bestd) { bestd = d2; bs = cs; be2 = ce; }
+            }
+            T dist = std::sqrt(bestd);
+            V3<T> n = dist > T(1e-9) ? (T(1) / dist) * (bs - be2) : nr;
+            emit(o, be2, bs - rc * n, n, dist - rc, delta);
+        }
+    } else {
+        int i = best - 3;
+        V3<T> L = ax[best];
+        V3<T> ec = bx.c;
+        for (int j = 0; j < 3; ++j) {
+            if (j == i) continue;
+            T dj = dot(col(bx.R, j), L);
+            o.note(double(dj));
+            ec = ec + ((dj >= T(0) ? T(1) : T(-1)) * bx.d[j]) * col(bx.R, j);
+        }
+        V3<T> e0 = ec - bx.d[i] * col(bx.R, i), e1 = ec + bx.d[i] * col(bx.R, i);
+        T s, t;
+        seg_seg(P0, P1, e0, e1, s, t);
+        V3<T> cs = P0 + s * (P1 - P0), ce = e0 + t * (e1 - e0);
+        T sp = dot(cs - ce, L) - rc;
+        emit(o, ce, cs - rc * L, L, sp, delta);
+    }
+}
+
+// Sutherland-Hodgman: keep the part of polygon `in` with dot(x, a) <= off.
+template <class T> inline int clip_poly(const V3<T>* in, int n, V3<T> a, T off, V3<T>* out) {
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        V3<T> p = in[k], q = in[(k + 1) % n];
+        T dp = dot(p, a) - off, dq = dot(q, a) - off;
+        if (dp <= T(0)) out[m++] = p;
+        if ((dp < T(0) && dq > T(0)) || (dp > T(0) && dq < T(0))) {
+            T t = dp / (dp - dq);
+            out[m++] = p + t * (q - p);
+        }
+    }
+    return m;
+}
+
+// N9: box vs box, n from A to B.  15 separating axes (A faces, B faces, 9 edge crosses).
+template <class T> inline void box_box(Out<T>& o, const Shape<T>& A, const Shape<T>& B, T delta) {
+    V3<T> d = B.c - A.c;
+    T sep[15];
+    V3<T> ax[15];
+    bool valid[15];
+    for (int k = 0; k < 15; ++k) {
+        V3<T> L;
+        if (k < 3) L = col(A.R, k);
+        else if (k < 6) L = col(B.R, k - 3);
+        else {
+            L = cross(col(A.R, (k - 6) / 3), col(B.R, (k - 6) % 3));
+            T l = len(L);
+            if (l < T(1e-6)) { valid[k] = false; sep[k] = T(-1e30); ax[k] = mk<T>(0, 0, 0); continue; }
+            L = (T(1) / l) * L;
+        }
+        if (dot(L, d) < T(0)) L = -L;
+        valid[k] = true;
+        ax[k] = L;
+        sep[k] = dot(d, L) - box_extent(A, L) - box_extent(B, L);
+    }
+    T hmin = std::min(std::min(std::min(A.d[0], A.d[1]), std::min(A.d[2], B.d[0])), std::min(B.d[1], B.d[2]));
+    int fa = 0, fb = 3, fe = -1;
+    for (int k = 1; k < 3; ++k) { o.note(double(sep[k]) - double(sep[fa])); if (sep[k] > sep[fa]) fa = k; }
+    for (int k = 4; k < 6; ++k) { o.note(double(sep[k]) - double(sep[fb])); if (sep[k] > sep[fb]) fb = k; }
+    for (int k = 6; k < 15; ++k)
+        if (valid[k]) { if (fe >= 0) o.note(double(sep[k]) - double(sep[fe])); if (fe < 0 || sep[k] > sep[fe]) fe = k; }
+    int best = fb;
+    {
+        T thr = sep[fb] + tie_tol(sep[fb], hmin);
+        o.note(double(sep[fa]) - double(thr));
+        if (sep[fa] > thr) best = fa;
+    }
+    if (fe >= 0) {
+        T thr = sep[best] + tie_tol(sep[best], hmin);
+        o.note(double(sep[fe]) - double(thr));
+        if (sep[fe] > thr) best = fe;
+    }
+    T smax = sep[0];
+    for (int k = 1; k < 15; ++k) if (valid[k] && sep[k] > smax) smax = sep[k];
+    o.note(double(smax) - double(delta));
+    o.decision = best;
+    if (smax >= delta) return;
+
+    if (best < 6) {
+        bool refA = best < 3;
+        const Shape<T>& Rf = refA ? A : B;
+        const Shape<T>& In = refA ? B : A;
+        int ri = refA ? best : best - 3;
+        V3<T> nref = refA ? ax[best] : -ax[best];  // outward normal of the reference face, toward In
+        // incident face: most anti-parallel to nref (lowest axis on ties)
+        int ii = 0;
+        T bd = std::fabs(dot(col(In.R, 0), nref));
+        for (int j = 1; j < 3; ++j) {
+            T dj = std::fabs(dot(col(In.R, j), nref));
+            o.note(double(dj) - double(bd));
+            if (dj > bd) { bd = dj; ii = j; }
+        }
+        T sgn = dot(col(In.R, ii), nref) >= T(0) ? T(-1) : T(1);
+        V3<T> fcen = In.c + (sgn * In.d[ii]) * col(In.R, ii);
+        int u = (ii + 1) % 3, v = (ii + 2) % 3;
+        V3<T> U = In.d[u] * col(In.R, u), W = In.d[v] * col(In.R, v);
+        V3<T> poly[16], tmp[16];
+        poly[0] = fcen + U + W; poly[1] = fcen - U + W; poly[2] = fcen - U - W; poly[3] = fcen + U - W;
+        int n = 4;
+        int r1 = (ri + 1) % 3, r2 = (ri + 2) % 3;
+        V3<T> a1 = col(Rf.R, r1), a2 = col(Rf.R, r2);
+        n = clip_poly(poly, n, a1, dot(Rf.c, a1) + Rf.d[r1], tmp);
+        n = clip_poly(tmp, n, -a1, -dot(Rf.c, a1) + Rf.d[r1], poly);
+        n = clip_poly(poly, n, a2, dot(Rf.c, a2) + Rf.d[r2], tmp);
+        n = clip_poly(tmp, n, -a2, -dot(Rf.c, a2) + Rf.d[r2], poly);
+        V3<T> nAB = refA ? nref : -nref;
+        for (int k = 0; k < n; ++k) {
+            V3<T> p = poly[k];
+            T s = dot(p - Rf.c, nref) - Rf.d[ri];
+            V3<T> onref = p - s * nref;
+            if (refA) emit(o, onref, p, nAB, s, delta);
+            else emit(o, p, onref, nAB, s, delta);
+        }
+    } else {
+        int ia = (best - 6) / 3, ib = (best - 6) % 3;
+        V3<T> L = ax[best];
+        V3<T> ca = A.c, cb = B.c;
+        for (int j = 0; j < 3; ++j) {
+            if (j != ia) { T dj = dot(col(A.R, j), L); o.note(double(dj)); ca = ca + ((dj >= T(0) ? T(1) : T(-1)) * A.d[j]) * col(A.R, j); }
+            if (j != ib) { T dj = dot(col(B.R, j), L); o.note(double(dj)); cb = cb + ((dj >= T(0) ? T(-1) : T(1)) * B.d[j]) * col(B.R, j); }
+        }
+        V3<T> a0 = ca - A.d[ia] * col(A.R, ia), a1 = ca + A.d[ia] * col(A.R, ia);
+        V3<T> b0 = cb - B.d[ib] * col(B.R, ib), b1 = cb + B.d[ib] * col(B.R, ib);
+        T s, t;
+        seg_seg(a0, a1, b0, b1, s, t);
+        V3<T> pa = a0 + s * (a1 - a0), pb = b0 + t * (b1 - b0);
+        emit(o, pa, pb, L, dot(pb - pa, L), delta);
+    }
+}
+
+// N6: capsule vs capsule, n from A to B.
+template <class T> inline void capsule_capsule(Out<T>& o, const Shape<T>& A, const Shape<T>& B, T delta) {
+    V3<T> a0 = A.p0(), a1 = A.p1(), b0 = B.p0(), b1 = B.p1();
+    V3<T> d1 = a1 - a0, d2 = b1 - b0;
+    V3<T> cr = cross(d1, d2);
+    T lhs = dot(cr, cr), rhs = T(1e-6) * dot(d1, d1) * dot(d2, d2);
+    o.note(double(lhs) - double(rhs));
+    if (lhs < rhs) {
+        // parallel: the overlap of B's projection onto A's segment gives two points
+        T dd = dot(d1, d1);
+        T s0 = dot(b0 - a0, d1) / dd, s1 = dot(b1 - a0, d1) / dd;
+        T lo = std::max(T(0), std::min(s0, s1)), hi = std::min(T(1), std::max(s0, s1));
+        o.note(double(hi) - double(lo));
+        if (lo < hi) {
+            o.decision = 1;
+            T ss[2] = {lo, hi};
+            for (int k = 0; k < 2; ++k) {
+                V3<T> pa = a0 + ss[k] * d1;
+                T t = closest_on_seg(b0, b1, pa);
+                sphere_sphere(o, pa, A.d[0], b0 + t * d2, B.d[0], delta);
+            }
+            return;
+        }
+    }
+    o.decision = 0;
+    T s, t;
+    seg_seg(a0, a1, b0, b1, s, t);
+    sphere_sphere(o, a0 + s * d1, A.d[0], b0 + t * d2, B.d[0], delta);
+}
+
+template <class T> inline void flip(Out<T>& o, int from) {
+    for (int k = from; k < o.n; ++k) o.pt[k].n = -o.pt[k].n;
+}
+
+// Type dispatch for two bodies (A = lower index).  kind = 3 * min(shape) + max(shape) style code.
+template <class T> inline void narrow(Out<T>& o, const Shape<T>& A, const Shape<T>& B, T delta) {
+    int ta = A.type, tb = B.type;
+    if (ta == SPHERE && tb == SPHERE) { sphere_sphere(o, A.c, A.d[0], B.c, B.d[0], delta); return; }
+    if (ta == SPHERE && tb == CAPSULE) {
+        T t = closest_on_seg(B.p0(), B.p1(), A.c);
+        sphere_sphere(o, A.c, A.d[0], B.p0() + t * (B.p1() - B.p0()), B.d[0], delta);
+        return;
+    }
+    if (ta == CAPSULE && tb == SPHERE) {
+        T t = closest_on_seg(A.p0(), A.p1(), B.c);
+        sphere_sphere(o, A.p0() + t * (A.p1() - A.p0()), A.d[0], B.c, B.d[0], delta);
+        return;
+    }
+    if (ta == CAPSULE && tb == CAPSULE) { capsule_capsule(o, A, B, delta); return; }
+    if (ta == BOX && tb == SPHERE) { box_sphere(o, A, B.c, B.d[0], delta); return; }
+    if (ta == SPHERE && tb == BOX) { box_sphere(o, B, A.c, A.d[0], delta); flip(o, 0); return; }
+    if (ta == BOX && tb == CAPSULE) { box_capsule(o, A, B, delta); return; }
+    if (ta == CAPSULE && tb == BOX) { box_capsule(o, B, A, delta); flip(o, 0); return; }
+    box_box(o, A, B, delta);
+}
+
+template <class T> inline void narrow_plane(Out<T>& o, T pz, const Shape<T>& B, T delta) {
+    if (B.type == SPHERE) plane_sphere(o, pz, B.c, B.d[0], delta);
+    else if (B.type == CAPSULE) { plane_sphere(o, pz, B.p0(), B.d[0], delta); plane_sphere(o, pz, B.p1(), B.d[0], delta); }
+    else plane_box(o, pz, B, delta);
+}
+
+// Manifold reduction to at most 4 points: deepest; farthest from it; largest triangle; the point
+// adding the most area outside the triangle.  Lowest index wins every tie.  Kept points stay in
+// their original order.
+template <class T> inline void reduce4(Out<T>& o) {
+    if (o.n <= 4) return;
+    int n = o.n;
+    bool used[16] = {false};
+    int k0 = 0;
+    for (int k = 1; k < n; ++k) { o.note(double(o.pt[k].s) - double(o.pt[k0].s)); if (o.pt[k].s < o.pt[k0].s) k0 = k; }
+    used[k0] = true;
+    int k1 = -1; T b1 = T(-1);
+    for (int k = 0; k < n; ++k) {
+        if (used[k]) continue;
+        V3<T> d = o.pt[k].p - o.pt[k0].p;
+        T v = dot(d, d);
+        if (k1 >= 0) o.note(double(v) - double(b1));
+        if (v > b1) { b1 = v; k1 = k; }
+    }
+    used[k1] = true;
+    int k2 = -1; T b2 = T(-1);
+    V3<T> e01 = o.pt[k1].p - o.pt[k0].p;
+    for (int k = 0; k < n; ++k) {
+        if (used[k]) continue;
+        V3<T> c = cross(e01, o.pt[k].p - o.pt[k0].p);
+        T v = dot(c, c);
+        if (k2 >= 0) o.note(double(v) - double(b2));
+        if (v > b2) { b2 = v; k2 = k; }
+    }
+    used[k2] = true;
+    V3<T> nt = cross(e01, o.pt[k2].p - o.pt[k0].p);
+    int tri[3] = {k0, k1, k2};
+    int k3 = -1; T b3 = T(-1e30);
+    for (int k = 0; k < n; ++k) {
+        if (used[k]) continue;
+        T best = T(-1e30);
+        for (int e = 0; e < 3; ++e) {
+            V3<T> pa = o.pt[tri[e]].p, pb = o.pt[tri[(e + 1) % 3]].p;
+            T v = -dot(cross(pb - pa, o.pt[k].p - pa), nt);
+            if (v > best) best = v;
+        }
+        if (k3 >= 0) o.note(double(best) - double(b3));
+        if (best > b3) { b3 = best; k3 = k; }
+    }
+    used[k3] = true;
+    int m = 0;
+    for (int k = 0; k < n; ++k) if (used[k]) o.pt[m++] = o.pt[k];
+    o.n = m;
+}
+
+// ----------------------------------------------------------------------------- solver rows
+// One contact point: the normal row.
+template <class T> struct CRow {
+    int a, b;  // body indices, -1 = plane/world
+    V3<T> rA, rB, n;
+    T mn, s0, e, vnpre;
+    T ln;
+};
+// One manifold: its points' normal rows plus the friction patch at the points' centroid (two
+// tangent rows bounded by mu times the summed normal impulse, and a torsional row about the
+// mean normal bounded by mu times the mean point radius times the summed normal impulse).
+template <class T> struct Manifold {
+    int a, b, first, count, colour, pair;
+    V3<T> rA, rB, nb, t1, t2;
+    T mt1, mt2, mtw, mu, rt;
+    T lt1, lt2, ltw;
+};
+template <class T> struct JState { T lp[3], la[2], ld; };
+
+template <class T> struct Env {
+    std::vector<Body<T>> bodies;
+    std::vector<Joint<T>> joints;
+    int status = 0;
+};
+
+template <class T> struct StepCtx {
+    const Params* P;
+    T delta, plane_z;
+    bool plane;
+    T plane_mu, plane_e;
+};
+
+template <class T> struct BodyView {
+    T invm;
+    M3<T> Iw;  // world inverse inertia, frozen for the step
+};
+
+template <class T> inline V3<T> vel_at(const Body<T>* b, V3<T> r) {
+    if (!b) return mk<T>(0, 0, 0);
+    return b->v + cross(b->w, r);
+}
+
+// Duff et al. 2017 branchless orthonormal basis of unit n: returns t1 (t2 = n x t1).
+template <class T> inline V3<T> onb_t1(V3<T> n) {
+    T sg = std::copysign(T(1), n.z);
+    T a = T(-1) / (sg + n.z);
+    T b = n.x * n.y * a;
+    return mk<T>(T(1) + sg * n.x * n.x * a, sg * b, -sg * n.x);
+}
+
+// Result of one env step for the test record.
+struct EnvRecord {
+    std::vector<PairRec> pairs;
+    std::vector<PointRec> points;
+    std::vector<BlockRec> blocks;
+    int64_t cnt[N_CNT];
+    double min_margin;
+};
+
+template <class T> struct Stepper {
+    const Params& P;
+    Env<T>& E;
+    EnvRecord* rec;
+    int env_id;
+    // per-step working state
+    std::vector<BodyView<T>> bv;
+    std::vector<V3<T>> x0, dx;  // step-start centre and its offset accumulated over substeps
+    std::vector<Q<T>> q0, dq;   // step-start orientation and the rotation accumulated since
+    std::vector<CRow<T>> rows;
+    std::vector<Manifold<T>> mans;
+    std::vector<JState<T>> js;
+    int ncol = 0;
+    std::vector<std::pair<int, int>> order;  // (colour, block id) solve order
+    T h = 0;
+
+    Stepper(const Params& p, Env<T>& e, EnvRecord* r, int id) : P(p), E(e), rec(r), env_id(id) {}
+
+    T invm(int i) const { return i < 0 ? T(0) : bv[i].invm; }
+    M3<T> Iw(int i) const { if (i < 0) { M3<T> z{}; return z; } return bv[i].Iw; }
+    bool dyn(int i) const { return i >= 0 && E.bodies[i].dyn(); }
+
+    Shape<T> shape_of(int i) const {
+        const Body<T>& b = E.bodies[i];
+        Shape<T> s;
+        s.type = b.shape;
+        s.c = b.x;
+        s.R = rotm(b.q);
+        s.d[0] = b.dims[0]; s.d[1] = b.dims[1]; s.d[2] = b.dims[2];
+        return s;
+    }
+
+    // Apply an impulse P (world) at arms rA, rB: -P on A, +P on B.
+    void apply(int a, int b, V3<T> rA, V3<T> rB, V3<T> Pv) {
+        if (dyn(a)) {
+            Body<T>& A = E.bodies[a];
+            A.v = A.v - invm(a) * Pv;
+            A.w = A.w - mul(bv[a].Iw, cross(rA, Pv));
+        }
+        if (dyn(b)) {
+            Body<T>& B = E.bodies[b];
+            B.v = B.v + invm(b) * Pv;
+            B.w = B.w + mul(bv[b].Iw, cross(rB, Pv));
+        }
+    }
+    void apply_ang(int a, int b, V3<T> Lv) {
+        if (dyn(a)) E.bodies[a].w = E.bodies[a].w - mul(bv[a].Iw, Lv);
+        if (dyn(b)) E.bodies[b].w = E.bodies[b].w + mul(bv[b].Iw, Lv);
+    }
+    T eff(int a, int b, V3<T> rA, V3<T> rB, V3<T> x) const {
+        T k = invm(a) + invm(b);
+        if (a >= 0) { V3<T> c = cross(rA, x); k = k + dot(c, mul(bv[a].Iw, c)); }
+        if (b >= 0) { V3<T> c = cross(rB, x); k = k + dot(c, mul(bv[b].Iw, c)); }
+        return k > T(0) ? T(1) / k : T(0);
+    }
+
+    // ------------------------------------------------------------- S0..S5: detection and rows
+    void prepare(double& min_margin, int64_t* cnt) {
+        const int n = int(E.bodies.size());
+        const T delta = T(P.contact_offset);
+        bv.resize(n); x0.resize(n); q0.resize(n); dx.assign(n, mk<T>(0, 0, 0)); dq.assign(n, Q<T>{1, 0, 0, 0});
+        for (int i = 0; i < n; ++i) {
+            Body<T>& b = E.bodies[i];
+            x0[i] = b.x; q0[i] = b.q;
+            bv[i].invm = b.dyn() ? b.invm : T(0);
+            bv[i].Iw = b.dyn() ? world_inv_inertia(b.q, b.invI) : M3<T>{};
+            if (b.dyn()) cnt[CNT_DYN]++; else cnt[CNT_STATIC]++;
+        }
+        // S1: AABBs from the start-of-step pose; add, multiply, abs and compare only.
+        std::vector<V3<T>> lo(n), hi(n);
+        for (int i = 0; i < n; ++i) {
+            const Body<T>& b = E.bodies[i];
+            M3<T> R = rotm(b.q);
+            V3<T> half;
+            for (int r = 0; r < 3; ++r) {
+                T hv;
+                if (b.shape == BOX)
+                    hv = (std::fabs(R.m[r][0]) * b.dims[0] + std::fabs(R.m[r][1]) * b.dims[1]) + std::fabs(R.m[r][2]) * b.dims[2];
+                else if (b.shape == SPHERE) hv = b.dims[0];
+                else hv = std::fabs(R.m[r][2]) * b.dims[1] + b.dims[0];
+                set(half, r, hv + delta);
+            }
+            lo[i] = b.x - half;
+            hi[i] = b.x + half;
+        }
+        // Joint filter: parent-child pairs never collide.
+        std::vector<uint64_t> jmask(n, 0);
+        for (const Joint<T>& j : E.joints)
+            if (j.parent >= 0) { jmask[j.parent] |= uint64_t(1) << j.child; jmask[j.child] |= uint64_t(1) << j.parent; }
+
+        const int cap = P.max_contacts_per_env > 0 ? P.max_contacts_per_env : 8 * n + 16;
+        rows.clear(); mans.clear();
+        // S2 + S3 in canonical order: for each a, partners b = a+1 .. n-1, then the plane.
+        for (int a = 0; a < n; ++a) {
+            for (int bb = a + 1; bb <= n; ++bb) {
+                bool isplane = bb == n;
+                cnt[CNT_PAIRS_TESTED]++;
+                const Body<T>& A = E.bodies[a];
+                if (isplane) {
+                    if (!P.plane_enabled || !A.dyn()) continue;
+                    if (!(lo[a].z <= T(P.plane_z))) continue;
+                } else {
+                    const Body<T>& B = E.bodies[bb];
+                    if (!A.dyn() && !B.dyn()) continue;
+                    if (jmask[a] >> bb & 1) continue;
+                    if (!(lo[a].x <= hi[bb].x && lo[bb].x <= hi[a].x && lo[a].y <= hi[bb].y && lo[bb].y <= hi[a].y &&
+                          lo[a].z <= hi[bb].z && lo[bb].z <= hi[a].z))
+                        continue;
+                }
+                cnt[CNT_CAND]++;
+                Out<T> o;
+                int kind;
+                V3<T> base, offB;  // contact points come relative to `base`; B's centre is at offB
+                if (isplane) {
+                    kind = 9 + A.shape;  // 9 plane-sphere, 10 plane-capsule, 11 plane-box
+                    // frame: origin at (x, y) of the body on the ground plane
+                    Shape<T> sb = shape_of(a);
+                    base = mk(A.x.x, A.x.y, T(P.plane_z));
+                    sb.c = mk(T(0), T(0), A.x.z - T(P.plane_z));
+                    narrow_plane(o, T(0), sb, delta);
+                    offB = sb.c;
+                } else {
+                    int sa = A.shape, sb = E.bodies[bb].shape;
+                    int lo_s = std::min(sa, sb), hi_s = std::max(sa, sb);
+                    kind = lo_s * 3 + hi_s;  // 0 ss,1 sc,2 sb,4 cc,5 cb,8 bb
+                    // frame: origin at A's centre (translation-invariant contact geometry)
+                    Shape<T> sa2 = shape_of(a), sb2 = shape_of(bb);
+                    base = A.x;
+                    sa2.c = mk<T>(0, 0, 0);
+                    sb2.c = E.bodies[bb].x - A.x;
+                    narrow(o, sa2, sb2, delta);
+                    offB = sb2.c;
+                }
+                cnt[CNT_KIND0 + kind]++;
+                reduce4(o);
+                if (o.margin < min_margin) min_margin = o.margin;
+                int pair_index = rec ? int(rec->pairs.size()) : 0;
+                int first = int(rows.size());
+                int keep = o.n;
+                if (first + keep > cap) { keep = cap - first; E.status |= ST_CONTACT_OVERFLOW; }
+                if (rec) rec->pairs.push_back(PairRec{env_id, a, isplane ? PLANE_ID : bb, keep, o.decision, kind, o.margin,
+                                                      0, 0, 0, 0, 0});
+                if (keep <= 0) continue;
+                int ia = isplane ? -1 : a, ib = isplane ? a : bb;
+                T mu, e;
+                if (isplane) { mu = (T(P.plane_friction) + A.mu) / T(2); e = std::max(T(P.plane_restitution), A.e); }
+                else { mu = (A.mu + E.bodies[bb].mu) / T(2); e = std::max(A.e, E.bodies[bb].e); }
+                // S4: one normal row per point (arms from the step-start centres).
+                V3<T> csum = mk<T>(0, 0, 0), nsum = mk<T>(0, 0, 0);
+                for (int k = 0; k < keep; ++k) {
+                    CRow<T> r;
+                    r.a = ia; r.b = ib;
+                    V3<T> p = o.pt[k].p;  // relative to `base`
+                    r.n = o.pt[k].n;
+                    r.rA = ia >= 0 ? p : mk<T>(0, 0, 0);
+                    r.rB = p - offB;
+                    V3<T> vrel = vel_at(&E.bodies[ib], r.rB) - (ia >= 0 ? vel_at(&E.bodies[ia], r.rA) : mk<T>(0, 0, 0));
+                    r.vnpre = dot(vrel, r.n);
+                    r.mn = eff(ia, ib, r.rA, r.rB, r.n);
+                    r.s0 = o.pt[k].s;
+                    r.e = e;
+                    r.ln = 0;
+                    rows.push_back(r);
+                    csum = csum + p;
+                    nsum = nsum + r.n;
+                }
+                // Friction patch at the centroid; tangent t1 along the pre-step sliding velocity
+                // there, else the Duff et al. basis of the mean normal.
+                Manifold<T> M;
+                M.a = ia; M.b = ib; M.first = first; M.count = keep; M.colour = 0; M.pair = pair_index;
+                V3<T> c = (T(1) / T(keep)) * csum;
+                M.nb = (T(1) / len(nsum)) * nsum;
+                M.rA = ia >= 0 ? c : mk<T>(0, 0, 0);
+                M.rB = c - offB;
+                V3<T> vrel = vel_at(&E.bodies[ib], M.rB) - (ia >= 0 ? vel_at(&E.bodies[ia], M.rA) : mk<T>(0, 0, 0));
+                V3<T> vt = vrel - dot(vrel, M.nb) * M.nb;
+                T vtl = len(vt);
+                if (std::fabs(double(vtl) - 1e-3) < min_margin) min_margin = std::fabs(double(vtl) - 1e-3);
+                M.t1 = vtl >= T(1e-3) ? (T(1) / vtl) * vt : onb_t1(M.nb);
+                M.t2 = cross(M.nb, M.t1);
+                M.mt1 = eff(ia, ib, M.rA, M.rB, M.t1);
+                M.mt2 = eff(ia, ib, M.rA, M.rB, M.t2);
+                T kw = (ia >= 0 ? dot(M.nb, mul(bv[ia].Iw, M.nb)) : T(0)) + dot(M.nb, mul(bv[ib].Iw, M.nb));
+                M.mtw = kw > T(0) ? T(1) / kw : T(0);
+                T rsum = 0;
+                for (int k = 0; k < keep; ++k) rsum = rsum + len(o.pt[k].p - c);
+                M.rt = rsum / T(keep);
+                M.mu = mu;
+                M.lt1 = M.lt2 = M.ltw = 0;
+                mans.push_back(M);
+            }
+        }
+        cnt[CNT_POINTS] += int64_t(rows.size());
+        cnt[CNT_MANIFOLDS] += int64_t(mans.size());
+        cnt[CNT_JOINTS] += int64_t(E.joints.size());
+        // S5: greedy colouring over blocks = joints (index order) ++ manifolds (canonical order).
+        std::vector<uint64_t> used(n, 0);
+        order.clear();
+        const int nj = int(E.joints.size());
+        std::vector<int> colour(nj + mans.size(), 0);
+        ncol = 0;
+        bool overflow = false;
+        for (int bidx = 0; bidx < int(colour.size()); ++bidx) {
+            int a, b;
+            if (bidx < nj) { a = E.joints[bidx].parent; b = E.joints[bidx].child; }
+            else { a = mans[bidx - nj].a; b = mans[bidx - nj].b; }
+            uint64_t u = 0;
+            if (dyn(a)) u |= used[a];
+            if (dyn(b)) u |= used[b];
+            int c = 0;
+            while (c < MAX_COLORS && (u >> c & 1)) ++c;
+            if (c >= MAX_COLORS) { overflow = true; c = MAX_COLORS; }
+            else {
+                if (dyn(a)) used[a] |= uint64_t(1) << c;
+                if (dyn(b)) used[b] |= uint64_t(1) << c;
+            }
+            colour[bidx] = c;
+            if (c + 1 > ncol) ncol = c + 1;
+        }
+        if (overflow) E.status |= ST_COLOR_OVERFLOW;
+        cnt[CNT_COLOURS] += ncol;
+        for (int c = 0; c <= MAX_COLORS; ++c)
+            for (int bidx = 0; bidx < int(colour.size()); ++bidx)
+                if (colour[bidx] == c) order.push_back({c, bidx});
+        for (int m = 0; m < int(mans.size()); ++m) mans[m].colour = colour[nj + m];
+        if (rec)
+            for (int bidx = 0; bidx < int(colour.size()); ++bidx)
+                rec->blocks.push_back(BlockRec{env_id, bidx < nj ? 0 : 1, bidx < nj ? bidx : bidx - nj, colour[bidx]});
+        js.assign(nj, JState<T>{{0, 0, 0}, {0, 0}, 0});
+    }
+
+    // ------------------------------------------------------------- joint block
+    struct JFrame { int a, b; V3<T> rA, rB, zA, b1, b2; };
+    JFrame jframe(const Joint<T>& j) const {
+        JFrame f;
+        f.a = j.parent; f.b = j.child;
+        Q<T> qa = j.parent >= 0 ? E.bodies[j.parent].q : Q<T>{1, 0, 0, 0};
+        const Body<T>& B = E.bodies[j.child];
+        f.rA = rotate(qa, j.aA);
+        f.rB = rotate(B.q, j.aB);
+        M3<T> Ra = rotm(qmul(qa, j.QA));
+        f.zA = col(Ra, 2); f.b1 = col(Ra, 0); f.b2 = col(Ra, 1);
+        return f;
+    }
+    V3<T> pos_of(int i) const { return i >= 0 ? E.bodies[i].x : mk<T>(0, 0, 0); }
+    V3<T> lin_of(int i) const { return i >= 0 ? E.bodies[i].v : mk<T>(0, 0, 0); }
+    V3<T> ang_of(int i) const { return i >= 0 ? E.bodies[i].w : mk<T>(0, 0, 0); }
+
+    // Drive error: twist of B's joint frame relative to A's about the joint axis, minus target.
+    T drive_error(const Joint<T>& j, T target) const {
+        Q<T> qa = j.parent >= 0 ? E.bodies[j.parent].q : Q<T>{1, 0, 0, 0};
+        Q<T> rel = qmul(qconj(qmul(qa, j.QA)), qmul(E.bodies[j.child].q, j.QB));
+        if (rel.w < T(0)) rel = Q<T>{-rel.w, -rel.x, -rel.y, -rel.z};
+        T th = T(2) * std::atan2(rel.z, rel.w);
+        T c = th - target;
+        const T pi = T(3.14159265358979323846);
+        while (c > pi) c = c - T(2) * pi;
+        while (c <= -pi) c = c + T(2) * pi;
+        return c;
+    }
+
+    void joint_warm(int ji) {
+        const Joint<T>& j = E.joints[ji];
+        JFrame f = jframe(j);
+        JState<T>& s = js[ji];
+        apply(f.a, f.b, f.rA, f.rB, mk(s.lp[0], s.lp[1], s.lp[2]));
+        apply_ang(f.a, f.b, s.la[0] * f.b1 + s.la[1] * f.b2);
+        apply_ang(f.a, f.b, s.ld * f.zA);
+    }
+
+    void joint_solve(int ji, const T* targets, bool velocity_pass) {
+        const Joint<T>& j = E.joints[ji];
+        JFrame f = jframe(j);
+        JState<T>& st = js[ji];
+        const T beta = velocity_pass ? T(0) : T(P.joint_baumgarte);
+        const int a = f.a, b = f.b;
+        // point block (3 rows, solved together)
+        {
+            M3<T> K{};
+            T im = invm(a) + invm(b);
+            for (int i = 0; i < 3; ++i) K.m[i][i] = im;
+            auto add_arm = [&](V3<T> r, const M3<T>& I) {
+                // subtract [r]x I [r]x
+                M3<T> S{{{0, -r.z, r.y}, {r.z, 0, -r.x}, {-r.y, r.x, 0}}};
+                M3<T> SI{}, SIS{};
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q)
+                        SI.m[p][q] = S.m[p][0] * I.m[0][q] + S.m[p][1] * I.m[1][q] + S.m[p][2] * I.m[2][q];
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q)
+                        SIS.m[p][q] = SI.m[p][0] * S.m[0][q] + SI.m[p][1] * S.m[1][q] + SI.m[p][2] * S.m[2][q];
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q) K.m[p][q] = K.m[p][q] - SIS.m[p][q];
+            };
+            if (a >= 0) add_arm(f.rA, bv[a].Iw);
+            add_arm(f.rB, bv[b].Iw);
+            V3<T> C = (pos_of(b) + f.rB) - (pos_of(a) + f.rA);
+            V3<T> Cd = (lin_of(b) + cross(ang_of(b), f.rB)) - (lin_of(a) + cross(ang_of(a), f.rA));
+            V3<T> rhs = Cd + (beta / T(P.dt)) * C;
+            // K^-1 via adjugate / determinant
+            T c00 = K.m[1][1] * K.m[2][2] - K.m[1][2] * K.m[2][1];
+            T c01 = K.m[0][2] * K.m[2][1] - K.m[0][1] * K.m[2][2];
+            T c02 = K.m[0][1] * K.m[1][2] - K.m[0][2] * K.m[1][1];
+            T c10 = K.m[1][2] * K.m[2][0] - K.m[1][0] * K.m[2][2];
+            T c11 = K.m[0][0] * K.m[2][2] - K.m[0][2] * K.m[2][0];
+            T c12 = K.m[0][2] * K.m[1][0] - K.m[0][0] * K.m[1][2];
+            T c20 = K.m[1][0] * K.m[2][1] - K.m[1][1] * K.m[2][0];
+            T c21 = K.m[0][1] * K.m[2][0] - K.m[0][0] * K.m[2][1];
+            T c22 = K.m[0][0] * K.m[1][1] - K.m[0][1] * K.m[1][0];
+            T det = K.m[0][0] * c00 + K.m[0][1] * c10 + K.m[0][2] * c20;
+            if (det != T(0)) {
+                T id = T(1) / det;
+                V3<T> lam = mk(-(c00 * rhs.x + c01 * rhs.y + c02 * rhs.z) * id,
+                               -(c10 * rhs.x + c11 * rhs.y + c12 * rhs.z) * id,
+                               -(c20 * rhs.x + c21 * rhs.y + c22 * rhs.z) * id);
+                st.lp[0] = st.lp[0] + lam.x; st.lp[1] = st.lp[1] + lam.y; st.lp[2] = st.lp[2] + lam.z;
+                apply(a, b, f.rA, f.rB, lam);
+            }
+        }
+        // angular block (2 rows keeping the joint axes aligned)
+        {
+            Q<T> qb = qmul(E.bodies[b].q, j.QB);
+            V3<T> zB = col(rotm(qb), 2);
+            V3<T> zc = cross(f.zA, zB);
+            T C1 = dot(f.b1, zc), C2 = dot(f.b2, zc);
+            V3<T> dw = ang_of(b) - ang_of(a);
+            T Cd1 = dot(f.b1, dw), Cd2 = dot(f.b2, dw);
+            M3<T> Isum{};
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) Isum.m[p][q] = (a >= 0 ? bv[a].Iw.m[p][q] : T(0)) + bv[b].Iw.m[p][q];
+            T k11 = dot(f.b1, mul(Isum, f.b1)), k12 = dot(f.b1, mul(Isum, f.b2)), k22 = dot(f.b2, mul(Isum, f.b2));
+            T r1 = Cd1 + (beta / T(P.dt)) * C1, r2 = Cd2 + (beta / T(P.dt)) * C2;
+            T det = k11 * k22 - k12 * k12;
+            if (det != T(0)) {
+                T id = T(1) / det;
+                T l1 = -(k22 * r1 - k12 * r2) * id;
+                T l2 = -(-k12 * r1 + k11 * r2) * id;
+                st.la[0] = st.la[0] + l1; st.la[1] = st.la[1] + l2;
+                apply_ang(a, b, l1 * f.b1 + l2 * f.b2);
+            }
+        }
+        // PD drive as a soft row about the joint axis
+        if (j.kp != T(0) || j.kd != T(0)) {
+            V3<T> ax = f.zA;
+            T k = dot(ax, mul(bv[b].Iw, ax)) + (a >= 0 ? dot(ax, mul(bv[a].Iw, ax)) : T(0));
+            T den = j.kd + h * j.kp;
+            T gamma = T(1) / (h * den);
+            T beta_d = h * j.kp / den;
+            T C = drive_error(j, targets[ji]);
+            T Cd = dot(ax, ang_of(b) - ang_of(a));
+            T dl = -(Cd + beta_d * C / h + gamma * st.ld) / (k + gamma);
+            st.ld = st.ld + dl;
+            apply_ang(a, b, dl * ax);
+        }
+    }
+
+    // ------------------------------------------------------------- manifold block
+    // Displacement of the body-fixed point x0 + r since the step start: dx + R(dq) r - r, with
+    // R(dq) r - r = 2 w (u x r) + 2 u x (u x r) for dq = (w, u) (no cancellation for small dq).
+    V3<T> point_disp(int i, V3<T> r) const {
+        const Q<T>& d = dq[i];
+        V3<T> u = mk(d.x, d.y, d.z);
+        V3<T> ur = cross(u, r);
+        return dx[i] + (T(2) * d.w) * ur + T(2) * cross(u, ur);
+    }
+    T current_sep(const CRow<T>& r) const {
+        V3<T> dA = r.a >= 0 ? point_disp(r.a, r.rA) : mk<T>(0, 0, 0);
+        V3<T> dB = point_disp(r.b, r.rB);
+        return r.s0 + dot(r.n, dB - dA);
+    }
+    V3<T> rel_vel(const CRow<T>& r) const {
+        V3<T> vb = E.bodies[r.b].v + cross(E.bodies[r.b].w, r.rB);
+        V3<T> va = r.a >= 0 ? E.bodies[r.a].v + cross(E.bodies[r.a].w, r.rA) : mk<T>(0, 0, 0);
+        return vb - va;
+    }
+    V3<T> rel_vel_patch(const Manifold<T>& m) const {
+        V3<T> vb = E.bodies[m.b].v + cross(E.bodies[m.b].w, m.rB);
+        V3<T> va = m.a >= 0 ? E.bodies[m.a].v + cross(E.bodies[m.a].w, m.rA) : mk<T>(0, 0, 0);
+        return vb - va;
+    }
+    void manifold_warm(const Manifold<T>& m) {
+        for (int k = 0; k < m.count; ++k) {
+            const CRow<T>& r = rows[m.first + k];
+            apply(r.a, r.b, r.rA, r.rB, r.ln * r.n);
+        }
+        apply(m.a, m.b, m.rA, m.rB, m.lt1 * m.t1 + m.lt2 * m.t2);
+        apply_ang(m.a, m.b, m.ltw * m.nb);
+    }
+    void manifold_solve(Manifold<T>& m, bool velocity_pass) {
+        for (int k = 0; k < m.count; ++k) {
+            CRow<T>& r = rows[m.first + k];
+            T s = current_sep(r);
+            T bias;
+            if (s > T(0)) bias = s / h;
+            else bias = velocity_pass ? T(0) : std::max(T(P.baumgarte) * s / h, -T(P.max_depen_vel));
+            T vn = dot(rel_vel(r), r.n);
+            T dl = -r.mn * (vn + bias);
+            T nl = std::max(r.ln + dl, T(0));
+            dl = nl - r.ln;
+            r.ln = nl;
+            apply(r.a, r.b, r.rA, r.rB, dl * r.n);
+        }
+        T lsum = 0;
+        for (int k = 0; k < m.count; ++k) lsum = lsum + rows[m.first + k].ln;
+        T lim = m.mu * lsum;
+        {
+            T vt = dot(rel_vel_patch(m), m.t1);
+            T nl = m.lt1 - m.mt1 * vt;
+            nl = std::min(std::max(nl, -lim), lim);
+            T dl = nl - m.lt1;
+            m.lt1 = nl;
+            apply(m.a, m.b, m.rA, m.rB, dl * m.t1);
+        }
+        {
+            T vt = dot(rel_vel_patch(m), m.t2);
+            T nl = m.lt2 - m.mt2 * vt;
+            nl = std::min(std::max(nl, -lim), lim);
+            T dl = nl - m.lt2;
+            m.lt2 = nl;
+            apply(m.a, m.b, m.rA, m.rB, dl * m.t2);
+        }
+        {
+            T limw = m.rt * lim;
+            T wr = dot(m.nb, ang_of(m.b) - ang_of(m.a));
+            T nl = m.ltw - m.mtw * wr;
+            nl = std::min(std::max(nl, -limw), limw);
+            T dl = nl - m.ltw;
+            m.ltw = nl;
+            apply_ang(m.a, m.b, dl * m.nb);
+        }
+    }
+
+    void manifold_restitution(const Manifold<T>& m) {
+        for (int k = 0; k < m.count; ++k) {
+            CRow<T>& r = rows[m.first + k];
+            if (!(r.vnpre < -T(P.bounce_threshold) && r.ln > T(0))) continue;
+            T vn = dot(rel_vel(r), r.n);
+            T dl = -r.mn * (vn + r.e * r.vnpre);
+            T nl = std::max(r.ln + dl, T(0));
+            dl = nl - r.ln;
+            r.ln = nl;
+            apply(r.a, r.b, r.rA, r.rB, dl * r.n);
+        }
+    }
+
+    void sweep(const T* targets, bool velocity_pass) {
+        const int nj = int(E.joints.size());
+        for (auto& ob : order) {
+            int bidx = ob.second;
+            if (bidx < nj) joint_solve(bidx, targets, velocity_pass);
+            else manifold_solve(mans[bidx - nj], velocity_pass);
+        }
+    }
+
+    // ------------------------------------------------------------- S0..S8 for one env
+    void step(const T* targets, int64_t* cnt, double& min_margin) {
+        const int n = int(E.bodies.size());
+        std::vector<Body<T>> saved = E.bodies;
+        prepare(min_margin, cnt);
+        const bool tgs = P.solver == 0;
+        const int S = tgs ? std::max(P.pos_iters, 1) : 1;
+        const int K = tgs ? 1 : std::max(P.pos_iters, 1);
+        h = T(P.dt) / T(S);
+        const V3<T> g = mk(T(P.gravity[0]), T(P.gravity[1]), T(P.gravity[2]));
+        const T ld = T(1) / (T(1) + h * T(P.lin_damping));
+        const T ad = T(1) / (T(1) + h * T(P.ang_damping));
+        const int nj = int(E.joints.size());
+        for (int s = 0; s < S; ++s) {
+            for (int i = 0; i < n; ++i) {
+                Body<T>& b = E.bodies[i];
+                if (!b.dyn()) continue;
+                b.v = ld * (b.v + h * g);
+                b.w = ad * b.w;
+            }
+            if (s > 0)
+                for (auto& ob : order) {
+                    if (ob.second < nj) joint_warm(ob.second);
+                    else manifold_warm(mans[ob.second - nj]);
+                }
+            for (int k = 0; k < K; ++k) {
+                // joint_iters - 1 joint-only passes (colour order), then the full sweep
+                for (int jx = 1; jx < P.joint_iters; ++jx)
+                    for (auto& ob : order)
+                        if (ob.second < nj) joint_solve(ob.second, targets, false);
+                sweep(targets, false);
+            }
+            for (int i = 0; i < n; ++i) {
+                Body<T>& b = E.bodies[i];
+                if (!b.dyn()) continue;
+                // symplectic Euler on the offsets from the step start: dx += h v and
+                // dq <- normalise(dq + h/2 (0, w) dq); then x = x0 + dx, q = normalise(dq q0)
+                dx[i] = dx[i] + h * b.v;
+                Q<T> wq{T(0), b.w.x, b.w.y, b.w.z};
+                Q<T> e = qmul(wq, dq[i]);
+                T hh = T(0.5) * h;
+                dq[i] = qnormalize(Q<T>{dq[i].w + hh * e.w, dq[i].x + hh * e.x, dq[i].y + hh * e.y, dq[i].z + hh * e.z});
+                b.x = x0[i] + dx[i];
+                b.q = qnormalize(qmul(dq[i], q0[i]));
+            }
+        }
+        for (int k = 0; k < P.vel_iters; ++k) sweep(targets, true);
+        for (auto& ob : order)
+            if (ob.second >= nj) manifold_restitution(mans[ob.second - nj]);
+        // S8: non-finite guard
+        bool bad = false;
+        for (int i = 0; i < n; ++i) {
+            const Body<T>& b = E.bodies[i];
+            T vals[13] = {b.x.x, b.x.y, b.x.z, b.q.w, b.q.x, b.q.y, b.q.z, b.v.x, b.v.y, b.v.z, b.w.x, b.w.y, b.w.z};
+            for (T v : vals) if (!std::isfinite(double(v))) bad = true;
+        }
+        if (bad) { E.bodies = saved; E.status |= ST_NONFINITE; }
+        if (rec) {
+            for (const Manifold<T>& m : mans) {
+                PairRec& pr = rec->pairs[m.pair];
+                pr.lt1 = double(m.lt1); pr.lt2 = double(m.lt2); pr.ltw = double(m.ltw);
+                pr.mu = double(m.mu); pr.rt = double(m.rt);
+                for (int k = 0; k < m.count; ++k) {
+                    const CRow<T>& r = rows[m.first + k];
+                    V3<T> p = r.rB + x0[r.b];
+                    rec->points.push_back(PointRec{env_id, m.pair, {double(p.x), double(p.y), double(p.z)},
+                                                   {double(r.n.x), double(r.n.y), double(r.n.z)}, double(r.s0),
+                                                   double(r.ln)});
+                }
+            }
+        }
+    }
+};
+
+// ----------------------------------------------------------------------------- batch handle
+struct Handle {
+    Params P;
+    int prec;
+    int n_envs;
+    std::vector<int> body_off, joint_off;
+    std::vector<Env<float>> ef;
+    std::vector<Env<double>> ed;
+    std::vector<float> targets;  // [total joints]
+    std::vector<EnvRecord> recs;
+};
+
+template <class T> static void load_env(Env<T>& E, const BodyDesc* bd, int nb, const JointDesc* jd, int nj) {
+    E.bodies.resize(nb);
+    for (int i = 0; i < nb; ++i) {
+        const BodyDesc& d = bd[i];
+        Body<T>& b = E.bodies[i];
+        b.shape = d.shape; b.flags = d.flags;
+        for (int k = 0; k < 3; ++k) b.dims[k] = T(d.dims[k]);
+        T m = d.mass > 0 ? T(d.mass) : T(d.density) * shape_volume<T>(d.shape, b.dims);
+        V3<T> I = shape_inertia<T>(d.shape, b.dims, m);
+        if (b.flags & STATIC) { b.invm = 0; b.invI = mk<T>(0, 0, 0); }
+        else { b.invm = T(1) / m; b.invI = mk(T(1) / I.x, T(1) / I.y, T(1) / I.z); }
+        b.mu = T(d.friction); b.e = T(d.restitution);
+        b.x = mk(T(d.pos[0]), T(d.pos[1]), T(d.pos[2]));
+        b.q = Q<T>{T(d.quat[0]), T(d.quat[1]), T(d.quat[2]), T(d.quat[3])};
+        b.v = mk(T(d.linvel[0]), T(d.linvel[1]), T(d.linvel[2]));
+        b.w = mk(T(d.angvel[0]), T(d.angvel[1]), T(d.angvel[2]));
+    }
+    E.joints.resize(nj);
+    for (int i = 0; i < nj; ++i) {
+        const JointDesc& d = jd[i];
+        Joint<T>& j = E.joints[i];
+        j.parent = d.parent; j.child = d.child;
+        j.aA = mk(T(d.frame_parent[0]), T(d.frame_parent[1]), T(d.frame_parent[2]));
+        j.QA = Q<T>{T(d.frame_parent[3]), T(d.frame_parent[4]), T(d.frame_parent[5]), T(d.frame_parent[6])};
+        j.aB = mk(T(d.frame_child[0]), T(d.frame_child[1]), T(d.frame_child[2]));
+        j.QB = Q<T>{T(d.frame_child[3]), T(d.frame_child[4]), T(d.frame_child[5]), T(d.frame_child[6])};
+        j.kp = T(d.kp); j.kd = T(d.kd); j.target = T(d.target);
+    }
+    E.status = 0;
+}
+
+template <class T> static void run_env(Handle& H, std::vector<Env<T>>& envs, int e, int n_steps, bool record) {
+    Env<T>& E = envs[e];
+    EnvRecord& R = H.recs[e];
+    std::vector<T> tg(E.joints.size());
+    for (size_t j = 0; j < tg.size(); ++j) tg[j] = T(H.targets[H.joint_off[e] + j]);
+    for (int s = 0; s < n_steps; ++s) {
+        if (E.status & ST_NONFINITE) break;
+        bool last = s == n_steps - 1;
+        if (last && record) { R.pairs.clear(); R.points.clear(); R.blocks.clear(); }
+        std::fill(R.cnt, R.cnt + N_CNT, 0);
+        R.min_margin = 1e30;
+        Stepper<T> st(H.P, E, (last && record) ? &R : nullptr, e);
+        st.step(tg.data(), R.cnt, R.min_margin);
+    }
+}
+
+template <class T> static void run_all(Handle& H, std::vector<Env<T>>& envs, int n_steps, int n_threads, bool record) {
+    const int E = H.n_envs;
+    if (n_threads <= 1) {
+        for (int e = 0; e < E; ++e) run_env(H, envs, e, n_steps, record);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < n_threads; ++t)
+        th.emplace_back([&, t]() {
+            for (int e = t; e < E; e += n_threads) run_env(H, envs, e, n_steps, record);
+        });
+    for (auto& x : th) x.join();
+}
+
+// State in SoA over all bodies: pos[3][B], quat[4][B], v[3][B], w[3][B] (double), status[E].
+template <class T> static void get_state_t(Handle* H, std::vector<Env<T>>& envs, double* pos, double* quat, double* v,
+                                           double* w, int32_t* status) {
+    const int B = H->body_off[H->n_envs];
+    for (int e = 0; e < H->n_envs; ++e) {
+        if (status) status[e] = envs[e].status;
+        for (size_t i = 0; i < envs[e].bodies.size(); ++i) {
+            const Body<T>& b = envs[e].bodies[i];
+            int g = H->body_off[e] + int(i);
+            pos[g] = double(b.x.x); pos[B + g] = double(b.x.y); pos[2 * B + g] = double(b.x.z);
+            quat[g] = double(b.q.w); quat[B + g] = double(b.q.x); quat[2 * B + g] = double(b.q.y); quat[3 * B + g] = double(b.q.z);
+            v[g] = double(b.v.x); v[B + g] = double(b.v.y); v[2 * B + g] = double(b.v.z);
+            w[g] = double(b.w.x); w[B + g] = double(b.w.y); w[2 * B + g] = double(b.w.z);
+        }
+    }
+}
+template <class T> static void set_state_t(Handle* H, std::vector<Env<T>>& envs, const double* pos, const double* quat,
+                                           const double* v, const double* w) {
+    const int B = H->body_off[H->n_envs];
+    for (int e = 0; e < H->n_envs; ++e) {
+        envs[e].status = 0;
+        for (size_t i = 0; i < envs[e].bodies.size(); ++i) {
+            Body<T>& b = envs[e].bodies[i];
+            int g = H->body_off[e] + int(i);
+            b.x = mk(T(pos[g]), T(pos[B + g]), T(pos[2 * B + g]));
+            b.q = Q<T>{T(quat[g]), T(quat[B + g]), T(quat[2 * B + g]), T(quat[3 * B + g])};
+            b.v = mk(T(v[g]), T(v[B + g]), T(v[2 * B + g]));
+            b.w = mk(T(w[g]), T(w[B + g]), T(w[2 * B + g]));
+        }
+    }
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+extern "C" {
+
+void* or_create(const Params* p, int n_envs, const int32_t* body_off, const BodyDesc* bodies,
+                const int32_t* joint_off, const JointDesc* joints, int precision) {
+    Handle* H = new Handle();
+    H->P = *p;
+    H->prec = precision;
+    H->n_envs = n_envs;
+    H->body_off.assign(body_off, body_off + n_envs + 1);
+    H->joint_off.assign(joint_off, joint_off + n_envs + 1);
+    if (precision == 64) H->ed.resize(n_envs); else H->ef.resize(n_envs);
+    H->recs.resize(n_envs);
+    for (int e = 0; e < n_envs; ++e) {
+        int b0 = body_off[e], nb = body_off[e + 1] - b0, j0 = joint_off[e], nj = joint_off[e + 1] - j0;
+        if (precision == 64) load_env(H->ed[e], bodies + b0, nb, joints + j0, nj);
+        else load_env(H->ef[e], bodies + b0, nb, joints + j0, nj);
+    }
+    int nj = joint_off[n_envs];
+    H->targets.resize(nj);
+    for (int j = 0; j < nj; ++j) H->targets[j] = joints[j].target;
+    return H;
+}
+
+void or_destroy(void* h) { delete static_cast<Handle*>(h); }
+
+void or_set_targets(void* h, const float* t) {
+    Handle* H = static_cast<Handle*>(h);
+    std::copy(t, t + H->targets.size(), H->targets.begin());
+}
+
+void or_step(void* h, int n_steps, int n_threads, int record) {
+    Handle* H = static_cast<Handle*>(h);
+    if (H->prec == 64) run_all(*H, H->ed, n_steps, n_threads, record != 0);
+    else run_all(*H, H->ef, n_steps, n_threads, record != 0);
+}
+
+void or_get_state(void* h, double* pos, double* quat, double* v, double* w, int32_t* status) {
+    Handle* H = static_cast<Handle*>(h);
+    if (H->prec == 64) get_state_t(H, H->ed, pos, quat, v, w, status);
+    else get_state_t(H, H->ef, pos, quat, v, w, status);
+}
+void or_set_state(void* h, const double* pos, const double* quat, const double* v, const double* w) {
+    Handle* H = static_cast<Handle*>(h);
+    if (H->prec == 64) set_state_t(H, H->ed, pos, quat, v, w);
+    else set_state_t(H, H->ef, pos, quat, v, w);
+}
+
+// Test record of the last recorded step.
+void or_record_sizes(void* h, int64_t* n_pairs, int64_t* n_points, int64_t* n_blocks) {
+    Handle* H = static_cast<Handle*>(h);
+    int64_t a = 0, b = 0, c = 0;
+    for (auto& r : H->recs) { a += int64_t(r.pairs.size()); b += int64_t(r.points.size()); c += int64_t(r.blocks.size()); }
+    *n_pairs = a; *n_points = b; *n_blocks = c;
+}
+// pairs: int32 [n][6] = env, a, b, npts, decision, kind; double [n][6] = decision margin and the
+// friction patch's lambda_t1, lambda_t2, lambda_twist, mu, torsional radius
+void or_record_pairs(void* h, int32_t* out, double* margin) {
+    Handle* H = static_cast<Handle*>(h);
+    int64_t k = 0;
+    for (auto& r : H->recs)
+        for (auto& p : r.pairs) {
+            int32_t* o = out + 6 * k;
+            o[0] = p.env; o[1] = p.a; o[2] = p.b; o[3] = p.npts; o[4] = p.decision; o[5] = p.kind;
+            double* m = margin + 6 * k;
+            m[0] = p.margin; m[1] = p.lt1; m[2] = p.lt2; m[3] = p.ltw; m[4] = p.mu; m[5] = p.rt;
+            ++k;
+        }
+}
+// points: int32 [n][2] = env, pair index (within the env's pair list); double [n][8] =
+// p(3), n(3), s0, lambda_n
+void or_record_points(void* h, int32_t* ids, double* out) {
+    Handle* H = static_cast<Handle*>(h);
+    int64_t k = 0;
+    for (auto& r : H->recs)
+        for (auto& p : r.points) {
+            ids[2 * k] = p.env; ids[2 * k + 1] = p.pair;
+            double* o = out + 8 * k;
+            for (int i = 0; i < 3; ++i) { o[i] = p.p[i]; o[3 + i] = p.n[i]; }
+            o[6] = p.s; o[7] = p.ln;
+            ++k;
+        }
+}
+// blocks: int32 [n][4] = env, kind (0 joint, 1 manifold), index, colour
+void or_record_blocks(void* h, int32_t* out) {
+    Handle* H = static_cast<Handle*>(h);
+    int64_t k = 0;
+    for (auto& r : H->recs)
+        for (auto& b : r.blocks) {
+            int32_t* o = out + 4 * k;
+            o[0] = b.env; o[1] = b.kind; o[2] = b.index; o[3] = b.colour;
+            ++k;
+        }
+}
+// Per-env work counters of the last step: int64 [E][N_CNT]; per-env minimum decision margin [E].
+int or_n_counters() { return N_CNT; }
+void or_env_counters(void* h, int64_t* out, double* min_margin) {
+    Handle* H = static_cast<Handle*>(h);
+    for (int e = 0; e < H->n_envs; ++e) {
+        for (int c = 0; c < N_CNT; ++c) out[int64_t(e) * N_CNT + c] = H->recs[e].cnt[c];
+        min_margin[e] = H->recs[e].min_margin;
+    }
+}
+
+// Mass properties exposed for the pins: volume and principal inertia for a given mass.
+void or_mass_props(int shape, const double* dims, double mass, double* volume, double* inertia) {
+    *volume = shape_volume<double>(shape, dims);
+    V3<double> I = shape_inertia<double>(shape, dims, mass);
+    inertia[0] = I.x; inertia[1] = I.y; inertia[2] = I.z;
+}
+
+// Narrowphase for one pair of free-standing shapes (A = shape a, B = shape b, n from A to B);
+// shape -1 means the ground plane at z = 0 (always A).  pose = (px, py, pz, qw, qx, qy, qz).
+// Returns the number of points written as double [k][7] = p, n, s.  *decision receives the
+// branch code.
+int or_narrow(int shape_a, const double* dims_a, const double* pose_a, int shape_b, const double* dims_b,
+              const double* pose_b, double delta, double* out, int32_t* decision) {
+    auto mkshape = [](int s, const double* d, const double* p) {
+        Shape<double> r;
+        r.type = s;
+        r.c = mk(p[0], p[1], p[2]);
+        r.R = rotm(Q<double>{p[3], p[4], p[5], p[6]});
+        r.d[0] = d[0]; r.d[1] = d[1]; r.d[2] = d[2];
+        return r;
+    };
+    Out<double> o;
+    Shape<double> B = mkshape(shape_b, dims_b, pose_b);
+    if (shape_a < 0) narrow_plane(o, 0.0, B, delta);
+    else narrow(o, mkshape(shape_a, dims_a, pose_a), B, delta);
+    reduce4(o);
+    for (int k = 0; k < o.n; ++k) {
+        double* r = out + 7 * k;
+        r[0] = o.pt[k].p.x; r[1] = o.pt[k].p.y; r[2] = o.pt[k].p.z;
+        r[3] = o.pt[k].n.x; r[4] = o.pt[k].n.y; r[5] = o.pt[k].n.z;
+        r[6] = o.pt[k].s;
+    }
+    *decision = o.decision;
+    return o.n;
+}
+
+// Separating-axis values of two boxes (15 axes: A faces, B faces, A_i x B_j), float64, for the
+// pins: sep[k] = gap along axis k (negative = overlap), valid[k] = 0 for a degenerate cross.
+void or_box_box_sat(const double* dims_a, const double* pose_a, const double* dims_b, const double* pose_b,
+                    double* sep, int32_t* valid) {
+    auto mkbox = [](const double* d, const double* p) {
+        Shape<double> r;
+        r.type = BOX;
+        r.c = mk(p[0], p[1], p[2]);
+        r.R = rotm(Q<double>{p[3], p[4], p[5], p[6]});
+        r.d[0] = d[0]; r.d[1] = d[1]; r.d[2] = d[2];
+        return r;
+    };
+    Shape<double> A = mkbox(dims_a, pose_a), B = mkbox(dims_b, pose_b);
+    V3<double> d = B.c - A.c;
+    for (int k = 0; k < 15; ++k) {
+        V3<double> L;
+        if (k < 3) L = col(A.R, k);
+        else if (k < 6) L = col(B.R, k - 3);
+        else {
+            L = cross(col(A.R, (k - 6) / 3), col(B.R, (k - 6) % 3));
+            double l = len(L);
+            if (l < 1e-6) { valid[k] = 0; sep[k] = -1e30; continue; }
+            L = (1.0 / l) * L;
+        }
+        valid[k] = 1;
+        sep[k] = std::fabs(dot(d, L)) - box_extent(A, L) - box_extent(B, L);
+    }
+}
+
+}  // extern "C"
+

@@ -1,0 +1,173 @@
+"""ctypes wrapper of the CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg use this module.  It
+loads ``liboracle.so`` built from ``ms_oracle.cpp`` with g++ (no GPU code, no shared source with
+the GPU library).  Descriptor arrays are the records produced by the input generators: the
+oracle reads them by byte layout (88-byte bodies, 76-byte joints, 84-byte parameters).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ms_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 76, 84
+N_COUNTERS = 20
+COUNTER_NAMES = ["pairs_tested", "candidates", "points", "manifolds", "colours", "dynamic", "static",
+                 "joints"] + [f"kind{k}" for k in range(12)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (-O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-pthread", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.or_create.restype = P
+        L.or_create.argtypes = [P, C.c_int, P, P, P, P, C.c_int]
+        L.or_destroy.argtypes = [P]
+        L.or_set_targets.argtypes = [P, P]
+        L.or_step.argtypes = [P, C.c_int, C.c_int, C.c_int]
+        L.or_get_state.argtypes = [P, P, P, P, P, P]
+        L.or_set_state.argtypes = [P, P, P, P, P]
+        L.or_record_sizes.argtypes = [P, P, P, P]
+        L.or_record_pairs.argtypes = [P, P, P]
+        L.or_record_points.argtypes = [P, P, P]
+        L.or_record_blocks.argtypes = [P, P]
+        L.or_n_counters.restype = C.c_int
+        L.or_env_counters.argtypes = [P, P, P]
+        L.or_mass_props.argtypes = [C.c_int, P, C.c_double, P, P]
+        L.or_narrow.restype = C.c_int
+        L.or_narrow.argtypes = [C.c_int, P, P, C.c_int, P, P, C.c_double, P, P]
+        L.or_box_box_sat.argtypes = [P, P, P, P, P, P]
+        assert L.or_n_counters() == N_COUNTERS
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """The step model on the CPU for a whole batch, in float32 (precision=32) or float64."""
+
+    def __init__(self, scene, precision: int = 32, params=None):
+        L = lib()
+        p = np.ascontiguousarray(scene.params if params is None else params)
+        assert p.dtype.itemsize == PARAMS_BYTES
+        self._keep = [p, np.ascontiguousarray(scene.body_off, np.int32), np.ascontiguousarray(scene.bodies),
+                      np.ascontiguousarray(scene.joint_off, np.int32), np.ascontiguousarray(scene.joints)]
+        assert self._keep[2].dtype.itemsize == BODY_BYTES and self._keep[4].dtype.itemsize == JOINT_BYTES
+        self.n_envs = scene.n_envs
+        self.n_bodies = scene.n_bodies
+        self.n_joints = scene.n_joints
+        self.precision = precision
+        self._h = L.or_create(_ptr(p), self.n_envs, _ptr(self._keep[1]), _ptr(self._keep[2]),
+                              _ptr(self._keep[3]), _ptr(self._keep[4]), precision)
+
+    def close(self):
+        if self._h:
+            lib().or_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_targets(self, targets):
+        t = np.ascontiguousarray(targets, dtype=np.float32)
+        assert t.shape == (self.n_joints,)
+        lib().or_set_targets(self._h, _ptr(t))
+
+    def step(self, n_steps: int = 1, n_threads: int = 1, record: bool = False):
+        lib().or_step(self._h, n_steps, n_threads, 1 if record else 0)
+
+    def state(self):
+        B, E = self.n_bodies, self.n_envs
+        pos, quat = np.zeros((3, B)), np.zeros((4, B))
+        v, w = np.zeros((3, B)), np.zeros((3, B))
+        st = np.zeros(E, np.int32)
+        lib().or_get_state(self._h, _ptr(pos), _ptr(quat), _ptr(v), _ptr(w), _ptr(st))
+        return dict(pos=pos, quat=quat, linvel=v, angvel=w, status=st)
+
+    def set_state(self, pos, quat, linvel, angvel):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (pos, quat, linvel, angvel)]
+        assert arrs[0].shape == (3, self.n_bodies) and arrs[1].shape == (4, self.n_bodies)
+        lib().or_set_state(self._h, *[_ptr(a) for a in arrs])
+
+    def record(self):
+        """The last recorded step: candidate pairs (env, a, b, n_points, decision, kind) with their
+        decision margin and friction patch (lambda_t1, lambda_t2, lambda_twist, mu, torsional
+        radius) in ``patch``; contact points (env, pair) + (p, n, s0, lambda_n); solver blocks
+        (env, kind, index, colour)."""
+        L = lib()
+        n = [C.c_int64(), C.c_int64(), C.c_int64()]
+        L.or_record_sizes(self._h, *[C.byref(x) for x in n])
+        npair, npt, nblk = (x.value for x in n)
+        pairs = np.zeros((npair, 6), np.int32)
+        pm = np.zeros((npair, 6))
+        ids = np.zeros((npt, 2), np.int32)
+        pts = np.zeros((npt, 8))
+        blocks = np.zeros((nblk, 4), np.int32)
+        L.or_record_pairs(self._h, _ptr(pairs), _ptr(pm))
+        L.or_record_points(self._h, _ptr(ids), _ptr(pts))
+        L.or_record_blocks(self._h, _ptr(blocks))
+        return dict(pairs=pairs, margin=pm[:, 0].copy(), patch=pm[:, 1:].copy(), point_ids=ids, points=pts,
+                    blocks=blocks)
+
+    def counters(self):
+        """Per-env work counters of the last step (int64 [E, N_COUNTERS]) and minimum margins."""
+        out = np.zeros((self.n_envs, N_COUNTERS), np.int64)
+        mm = np.zeros(self.n_envs)
+        lib().or_env_counters(self._h, _ptr(out), _ptr(mm))
+        return out, mm
+
+
+def mass_props(shape: int, dims, mass: float):
+    d = np.ascontiguousarray(dims, dtype=np.float64)
+    vol = C.c_double()
+    inertia = np.zeros(3)
+    lib().or_mass_props(shape, _ptr(d), mass, C.byref(vol), _ptr(inertia))
+    return vol.value, inertia
+
+
+def narrow(shape_a, dims_a, pose_a, shape_b, dims_b, pose_b, delta=0.01):
+    """Contact points of one pair of shapes in float64: array [k, 7] = p(3), n(3), s, and the
+    branch code.  shape_a = -1 is the ground plane z = 0."""
+    da = np.ascontiguousarray(dims_a if dims_a is not None else np.zeros(3), dtype=np.float64)
+    pa = np.ascontiguousarray(pose_a if pose_a is not None else [0, 0, 0, 1, 0, 0, 0], dtype=np.float64)
+    db = np.ascontiguousarray(dims_b, dtype=np.float64)
+    pb = np.ascontiguousarray(pose_b, dtype=np.float64)
+    out = np.zeros((16, 7))
+    dec = C.c_int32()
+    k = lib().or_narrow(shape_a, _ptr(da), _ptr(pa), shape_b, _ptr(db), _ptr(pb), delta, _ptr(out), C.byref(dec))
+    return out[:k].copy(), dec.value
+
+
+def box_box_sat(dims_a, pose_a, dims_b, pose_b):
+    """The 15 separating-axis gaps of two boxes (float64) and their validity flags."""
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (dims_a, pose_a, dims_b, pose_b)]
+    sep = np.zeros(15)
+    valid = np.zeros(15, np.int32)
+    lib().or_box_box_sat(*[_ptr(a) for a in arrs], _ptr(sep), _ptr(valid))
+    return sep, valid.astype(bool)
