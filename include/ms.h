@@ -124,6 +124,7 @@ typedef struct {
     int32_t max_contacts_per_env;
     int32_t debug_export;
     int32_t joint_iters;
+    int32_t max_manifolds_per_env;
 } ms_sim_params;
 
 /* Caller-owned device buffers in structure-of-arrays form over all B bodies of the batch:
@@ -179,27 +180,45 @@ ms_status ms_get_state(ms_batch* b, const ms_state_view* dst, void* hip_stream);
 ms_status ms_get_layout(ms_batch* b, int32_t* host_env_body_off, int32_t* host_env_joint_off);
 ms_status ms_get_sizes(ms_batch* b, int32_t* n_envs, int32_t* n_bodies, int32_t* n_joints);
 
-/* Contact export of the last step (requires debug_export).  Synchronises `hip_stream`.
- * For every env, the candidate pairs in canonical order are written to pairs[] as
- * int32 records {env, a, b, n_points, decision}; the plane is body 0xFFFF.  points[] receives
- * float records {px, py, pz, nx, ny, nz, s, lambda_n, lambda_t1, lambda_t2} for every kept
- * point, pair by pair, and colour[] the colour of each manifold with points.  *n_pairs and
- * *n_points receive the totals; buffers may be NULL to query the counts. */
+/* Contact export of the last step of the last ms_step call (requires debug_export; synchronises
+ * `hip_stream`).  Per env, in canonical pair order, host_pairs receives int32 records
+ * {env, a, b, kept_points, decision} for every candidate pair (b = 0xFFFF is the ground plane;
+ * decision is the narrowphase branch: the separating axis for box pairs, the parallel branch for
+ * capsule pairs, the inside face for sphere-box).  host_points receives float records
+ * {px, py, pz, nx, ny, nz, s0, lambda_n} for every kept point (world frame, normal from A to B,
+ * step-start separation, final normal impulse), and host_manifolds float records
+ * {env, pair index within the env, colour, lambda_t1, lambda_t2, lambda_twist, mu, r_twist} per
+ * manifold.  Buffers may be NULL (counts only); records beyond a *_cap are dropped. */
 ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, float* host_points,
-                          int32_t points_cap, int32_t* n_pairs, int32_t* n_points, void* hip_stream);
+                          int32_t points_cap, float* host_manifolds, int32_t manifolds_cap,
+                          int32_t* n_pairs, int32_t* n_points, int32_t* n_manifolds, void* hip_stream);
+
+/* Execution plan of a batch: number of env tiles, launch grid, LDS bytes per workgroup and the
+ * lanes serving each env (host array of n_envs entries, may be NULL). */
+ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds_bytes,
+                      int32_t* host_env_lanes);
 
 ms_status ms_destroy_batch(ms_batch* b);
 
-/* Fused step over several batches in one launch: the env tiles of every batch are concatenated
- * into one work list (the serving path).  targets[i] as in ms_step for batch i. */
+/* Fused step over several batches in one launch (the serving path): the env tiles of every
+ * batch are concatenated into one work list.  dev_targets (may be NULL) holds per-batch target
+ * pointers as in ms_step.  dev_scratch is caller device memory of at least
+ * ms_query_step_many_bytes() bytes (256-byte aligned) that receives the combined work list; it
+ * must not be reused until the stream has passed this launch.  The batches must live on the
+ * current device. */
+ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, size_t* bytes);
 ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches,
-                       int32_t n_steps, void* hip_stream);
+                       int32_t n_steps, void* dev_scratch, size_t scratch_bytes, void* hip_stream);
 
 /* Thread-local message of the last non-OK status returned on this thread. */
 const char* ms_last_error(void);
 
 /* Library version string. */
 const char* ms_version(void);
+
+/* Host-only consistency check of the kernel's LDS layout and pair indexing for every supported
+ * env size; returns 0 when consistent.  Touches no device. */
+int ms_selfcheck(void);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,7 @@ struct Params {
     int32_t max_contacts_per_env;
     int32_t debug_export;
     int32_t joint_iters;
+    int32_t max_manifolds_per_env;
 };
 static_assert(sizeof(BodyDesc) == 88, "body record layout");
 static_assert(sizeof(JointDesc) == 76, "joint record layout");
@@ -124,12 +125,14 @@ template <class T> inline V3<T> mulT(const M3<T>& a, V3<T> v) {
 template <class T> inline V3<T> col(const M3<T>& a, int j) { return {a.m[0][j], a.m[1][j], a.m[2][j]}; }
 template <class T> inline V3<T> rotate(Q<T> q, V3<T> v) { return mul(rotm(q), v); }
 
-// Symmetric world inverse inertia R diag(d) R^T.
+// Symmetric world inverse inertia R diag(d) R^T (upper triangle computed, then mirrored).
 template <class T> inline M3<T> world_inv_inertia(Q<T> q, V3<T> d) {
     M3<T> r = rotm(q), o;
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
+        for (int j = i; j < 3; ++j) {
             o.m[i][j] = r.m[i][0] * d.x * r.m[j][0] + r.m[i][1] * d.y * r.m[j][1] + r.m[i][2] * d.z * r.m[j][2];
+            o.m[j][i] = o.m[i][j];
+        }
     return o;
 }
 
@@ -424,14 +427,14 @@ template <class T> inline void box_capsule(Out<T>& o, const Shape<T>& bx, const 
     }
 }
 
-// Sutherland-Hodgman: keep the part of polygon `in` with dot(x, a) <= off.
+// Sutherland-Hodgman: keep the part of polygon `in` with dot(x, a) <= off (at most 8 vertices).
 template <class T> inline int clip_poly(const V3<T>* in, int n, V3<T> a, T off, V3<T>* out) {
     int m = 0;
     for (int k = 0; k < n; ++k) {
         V3<T> p = in[k], q = in[(k + 1) % n];
         T dp = dot(p, a) - off, dq = dot(q, a) - off;
-        if (dp <= T(0)) out[m++] = p;
-        if ((dp < T(0) && dq > T(0)) || (dp > T(0) && dq < T(0))) {
+        if (dp <= T(0) && m < 8) out[m++] = p;
+        if (((dp < T(0) && dq > T(0)) || (dp > T(0) && dq < T(0))) && m < 8) {
             T t = dp / (dp - dq);
             out[m++] = p + t * (q - p);
         }
@@ -607,13 +610,14 @@ template <class T> inline void reduce4(Out<T>& o) {
     int k0 = 0;
     for (int k = 1; k < n; ++k) { o.note(double(o.pt[k].s) - double(o.pt[k0].s)); if (o.pt[k].s < o.pt[k0].s) k0 = k; }
     used[k0] = true;
+    // each selection starts from the first unused point, so an index is always valid
     int k1 = -1; T b1 = T(-1);
     for (int k = 0; k < n; ++k) {
         if (used[k]) continue;
         V3<T> d = o.pt[k].p - o.pt[k0].p;
         T v = dot(d, d);
         if (k1 >= 0) o.note(double(v) - double(b1));
-        if (v > b1) { b1 = v; k1 = k; }
+        if (k1 < 0 || v > b1) { b1 = v; k1 = k; }
     }
     used[k1] = true;
     int k2 = -1; T b2 = T(-1);
@@ -623,7 +627,7 @@ template <class T> inline void reduce4(Out<T>& o) {
         V3<T> c = cross(e01, o.pt[k].p - o.pt[k0].p);
         T v = dot(c, c);
         if (k2 >= 0) o.note(double(v) - double(b2));
-        if (v > b2) { b2 = v; k2 = k; }
+        if (k2 < 0 || v > b2) { b2 = v; k2 = k; }
     }
     used[k2] = true;
     V3<T> nt = cross(e01, o.pt[k2].p - o.pt[k0].p);
@@ -638,7 +642,7 @@ template <class T> inline void reduce4(Out<T>& o) {
             if (v > best) best = v;
         }
         if (k3 >= 0) o.note(double(best) - double(b3));
-        if (best > b3) { b3 = best; k3 = k; }
+        if (k3 < 0 || best > b3) { b3 = best; k3 = k; }
     }
     used[k3] = true;
     int m = 0;
@@ -659,6 +663,7 @@ template <class T> struct CRow {
 // mean normal bounded by mu times the mean point radius times the summed normal impulse).
 template <class T> struct Manifold {
     int a, b, first, count, colour, pair;
+    V3<T> base, offB;  // frame of the contact geometry (for the record)
     V3<T> rA, rB, nb, t1, t2;
     T mt1, mt2, mtw, mu, rt;
     T lt1, lt2, ltw;
@@ -686,6 +691,33 @@ template <class T> struct BodyView {
 template <class T> inline V3<T> vel_at(const Body<T>* b, V3<T> r) {
     if (!b) return mk<T>(0, 0, 0);
     return b->v + cross(b->w, r);
+}
+
+// atan(t) for t in [0, 1]: two half-angle reductions, tan(a/2) = t / (1 + sqrt(1 + t^2)), bring
+// the argument below tan(pi/16) ~ 0.2; the alternating Taylor series to u^15 then has a
+// truncation error below 1e-13; the angle is scaled back by 4.
+template <class T> inline T atan_unit(T t) {
+    T u = t / (T(1) + std::sqrt(T(1) + t * t));
+    u = u / (T(1) + std::sqrt(T(1) + u * u));
+    T u2 = u * u;
+    T p = T(1) / T(15);
+    p = T(1) / T(13) - u2 * p;
+    p = T(1) / T(11) - u2 * p;
+    p = T(1) / T(9) - u2 * p;
+    p = T(1) / T(7) - u2 * p;
+    p = T(1) / T(5) - u2 * p;
+    p = T(1) / T(3) - u2 * p;
+    p = T(1) - u2 * p;
+    return T(4) * (u * p);
+}
+// atan2(y, x) for x >= 0 (result in [-pi/2, pi/2]) from atan_unit and the reflection
+// atan(t) = pi/2 - atan(1/t).
+template <class T> inline T atan2_pos(T y, T x) {
+    T ay = std::fabs(y);
+    T a;
+    if (ay <= x) a = x > T(0) ? atan_unit(ay / x) : T(0);
+    else a = T(3.14159265358979323846) / T(2) - atan_unit(x / ay);
+    return y < T(0) ? -a : a;
 }
 
 // Duff et al. 2017 branchless orthonormal basis of unit n: returns t1 (t2 = n x t1).
@@ -795,7 +827,12 @@ template <class T> struct Stepper {
         for (const Joint<T>& j : E.joints)
             if (j.parent >= 0) { jmask[j.parent] |= uint64_t(1) << j.child; jmask[j.child] |= uint64_t(1) << j.parent; }
 
-        const int cap = P.max_contacts_per_env > 0 ? P.max_contacts_per_env : 8 * n + 16;
+        // Capacities from the dynamic body count: points min(8 n_dyn + 16, 384), manifolds
+        // min(4 n_dyn + 16, 192), unless the parameters set them.
+        int n_dyn = 0;
+        for (int i = 0; i < n; ++i) n_dyn += E.bodies[i].dyn() ? 1 : 0;
+        const int cap = P.max_contacts_per_env > 0 ? P.max_contacts_per_env : std::min(8 * n_dyn + 16, 384);
+        const int mcap = P.max_manifolds_per_env > 0 ? P.max_manifolds_per_env : std::min(4 * n_dyn + 16, 192);
         rows.clear(); mans.clear();
         // S2 + S3 in canonical order: for each a, partners b = a+1 .. n-1, then the plane.
         for (int a = 0; a < n; ++a) {
@@ -844,7 +881,9 @@ template <class T> struct Stepper {
                 int pair_index = rec ? int(rec->pairs.size()) : 0;
                 int first = int(rows.size());
                 int keep = o.n;
+                // overflow keeps the first points / manifolds in canonical pair order
                 if (first + keep > cap) { keep = cap - first; E.status |= ST_CONTACT_OVERFLOW; }
+                if (keep > 0 && int(mans.size()) >= mcap) { keep = 0; E.status |= ST_CONTACT_OVERFLOW; }
                 if (rec) rec->pairs.push_back(PairRec{env_id, a, isplane ? PLANE_ID : bb, keep, o.decision, kind, o.margin,
                                                       0, 0, 0, 0, 0});
                 if (keep <= 0) continue;
@@ -875,6 +914,7 @@ template <class T> struct Stepper {
                 // there, else the Duff et al. basis of the mean normal.
                 Manifold<T> M;
                 M.a = ia; M.b = ib; M.first = first; M.count = keep; M.colour = 0; M.pair = pair_index;
+                M.base = base; M.offB = offB;
                 V3<T> c = (T(1) / T(keep)) * csum;
                 M.nb = (T(1) / len(nsum)) * nsum;
                 M.rA = ia >= 0 ? c : mk<T>(0, 0, 0);
@@ -958,11 +998,12 @@ template <class T> struct Stepper {
         Q<T> qa = j.parent >= 0 ? E.bodies[j.parent].q : Q<T>{1, 0, 0, 0};
         Q<T> rel = qmul(qconj(qmul(qa, j.QA)), qmul(E.bodies[j.child].q, j.QB));
         if (rel.w < T(0)) rel = Q<T>{-rel.w, -rel.x, -rel.y, -rel.z};
-        T th = T(2) * std::atan2(rel.z, rel.w);
+        T th = T(2) * atan2_pos(rel.z, rel.w);
         T c = th - target;
+        // wrap into (-pi, pi] with the exact IEEE remainder (non-finite stays non-finite)
         const T pi = T(3.14159265358979323846);
-        while (c > pi) c = c - T(2) * pi;
-        while (c <= -pi) c = c + T(2) * pi;
+        c = std::remainder(c, T(2) * pi);
+        if (c <= -pi) c = c + T(2) * pi;
         return c;
     }
 
@@ -1223,7 +1264,7 @@ template <class T> struct Stepper {
                 pr.mu = double(m.mu); pr.rt = double(m.rt);
                 for (int k = 0; k < m.count; ++k) {
                     const CRow<T>& r = rows[m.first + k];
-                    V3<T> p = r.rB + x0[r.b];
+                    V3<T> p = m.base + (r.a >= 0 ? r.rA : r.rB + m.offB);
                     rec->points.push_back(PointRec{env_id, m.pair, {double(p.x), double(p.y), double(p.z)},
                                                    {double(r.n.x), double(r.n.y), double(r.n.z)}, double(r.s0),
                                                    double(r.ln)});
@@ -1444,6 +1485,10 @@ void or_env_counters(void* h, int64_t* out, double* min_margin) {
         min_margin[e] = H->recs[e].min_margin;
     }
 }
+
+// The drive's arctangent, exposed for the pins (float64 and float32).
+double or_atan2_pos64(double y, double x) { return atan2_pos<double>(y, x); }
+float or_atan2_pos32(float y, float x) { return atan2_pos<float>(y, x); }
 
 // Mass properties exposed for the pins: volume and principal inertia for a given mass.
 void or_mass_props(int shape, const double* dims, double mass, double* volume, double* inertia) {

@@ -3,7 +3,7 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg use this module.  It
 loads ``liboracle.so`` built from ``ms_oracle.cpp`` with g++ (no GPU code, no shared source with
 the GPU library).  Descriptor arrays are the records produced by the input generators: the
-oracle reads them by byte layout (88-byte bodies, 76-byte joints, 84-byte parameters).
+oracle reads them by byte layout (88-byte bodies, 76-byte joints, 88-byte parameters).
 """
 from __future__ import annotations
 
@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "ms_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 76, 84
+BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 76, 88
 N_COUNTERS = 20
 COUNTER_NAMES = ["pairs_tested", "candidates", "points", "manifolds", "colours", "dynamic", "static",
                  "joints"] + [f"kind{k}" for k in range(12)]

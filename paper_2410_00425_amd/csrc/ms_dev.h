@@ -1,0 +1,133 @@
+// ms_dev.h — library-internal types shared by the host runtime and the step kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msdev {
+
+constexpr int WAVE = 64;
+constexpr int MAX_BODIES = 64;
+constexpr int MAX_JOINTS = 64;
+constexpr int PLANE = 0xFFFF;
+constexpr int N_COLOURS = 64;  // colours 0..63 are parallel; colour 64 is the serial overflow
+
+// Body parameter record in HBM: three float4 per body, component-plane major ([3][B]):
+//   p0 = {shape | flags << 8 (int bits), inverse mass, friction, restitution}
+//   p1 = {dim0, dim1, dim2, 0}
+//   p2 = {principal inverse inertia x, y, z, 0}
+// Joint record in HBM: JREC floats per joint: parent, child (int bits), anchor A (3), frame
+// rotation A (4), anchor B (3), frame rotation B (4), kp, kd.
+constexpr int JREC = 18;
+
+// One batch as the kernels see it (device memory, read by every tile of the batch).
+struct BatchDev {
+    float* pos;     // [3][B]
+    float* quat;    // [4][B]
+    float* vel;     // [3][B]
+    float* angvel;  // [3][B]
+    int* status;    // [E]
+    const float4* bpar;   // [3][B]
+    const int* body_off;  // [E + 1]
+    const int* joint_off; // [E + 1]
+    const float* jrec;    // [J][JREC]
+    const float* targets; // [J]
+    int B, E, J, pad0;
+    // step model parameters
+    float dt, gx, gy, gz;
+    int S, K, V, JI;       // substeps, iterations per substep, velocity iterations, joint passes
+    float plane_z, plane_mu, plane_e, delta;
+    int plane, pad1, pad2, pad3;
+    float beta, max_depen, beta_j, bounce;
+    float lin_damp, ang_damp, pad4, pad5;
+    // debug export of the last step of a launch (null when off)
+    int* dbg_pairs;        // [sum P_e][4]: a, b, kept points, decision
+    const int* dbg_pair_off;
+    float* dbg_pts;        // [sum cap_e][8]: p (3), n (3), s0, lambda_n
+    const int* dbg_pt_off;
+    float* dbg_man;        // [sum mcap_e][8]: pair index, colour, lt1, lt2, ltw, mu, rt, count
+    const int* dbg_man_off;
+    int* dbg_counts;       // [E][4]: candidates, points, manifolds, colours
+};
+
+// One env slot of a tile (host-computed).
+struct TileEnv {
+    int batch;    // index into the launch's batch table
+    int env;      // env id within the batch
+    int lds_off;  // word offset of the env's LDS region within the workgroup's LDS
+    int n;        // bodies
+    int nj;       // joints
+    int cap;      // contact point capacity
+    int mcap;     // manifold capacity
+    int pad;
+};
+
+// A tile: `count` envs (consecutive TileEnv records from `first`), `lanes` lanes per env.
+struct Tile {
+    int first;
+    int count;
+    int lanes;
+    int lds_words;
+};
+
+// Word offsets of one env's arrays (component-major planes of length n / cap / mcap).
+struct Lay {
+    int n, nj, cap, mcap, P;
+    // bodies
+    int X0, Q0, DX, DQ, QC, V, W, V0, W0, INVM, IB, IW, AABB, SH, DIM, MU, EE, CM, JM;
+    int JNT, CAND, PT, MAN, BCOL, ORDER, SCHED, JSCHED, CSTART, SCAL;
+    int total;  // words, a multiple of 4
+};
+__host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
+    Lay L;
+    L.n = n; L.nj = nj; L.cap = cap; L.mcap = mcap; L.P = n * (n + 1) / 2;
+    int o = 0;
+    L.X0 = o; o += 3 * n;
+    L.Q0 = o; o += 4 * n;
+    L.DX = o; o += 3 * n;
+    L.DQ = o; o += 4 * n;
+    L.QC = o; o += 4 * n;
+    L.V = o; o += 3 * n;
+    L.W = o; o += 3 * n;
+    L.V0 = o; o += 3 * n;
+    L.W0 = o; o += 3 * n;
+    L.INVM = o; o += n;
+    L.IB = o; o += 3 * n;  // principal inverse inertia (body frame)
+    L.IW = o; o += 6 * n;  // world inverse inertia, frozen for the step
+    L.AABB = o; o += 6 * n;
+    L.SH = o; o += n;
+    L.DIM = o; o += 3 * n;
+    L.MU = o; o += n;
+    L.EE = o; o += n;
+    L.CM = o; o += 2 * n;  // colour masks (u64)
+    L.JM = o; o += 2 * n;  // jointed-partner masks (u64)
+    // 55 n words so far
+    L.JNT = o; o += 26 * nj;
+    L.CAND = o; o += (L.P + 1) / 2;
+    L.PT = o; o += 14 * cap;
+    L.MAN = o; o += 22 * mcap;
+    L.BCOL = o; o += (nj + mcap + 1) / 2;
+    L.ORDER = o; o += (nj + mcap + 1) / 2;
+    L.SCHED = o; o += nj + mcap + 66;
+    L.JSCHED = o; o += nj + mcap + 66;
+    L.CSTART = o; o += 68;
+    L.SCAL = o; o += 16;
+    L.total = (o + 3) & ~3;
+    return L;
+}
+// LDS words needed by one env.
+inline int env_lds_words(int n, int nj, int cap, int mcap) { return make_lay(n, nj, cap, mcap).total; }
+
+// Pair index k in canonical order -> (a, b) with a < b <= n (b = n is the plane).
+__host__ __device__ inline void pair_of(int k, int n, int& a, int& b) {
+    // row a starts at a (2n - a + 1) / 2
+    float fn = float(2 * n + 1);
+    int aa = int((fn - sqrtf(fn * fn - 8.0f * float(k))) * 0.5f);
+    aa = (aa < 0 ? 0 : (aa > n - 1 ? n - 1 : aa));
+    while (aa > 0 && aa * (2 * n - aa + 1) / 2 > k) --aa;
+    while (aa + 1 < n && (aa + 1) * (2 * n - aa) / 2 <= k) ++aa;
+    a = aa;
+    b = a + 1 + (k - a * (2 * n - a + 1) / 2);
+}
+
+
+}  // namespace msdev

@@ -1,0 +1,685 @@
+// ms_host.cpp — host runtime of libms: validation, workspace layout, env-tile planning,
+// launches and the C ABI declared in include/ms.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ms.h"
+#include "ms_dev.h"
+
+using namespace msdev;
+
+extern "C" __global__ void ms_step_kernel(const BatchDev* batches, const Tile* tiles, int n_tiles, const TileEnv* tenv,
+                                          int n_steps);
+extern "C" __global__ void ms_reset_kernel(BatchDev bd, const int* env_ids, int n_ids, const float* spos,
+                                           const float* squat, const float* svel, const float* sang);
+
+namespace {
+
+thread_local std::string g_err;
+
+ms_status fail(ms_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ms_status fail(ms_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_OK(call)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return fail(MS_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Per-env sizes used by the planner.
+struct EnvInfo {
+    int n, nj, n_dyn, cap, mcap, words, lanes;
+};
+
+// Lanes per env: enough lanes for the env's parallel work, then widened until 64 / G envs of
+// this size fit the tile LDS budget.
+int pick_lanes(const EnvInfo& e, int forced, int tile_budget_words) {
+    if (forced > 0) return forced;
+    int G;
+    if (e.n <= 2 && e.nj == 0) G = 8;
+    else if (e.n <= 6) G = 16;
+    else if (e.n <= 14) G = 32;
+    else G = 64;
+    while (G < 64 && (WAVE / G) * e.words > tile_budget_words) G *= 2;
+    return G;
+}
+
+struct Plan {
+    std::vector<EnvInfo> info;
+    std::vector<Tile> tiles;
+    std::vector<TileEnv> tenv;
+    int max_tile_words = 0;
+    // debug offsets
+    std::vector<int> dbg_pair_off, dbg_pt_off, dbg_man_off;
+};
+
+// Workspace sections (byte offsets from the workspace base).
+struct WsLayout {
+    size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, status, bpar, body_off, joint_off, jrec, targets, tiles,
+        tenv, bd, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
+};
+
+ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
+    if (!p || !s) return fail(MS_E_INVALID_ARG, "null params or scene");
+    if (s->n_envs <= 0) return fail(MS_E_INVALID_ARG, "n_envs must be positive (got %d)", s->n_envs);
+    if (!s->env_body_off || !s->env_joint_off || !s->bodies) return fail(MS_E_INVALID_ARG, "null scene arrays");
+    if (!(p->dt > 0.0f) || !std::isfinite(p->dt)) return fail(MS_E_INVALID_ARG, "dt must be positive");
+    if (p->pos_iters < 1 || p->pos_iters > 256) return fail(MS_E_INVALID_ARG, "pos_iters out of range [1, 256]");
+    if (p->vel_iters < 0 || p->vel_iters > 256) return fail(MS_E_INVALID_ARG, "vel_iters out of range [0, 256]");
+    if (p->solver != MS_SOLVER_TGS && p->solver != MS_SOLVER_PGS) return fail(MS_E_INVALID_ARG, "unknown solver");
+    if (p->joint_iters < 0 || p->joint_iters > 64) return fail(MS_E_INVALID_ARG, "joint_iters out of range [0, 64]");
+    if (s->env_body_off[0] != 0 || s->env_joint_off[0] != 0) return fail(MS_E_INVALID_ARG, "offsets must start at 0");
+    for (int e = 0; e < s->n_envs; ++e) {
+        int nb = s->env_body_off[e + 1] - s->env_body_off[e];
+        int nj = s->env_joint_off[e + 1] - s->env_joint_off[e];
+        if (nb < 1 || nb > MS_MAX_BODIES_PER_ENV)
+            return fail(MS_E_CAPACITY, "env %d has %d bodies (1..%d supported)", e, nb, MS_MAX_BODIES_PER_ENV);
+        if (nj < 0 || nj > MS_MAX_JOINTS_PER_ENV)
+            return fail(MS_E_CAPACITY, "env %d has %d joints (0..%d supported)", e, nj, MS_MAX_JOINTS_PER_ENV);
+        if (nj > 0 && !s->joints) return fail(MS_E_INVALID_ARG, "null joints array");
+        for (int i = 0; i < nb; ++i) {
+            const ms_body_desc& b = s->bodies[s->env_body_off[e] + i];
+            if (b.shape < MS_SPHERE || b.shape > MS_BOX) return fail(MS_E_INVALID_ARG, "env %d body %d: bad shape", e, i);
+            if ((b.flags & ~MS_BODY_STATIC) != 0) return fail(MS_E_INVALID_ARG, "env %d body %d: bad flags", e, i);
+            int nd = b.shape == MS_SPHERE ? 1 : (b.shape == MS_CAPSULE ? 2 : 3);
+            for (int k = 0; k < nd; ++k)
+                if (!(b.dims[k] > 0.0f) || !std::isfinite(b.dims[k]))
+                    return fail(MS_E_INVALID_ARG, "env %d body %d: dims must be positive", e, i);
+            if (b.shape == MS_CAPSULE && b.dims[1] < 0.0f) return fail(MS_E_INVALID_ARG, "bad capsule");
+            if (!(b.flags & MS_BODY_STATIC) && !(b.mass > 0.0f) && !(b.density > 0.0f))
+                return fail(MS_E_INVALID_ARG, "env %d body %d: dynamic body needs mass or density", e, i);
+        }
+        for (int j = 0; j < nj; ++j) {
+            const ms_joint_desc& d = s->joints[s->env_joint_off[e] + j];
+            if (d.parent < -1 || d.parent >= nb || d.child < 0 || d.child >= nb || d.parent == d.child)
+                return fail(MS_E_INVALID_ARG, "env %d joint %d: bad body index", e, j);
+            if (s->bodies[s->env_body_off[e] + d.child].flags & MS_BODY_STATIC)
+                return fail(MS_E_INVALID_ARG, "env %d joint %d: child must be dynamic", e, j);
+            if (!std::isfinite(d.target) || !std::isfinite(d.kp) || !std::isfinite(d.kd) || d.kp < 0 || d.kd < 0)
+                return fail(MS_E_INVALID_ARG, "env %d joint %d: kp, kd must be finite and >= 0, target finite", e, j);
+        }
+    }
+    return MS_OK;
+}
+
+void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* plan, Plan& out) {
+    const int E = s->n_envs;
+    const int forced = plan ? plan->lanes_per_env : 0;
+    const bool pack = plan ? plan->pack != 0 : true;
+    const int budget = 8192;  // tile LDS budget in words (32 KiB) unless one env needs more
+    out.info.resize(E);
+    for (int e = 0; e < E; ++e) {
+        EnvInfo& I = out.info[e];
+        I.n = s->env_body_off[e + 1] - s->env_body_off[e];
+        I.nj = s->env_joint_off[e + 1] - s->env_joint_off[e];
+        I.n_dyn = 0;
+        for (int i = 0; i < I.n; ++i) I.n_dyn += (s->bodies[s->env_body_off[e] + i].flags & MS_BODY_STATIC) ? 0 : 1;
+        I.cap = p->max_contacts_per_env > 0 ? p->max_contacts_per_env : std::min(8 * I.n_dyn + 16, 384);
+        I.mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(4 * I.n_dyn + 16, 192);
+        I.words = env_lds_words(I.n, I.nj, I.cap, I.mcap);
+        I.lanes = pick_lanes(I, forced, budget);
+    }
+    std::vector<int> order(E);
+    for (int e = 0; e < E; ++e) order[e] = e;
+    if (pack)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            if (out.info[a].lanes != out.info[b].lanes) return out.info[a].lanes < out.info[b].lanes;
+            return out.info[a].words < out.info[b].words;
+        });
+    out.tiles.clear();
+    out.tenv.clear();
+    out.max_tile_words = 0;
+    Tile cur{0, 0, 0, 0};
+    for (int k = 0; k < E; ++k) {
+        int e = order[k];
+        const EnvInfo& I = out.info[e];
+        bool fits = cur.count > 0 && cur.lanes == I.lanes && cur.count < WAVE / I.lanes &&
+                    cur.lds_words + I.words <= std::max(budget, I.words);
+        if (!fits) {
+            if (cur.count > 0) out.tiles.push_back(cur);
+            cur = Tile{int(out.tenv.size()), 0, I.lanes, 0};
+        }
+        out.tenv.push_back(TileEnv{0, e, cur.lds_words, I.n, I.nj, I.cap, I.mcap, 0});
+        cur.lds_words += I.words;
+        cur.count++;
+    }
+    if (cur.count > 0) out.tiles.push_back(cur);
+    for (const Tile& t : out.tiles) out.max_tile_words = std::max(out.max_tile_words, t.lds_words);
+    out.dbg_pair_off.assign(E + 1, 0);
+    out.dbg_pt_off.assign(E + 1, 0);
+    out.dbg_man_off.assign(E + 1, 0);
+    for (int e = 0; e < E; ++e) {
+        const EnvInfo& I = out.info[e];
+        out.dbg_pair_off[e + 1] = out.dbg_pair_off[e] + I.n * (I.n + 1) / 2;
+        out.dbg_pt_off[e + 1] = out.dbg_pt_off[e] + I.cap;
+        out.dbg_man_off[e + 1] = out.dbg_man_off[e] + I.mcap;
+    }
+}
+
+WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& pl) {
+    WsLayout L{};
+    const size_t E = size_t(s->n_envs), B = size_t(s->env_body_off[s->n_envs]), J = size_t(s->env_joint_off[s->n_envs]);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 4)); return r; };
+    L.pos = take(3 * B * 4); L.quat = take(4 * B * 4); L.vel = take(3 * B * 4); L.angvel = take(3 * B * 4);
+    L.ipos = take(3 * B * 4); L.iquat = take(4 * B * 4); L.ivel = take(3 * B * 4); L.iang = take(3 * B * 4);
+    L.status = take(E * 4);
+    L.bpar = take(3 * B * 16);
+    L.body_off = take((E + 1) * 4);
+    L.joint_off = take((E + 1) * 4);
+    L.jrec = take(J * JREC * 4);
+    L.targets = take(J * 4);
+    L.tiles = take(pl.tiles.size() * sizeof(Tile));
+    L.tenv = take(pl.tenv.size() * sizeof(TileEnv));
+    L.bd = take(sizeof(BatchDev));
+    if (p->debug_export) {
+        L.dbg_pairs = take(size_t(pl.dbg_pair_off[E]) * 16);
+        L.dbg_pair_off = take((E + 1) * 4);
+        L.dbg_pts = take(size_t(pl.dbg_pt_off[E]) * 32);
+        L.dbg_pt_off = take((E + 1) * 4);
+        L.dbg_man = take(size_t(pl.dbg_man_off[E]) * 32);
+        L.dbg_man_off = take((E + 1) * 4);
+        L.dbg_counts = take(E * 16);
+    }
+    L.total = o;
+    return L;
+}
+
+// Mass properties (uniform density; centre of mass at the shape centre).
+void mass_props(const ms_body_desc& b, float& invm, float inv_inertia[3]) {
+    if (b.flags & MS_BODY_STATIC) { invm = 0.0f; inv_inertia[0] = inv_inertia[1] = inv_inertia[2] = 0.0f; return; }
+    // float32 throughout, in the order of the step model's definition (uniform density).
+    float m;
+    if (b.mass > 0.0f) m = b.mass;
+    else {
+        float fd0 = b.dims[0], fd1 = b.dims[1], fd2 = b.dims[2];
+        const float fpi = 3.14159265358979323846f;
+        float fv;
+        if (b.shape == MS_SPHERE) fv = 4.0f / 3.0f * fpi * fd0 * fd0 * fd0;
+        else if (b.shape == MS_CAPSULE) { float L = 2.0f * fd1; fv = fpi * fd0 * fd0 * L + 4.0f / 3.0f * fpi * fd0 * fd0 * fd0; }
+        else fv = 8.0f * fd0 * fd1 * fd2;
+        m = b.density * fv;
+    }
+    float I[3];
+    float f0 = b.dims[0], f1 = b.dims[1], f2 = b.dims[2];
+    if (b.shape == MS_SPHERE) { float i = 2.0f / 5.0f * m * f0 * f0; I[0] = I[1] = I[2] = i; }
+    else if (b.shape == MS_BOX) {
+        float a = 2.0f * f0, bb = 2.0f * f1, c = 2.0f * f2;
+        I[0] = m / 12.0f * (bb * bb + c * c); I[1] = m / 12.0f * (a * a + c * c); I[2] = m / 12.0f * (a * a + bb * bb);
+    } else {
+        const float fpi = 3.14159265358979323846f;
+        float r = f0, L = 2.0f * f1;
+        float vc = fpi * r * r * L, vs = 4.0f / 3.0f * fpi * r * r * r;
+        float rho = m / (vc + vs);
+        float mc = rho * vc, ms = rho * vs;
+        float izz = mc * r * r / 2.0f + ms * 2.0f * r * r / 5.0f;
+        float ixx = mc * (L * L / 12.0f + r * r / 4.0f) + ms * (2.0f * r * r / 5.0f + L * L / 4.0f + 3.0f * L * r / 8.0f);
+        I[0] = ixx; I[1] = ixx; I[2] = izz;
+    }
+    invm = 1.0f / m;
+    for (int k = 0; k < 3; ++k) inv_inertia[k] = 1.0f / I[k];
+}
+
+}  // namespace
+
+struct ms_batch {
+    ms_sim_params P;
+    int E = 0, B = 0, J = 0;
+    std::vector<int> body_off, joint_off;
+    Plan plan;
+    WsLayout lay;
+    char* ws = nullptr;
+    BatchDev hbd;
+    BatchDev* dbd = nullptr;
+    int device = 0;
+    int grid = 0;
+    size_t lds_bytes = 0;
+};
+
+namespace {
+template <class T> T* at(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
+
+void fill_batchdev(ms_batch* b) {
+    BatchDev& d = b->hbd;
+    std::memset(&d, 0, sizeof(d));
+    char* w = b->ws;
+    const WsLayout& L = b->lay;
+    d.pos = at<float>(w, L.pos); d.quat = at<float>(w, L.quat); d.vel = at<float>(w, L.vel); d.angvel = at<float>(w, L.angvel);
+    d.status = at<int>(w, L.status);
+    d.bpar = at<float4>(w, L.bpar);
+    d.body_off = at<int>(w, L.body_off); d.joint_off = at<int>(w, L.joint_off);
+    d.jrec = at<float>(w, L.jrec); d.targets = at<float>(w, L.targets);
+    d.B = b->B; d.E = b->E; d.J = b->J;
+    const ms_sim_params& p = b->P;
+    d.dt = p.dt; d.gx = p.gravity[0]; d.gy = p.gravity[1]; d.gz = p.gravity[2];
+    bool tgs = p.solver == MS_SOLVER_TGS;
+    d.S = tgs ? std::max(p.pos_iters, 1) : 1;
+    d.K = tgs ? 1 : std::max(p.pos_iters, 1);
+    d.V = p.vel_iters;
+    d.JI = std::max(p.joint_iters, 1);
+    d.plane_z = p.plane_z; d.plane_mu = p.plane_friction; d.plane_e = p.plane_restitution; d.delta = p.contact_offset;
+    d.plane = p.plane_enabled ? 1 : 0;
+    d.beta = p.baumgarte; d.max_depen = p.max_depen_vel; d.beta_j = p.joint_baumgarte; d.bounce = p.bounce_threshold;
+    d.lin_damp = p.lin_damping; d.ang_damp = p.ang_damping;
+    if (p.debug_export) {
+        d.dbg_pairs = at<int>(w, L.dbg_pairs); d.dbg_pair_off = at<int>(w, L.dbg_pair_off);
+        d.dbg_pts = at<float>(w, L.dbg_pts); d.dbg_pt_off = at<int>(w, L.dbg_pt_off);
+        d.dbg_man = at<float>(w, L.dbg_man); d.dbg_man_off = at<int>(w, L.dbg_man_off);
+        d.dbg_counts = at<int>(w, L.dbg_counts);
+    }
+}
+}  // namespace
+
+extern "C" {
+
+const char* ms_last_error(void) { return g_err.c_str(); }
+const char* ms_version(void) { return "libms 0.1 (gfx950)"; }
+
+// Host-side consistency check of the kernel indexing (no device needed): every LDS array of the
+// env layout lies inside its allocation and the pair decode enumerates exactly the canonical
+// order (a, b), a < b <= n, for every supported body count.  Returns 0 when consistent.
+int ms_selfcheck(void) {
+    for (int n = 1; n <= MAX_BODIES; ++n) {
+        const int P = n * (n + 1) / 2;
+        int k = 0;
+        for (int a = 0; a < n; ++a)
+            for (int b = a + 1; b <= n; ++b, ++k) {
+                int pa, pb;
+                pair_of(k, n, pa, pb);
+                if (pa != a || pb != b) return 1;
+            }
+        if (k != P) return 2;
+        for (int nj = 0; nj <= MAX_JOINTS; nj += 7)
+            for (int cap = 1; cap <= 512; cap = cap * 2 + 1)
+                for (int mcap = 1; mcap <= cap; mcap = mcap * 2 + 1) {
+                    Lay L = make_lay(n, nj, cap, mcap);
+                    int ends[] = {L.JM + 2 * n, L.JNT + 26 * nj, L.CAND + (P + 1) / 2, L.PT + 14 * cap,
+                                  L.MAN + 22 * mcap, L.BCOL + (nj + mcap + 1) / 2, L.ORDER + (nj + mcap + 1) / 2,
+                                  L.SCHED + nj + mcap + 66, L.JSCHED + nj + mcap + 66, L.CSTART + 68, L.SCAL + 16};
+                    for (int e : ends)
+                        if (e > L.total) return 3;
+                    if (L.SCAL + 16 > L.total || (L.total & 3)) return 4;
+                }
+    }
+    return 0;
+}
+
+static ms_status validate_plan(const ms_plan* plan) {
+    if (!plan) return MS_OK;
+    int g = plan->lanes_per_env;
+    if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
+        return fail(MS_E_INVALID_ARG, "lanes_per_env must be 0 or a power of two <= 64 (got %d)", g);
+    if (plan->max_resident_groups < 0) return fail(MS_E_INVALID_ARG, "max_resident_groups must be >= 0");
+    return MS_OK;
+}
+
+ms_status ms_query_batch_bytes(const ms_sim_params* params, const ms_scene_desc* scene, const ms_plan* plan,
+                               size_t* bytes) {
+    if (!bytes) return fail(MS_E_INVALID_ARG, "null bytes");
+    ms_status st = validate(params, scene);
+    if (st == MS_OK) st = validate_plan(plan);
+    if (st != MS_OK) return st;
+    Plan pl;
+    plan_batch(params, scene, plan, pl);
+    *bytes = layout_ws(params, scene, pl).total;
+    return MS_OK;
+}
+
+ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scene, const ms_plan* plan,
+                          void* dev_workspace, size_t ws_bytes, void* hip_stream, ms_batch** out) {
+    if (!out) return fail(MS_E_INVALID_ARG, "null out");
+    *out = nullptr;
+    ms_status st = validate(params, scene);
+    if (st == MS_OK) st = validate_plan(plan);
+    if (st != MS_OK) return st;
+    if (!dev_workspace) return fail(MS_E_INVALID_ARG, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN) return fail(MS_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    ms_batch* b = new ms_batch();
+    b->P = *params;
+    b->E = scene->n_envs;
+    b->B = scene->env_body_off[b->E];
+    b->J = scene->env_joint_off[b->E];
+    b->body_off.assign(scene->env_body_off, scene->env_body_off + b->E + 1);
+    b->joint_off.assign(scene->env_joint_off, scene->env_joint_off + b->E + 1);
+    plan_batch(params, scene, plan, b->plan);
+    b->lay = layout_ws(params, scene, b->plan);
+    if (ws_bytes < b->lay.total) {
+        size_t need = b->lay.total;
+        delete b;
+        return fail(MS_E_NO_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    }
+    b->ws = static_cast<char*>(dev_workspace);
+    if (hipGetDevice(&b->device) != hipSuccess) { delete b; return fail(MS_E_DEVICE, "hipGetDevice failed"); }
+    fill_batchdev(b);
+    b->lds_bytes = size_t(b->plan.max_tile_words) * 4;
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess) max_lds = 65536;
+    if (b->lds_bytes > size_t(max_lds)) {
+        size_t need = b->lds_bytes;
+        delete b;
+        return fail(MS_E_CAPACITY, "an env tile needs %zu bytes of LDS; the device allows %d", need, max_lds);
+    }
+    const int n_tiles = int(b->plan.tiles.size());
+    b->grid = n_tiles;
+    if (plan && plan->max_resident_groups > 0) b->grid = std::min(n_tiles, plan->max_resident_groups);
+
+    // host staging
+    const size_t B = b->B, E = b->E, J = b->J;
+    std::vector<float> hs(13 * B);
+    std::vector<float4> bp(3 * B);
+    for (size_t i = 0; i < B; ++i) {
+        const ms_body_desc& d = scene->bodies[i];
+        for (int r = 0; r < 3; ++r) hs[r * B + i] = d.pos[r];
+        for (int r = 0; r < 4; ++r) hs[3 * B + r * B + i] = d.quat[r];
+        for (int r = 0; r < 3; ++r) hs[7 * B + r * B + i] = d.linvel[r];
+        for (int r = 0; r < 3; ++r) hs[10 * B + r * B + i] = d.angvel[r];
+        float invm, iI[3];
+        mass_props(d, invm, iI);
+        int code = d.shape | (d.flags << 8);
+        float codef;
+        std::memcpy(&codef, &code, 4);
+        bp[i] = float4{codef, invm, d.friction, d.restitution};
+        bp[B + i] = float4{d.dims[0], d.dims[1], d.dims[2], 0.0f};
+        bp[2 * B + i] = float4{iI[0], iI[1], iI[2], 0.0f};
+    }
+    std::vector<float> jr(std::max<size_t>(J, 1) * JREC);
+    std::vector<float> tg(std::max<size_t>(J, 1));
+    for (size_t j = 0; j < J; ++j) {
+        const ms_joint_desc& d = scene->joints[j];
+        float* r = &jr[j * JREC];
+        std::memcpy(&r[0], &d.parent, 4);
+        std::memcpy(&r[1], &d.child, 4);
+        for (int k = 0; k < 3; ++k) r[2 + k] = d.frame_parent[k];
+        for (int k = 0; k < 4; ++k) r[5 + k] = d.frame_parent[3 + k];
+        for (int k = 0; k < 3; ++k) r[9 + k] = d.frame_child[k];
+        for (int k = 0; k < 4; ++k) r[12 + k] = d.frame_child[3 + k];
+        r[16] = d.kp;
+        r[17] = d.kd;
+        tg[j] = d.target;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    char* w = b->ws;
+    const WsLayout& L = b->lay;
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    std::vector<int> zeros(E, 0);
+    hipError_t e = hipSuccess;
+    const size_t p3 = 3 * B * 4, p4 = 4 * B * 4;
+    if (e == hipSuccess) e = up(L.pos, &hs[0], p3);
+    if (e == hipSuccess) e = up(L.quat, &hs[3 * B], p4);
+    if (e == hipSuccess) e = up(L.vel, &hs[7 * B], p3);
+    if (e == hipSuccess) e = up(L.angvel, &hs[10 * B], p3);
+    if (e == hipSuccess) e = up(L.ipos, &hs[0], p3);
+    if (e == hipSuccess) e = up(L.iquat, &hs[3 * B], p4);
+    if (e == hipSuccess) e = up(L.ivel, &hs[7 * B], p3);
+    if (e == hipSuccess) e = up(L.iang, &hs[10 * B], p3);
+    if (e == hipSuccess) e = up(L.status, zeros.data(), E * 4);
+    if (e == hipSuccess) e = up(L.bpar, bp.data(), 3 * B * 16);
+    if (e == hipSuccess) e = up(L.body_off, b->body_off.data(), (E + 1) * 4);
+    if (e == hipSuccess) e = up(L.joint_off, b->joint_off.data(), (E + 1) * 4);
+    if (e == hipSuccess) e = up(L.jrec, jr.data(), J * JREC * 4);
+    if (e == hipSuccess) e = up(L.targets, tg.data(), J * 4);
+    if (e == hipSuccess) e = up(L.tiles, b->plan.tiles.data(), b->plan.tiles.size() * sizeof(Tile));
+    if (e == hipSuccess) e = up(L.tenv, b->plan.tenv.data(), b->plan.tenv.size() * sizeof(TileEnv));
+    if (e == hipSuccess) e = up(L.bd, &b->hbd, sizeof(BatchDev));
+    if (params->debug_export) {
+        if (e == hipSuccess) e = up(L.dbg_pair_off, b->plan.dbg_pair_off.data(), (E + 1) * 4);
+        if (e == hipSuccess) e = up(L.dbg_pt_off, b->plan.dbg_pt_off.data(), (E + 1) * 4);
+        if (e == hipSuccess) e = up(L.dbg_man_off, b->plan.dbg_man_off.data(), (E + 1) * 4);
+        std::vector<int> zc(4 * E, 0);
+        if (e == hipSuccess) e = up(L.dbg_counts, zc.data(), 16 * E);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    // the staging vectors go out of scope here: wait for the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(MS_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    b->dbd = at<BatchDev>(w, L.bd);
+    *out = b;
+    return MS_OK;
+}
+
+ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (n_steps < 1) return fail(MS_E_INVALID_ARG, "n_steps must be >= 1 (got %d)", n_steps);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (dev_targets && b->J > 0)
+        HIP_OK(hipMemcpyAsync(const_cast<float*>(b->hbd.targets), dev_targets, size_t(b->J) * 4, hipMemcpyDeviceToDevice, s));
+    const int n_tiles = int(b->plan.tiles.size());
+    hipLaunchKernelGGL(ms_step_kernel, dim3(b->grid), dim3(WAVE), b->lds_bytes, s, b->dbd,
+                       at<Tile>(b->ws, b->lay.tiles), n_tiles, at<TileEnv>(b->ws, b->lay.tenv), int(n_steps));
+    HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+ms_status ms_reset_envs(ms_batch* b, const int32_t* dev_env_ids, int32_t n_ids, const ms_state_view* src,
+                        void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (n_ids < 0) return fail(MS_E_INVALID_ARG, "n_ids must be >= 0");
+    if (n_ids == 0) return MS_OK;
+    if (!dev_env_ids) return fail(MS_E_INVALID_ARG, "null env ids");
+    const float *sp, *sq, *sv, *sw;
+    if (src) {
+        if (!src->pos || !src->quat || !src->linvel || !src->angvel) return fail(MS_E_INVALID_ARG, "null source plane");
+        sp = src->pos; sq = src->quat; sv = src->linvel; sw = src->angvel;
+    } else {
+        sp = at<float>(b->ws, b->lay.ipos); sq = at<float>(b->ws, b->lay.iquat);
+        sv = at<float>(b->ws, b->lay.ivel); sw = at<float>(b->ws, b->lay.iang);
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(ms_reset_kernel, dim3(n_ids), dim3(WAVE), 0, s, b->hbd, dev_env_ids, int(n_ids), sp, sq, sv, sw);
+    HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+ms_status ms_get_state(ms_batch* b, const ms_state_view* dst, void* hip_stream) {
+    if (!b || !dst) return fail(MS_E_INVALID_ARG, "null batch or view");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t B = b->B;
+    if (dst->pos) HIP_OK(hipMemcpyAsync(dst->pos, b->hbd.pos, 3 * B * 4, hipMemcpyDeviceToDevice, s));
+    if (dst->quat) HIP_OK(hipMemcpyAsync(dst->quat, b->hbd.quat, 4 * B * 4, hipMemcpyDeviceToDevice, s));
+    if (dst->linvel) HIP_OK(hipMemcpyAsync(dst->linvel, b->hbd.vel, 3 * B * 4, hipMemcpyDeviceToDevice, s));
+    if (dst->angvel) HIP_OK(hipMemcpyAsync(dst->angvel, b->hbd.angvel, 3 * B * 4, hipMemcpyDeviceToDevice, s));
+    if (dst->status) HIP_OK(hipMemcpyAsync(dst->status, b->hbd.status, size_t(b->E) * 4, hipMemcpyDeviceToDevice, s));
+    return MS_OK;
+}
+
+ms_status ms_get_layout(ms_batch* b, int32_t* host_env_body_off, int32_t* host_env_joint_off) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (host_env_body_off) std::copy(b->body_off.begin(), b->body_off.end(), host_env_body_off);
+    if (host_env_joint_off) std::copy(b->joint_off.begin(), b->joint_off.end(), host_env_joint_off);
+    return MS_OK;
+}
+
+ms_status ms_get_sizes(ms_batch* b, int32_t* n_envs, int32_t* n_bodies, int32_t* n_joints) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (n_envs) *n_envs = b->E;
+    if (n_bodies) *n_bodies = b->B;
+    if (n_joints) *n_joints = b->J;
+    return MS_OK;
+}
+
+ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds_bytes, int32_t* host_env_lanes) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (n_tiles) *n_tiles = int(b->plan.tiles.size());
+    if (grid) *grid = b->grid;
+    if (lds_bytes) *lds_bytes = int(b->lds_bytes);
+    if (host_env_lanes)
+        for (int e = 0; e < b->E; ++e) host_env_lanes[e] = b->plan.info[e].lanes;
+    return MS_OK;
+}
+
+ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, float* host_points, int32_t points_cap,
+                          float* host_manifolds, int32_t manifolds_cap, int32_t* n_pairs, int32_t* n_points,
+                          int32_t* n_manifolds, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (!b->P.debug_export) return fail(MS_E_STATE, "contact export needs debug_export in the sim params");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_OK(hipStreamSynchronize(s));
+    const int E = b->E;
+    const Plan& pl = b->plan;
+    std::vector<int> counts(size_t(E) * 4);
+    HIP_OK(hipMemcpy(counts.data(), b->hbd.dbg_counts, size_t(E) * 16, hipMemcpyDeviceToHost));
+    std::vector<int> dp(size_t(pl.dbg_pair_off[E]) * 4);
+    std::vector<float> dpt(size_t(pl.dbg_pt_off[E]) * 8), dm(size_t(pl.dbg_man_off[E]) * 8);
+    if (!dp.empty()) HIP_OK(hipMemcpy(dp.data(), b->hbd.dbg_pairs, dp.size() * 4, hipMemcpyDeviceToHost));
+    if (!dpt.empty()) HIP_OK(hipMemcpy(dpt.data(), b->hbd.dbg_pts, dpt.size() * 4, hipMemcpyDeviceToHost));
+    if (!dm.empty()) HIP_OK(hipMemcpy(dm.data(), b->hbd.dbg_man, dm.size() * 4, hipMemcpyDeviceToHost));
+    int np = 0, npt = 0, nm = 0;
+    for (int e = 0; e < E; ++e) {
+        const EnvInfo& I = pl.info[e];
+        int nc = std::min(std::max(counts[4 * e], 0), I.n * (I.n + 1) / 2);
+        int nps = std::min(std::max(counts[4 * e + 1], 0), I.cap);
+        int nms = std::min(std::max(counts[4 * e + 2], 0), I.mcap);
+        for (int k = 0; k < nc; ++k, ++np) {
+            if (host_pairs && np < pairs_cap) {
+                const int* r = &dp[4 * size_t(pl.dbg_pair_off[e] + k)];
+                int32_t* o = host_pairs + 5 * size_t(np);
+                o[0] = e; o[1] = r[0]; o[2] = r[1]; o[3] = r[2]; o[4] = r[3];
+            }
+        }
+        for (int k = 0; k < nps; ++k, ++npt) {
+            if (host_points && npt < points_cap) {
+                const float* r = &dpt[8 * size_t(pl.dbg_pt_off[e] + k)];
+                std::copy(r, r + 8, host_points + 8 * size_t(npt));
+            }
+        }
+        for (int k = 0; k < nms; ++k, ++nm) {
+            if (host_manifolds && nm < manifolds_cap) {
+                const float* r = &dm[8 * size_t(pl.dbg_man_off[e] + k)];
+                float* o = host_manifolds + 8 * size_t(nm);
+                int pair_idx, colour;
+                std::memcpy(&pair_idx, &r[0], 4);
+                std::memcpy(&colour, &r[1], 4);
+                o[0] = float(e); o[1] = float(pair_idx); o[2] = float(colour);
+                o[3] = r[2]; o[4] = r[3]; o[5] = r[4]; o[6] = r[5]; o[7] = r[6];
+            }
+        }
+    }
+    if (n_pairs) *n_pairs = np;
+    if (n_points) *n_points = npt;
+    if (n_manifolds) *n_manifolds = nm;
+    return MS_OK;
+}
+
+ms_status ms_destroy_batch(ms_batch* b) {
+    delete b;
+    return MS_OK;
+}
+
+// ----------------------------------------------------------------------------- fused multi-batch step
+static size_t many_bytes(ms_batch* const* batches, int32_t n) {
+    size_t tiles = 0, tenv = 0;
+    for (int i = 0; i < n; ++i) { tiles += batches[i]->plan.tiles.size(); tenv += batches[i]->plan.tenv.size(); }
+    return align_up(size_t(n) * sizeof(BatchDev)) + align_up(tiles * sizeof(Tile)) + align_up(tenv * sizeof(TileEnv));
+}
+
+ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, size_t* bytes) {
+    if (!batches || n_batches <= 0 || !bytes) return fail(MS_E_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < n_batches; ++i)
+        if (!batches[i]) return fail(MS_E_INVALID_ARG, "null batch %d", i);
+    *bytes = many_bytes(batches, n_batches);
+    return MS_OK;
+}
+
+namespace {
+// Pinned host staging for the combined work list, reused once the previous upload completed.
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    int device = -1;
+    bool pending = false;
+};
+thread_local Staging g_stage;
+}  // namespace
+
+ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches, int32_t n_steps,
+                       void* dev_scratch, size_t scratch_bytes, void* hip_stream) {
+    if (!batches || n_batches <= 0) return fail(MS_E_INVALID_ARG, "bad batch list");
+    if (n_steps < 1) return fail(MS_E_INVALID_ARG, "n_steps must be >= 1");
+    for (int i = 0; i < n_batches; ++i)
+        if (!batches[i]) return fail(MS_E_INVALID_ARG, "null batch %d", i);
+    const size_t need = many_bytes(batches, n_batches);
+    if (!dev_scratch || scratch_bytes < need)
+        return fail(MS_E_NO_WORKSPACE, "scratch of %zu bytes, %zu needed", scratch_bytes, need);
+    if (reinterpret_cast<uintptr_t>(dev_scratch) % ALIGN) return fail(MS_E_INVALID_ARG, "scratch must be 256-byte aligned");
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Staging& st = g_stage;
+    if (st.device != dev) {
+        if (st.ev) { (void)hipEventSynchronize(st.ev); (void)hipEventDestroy(st.ev); st.ev = nullptr; }
+        st.device = dev;
+        st.pending = false;
+        HIP_OK(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
+    }
+    if (st.pending) { HIP_OK(hipEventSynchronize(st.ev)); st.pending = false; }
+    if (st.cap < need) {
+        if (st.host) HIP_OK(hipHostFree(st.host));
+        st.host = nullptr;
+        st.cap = 0;
+        HIP_OK(hipHostMalloc(&st.host, need, hipHostMallocDefault));
+        st.cap = need;
+    }
+    char* h = static_cast<char*>(st.host);
+    BatchDev* tb = reinterpret_cast<BatchDev*>(h);
+    Tile* tt = reinterpret_cast<Tile*>(h + align_up(size_t(n_batches) * sizeof(BatchDev)));
+    size_t n_tiles = 0, n_tenv = 0;
+    for (int i = 0; i < n_batches; ++i) n_tiles += batches[i]->plan.tiles.size();
+    TileEnv* te = reinterpret_cast<TileEnv*>(reinterpret_cast<char*>(tt) + align_up(n_tiles * sizeof(Tile)));
+    size_t max_lds = 0, kt = 0;
+    for (int i = 0; i < n_batches; ++i) {
+        ms_batch* b = batches[i];
+        tb[i] = b->hbd;
+        for (const Tile& t : b->plan.tiles) {
+            Tile u = t;
+            u.first += int(n_tenv);
+            tt[kt++] = u;
+        }
+        for (const TileEnv& e : b->plan.tenv) {
+            TileEnv f = e;
+            f.batch = i;
+            te[n_tenv++] = f;
+        }
+        max_lds = std::max(max_lds, b->lds_bytes);
+        if (dev_targets && dev_targets[i] && b->J > 0)
+            HIP_OK(hipMemcpyAsync(const_cast<float*>(b->hbd.targets), dev_targets[i], size_t(b->J) * 4,
+                                  hipMemcpyDeviceToDevice, s));
+    }
+    HIP_OK(hipMemcpyAsync(dev_scratch, st.host, need, hipMemcpyHostToDevice, s));
+    HIP_OK(hipEventRecord(st.ev, s));
+    st.pending = true;
+    char* d = static_cast<char*>(dev_scratch);
+    const BatchDev* dtb = reinterpret_cast<const BatchDev*>(d);
+    const Tile* dtt = reinterpret_cast<const Tile*>(d + (reinterpret_cast<char*>(tt) - h));
+    const TileEnv* dte = reinterpret_cast<const TileEnv*>(d + (reinterpret_cast<char*>(te) - h));
+    hipLaunchKernelGGL(ms_step_kernel, dim3(unsigned(n_tiles)), dim3(WAVE), max_lds, s, dtb, dtt, int(n_tiles), dte,
+                       int(n_steps));
+    HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1426 @@
+// ms_step.hip — fused batched rigid-body step for CDNA4 (gfx950).
+//
+// One 64-lane wavefront per workgroup.  A workgroup takes tiles from a static work list; a tile
+// packs 64 / G envs and G lanes serve each env.  For the whole launch an env's bodies, contact
+// rows, friction patches, joints and colour schedule live in LDS: HBM is read once at the start
+// (state, body parameters, joints, drive targets) and written once at the end (state, status),
+// however many steps the launch runs.
+//
+// Step model (the paper relies on a GPU rigid-body solver tuned by position / velocity
+// iteration counts, App. E Setup, with PD joint drives, App. B; its equations are not given):
+//   S0 frozen step-start pose, world inverse inertia and velocities;
+//   S1 exact AABBs (no contraction: identical candidate lists on any IEEE-754 binary32 target);
+//   S2 all pairs of the env in canonical (a, b) order, ground plane last, with the static-static
+//      and jointed parent-child filters;
+//   S3 narrowphase in a frame centred on body A (sphere, capsule, box, plane), <= 4 points;
+//   S4 normal rows per point, one friction patch per manifold (two tangents + twist);
+//   S5 greedy colouring over joints then manifolds; the colour order fixes the Gauss-Seidel order;
+//   S6 substeps: gravity, warm start, joint-only passes, coloured sweep, integration of the
+//      offsets from the step-start pose;
+//   S7 velocity sweeps and the restitution pass; S8 non-finite guard and write-back.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ms_dev.h"
+
+using namespace msdev;
+
+namespace {
+
+// ----------------------------------------------------------------------------- small math
+struct V3 { float x, y, z; };
+struct Qt { float w, x, y, z; };
+
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a) { return {-a.x, -a.y, -a.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross3(V3 a, V3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float len3(V3 a) { return sqrtf(dot3(a, a)); }
+__device__ __forceinline__ float comp(V3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+__device__ __forceinline__ void setc(V3& a, int i, float v) {
+    if (i == 0) a.x = v; else if (i == 1) a.y = v; else a.z = v;
+}
+
+__device__ __forceinline__ Qt qmul(Qt a, Qt b) {
+    return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+            a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+__device__ __forceinline__ Qt qnorm(Qt a) {
+    float inv = 1.0f / sqrtf(a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z);
+    return {a.w * inv, a.x * inv, a.y * inv, a.z * inv};
+}
+
+// 3x3 rotation (row-major) of a unit quaternion.
+struct M3 { float m[3][3]; };
+__device__ __forceinline__ M3 rotm(Qt q) {
+    float xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+    float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+    float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+    M3 r;
+    r.m[0][0] = 1.0f - 2.0f * (yy + zz); r.m[0][1] = 2.0f * (xy - wz);        r.m[0][2] = 2.0f * (xz + wy);
+    r.m[1][0] = 2.0f * (xy + wz);        r.m[1][1] = 1.0f - 2.0f * (xx + zz); r.m[1][2] = 2.0f * (yz - wx);
+    r.m[2][0] = 2.0f * (xz - wy);        r.m[2][1] = 2.0f * (yz + wx);        r.m[2][2] = 1.0f - 2.0f * (xx + yy);
+    return r;
+}
+__device__ __forceinline__ V3 mulv(const M3& a, V3 v) {
+    return {a.m[0][0] * v.x + a.m[0][1] * v.y + a.m[0][2] * v.z, a.m[1][0] * v.x + a.m[1][1] * v.y + a.m[1][2] * v.z,
+            a.m[2][0] * v.x + a.m[2][1] * v.y + a.m[2][2] * v.z};
+}
+__device__ __forceinline__ V3 mulTv(const M3& a, V3 v) {
+    return {a.m[0][0] * v.x + a.m[1][0] * v.y + a.m[2][0] * v.z, a.m[0][1] * v.x + a.m[1][1] * v.y + a.m[2][1] * v.z,
+            a.m[0][2] * v.x + a.m[1][2] * v.y + a.m[2][2] * v.z};
+}
+__device__ __forceinline__ V3 colm(const M3& a, int j) { return {a.m[0][j], a.m[1][j], a.m[2][j]}; }
+
+// Symmetric 3x3 stored as xx, yy, zz, xy, xz, yz.
+struct S6 { float xx, yy, zz, xy, xz, yz; };
+__device__ __forceinline__ V3 muls(const S6& s, V3 v) {
+    return {s.xx * v.x + s.xy * v.y + s.xz * v.z, s.xy * v.x + s.yy * v.y + s.yz * v.z,
+            s.xz * v.x + s.yz * v.y + s.zz * v.z};
+}
+
+// ----------------------------------------------------------------------------- LDS layout
+// (Lay / make_lay live in ms_dev.h: one definition for the kernel and the host planner)
+// Contact-row planes (length cap): rA 0..2, rB 3..5, n 6..8, mn 9, s0 10, e 11, vnpre 12, ln 13.
+enum { R_RA = 0, R_RB = 3, R_N = 6, R_MN = 9, R_S0 = 10, R_E = 11, R_VN = 12, R_LN = 13 };
+// Manifold planes (length mcap): header 0 (a | b << 8 as int), 1 (first | count << 16),
+// rA 2..4, rB 5..7, nb 8..10, t1 11..13, mt1 14, mt2 15, mtw 16, mu 17, rt 18, lt1 19, lt2 20, ltw 21.
+enum { M_AB = 0, M_FC = 1, M_RA = 2, M_RB = 5, M_NB = 8, M_T1 = 11, M_MT1 = 14, M_MT2 = 15, M_MTW = 16,
+       M_MU = 17, M_RT = 18, M_LT1 = 19, M_LT2 = 20, M_LTW = 21 };
+// Joint record in LDS (26 words): parent, child, aA 2..4, QA 5..8, aB 9..11, QB 12..15, kp 16,
+// kd 17, target 18, lp 19..21, la 22..23, ld 24.
+enum { J_PA = 0, J_CH = 1, J_AA = 2, J_QA = 5, J_AB = 9, J_QB = 12, J_KP = 16, J_KD = 17, J_TG = 18,
+       J_LP = 19, J_LA = 22, J_LD = 24, J_WORDS = 26 };
+// Scalars.
+enum { SC_NCAND = 0, SC_NPTS = 1, SC_NMAN = 2, SC_NCOL = 3, SC_STATUS = 4, SC_NSCHED = 5, SC_NJSCHED = 6,
+       SC_NDYN = 7 };
+
+struct EnvCtx {
+    float* L;       // LDS base of the env
+    Lay lay;
+    const BatchDev* bd;
+    int env, b0, j0;
+    bool active;
+};
+
+__device__ __forceinline__ int* iptr(float* p) { return reinterpret_cast<int*>(p); }
+__device__ __forceinline__ uint16_t* hptr(float* p) { return reinterpret_cast<uint16_t*>(p); }
+
+__device__ __forceinline__ V3 ld3(const float* L, int off, int n, int i) {
+    return {L[off + i], L[off + n + i], L[off + 2 * n + i]};
+}
+__device__ __forceinline__ void st3(float* L, int off, int n, int i, V3 v) {
+    L[off + i] = v.x; L[off + n + i] = v.y; L[off + 2 * n + i] = v.z;
+}
+__device__ __forceinline__ Qt ld4(const float* L, int off, int n, int i) {
+    return {L[off + i], L[off + n + i], L[off + 2 * n + i], L[off + 3 * n + i]};
+}
+__device__ __forceinline__ void st4(float* L, int off, int n, int i, Qt q) {
+    L[off + i] = q.w; L[off + n + i] = q.x; L[off + 2 * n + i] = q.y; L[off + 3 * n + i] = q.z;
+}
+
+// ----------------------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
+    return v;
+}
+__device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int g, int G) {
+    return G == 64 ? ballot : (ballot >> (g * G)) & ((uint64_t(1) << G) - 1);
+}
+__device__ __forceinline__ int prefix_in_group(uint64_t gb, int li) {
+    return __popcll(gb & ((uint64_t(1) << li) - 1));
+}
+// Exclusive prefix sum of v over the lanes of a group (G a power of two <= 64) and the total.
+__device__ __forceinline__ int group_scan(int v, int li, int G, int& total) {
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d);
+        if (d < G && li >= d) x += y;
+    }
+    int lane = threadIdx.x;
+    total = __shfl(x, (lane / G) * G + G - 1);
+    return x - v;
+}
+
+// ----------------------------------------------------------------------------- body access
+struct BodyRef {
+    float invm;
+    S6 Iw;
+    bool dyn;
+};
+__device__ __forceinline__ bool is_dyn(const EnvCtx& c, int i) {
+    return i >= 0 && !((iptr(c.L + c.lay.SH)[i] >> 8) & 1);
+}
+__device__ __forceinline__ S6 load_iw(const EnvCtx& c, int i) {
+    const float* L = c.L + c.lay.IW;
+    int n = c.lay.n;
+    return S6{L[i], L[n + i], L[2 * n + i], L[3 * n + i], L[4 * n + i], L[5 * n + i]};
+}
+
+// ----------------------------------------------------------------------------- narrowphase
+struct Pt { V3 p, n; float s; };
+struct NOut {
+    Pt pt[8];
+    int n;
+    int decision;
+};
+struct Shp {
+    int type;
+    V3 c;
+    M3 R;
+    float d[3];
+    __device__ V3 p0() const { return c - d[1] * colm(R, 2); }
+    __device__ V3 p1() const { return c + d[1] * colm(R, 2); }
+};
+
+__device__ __forceinline__ void emit(NOut& o, V3 pa, V3 pb, V3 n, float s, float delta) {
+    if (s < delta && o.n < 8) {
+        o.pt[o.n].p = 0.5f * (pa + pb);
+        o.pt[o.n].n = n;
+        o.pt[o.n].s = s;
+        o.n++;
+    }
+}
+
+__device__ __forceinline__ float clamp01(float v) { return v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v); }
+
+// Segment-segment closest parameters (clamped-parameter method, Ericson RTCD 5.1.9).
+__device__ void seg_seg(V3 p1, V3 q1, V3 p2, V3 q2, float& s, float& t) {
+    V3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
+    float a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+    const float eps = 1e-12f;
+    if (a <= eps && e <= eps) { s = 0.0f; t = 0.0f; return; }
+    if (a <= eps) { s = 0.0f; t = clamp01(f / e); return; }
+    float c = dot3(d1, r);
+    if (e <= eps) { t = 0.0f; s = clamp01(-c / a); return; }
+    float b = dot3(d1, d2);
+    float den = a * e - b * b;
+    s = den != 0.0f ? clamp01((b * f - c * e) / den) : 0.0f;
+    t = (b * s + f) / e;
+    if (t < 0.0f) { t = 0.0f; s = clamp01(-c / a); }
+    else if (t > 1.0f) { t = 1.0f; s = clamp01((b - c) / a); }
+}
+__device__ __forceinline__ float seg_point(V3 p0, V3 p1, V3 x) {
+    V3 d = p1 - p0;
+    float dd = dot3(d, d);
+    if (dd <= 1e-12f) return 0.0f;
+    return clamp01(dot3(x - p0, d) / dd);
+}
+
+__device__ void np_sphere_sphere(NOut& o, V3 ca, float ra, V3 cb, float rb, float delta) {
+    V3 d = cb - ca;
+    float dist = len3(d);
+    V3 n = dist < 1e-9f ? v3(0.0f, 0.0f, 1.0f) : (1.0f / dist) * d;
+    emit(o, ca + ra * n, cb - rb * n, n, dist - ra - rb, delta);
+}
+
+__device__ void np_plane_sphere(NOut& o, V3 c, float r, float delta) {
+    V3 n = v3(0.0f, 0.0f, 1.0f);
+    emit(o, v3(c.x, c.y, 0.0f), c - r * n, n, c.z - r, delta);
+}
+
+__device__ void np_plane_box(NOut& o, const Shp& b, float delta) {
+    for (int k = 0; k < 8; ++k) {
+        V3 l = v3((k & 1) ? b.d[0] : -b.d[0], (k & 2) ? b.d[1] : -b.d[1], (k & 4) ? b.d[2] : -b.d[2]);
+        V3 c = b.c + mulv(b.R, l);
+        emit(o, v3(c.x, c.y, 0.0f), c, v3(0.0f, 0.0f, 1.0f), c.z, delta);
+    }
+}
+
+__device__ void np_box_sphere(NOut& o, const Shp& bx, V3 c, float r, float delta) {
+    V3 l = mulTv(bx.R, c - bx.c);
+    V3 q = l;
+    for (int i = 0; i < 3; ++i) {
+        float v = comp(l, i), h = bx.d[i];
+        setc(q, i, v < -h ? -h : (v > h ? h : v));
+    }
+    V3 dl = l - q;
+    float d2 = dot3(dl, dl);
+    if (d2 > 0.0f) {
+        o.decision = 0;
+        float dist = sqrtf(d2);
+        V3 n = mulv(bx.R, (1.0f / dist) * dl);
+        emit(o, bx.c + mulv(bx.R, q), c - r * n, n, dist - r, delta);
+    } else {
+        int best = 0;
+        float bd = bx.d[0] - fabsf(l.x);
+        for (int i = 1; i < 3; ++i) {
+            float di = bx.d[i] - fabsf(comp(l, i));
+            if (di < bd) { bd = di; best = i; }
+        }
+        float sg = comp(l, best) >= 0.0f ? 1.0f : -1.0f;
+        V3 nl = v3(0.0f, 0.0f, 0.0f);
+        setc(nl, best, sg);
+        V3 n = mulv(bx.R, nl);
+        V3 face = l;
+        setc(face, best, sg * bx.d[best]);
+        o.decision = 1 + best;
+        emit(o, bx.c + mulv(bx.R, face), c - r * n, n, -bd - r, delta);
+    }
+}
+
+__device__ __forceinline__ float box_ext(const Shp& b, V3 L) {
+    return (b.d[0] * fabsf(dot3(colm(b.R, 0), L)) + b.d[1] * fabsf(dot3(colm(b.R, 1), L))) +
+           b.d[2] * fabsf(dot3(colm(b.R, 2), L));
+}
+__device__ __forceinline__ float tie_tol(float s, float hmin) { return 0.05f * fabsf(s) + 0.01f * hmin; }
+
+__device__ void clip_slab(V3 p0, V3 p1, V3 c, V3 a, float h, float& t0, float& t1) {
+    float u0 = dot3(p0 - c, a), du = dot3(p1 - p0, a);
+    if (fabsf(du) < 1e-12f) {
+        if (u0 > h || u0 < -h) { t0 = 1.0f; t1 = 0.0f; }
+        return;
+    }
+    float ta = (-h - u0) / du, tb = (h - u0) / du;
+    if (ta > tb) { float tmp = ta; ta = tb; tb = tmp; }
+    if (ta > t0) t0 = ta;
+    if (tb < t1) t1 = tb;
+}
+
+__device__ void np_box_capsule(NOut& o, const Shp& bx, const Shp& cp, float delta) {
+    V3 P0 = cp.p0(), P1 = cp.p1(), u = colm(cp.R, 2);
+    float rc = cp.d[0], hl = cp.d[1];
+    V3 dc = cp.c - bx.c;
+    float sep[6];
+    V3 ax[6];
+    bool valid[6];
+    for (int i = 0; i < 3; ++i) {
+        V3 L = colm(bx.R, i);
+        if (dot3(L, dc) < 0.0f) L = -L;
+        ax[i] = L; valid[i] = true;
+        sep[i] = dot3(dc, L) - hl * fabsf(dot3(u, L)) - bx.d[i] - rc;
+    }
+    for (int i = 0; i < 3; ++i) {
+        V3 L = cross3(u, colm(bx.R, i));
+        float l = len3(L);
+        valid[3 + i] = l >= 1e-6f;
+        if (!valid[3 + i]) { sep[3 + i] = -1e30f; ax[3 + i] = v3(0.0f, 0.0f, 0.0f); continue; }
+        L = (1.0f / l) * L;
+        if (dot3(L, dc) < 0.0f) L = -L;
+        ax[3 + i] = L;
+        sep[3 + i] = dot3(dc, L) - hl * fabsf(dot3(u, L)) - box_ext(bx, L) - rc;
+    }
+    float hmin = fminf(fminf(bx.d[0], bx.d[1]), fminf(bx.d[2], rc));
+    int bf = 0;
+    for (int i = 1; i < 3; ++i) if (sep[i] > sep[bf]) bf = i;
+    int be = -1;
+    for (int i = 3; i < 6; ++i) if (valid[i] && (be < 0 || sep[i] > sep[be])) be = i;
+    int best = bf;
+    if (be >= 0 && sep[be] > sep[bf] + tie_tol(sep[bf], hmin)) best = be;
+    float smax = sep[0];
+    for (int i = 1; i < 6; ++i) if (valid[i] && sep[i] > smax) smax = sep[i];
+    o.decision = best;
+    if (smax >= delta) return;
+    if (best < 3) {
+        int i = best;
+        V3 nr = ax[i];
+        int j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+        float t0 = 0.0f, t1 = 1.0f;
+        clip_slab(P0, P1, bx.c, colm(bx.R, j1), bx.d[j1], t0, t1);
+        clip_slab(P0, P1, bx.c, colm(bx.R, j2), bx.d[j2], t0, t1);
+        if (t0 <= t1) {
+            int np = t1 > t0 ? 2 : 1;
+            for (int k = 0; k < np; ++k) {
+                float tk = k == 0 ? t0 : t1;
+                V3 C = P0 + tk * (P1 - P0);
+                float above = dot3(C - bx.c, nr) - bx.d[i];
+                emit(o, C - above * nr, C - rc * nr, nr, above - rc, delta);
+            }
+        } else {
+            o.decision = 6 + i;
+            float bestd = 1e30f;
+            V3 bs = v3(0.0f, 0.0f, 0.0f), be2 = v3(0.0f, 0.0f, 0.0f);
+            V3 fc = bx.c + bx.d[i] * nr;
+            for (int k = 0; k < 4; ++k) {
+                int along = (k < 2) ? j1 : j2, other = (k < 2) ? j2 : j1;
+                float sg = (k & 1) ? 1.0f : -1.0f;
+                V3 ec = fc + (sg * bx.d[other]) * colm(bx.R, other);
+                V3 e0 = ec - bx.d[along] * colm(bx.R, along), e1 = ec + bx.d[along] * colm(bx.R, along);
+                float s, t;
+                seg_seg(P0, P1, e0, e1, s, t);
+                V3 cs = P0 + s * (P1 - P0), ce = e0 + t * (e1 - e0);
+                V3 dd = cs - ce;
+                float d2 = dot3(dd, dd);
+                if (d2 < bestd) { bestd = d2; bs = cs; be2 = ce; }
+            }
+            float dist = sqrtf(bestd);
+            V3 n = dist > 1e-9f ? (1.0f / dist) * (bs - be2) : nr;
+            emit(o, be2, bs - rc * n, n, dist - rc, delta);
+        }
+    } else {
+        int i = best - 3;
+        V3 L = ax[best];
+        V3 ec = bx.c;
+        for (int j = 0; j < 3; ++j) {
+            if (j == i) continue;
+            float dj = dot3(colm(bx.R, j), L);
+            ec = ec + ((dj >= 0.0f ? 1.0f : -1.0f) * bx.d[j]) * colm(bx.R, j);
+        }
+        V3 e0 = ec - bx.d[i] * colm(bx.R, i), e1 = ec + bx.d[i] * colm(bx.R, i);
+        float s, t;
+        seg_seg(P0, P1, e0, e1, s, t);
+        V3 cs = P0 + s * (P1 - P0), ce = e0 + t * (e1 - e0);
+        emit(o, ce, cs - rc * L, L, dot3(cs - ce, L) - rc, delta);
+    }
+}
+
+// Keep the part of polygon `in` (n vertices) with dot(x, a) <= off (at most 8 vertices out).
+__device__ int clip_poly(const V3* in, int n, V3 a, float off, V3* out) {
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        V3 p = in[k], q = in[(k + 1) % n];
+        float dp = dot3(p, a) - off, dq = dot3(q, a) - off;
+        if (dp <= 0.0f && m < 8) out[m++] = p;
+        if (((dp < 0.0f && dq > 0.0f) || (dp > 0.0f && dq < 0.0f)) && m < 8) {
+            float t = dp / (dp - dq);
+            out[m++] = p + t * (q - p);
+        }
+    }
+    return m;
+}
+
+__device__ void np_box_box(NOut& o, const Shp& A, const Shp& B, float delta) {
+    V3 d = B.c - A.c;
+    float sep[15];
+    V3 ax[15];
+    bool valid[15];
+    for (int k = 0; k < 15; ++k) {
+        V3 L;
+        if (k < 3) L = colm(A.R, k);
+        else if (k < 6) L = colm(B.R, k - 3);
+        else {
+            L = cross3(colm(A.R, (k - 6) / 3), colm(B.R, (k - 6) % 3));
+            float l = len3(L);
+            if (l < 1e-6f) { valid[k] = false; sep[k] = -1e30f; ax[k] = v3(0.0f, 0.0f, 0.0f); continue; }
+            L = (1.0f / l) * L;
+        }
+        if (dot3(L, d) < 0.0f) L = -L;
+        valid[k] = true;
+        ax[k] = L;
+        sep[k] = dot3(d, L) - box_ext(A, L) - box_ext(B, L);
+    }
+    float hmin = fminf(fminf(fminf(A.d[0], A.d[1]), fminf(A.d[2], B.d[0])), fminf(B.d[1], B.d[2]));
+    int fa = 0, fb = 3, fe = -1;
+    for (int k = 1; k < 3; ++k) if (sep[k] > sep[fa]) fa = k;
+    for (int k = 4; k < 6; ++k) if (sep[k] > sep[fb]) fb = k;
+    for (int k = 6; k < 15; ++k) if (valid[k] && (fe < 0 || sep[k] > sep[fe])) fe = k;
+    int best = fb;
+    if (sep[fa] > sep[fb] + tie_tol(sep[fb], hmin)) best = fa;
+    if (fe >= 0 && sep[fe] > sep[best] + tie_tol(sep[best], hmin)) best = fe;
+    float smax = sep[0];
+    for (int k = 1; k < 15; ++k) if (valid[k] && sep[k] > smax) smax = sep[k];
+    o.decision = best;
+    if (smax >= delta) return;
+    if (best < 6) {
+        bool refA = best < 3;
+        const Shp& Rf = refA ? A : B;
+        const Shp& In = refA ? B : A;
+        int ri = refA ? best : best - 3;
+        V3 nref = refA ? ax[best] : -ax[best];
+        int ii = 0;
+        float bd = fabsf(dot3(colm(In.R, 0), nref));
+        for (int j = 1; j < 3; ++j) {
+            float dj = fabsf(dot3(colm(In.R, j), nref));
+            if (dj > bd) { bd = dj; ii = j; }
+        }
+        float sgn = dot3(colm(In.R, ii), nref) >= 0.0f ? -1.0f : 1.0f;
+        V3 fcen = In.c + (sgn * In.d[ii]) * colm(In.R, ii);
+        int u = (ii + 1) % 3, v = (ii + 2) % 3;
+        V3 U = In.d[u] * colm(In.R, u), Wv = In.d[v] * colm(In.R, v);
+        V3 poly[8], tmp[8];
+        poly[0] = fcen + U + Wv; poly[1] = fcen - U + Wv; poly[2] = fcen - U - Wv; poly[3] = fcen + U - Wv;
+        int n = 4;
+        int r1 = (ri + 1) % 3, r2 = (ri + 2) % 3;
+        V3 a1 = colm(Rf.R, r1), a2 = colm(Rf.R, r2);
+        n = clip_poly(poly, n, a1, dot3(Rf.c, a1) + Rf.d[r1], tmp);
+        n = clip_poly(tmp, n, -a1, -dot3(Rf.c, a1) + Rf.d[r1], poly);
+        n = clip_poly(poly, n, a2, dot3(Rf.c, a2) + Rf.d[r2], tmp);
+        n = clip_poly(tmp, n, -a2, -dot3(Rf.c, a2) + Rf.d[r2], poly);
+        V3 nAB = refA ? nref : -nref;
+        for (int k = 0; k < n; ++k) {
+            V3 p = poly[k];
+            float s = dot3(p - Rf.c, nref) - Rf.d[ri];
+            V3 onref = p - s * nref;
+            if (refA) emit(o, onref, p, nAB, s, delta);
+            else emit(o, p, onref, nAB, s, delta);
+        }
+    } else {
+        int ia = (best - 6) / 3, ib = (best - 6) % 3;
+        V3 L = ax[best];
+        V3 ca = A.c, cb = B.c;
+        for (int j = 0; j < 3; ++j) {
+            if (j != ia) { float dj = dot3(colm(A.R, j), L); ca = ca + ((dj >= 0.0f ? 1.0f : -1.0f) * A.d[j]) * colm(A.R, j); }
+            if (j != ib) { float dj = dot3(colm(B.R, j), L); cb = cb + ((dj >= 0.0f ? -1.0f : 1.0f) * B.d[j]) * colm(B.R, j); }
+        }
+        V3 a0 = ca - A.d[ia] * colm(A.R, ia), a1 = ca + A.d[ia] * colm(A.R, ia);
+        V3 b0 = cb - B.d[ib] * colm(B.R, ib), b1 = cb + B.d[ib] * colm(B.R, ib);
+        float s, t;
+        seg_seg(a0, a1, b0, b1, s, t);
+        V3 pa = a0 + s * (a1 - a0), pb = b0 + t * (b1 - b0);
+        emit(o, pa, pb, L, dot3(pb - pa, L), delta);
+    }
+}
+
+__device__ void np_capsule_capsule(NOut& o, const Shp& A, const Shp& B, float delta) {
+    V3 a0 = A.p0(), a1 = A.p1(), b0 = B.p0(), b1 = B.p1();
+    V3 d1 = a1 - a0, d2 = b1 - b0;
+    V3 cr = cross3(d1, d2);
+    if (dot3(cr, cr) < 1e-6f * dot3(d1, d1) * dot3(d2, d2)) {
+        float dd = dot3(d1, d1);
+        float s0 = dot3(b0 - a0, d1) / dd, s1 = dot3(b1 - a0, d1) / dd;
+        float lo = fmaxf(0.0f, fminf(s0, s1)), hi = fminf(1.0f, fmaxf(s0, s1));
+        if (lo < hi) {
+            o.decision = 1;
+            for (int k = 0; k < 2; ++k) {
+                V3 pa = a0 + (k == 0 ? lo : hi) * d1;
+                float t = seg_point(b0, b1, pa);
+                np_sphere_sphere(o, pa, A.d[0], b0 + t * d2, B.d[0], delta);
+            }
+            return;
+        }
+    }
+    o.decision = 0;
+    float s, t;
+    seg_seg(a0, a1, b0, b1, s, t);
+    np_sphere_sphere(o, a0 + s * d1, A.d[0], b0 + t * d2, B.d[0], delta);
+}
+
+__device__ void np_flip(NOut& o) {
+    for (int k = 0; k < o.n; ++k) o.pt[k].n = -o.pt[k].n;
+}
+
+__device__ void np_pair(NOut& o, const Shp& A, const Shp& B, float delta) {
+    int ta = A.type, tb = B.type;
+    if (ta == 0 && tb == 0) { np_sphere_sphere(o, A.c, A.d[0], B.c, B.d[0], delta); return; }
+    if (ta == 0 && tb == 1) {
+        float t = seg_point(B.p0(), B.p1(), A.c);
+        np_sphere_sphere(o, A.c, A.d[0], B.p0() + t * (B.p1() - B.p0()), B.d[0], delta);
+        return;
+    }
+    if (ta == 1 && tb == 0) {
+        float t = seg_point(A.p0(), A.p1(), B.c);
+        np_sphere_sphere(o, A.p0() + t * (A.p1() - A.p0()), A.d[0], B.c, B.d[0], delta);
+        return;
+    }
+    if (ta == 1 && tb == 1) { np_capsule_capsule(o, A, B, delta); return; }
+    if (ta == 2 && tb == 0) { np_box_sphere(o, A, B.c, B.d[0], delta); return; }
+    if (ta == 0 && tb == 2) { np_box_sphere(o, B, A.c, A.d[0], delta); np_flip(o); return; }
+    if (ta == 2 && tb == 1) { np_box_capsule(o, A, B, delta); return; }
+    if (ta == 1 && tb == 2) { np_box_capsule(o, B, A, delta); np_flip(o); return; }
+    np_box_box(o, A, B, delta);
+}
+
+__device__ void np_plane(NOut& o, const Shp& B, float delta) {
+    if (B.type == 0) np_plane_sphere(o, B.c, B.d[0], delta);
+    else if (B.type == 1) { np_plane_sphere(o, B.p0(), B.d[0], delta); np_plane_sphere(o, B.p1(), B.d[0], delta); }
+    else np_plane_box(o, B, delta);
+}
+
+// <= 4 points: deepest; farthest from it; largest triangle; most area added outside the
+// triangle; lowest index on ties; kept points in their original order.
+__device__ void reduce4(NOut& o) {
+    if (o.n <= 4) return;
+    int n = o.n;
+    unsigned used = 0;
+    int k0 = 0;
+    for (int k = 1; k < n; ++k) if (o.pt[k].s < o.pt[k0].s) k0 = k;
+    used |= 1u << k0;
+    // each selection starts from the first unused point, so an index is always valid
+    int k1 = k0 == 0 ? 1 : 0; float b1 = -1.0f;
+    for (int k = 0; k < n; ++k) {
+        if (used >> k & 1) continue;
+        V3 d = o.pt[k].p - o.pt[k0].p;
+        float v = dot3(d, d);
+        if (v > b1) { b1 = v; k1 = k; }
+    }
+    used |= 1u << k1;
+    int k2 = 0;
+    while (used >> k2 & 1) ++k2;
+    float b2 = -1.0f;
+    V3 e01 = o.pt[k1].p - o.pt[k0].p;
+    for (int k = 0; k < n; ++k) {
+        if (used >> k & 1) continue;
+        V3 c = cross3(e01, o.pt[k].p - o.pt[k0].p);
+        float v = dot3(c, c);
+        if (v > b2) { b2 = v; k2 = k; }
+    }
+    used |= 1u << k2;
+    V3 nt = cross3(e01, o.pt[k2].p - o.pt[k0].p);
+    int tri[3] = {k0, k1, k2};
+    int k3 = 0;
+    while (used >> k3 & 1) ++k3;
+    float b3 = -1e30f;
+    for (int k = 0; k < n; ++k) {
+        if (used >> k & 1) continue;
+        float best = -1e30f;
+        for (int e = 0; e < 3; ++e) {
+            V3 pa = o.pt[tri[e]].p, pb = o.pt[tri[(e + 1) % 3]].p;
+            float v = -dot3(cross3(pb - pa, o.pt[k].p - pa), nt);
+            if (v > best) best = v;
+        }
+        if (best > b3) { b3 = best; k3 = k; }
+    }
+    used |= 1u << k3;
+    int m = 0;
+    for (int k = 0; k < n; ++k)
+        if (used >> k & 1) o.pt[m++] = o.pt[k];
+    o.n = m;
+}
+
+// Duff et al. 2017 orthonormal basis: t1 for unit n (t2 = n x t1).
+__device__ __forceinline__ V3 onb_t1(V3 n) {
+    float sg = copysignf(1.0f, n.z);
+    float a = -1.0f / (sg + n.z);
+    float b = n.x * n.y * a;
+    return v3(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
+}
+
+// ----------------------------------------------------------------------------- LDS body helpers
+__device__ __forceinline__ float invm_of(const EnvCtx& c, int i) { return i < 0 ? 0.0f : c.L[c.lay.INVM + i]; }
+__device__ __forceinline__ V3 v_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.V, c.lay.n, i); }
+__device__ __forceinline__ V3 w_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.W, c.lay.n, i); }
+
+// Apply impulse P at arms rA, rB: -P on A, +P on B (dynamic bodies only).
+__device__ __forceinline__ void apply_lin(const EnvCtx& c, int a, int b, V3 rA, V3 rB, V3 P) {
+    int n = c.lay.n;
+    if (is_dyn(c, a)) {
+        float im = c.L[c.lay.INVM + a];
+        S6 I = load_iw(c, a);
+        st3(c.L, c.lay.V, n, a, ld3(c.L, c.lay.V, n, a) - im * P);
+        st3(c.L, c.lay.W, n, a, ld3(c.L, c.lay.W, n, a) - muls(I, cross3(rA, P)));
+    }
+    if (is_dyn(c, b)) {
+        float im = c.L[c.lay.INVM + b];
+        S6 I = load_iw(c, b);
+        st3(c.L, c.lay.V, n, b, ld3(c.L, c.lay.V, n, b) + im * P);
+        st3(c.L, c.lay.W, n, b, ld3(c.L, c.lay.W, n, b) + muls(I, cross3(rB, P)));
+    }
+}
+__device__ __forceinline__ void apply_ang(const EnvCtx& c, int a, int b, V3 Lv) {
+    int n = c.lay.n;
+    if (is_dyn(c, a)) st3(c.L, c.lay.W, n, a, ld3(c.L, c.lay.W, n, a) - muls(load_iw(c, a), Lv));
+    if (is_dyn(c, b)) st3(c.L, c.lay.W, n, b, ld3(c.L, c.lay.W, n, b) + muls(load_iw(c, b), Lv));
+}
+__device__ __forceinline__ float eff_mass(const EnvCtx& c, int a, int b, V3 rA, V3 rB, V3 x) {
+    float k = invm_of(c, a) + invm_of(c, b);
+    if (a >= 0) { V3 cr = cross3(rA, x); k += dot3(cr, muls(load_iw(c, a), cr)); }
+    if (b >= 0) { V3 cr = cross3(rB, x); k += dot3(cr, muls(load_iw(c, b), cr)); }
+    return k > 0.0f ? 1.0f / k : 0.0f;
+}
+
+__device__ __forceinline__ Shp shape_of(const EnvCtx& c, int i, V3 centre) {
+    Shp s;
+    const Lay& l = c.lay;
+    s.type = iptr(c.L + l.SH)[i] & 0xFF;
+    s.c = centre;
+    s.R = rotm(ld4(c.L, l.Q0, l.n, i));
+    s.d[0] = c.L[l.DIM + i]; s.d[1] = c.L[l.DIM + l.n + i]; s.d[2] = c.L[l.DIM + 2 * l.n + i];
+    return s;
+}
+
+// Displacement of the body-fixed point x0 + r since the step start: dx + R(dq) r - r.
+__device__ __forceinline__ V3 point_disp(const EnvCtx& c, int i, V3 r) {
+    Qt d = ld4(c.L, c.lay.DQ, c.lay.n, i);
+    V3 u = v3(d.x, d.y, d.z);
+    V3 ur = cross3(u, r);
+    return ld3(c.L, c.lay.DX, c.lay.n, i) + (2.0f * d.w) * ur + 2.0f * cross3(u, ur);
+}
+
+// ----------------------------------------------------------------------------- manifold block
+__device__ __forceinline__ float mf(const EnvCtx& c, int plane, int m) { return c.L[c.lay.MAN + plane * c.lay.mcap + m]; }
+__device__ __forceinline__ float& mfr(const EnvCtx& c, int plane, int m) { return c.L[c.lay.MAN + plane * c.lay.mcap + m]; }
+__device__ __forceinline__ V3 mf3(const EnvCtx& c, int plane, int m) {
+    return v3(mf(c, plane, m), mf(c, plane + 1, m), mf(c, plane + 2, m));
+}
+__device__ __forceinline__ float& pr(const EnvCtx& c, int plane, int k) { return c.L[c.lay.PT + plane * c.lay.cap + k]; }
+__device__ __forceinline__ V3 pr3(const EnvCtx& c, int plane, int k) {
+    return v3(pr(c, plane, k), pr(c, plane + 1, k), pr(c, plane + 2, k));
+}
+
+__device__ __forceinline__ void man_header(const EnvCtx& c, int m, int& a, int& b, int& first, int& cnt) {
+    int ab = iptr(c.L + c.lay.MAN + M_AB * c.lay.mcap)[m];
+    int fc = iptr(c.L + c.lay.MAN + M_FC * c.lay.mcap)[m];
+    a = (ab & 0xFF) == 0xFF ? -1 : (ab & 0xFF);
+    b = (ab >> 8) & 0xFF;
+    first = fc & 0xFFFF;
+    cnt = fc >> 16;
+}
+
+__device__ void manifold_warm(const EnvCtx& c, int m) {
+    int a, b, first, cnt;
+    man_header(c, m, a, b, first, cnt);
+    for (int k = first; k < first + cnt; ++k)
+        apply_lin(c, a, b, pr3(c, R_RA, k), pr3(c, R_RB, k), pr(c, R_LN, k) * pr3(c, R_N, k));
+    V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m);
+    V3 t2 = cross3(nb, t1);
+    apply_lin(c, a, b, mf3(c, M_RA, m), mf3(c, M_RB, m), mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * t2);
+    apply_ang(c, a, b, mf(c, M_LTW, m) * nb);
+}
+
+__device__ __forceinline__ V3 rel_vel(const EnvCtx& c, int a, int b, V3 rA, V3 rB) {
+    V3 vb = v_of(c, b) + cross3(w_of(c, b), rB);
+    V3 va = a >= 0 ? v_of(c, a) + cross3(w_of(c, a), rA) : v3(0, 0, 0);
+    return vb - va;
+}
+
+__device__ void manifold_solve(const EnvCtx& c, int m, float h, bool vpass) {
+    const BatchDev& bd = *c.bd;
+    int a, b, first, cnt;
+    man_header(c, m, a, b, first, cnt);
+    float lsum = 0.0f;
+    for (int k = first; k < first + cnt; ++k) {
+        V3 rA = pr3(c, R_RA, k), rB = pr3(c, R_RB, k), n = pr3(c, R_N, k);
+        V3 dA = a >= 0 ? point_disp(c, a, rA) : v3(0, 0, 0);
+        V3 dB = point_disp(c, b, rB);
+        float s = pr(c, R_S0, k) + dot3(n, dB - dA);
+        float bias;
+        if (s > 0.0f) bias = s / h;
+        else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
+        float vn = dot3(rel_vel(c, a, b, rA, rB), n);
+        float dl = -pr(c, R_MN, k) * (vn + bias);
+        float old = pr(c, R_LN, k);
+        float nl = fmaxf(old + dl, 0.0f);
+        pr(c, R_LN, k) = nl;
+        apply_lin(c, a, b, rA, rB, (nl - old) * n);
+        lsum += nl;
+    }
+    float lim = mf(c, M_MU, m) * lsum;
+    V3 rA = mf3(c, M_RA, m), rB = mf3(c, M_RB, m), nb = mf3(c, M_NB, m), t1 = mf3(c, M_T1, m);
+    V3 t2 = cross3(nb, t1);
+    {
+        float vt = dot3(rel_vel(c, a, b, rA, rB), t1);
+        float old = mf(c, M_LT1, m);
+        float nl = fminf(fmaxf(old - mf(c, M_MT1, m) * vt, -lim), lim);
+        mfr(c, M_LT1, m) = nl;
+        apply_lin(c, a, b, rA, rB, (nl - old) * t1);
+    }
+    {
+        float vt = dot3(rel_vel(c, a, b, rA, rB), t2);
+        float old = mf(c, M_LT2, m);
+        float nl = fminf(fmaxf(old - mf(c, M_MT2, m) * vt, -lim), lim);
+        mfr(c, M_LT2, m) = nl;
+        apply_lin(c, a, b, rA, rB, (nl - old) * t2);
+    }
+    {
+        float limw = mf(c, M_RT, m) * lim;
+        float wr = dot3(nb, w_of(c, b) - w_of(c, a));
+        float old = mf(c, M_LTW, m);
+        float nl = fminf(fmaxf(old - mf(c, M_MTW, m) * wr, -limw), limw);
+        mfr(c, M_LTW, m) = nl;
+        apply_ang(c, a, b, (nl - old) * nb);
+    }
+}
+
+__device__ void manifold_restitution(const EnvCtx& c, int m) {
+    const BatchDev& bd = *c.bd;
+    int a, b, first, cnt;
+    man_header(c, m, a, b, first, cnt);
+    for (int k = first; k < first + cnt; ++k) {
+        float vpre = pr(c, R_VN, k);
+        float old = pr(c, R_LN, k);
+        if (!(vpre < -bd.bounce && old > 0.0f)) continue;
+        V3 rA = pr3(c, R_RA, k), rB = pr3(c, R_RB, k), n = pr3(c, R_N, k);
+        float vn = dot3(rel_vel(c, a, b, rA, rB), n);
+        float dl = -pr(c, R_MN, k) * (vn + pr(c, R_E, k) * vpre);
+        float nl = fmaxf(old + dl, 0.0f);
+        pr(c, R_LN, k) = nl;
+        apply_lin(c, a, b, rA, rB, (nl - old) * n);
+    }
+}
+
+// ----------------------------------------------------------------------------- joint block
+// Arctangent of the drive angle from correctly rounded +, *, / and sqrt only: two half-angle
+// steps tan(a/2) = t / (1 + sqrt(1 + t^2)) take t in [0, 1] below tan(pi/16), then the
+// alternating series u - u^3/3 + ... - u^15/15 (Horner) and a factor 4.
+__device__ __forceinline__ float atan_01(float t) {
+    float u = t / (1.0f + sqrtf(1.0f + t * t));
+    u = u / (1.0f + sqrtf(1.0f + u * u));
+    float u2 = u * u;
+    float p = 1.0f / 15.0f;
+    p = 1.0f / 13.0f - u2 * p;
+    p = 1.0f / 11.0f - u2 * p;
+    p = 1.0f / 9.0f - u2 * p;
+    p = 1.0f / 7.0f - u2 * p;
+    p = 1.0f / 5.0f - u2 * p;
+    p = 1.0f / 3.0f - u2 * p;
+    p = 1.0f - u2 * p;
+    return 4.0f * (u * p);
+}
+// atan2(y, w) for w >= 0, via atan(t) = pi/2 - atan(1/t) above the diagonal.
+__device__ __forceinline__ float atan2_w(float y, float w) {
+    float ay = fabsf(y);
+    float a;
+    if (ay <= w) a = w > 0.0f ? atan_01(ay / w) : 0.0f;
+    else a = 3.14159265358979323846f / 2.0f - atan_01(w / ay);
+    return y < 0.0f ? -a : a;
+}
+
+struct JFrame { int a, b; V3 rA, rB, zA, b1, b2; };
+__device__ __forceinline__ float* jrec(const EnvCtx& c, int j) { return c.L + c.lay.JNT + J_WORDS * j; }
+__device__ __forceinline__ V3 x_of(const EnvCtx& c, int i) {
+    return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.X0, c.lay.n, i) + ld3(c.L, c.lay.DX, c.lay.n, i);
+}
+__device__ __forceinline__ Qt qc_of(const EnvCtx& c, int i) {
+    return i < 0 ? Qt{1.0f, 0.0f, 0.0f, 0.0f} : ld4(c.L, c.lay.QC, c.lay.n, i);
+}
+
+__device__ JFrame joint_frame(const EnvCtx& c, int j) {
+    const float* J = jrec(c, j);
+    JFrame f;
+    f.a = reinterpret_cast<const int*>(J)[J_PA];
+    f.b = reinterpret_cast<const int*>(J)[J_CH];
+    Qt qa = qc_of(c, f.a), qb = qc_of(c, f.b);
+    f.rA = mulv(rotm(qa), v3(J[J_AA], J[J_AA + 1], J[J_AA + 2]));
+    f.rB = mulv(rotm(qb), v3(J[J_AB], J[J_AB + 1], J[J_AB + 2]));
+    M3 Ra = rotm(qmul(qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]}));
+    f.zA = colm(Ra, 2); f.b1 = colm(Ra, 0); f.b2 = colm(Ra, 1);
+    return f;
+}
+
+__device__ void joint_warm(const EnvCtx& c, int j) {
+    JFrame f = joint_frame(c, j);
+    float* J = jrec(c, j);
+    apply_lin(c, f.a, f.b, f.rA, f.rB, v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]));
+    apply_ang(c, f.a, f.b, J[J_LA] * f.b1 + J[J_LA + 1] * f.b2);
+    apply_ang(c, f.a, f.b, J[J_LD] * f.zA);
+}
+
+__device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
+    const BatchDev& bd = *c.bd;
+    JFrame f = joint_frame(c, j);
+    float* J = jrec(c, j);
+    const int a = f.a, b = f.b;
+    const float brate = vpass ? 0.0f : bd.beta_j / bd.dt;
+    S6 Ia = a >= 0 ? load_iw(c, a) : S6{0, 0, 0, 0, 0, 0};
+    S6 Ib = load_iw(c, b);
+    // point block: K = (mA^-1 + mB^-1) I - [rA]x IA [rA]x - [rB]x IB [rB]x
+    {
+        float im = invm_of(c, a) + invm_of(c, b);
+        float K[3][3] = {{im, 0, 0}, {0, im, 0}, {0, 0, im}};
+        for (int side = 0; side < 2; ++side) {
+            if (side == 0 && a < 0) continue;
+            V3 r = side == 0 ? f.rA : f.rB;
+            const S6& I = side == 0 ? Ia : Ib;
+            float Im[3][3] = {{I.xx, I.xy, I.xz}, {I.xy, I.yy, I.yz}, {I.xz, I.yz, I.zz}};
+            float Sx[3][3] = {{0, -r.z, r.y}, {r.z, 0, -r.x}, {-r.y, r.x, 0}};
+            float SI[3][3];
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) SI[p][q] = Sx[p][0] * Im[0][q] + Sx[p][1] * Im[1][q] + Sx[p][2] * Im[2][q];
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) K[p][q] -= SI[p][0] * Sx[0][q] + SI[p][1] * Sx[1][q] + SI[p][2] * Sx[2][q];
+        }
+        V3 C = (x_of(c, b) + f.rB) - (x_of(c, a) + f.rA);
+        V3 Cd = (v_of(c, b) + cross3(w_of(c, b), f.rB)) - (v_of(c, a) + cross3(w_of(c, a), f.rA));
+        V3 rhs = Cd + brate * C;
+        float c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+        float c01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
+        float c02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+        float c10 = K[1][2] * K[2][0] - K[1][0] * K[2][2];
+        float c11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
+        float c12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
+        float c20 = K[1][0] * K[2][1] - K[1][1] * K[2][0];
+        float c21 = K[0][1] * K[2][0] - K[0][0] * K[2][1];
+        float c22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+        float det = K[0][0] * c00 + K[0][1] * c10 + K[0][2] * c20;
+        if (det != 0.0f) {
+            float id = 1.0f / det;
+            V3 lam = v3(-(c00 * rhs.x + c01 * rhs.y + c02 * rhs.z) * id, -(c10 * rhs.x + c11 * rhs.y + c12 * rhs.z) * id,
+                        -(c20 * rhs.x + c21 * rhs.y + c22 * rhs.z) * id);
+            J[J_LP] += lam.x; J[J_LP + 1] += lam.y; J[J_LP + 2] += lam.z;
+            apply_lin(c, a, b, f.rA, f.rB, lam);
+        }
+    }
+    // angular block: keep the joint axes aligned (2 rows)
+    {
+        Qt qb = qmul(qc_of(c, b), Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
+        V3 zB = colm(rotm(qb), 2);
+        V3 zc = cross3(f.zA, zB);
+        float C1 = dot3(f.b1, zc), C2 = dot3(f.b2, zc);
+        V3 dw = w_of(c, b) - w_of(c, a);
+        float Cd1 = dot3(f.b1, dw), Cd2 = dot3(f.b2, dw);
+        S6 Is{Ia.xx + Ib.xx, Ia.yy + Ib.yy, Ia.zz + Ib.zz, Ia.xy + Ib.xy, Ia.xz + Ib.xz, Ia.yz + Ib.yz};
+        float k11 = dot3(f.b1, muls(Is, f.b1)), k12 = dot3(f.b1, muls(Is, f.b2)), k22 = dot3(f.b2, muls(Is, f.b2));
+        float r1 = Cd1 + brate * C1, r2 = Cd2 + brate * C2;
+        float det = k11 * k22 - k12 * k12;
+        if (det != 0.0f) {
+            float id = 1.0f / det;
+            float l1 = -(k22 * r1 - k12 * r2) * id;
+            float l2 = -(-k12 * r1 + k11 * r2) * id;
+            J[J_LA] += l1; J[J_LA + 1] += l2;
+            apply_ang(c, a, b, l1 * f.b1 + l2 * f.b2);
+        }
+    }
+    // PD drive: soft row about the joint axis
+    float kp = J[J_KP], kd = J[J_KD];
+    if (kp != 0.0f || kd != 0.0f) {
+        V3 ax = f.zA;
+        float k = dot3(ax, muls(Ib, ax)) + (a >= 0 ? dot3(ax, muls(Ia, ax)) : 0.0f);
+        float den = kd + h * kp;
+        float gamma = 1.0f / (h * den);
+        float beta_d = h * kp / den;
+        Qt qa = qmul(qc_of(c, a), Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]});
+        Qt qbf = qmul(qc_of(c, b), Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
+        Qt rel = qmul(Qt{qa.w, -qa.x, -qa.y, -qa.z}, qbf);
+        if (rel.w < 0.0f) rel = Qt{-rel.w, -rel.x, -rel.y, -rel.z};
+        float th = 2.0f * atan2_w(rel.z, rel.w);
+        float C = th - J[J_TG];
+        // wrap into (-pi, pi] with the exact IEEE remainder (non-finite stays non-finite)
+        const float pi = 3.14159265358979323846f;
+        C = remainderf(C, 2.0f * pi);
+        if (C <= -pi) C += 2.0f * pi;
+        float Cd = dot3(ax, w_of(c, b) - w_of(c, a));
+        float dl = -(Cd + beta_d * C / h + gamma * J[J_LD]) / (k + gamma);
+        J[J_LD] += dl;
+        apply_ang(c, a, b, dl * ax);
+    }
+}
+
+// ----------------------------------------------------------------------------- S1 AABB (exact)
+__device__ void body_aabb(const EnvCtx& c, int i) {
+#pragma clang fp contract(off)
+    const Lay& l = c.lay;
+    const int n = l.n;
+    Qt q = ld4(c.L, l.Q0, n, i);
+    float xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+    float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+    float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
+    float R[3][3];
+    R[0][0] = 1.0f - 2.0f * (yy + zz); R[0][1] = 2.0f * (xy - wz);        R[0][2] = 2.0f * (xz + wy);
+    R[1][0] = 2.0f * (xy + wz);        R[1][1] = 1.0f - 2.0f * (xx + zz); R[1][2] = 2.0f * (yz - wx);
+    R[2][0] = 2.0f * (xz - wy);        R[2][1] = 2.0f * (yz + wx);        R[2][2] = 1.0f - 2.0f * (xx + yy);
+    int shape = iptr(c.L + l.SH)[i] & 0xFF;
+    float d0 = c.L[l.DIM + i], d1 = c.L[l.DIM + n + i], d2 = c.L[l.DIM + 2 * n + i];
+    float delta = c.bd->delta;
+    for (int r = 0; r < 3; ++r) {
+        float hv;
+        if (shape == 2) {
+            float t0 = fabsf(R[r][0]) * d0;
+            float t1 = fabsf(R[r][1]) * d1;
+            float t2 = fabsf(R[r][2]) * d2;
+            hv = (t0 + t1) + t2;
+        } else if (shape == 0) {
+            hv = d0;
+        } else {
+            float t = fabsf(R[r][2]) * d1;
+            hv = t + d0;
+        }
+        float half = hv + delta;
+        float x = c.L[l.X0 + r * n + i];
+        c.L[l.AABB + r * n + i] = x - half;
+        c.L[l.AABB + (3 + r) * n + i] = x + half;
+    }
+}
+
+__device__ __forceinline__ bool aabb_overlap(const EnvCtx& c, int a, int b) {
+    const float* A = c.L + c.lay.AABB;
+    const int n = c.lay.n;
+    for (int r = 0; r < 3; ++r)
+        if (!(A[r * n + a] <= A[(3 + r) * n + b] && A[r * n + b] <= A[(3 + r) * n + a])) return false;
+    return true;
+}
+
+// (pair_of lives in ms_dev.h)
+
+// ----------------------------------------------------------------------------- schedule runner
+enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
+
+// Walk a schedule: entry e = (start | count << 16) into the colour order; blocks of one entry
+// touch disjoint dynamic bodies, so the lanes of the group run them concurrently.  `emax` is
+// the wave-wide maximum number of entries (every lane reaches every barrier).
+__device__ void run_schedule(const EnvCtx& c, int sched_off, int nsched, int emax, int op, float h, int li) {
+    const Lay& l = c.lay;
+    const int* SCH = reinterpret_cast<const int*>(c.L + sched_off);
+    const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
+    for (int e = 0; e < emax; ++e) {
+        if (e < nsched) {
+            int ent = SCH[e];
+            int start = ent & 0xFFFF, cnt = ent >> 16;
+            if (li < cnt) {
+                int blk = ORD[start + li];
+                if (blk < l.nj) {
+                    if (op == OP_WARM) joint_warm(c, blk);
+                    else if (op == OP_SOLVE || op == OP_JOINT) joint_solve(c, blk, h, false);
+                    else if (op == OP_VSOLVE) joint_solve(c, blk, h, true);
+                } else {
+                    int m = blk - l.nj;
+                    if (op == OP_WARM) manifold_warm(c, m);
+                    else if (op == OP_SOLVE) manifold_solve(c, m, h, false);
+                    else if (op == OP_VSOLVE) manifold_solve(c, m, h, true);
+                    else if (op == OP_REST) manifold_restitution(c, m);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------- S5 colouring
+// Serial greedy colouring by the group leader: blocks = joints (index order) then manifolds
+// (canonical order); each block takes the smallest colour unused by its dynamic bodies.  Then a
+// stable counting sort by colour and the two schedules (all blocks; joints only).
+__device__ void colour_env(const EnvCtx& c, int G) {
+    const Lay& l = c.lay;
+    int* SC = iptr(c.L + l.SCAL);
+    const int nman = SC[SC_NMAN];
+    const int nb = l.nj + nman;
+    uint16_t* BC = reinterpret_cast<uint16_t*>(c.L + l.BCOL);
+    uint16_t* ORD = reinterpret_cast<uint16_t*>(c.L + l.ORDER);
+    int* CS = iptr(c.L + l.CSTART);
+    int* CMi = iptr(c.L + l.CM);
+    for (int k = 0; k <= N_COLOURS + 1; ++k) CS[k] = 0;
+    int ncol = 0;
+    bool overflow = false;
+    for (int blk = 0; blk < nb; ++blk) {
+        int a, b;
+        if (blk < l.nj) {
+            const int* J = reinterpret_cast<const int*>(jrec(c, blk));
+            a = J[J_PA]; b = J[J_CH];
+        } else {
+            int f, cnt;
+            man_header(c, blk - l.nj, a, b, f, cnt);
+        }
+        bool da = is_dyn(c, a), db = is_dyn(c, b);
+        uint64_t u = 0;
+        if (da) u |= uint64_t(uint32_t(CMi[2 * a])) | (uint64_t(uint32_t(CMi[2 * a + 1])) << 32);
+        if (db) u |= uint64_t(uint32_t(CMi[2 * b])) | (uint64_t(uint32_t(CMi[2 * b + 1])) << 32);
+        int col;
+        if (~u == 0) { col = N_COLOURS; overflow = true; }
+        else {
+            col = __ffsll((unsigned long long)(~u)) - 1;
+            uint64_t bit = uint64_t(1) << col;
+            if (da) { uint64_t m = (uint64_t(uint32_t(CMi[2 * a])) | (uint64_t(uint32_t(CMi[2 * a + 1])) << 32)) | bit;
+                      CMi[2 * a] = int(uint32_t(m)); CMi[2 * a + 1] = int(uint32_t(m >> 32)); }
+            if (db) { uint64_t m = (uint64_t(uint32_t(CMi[2 * b])) | (uint64_t(uint32_t(CMi[2 * b + 1])) << 32)) | bit;
+                      CMi[2 * b] = int(uint32_t(m)); CMi[2 * b + 1] = int(uint32_t(m >> 32)); }
+        }
+        BC[blk] = uint16_t(col);
+        CS[col + 1] += 1;
+        if (col + 1 > ncol) ncol = col + 1;
+    }
+    if (overflow) SC[SC_STATUS] |= 4;
+    for (int k = 0; k <= N_COLOURS; ++k) CS[k + 1] += CS[k];
+    // stable scatter, using the joint schedule area as per-colour cursors
+    int* cur = iptr(c.L + l.JSCHED);
+    for (int k = 0; k <= N_COLOURS; ++k) cur[k] = CS[k];
+    for (int blk = 0; blk < nb; ++blk) ORD[cur[BC[blk]]++] = uint16_t(blk);
+    int* SCH = iptr(c.L + l.SCHED);
+    int ns = 0;
+    for (int col = 0; col < ncol; ++col) {
+        int s0 = CS[col], cnt = CS[col + 1] - s0;
+        if (col < N_COLOURS) {
+            for (int o = 0; o < cnt; o += G) SCH[ns++] = (s0 + o) | (min(G, cnt - o) << 16);
+        } else {
+            for (int o = 0; o < cnt; ++o) SCH[ns++] = (s0 + o) | (1 << 16);
+        }
+    }
+    int* JS = iptr(c.L + l.JSCHED);
+    int njs = 0;
+    if (l.nj > 0) {
+        for (int col = 0; col < ncol; ++col) {
+            int s0 = CS[col], cnt = 0;
+            while (s0 + cnt < CS[col + 1] && ORD[s0 + cnt] < l.nj) ++cnt;
+            if (col < N_COLOURS) {
+                for (int o = 0; o < cnt; o += G) JS[njs++] = (s0 + o) | (min(G, cnt - o) << 16);
+            } else {
+                for (int o = 0; o < cnt; ++o) JS[njs++] = (s0 + o) | (1 << 16);
+            }
+        }
+    }
+    SC[SC_NCOL] = ncol;
+    SC[SC_NSCHED] = ns;
+    SC[SC_NJSCHED] = njs;
+}
+
+}  // namespace
+
+// ============================================================================= step kernel
+extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* __restrict__ batches,
+                                                              const Tile* __restrict__ tiles, int n_tiles,
+                                                              const TileEnv* __restrict__ tenv, int n_steps) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x;
+
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const Tile tile = tiles[t];
+        const int G = tile.lanes;
+        const int g = lane / G, li = lane % G;
+        EnvCtx c;
+        c.active = g < tile.count;
+        TileEnv te = c.active ? tenv[tile.first + g] : tenv[tile.first];
+        c.bd = &batches[te.batch];
+        c.env = te.env;
+        c.L = lds + te.lds_off;
+        c.lay = make_lay(te.n, te.nj, te.cap, te.mcap);
+        const BatchDev& bd = *c.bd;
+        const Lay& l = c.lay;
+        const int n = l.n;
+        const int nj = l.nj;
+        const int nA = c.active ? n : 0;    // bodies this lane's group owns
+        const int njA = c.active ? nj : 0;
+        c.b0 = bd.body_off[c.env];
+        c.j0 = bd.joint_off[c.env];
+        int* SC = iptr(c.L + l.SCAL);
+        const int B = bd.B;
+
+        // ------------------------------------------------------------- load (once per launch)
+        for (int i = li; i < nA; i += G) {
+            int gi = c.b0 + i;
+            for (int r = 0; r < 3; ++r) c.L[l.X0 + r * n + i] = bd.pos[r * B + gi];
+            for (int r = 0; r < 4; ++r) c.L[l.QC + r * n + i] = bd.quat[r * B + gi];
+            for (int r = 0; r < 3; ++r) c.L[l.V + r * n + i] = bd.vel[r * B + gi];
+            for (int r = 0; r < 3; ++r) c.L[l.W + r * n + i] = bd.angvel[r * B + gi];
+            float4 p0 = bd.bpar[gi], p1 = bd.bpar[B + gi], p2 = bd.bpar[2 * B + gi];
+            int sh = __float_as_int(p0.x);
+            iptr(c.L + l.SH)[i] = sh;
+            bool dyn = !((sh >> 8) & 1);
+            c.L[l.INVM + i] = dyn ? p0.y : 0.0f;
+            c.L[l.MU + i] = p0.z;
+            c.L[l.EE + i] = p0.w;
+            c.L[l.DIM + i] = p1.x; c.L[l.DIM + n + i] = p1.y; c.L[l.DIM + 2 * n + i] = p1.z;
+            c.L[l.IB + i] = dyn ? p2.x : 0.0f;
+            c.L[l.IB + n + i] = dyn ? p2.y : 0.0f;
+            c.L[l.IB + 2 * n + i] = dyn ? p2.z : 0.0f;
+            st3(c.L, l.DX, n, i, v3(0, 0, 0));
+        }
+        for (int j = li; j < njA; j += G) {
+            const float* src = bd.jrec + size_t(c.j0 + j) * JREC;
+            float* J = jrec(c, j);
+            for (int w = 0; w < JREC; ++w) J[w] = src[w];
+            J[J_TG] = bd.targets[c.j0 + j];
+        }
+        if (c.active && li == 0) SC[SC_STATUS] = bd.status[c.env];
+        __syncthreads();
+        // jointed-partner masks (parent-child pairs never collide)
+        for (int i = li; i < nA; i += G) {
+            uint64_t m = 0;
+            for (int j = 0; j < nj; ++j) {
+                const int* J = reinterpret_cast<const int*>(jrec(c, j));
+                int pa = J[J_PA], ch = J[J_CH];
+                if (pa < 0) continue;
+                if (pa == i) m |= uint64_t(1) << ch;
+                if (ch == i) m |= uint64_t(1) << pa;
+            }
+            iptr(c.L + l.JM)[2 * i] = int(uint32_t(m));
+            iptr(c.L + l.JM)[2 * i + 1] = int(uint32_t(m >> 32));
+        }
+        __syncthreads();
+
+        for (int step = 0; step < n_steps; ++step) {
+            const bool frozen = !c.active || (SC[SC_STATUS] & 1);
+            const int nn = frozen ? 0 : n;
+            const int S = bd.S, K = bd.K;
+            const float h = bd.dt / float(S);
+            const bool dbg = bd.dbg_pairs != nullptr && step == n_steps - 1 && !frozen;
+            if (bd.dbg_pairs != nullptr && step == n_steps - 1 && frozen && c.active && li == 0) {
+                int* dc = bd.dbg_counts + 4 * c.env;
+                dc[0] = 0; dc[1] = 0; dc[2] = 0; dc[3] = 0;
+            }
+            __syncthreads();
+
+            // --------------------------------------------------------- S0 + S1
+            for (int i = li; i < nn; i += G) {
+                V3 x0 = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
+                st3(c.L, l.X0, n, i, x0);
+                st4(c.L, l.Q0, n, i, ld4(c.L, l.QC, n, i));
+                st3(c.L, l.DX, n, i, v3(0, 0, 0));
+                st4(c.L, l.DQ, n, i, Qt{1.0f, 0.0f, 0.0f, 0.0f});
+                st3(c.L, l.V0, n, i, ld3(c.L, l.V, n, i));
+                st3(c.L, l.W0, n, i, ld3(c.L, l.W, n, i));
+                // world inverse inertia R diag(I^-1) R^T from the step-start orientation
+                M3 R = rotm(ld4(c.L, l.Q0, n, i));
+                float d0 = c.L[l.IB + i], d1 = c.L[l.IB + n + i], d2 = c.L[l.IB + 2 * n + i];
+                float Iw[3][3];
+                for (int p = 0; p < 3; ++p)
+                    for (int q = p; q < 3; ++q)
+                        Iw[p][q] = R.m[p][0] * d0 * R.m[q][0] + R.m[p][1] * d1 * R.m[q][1] + R.m[p][2] * d2 * R.m[q][2];
+                c.L[l.IW + i] = Iw[0][0]; c.L[l.IW + n + i] = Iw[1][1]; c.L[l.IW + 2 * n + i] = Iw[2][2];
+                c.L[l.IW + 3 * n + i] = Iw[0][1]; c.L[l.IW + 4 * n + i] = Iw[0][2]; c.L[l.IW + 5 * n + i] = Iw[1][2];
+                body_aabb(c, i);
+                iptr(c.L + l.CM)[2 * i] = 0;
+                iptr(c.L + l.CM)[2 * i + 1] = 0;
+            }
+            // joint impulses start every step from zero (no cross-step warm start)
+            for (int j = li; j < (frozen ? 0 : nj); j += G) {
+                float* J = jrec(c, j);
+                for (int w = J_LP; w <= J_LD; ++w) J[w] = 0.0f;
+            }
+            __syncthreads();
+
+            // --------------------------------------------------------- S2 candidate pairs
+            const int P = frozen ? 0 : l.P;
+            int ncand = 0;
+            {
+                const int nch = wave_max((P + G - 1) / G);
+                uint16_t* CAND = reinterpret_cast<uint16_t*>(c.L + l.CAND);
+                const int* JMi = iptr(c.L + l.JM);
+                for (int ch = 0; ch < nch; ++ch) {
+                    int k = ch * G + li;
+                    bool cand = false;
+                    int a = 0, b = 0;
+                    if (k < P) {
+                        pair_of(k, n, a, b);
+                        if (b == n) {
+                            cand = bd.plane && is_dyn(c, a) && c.L[l.AABB + 2 * n + a] <= bd.plane_z;
+                        } else {
+                            bool jointed = b < 32 ? ((JMi[2 * a] >> b) & 1) : ((JMi[2 * a + 1] >> (b - 32)) & 1);
+                            cand = (is_dyn(c, a) || is_dyn(c, b)) && !jointed && aabb_overlap(c, a, b);
+                        }
+                    }
+                    uint64_t gb = group_bits(__ballot(cand), g, G);
+                    if (cand) CAND[ncand + prefix_in_group(gb, li)] = uint16_t(a | (b << 8));
+                    ncand += __popcll(gb);
+                }
+            }
+            __syncthreads();
+
+            // --------------------------------------------------------- S3 + S4 narrowphase, rows
+            int npts = 0, nman = 0;
+            bool overflow = false;
+            {
+                const int nch = wave_max((ncand + G - 1) / G);
+                const uint16_t* CAND = reinterpret_cast<const uint16_t*>(c.L + l.CAND);
+                const float delta = bd.delta;
+                int dpo = 0, dmo = 0, dpp = 0;
+                if (dbg) { dpp = bd.dbg_pair_off[c.env]; dpo = bd.dbg_pt_off[c.env]; dmo = bd.dbg_man_off[c.env]; }
+                for (int ch = 0; ch < nch; ++ch) {
+                    int k = ch * G + li;
+                    NOut o;
+                    o.n = 0;
+                    o.decision = 0;
+                    int a = 0, b = 0;
+                    bool plane = false;
+                    V3 base = v3(0, 0, 0), offB = v3(0, 0, 0);
+                    if (k < ncand) {
+                        int code = CAND[k];
+                        a = code & 0xFF;
+                        b = code >> 8;
+                        plane = b == n;
+                        V3 xa = ld3(c.L, l.X0, n, a);
+                        if (plane) {
+                            Shp sb = shape_of(c, a, v3(0.0f, 0.0f, xa.z - bd.plane_z));
+                            base = v3(xa.x, xa.y, bd.plane_z);
+                            offB = sb.c;
+                            np_plane(o, sb, delta);
+                        } else {
+                            Shp sa = shape_of(c, a, v3(0, 0, 0));
+                            Shp sb = shape_of(c, b, ld3(c.L, l.X0, n, b) - xa);
+                            base = xa;
+                            offB = sb.c;
+                            np_pair(o, sa, sb, delta);
+                        }
+                        reduce4(o);
+                    }
+                    int tot;
+                    int pre = group_scan(o.n, li, G, tot);
+                    int keep = min(max(l.cap - (npts + pre), 0), o.n);
+                    bool ovf = keep < o.n;
+                    int mtot;
+                    int mpre = group_scan(keep > 0 ? 1 : 0, li, G, mtot);
+                    if (keep > 0 && nman + mpre >= l.mcap) { keep = 0; ovf = true; }
+                    int ktot;
+                    int kpre = group_scan(keep, li, G, ktot);
+                    int m_idx = nman + mpre;
+                    int first = npts + kpre;
+                    overflow |= group_bits(__ballot(ovf), g, G) != 0;
+                    if (k < ncand && dbg) {
+                        int* dp = bd.dbg_pairs + 4 * size_t(dpp + k);
+                        dp[0] = a; dp[1] = plane ? PLANE : b; dp[2] = keep; dp[3] = o.decision;
+                    }
+                    if (keep > 0) {
+                        int ia = plane ? -1 : a, ib = plane ? a : b;
+                        float mu, e;
+                        if (plane) { mu = (bd.plane_mu + c.L[l.MU + a]) / 2.0f; e = fmaxf(bd.plane_e, c.L[l.EE + a]); }
+                        else { mu = (c.L[l.MU + a] + c.L[l.MU + b]) / 2.0f; e = fmaxf(c.L[l.EE + a], c.L[l.EE + b]); }
+                        V3 csum = v3(0, 0, 0), nsum = v3(0, 0, 0);
+                        for (int q = 0; q < keep; ++q) {
+                            int kk = first + q;
+                            V3 p = o.pt[q].p, nv = o.pt[q].n;
+                            V3 rA = ia >= 0 ? p : v3(0, 0, 0);
+                            V3 rB = p - offB;
+                            V3 vrel = rel_vel(c, ia, ib, rA, rB);
+                            pr(c, R_RA, kk) = rA.x; pr(c, R_RA + 1, kk) = rA.y; pr(c, R_RA + 2, kk) = rA.z;
+                            pr(c, R_RB, kk) = rB.x; pr(c, R_RB + 1, kk) = rB.y; pr(c, R_RB + 2, kk) = rB.z;
+                            pr(c, R_N, kk) = nv.x; pr(c, R_N + 1, kk) = nv.y; pr(c, R_N + 2, kk) = nv.z;
+                            pr(c, R_MN, kk) = eff_mass(c, ia, ib, rA, rB, nv);
+                            pr(c, R_S0, kk) = o.pt[q].s;
+                            pr(c, R_E, kk) = e;
+                            pr(c, R_VN, kk) = dot3(vrel, nv);
+                            pr(c, R_LN, kk) = 0.0f;
+                            csum = csum + p;
+                            nsum = nsum + nv;
+                            if (dbg) {
+                                float* dq = bd.dbg_pts + 8 * size_t(dpo + kk);
+                                V3 pw = base + p;
+                                dq[0] = pw.x; dq[1] = pw.y; dq[2] = pw.z; dq[3] = nv.x; dq[4] = nv.y; dq[5] = nv.z;
+                                dq[6] = o.pt[q].s; dq[7] = 0.0f;
+                            }
+                        }
+                        V3 cc = (1.0f / float(keep)) * csum;
+                        V3 nb = (1.0f / len3(nsum)) * nsum;
+                        V3 rA = ia >= 0 ? cc : v3(0, 0, 0);
+                        V3 rB = cc - offB;
+                        V3 vrel = rel_vel(c, ia, ib, rA, rB);
+                        V3 vt = vrel - dot3(vrel, nb) * nb;
+                        float vtl = len3(vt);
+                        V3 t1 = vtl >= 1e-3f ? (1.0f / vtl) * vt : onb_t1(nb);
+                        V3 t2 = cross3(nb, t1);
+                        float kw = (ia >= 0 ? dot3(nb, muls(load_iw(c, ia), nb)) : 0.0f) + dot3(nb, muls(load_iw(c, ib), nb));
+                        float rsum = 0.0f;
+                        for (int q = 0; q < keep; ++q) rsum += len3(o.pt[q].p - cc);
+                        int m = m_idx;
+                        iptr(c.L + l.MAN + M_AB * l.mcap)[m] = (ia < 0 ? 0xFF : ia) | (ib << 8);
+                        iptr(c.L + l.MAN + M_FC * l.mcap)[m] = first | (keep << 16);
+                        mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
+                        mfr(c, M_RB, m) = rB.x; mfr(c, M_RB + 1, m) = rB.y; mfr(c, M_RB + 2, m) = rB.z;
+                        mfr(c, M_NB, m) = nb.x; mfr(c, M_NB + 1, m) = nb.y; mfr(c, M_NB + 2, m) = nb.z;
+                        mfr(c, M_T1, m) = t1.x; mfr(c, M_T1 + 1, m) = t1.y; mfr(c, M_T1 + 2, m) = t1.z;
+                        mfr(c, M_MT1, m) = eff_mass(c, ia, ib, rA, rB, t1);
+                        mfr(c, M_MT2, m) = eff_mass(c, ia, ib, rA, rB, t2);
+                        mfr(c, M_MTW, m) = kw > 0.0f ? 1.0f / kw : 0.0f;
+                        mfr(c, M_MU, m) = mu;
+                        mfr(c, M_RT, m) = rsum / float(keep);
+                        mfr(c, M_LT1, m) = 0.0f; mfr(c, M_LT2, m) = 0.0f; mfr(c, M_LTW, m) = 0.0f;
+                        if (dbg) {
+                            float* dm = bd.dbg_man + 8 * size_t(dmo + m);
+                            dm[0] = __int_as_float(k);
+                            dm[7] = __int_as_float(keep);
+                        }
+                    }
+                    npts += ktot;
+                    int mkept;
+                    group_scan(keep > 0 ? 1 : 0, li, G, mkept);
+                    nman += mkept;
+                }
+            }
+            if (!frozen && li == 0) {
+                SC[SC_NCAND] = ncand;
+                SC[SC_NPTS] = npts;
+                SC[SC_NMAN] = nman;
+                if (overflow) SC[SC_STATUS] |= 2;
+            }
+            __syncthreads();
+
+            // --------------------------------------------------------- S5 colouring
+            if (!frozen && li == 0) colour_env(c, G);
+            __syncthreads();
+            const int ns = frozen ? 0 : SC[SC_NSCHED];
+            const int njs = frozen ? 0 : SC[SC_NJSCHED];
+            const int ns_max = wave_max(ns), njs_max = wave_max(njs);
+            const int JI = bd.JI;
+
+            // --------------------------------------------------------- S6 substeps
+            const float ldmp = 1.0f / (1.0f + h * bd.lin_damp);
+            const float admp = 1.0f / (1.0f + h * bd.ang_damp);
+            for (int s = 0; s < S; ++s) {
+                for (int i = li; i < nn; i += G) {
+                    if (!is_dyn(c, i)) continue;
+                    V3 v = ld3(c.L, l.V, n, i);
+                    v = ldmp * (v + h * v3(bd.gx, bd.gy, bd.gz));
+                    st3(c.L, l.V, n, i, v);
+                    st3(c.L, l.W, n, i, admp * ld3(c.L, l.W, n, i));
+                }
+                __syncthreads();
+                if (s > 0) run_schedule(c, l.SCHED, ns, ns_max, OP_WARM, h, li);
+                for (int it = 0; it < K; ++it) {
+                    for (int jx = 1; jx < JI; ++jx) run_schedule(c, l.JSCHED, njs, njs_max, OP_JOINT, h, li);
+                    run_schedule(c, l.SCHED, ns, ns_max, OP_SOLVE, h, li);
+                }
+                // integrate the offsets from the step-start pose
+                for (int i = li; i < nn; i += G) {
+                    if (!is_dyn(c, i)) continue;
+                    V3 v = ld3(c.L, l.V, n, i), w = ld3(c.L, l.W, n, i);
+                    st3(c.L, l.DX, n, i, ld3(c.L, l.DX, n, i) + h * v);
+                    Qt d = ld4(c.L, l.DQ, n, i);
+                    Qt e = qmul(Qt{0.0f, w.x, w.y, w.z}, d);
+                    float hh = 0.5f * h;
+                    d = qnorm(Qt{d.w + hh * e.w, d.x + hh * e.x, d.y + hh * e.y, d.z + hh * e.z});
+                    st4(c.L, l.DQ, n, i, d);
+                    st4(c.L, l.QC, n, i, qnorm(qmul(d, ld4(c.L, l.Q0, n, i))));
+                }
+                __syncthreads();
+            }
+            // --------------------------------------------------------- S7
+            for (int it = 0; it < bd.V; ++it) run_schedule(c, l.SCHED, ns, ns_max, OP_VSOLVE, h, li);
+            run_schedule(c, l.SCHED, ns, ns_max, OP_REST, h, li);
+
+            // --------------------------------------------------------- S8 non-finite guard
+            bool bad = false;
+            for (int i = li; i < nn; i += G) {
+                V3 x = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
+                Qt q = ld4(c.L, l.QC, n, i);
+                V3 v = ld3(c.L, l.V, n, i), w = ld3(c.L, l.W, n, i);
+                float vals[13] = {x.x, x.y, x.z, q.w, q.x, q.y, q.z, v.x, v.y, v.z, w.x, w.y, w.z};
+                for (int r = 0; r < 13; ++r) bad |= !isfinite(vals[r]);
+            }
+            bool anybad = group_bits(__ballot(bad), g, G) != 0;
+            if (anybad) {
+                for (int i = li; i < nn; i += G) {
+                    st3(c.L, l.DX, n, i, v3(0, 0, 0));
+                    st4(c.L, l.QC, n, i, ld4(c.L, l.Q0, n, i));
+                    st3(c.L, l.V, n, i, ld3(c.L, l.V0, n, i));
+                    st3(c.L, l.W, n, i, ld3(c.L, l.W0, n, i));
+                }
+                if (li == 0) SC[SC_STATUS] |= 1;
+            }
+            __syncthreads();
+            // --------------------------------------------------------- debug export
+            if (dbg) {
+                int dpo = bd.dbg_pt_off[c.env], dmo = bd.dbg_man_off[c.env];
+                for (int k = li; k < npts; k += G) bd.dbg_pts[8 * size_t(dpo + k) + 7] = pr(c, R_LN, k);
+                const uint16_t* BC = reinterpret_cast<const uint16_t*>(c.L + l.BCOL);
+                for (int m = li; m < nman; m += G) {
+                    float* dm = bd.dbg_man + 8 * size_t(dmo + m);
+                    dm[1] = __int_as_float(int(BC[nj + m]));
+                    dm[2] = mf(c, M_LT1, m); dm[3] = mf(c, M_LT2, m); dm[4] = mf(c, M_LTW, m);
+                    dm[5] = mf(c, M_MU, m); dm[6] = mf(c, M_RT, m);
+                }
+                if (li == 0) {
+                    int* dc = bd.dbg_counts + 4 * c.env;
+                    dc[0] = ncand; dc[1] = npts; dc[2] = nman; dc[3] = SC[SC_NCOL];
+                }
+            }
+        }
+        __syncthreads();
+        // ------------------------------------------------------------- store
+        for (int i = li; i < nA; i += G) {
+            int gi = c.b0 + i;
+            V3 x = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
+            bd.pos[gi] = x.x; bd.pos[B + gi] = x.y; bd.pos[2 * B + gi] = x.z;
+            for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = c.L[l.QC + r * n + i];
+            for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = c.L[l.V + r * n + i];
+            for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = c.L[l.W + r * n + i];
+        }
+        if (c.active && li == 0) bd.status[c.env] = SC[SC_STATUS];
+        __syncthreads();
+    }
+}
+
+// ============================================================================= reset kernel
+// Write the state of the listed envs from a source (the batch's initial state or caller SoA
+// arrays of the same shape) and clear their status.  One workgroup per listed env.
+extern "C" __global__ void __launch_bounds__(64) ms_reset_kernel(BatchDev bd, const int* __restrict__ env_ids,
+                                                               int n_ids, const float* __restrict__ spos,
+                                                               const float* __restrict__ squat,
+                                                               const float* __restrict__ svel,
+                                                               const float* __restrict__ sang) {
+    int k = blockIdx.x;
+    if (k >= n_ids) return;
+    int e = env_ids[k];
+    if (e < 0 || e >= bd.E) return;
+    int b0 = bd.body_off[e], b1 = bd.body_off[e + 1];
+    const int B = bd.B;
+    for (int gi = b0 + int(threadIdx.x); gi < b1; gi += blockDim.x) {
+        for (int r = 0; r < 3; ++r) bd.pos[r * B + gi] = spos[r * B + gi];
+        for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = squat[r * B + gi];
+        for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = svel[r * B + gi];
+        for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = sang[r * B + gi];
+    }
+    if (threadIdx.x == 0) bd.status[e] = 0;
+}

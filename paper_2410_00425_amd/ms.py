@@ -1,0 +1,247 @@
+"""Python binding of libms (argument marshalling only).
+
+Every step of the simulation runs in the HIP kernels of ``libms.so``; this module converts numpy
+descriptors and torch device tensors into the C ABI's plain pointers.  torch provides the
+device memory (the caller-owned workspace and state buffers) and the stream.  Importing it
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import scenes
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libms.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_00425_amd.build` "
+                      "(hipcc, gfx950) before using the GPU step")
+
+_lib = C.CDLL(LIB_PATH)
+
+MS_OK, MS_E_INVALID_ARG, MS_E_NO_WORKSPACE, MS_E_BUDGET, MS_E_DEVICE, MS_E_CAPACITY, MS_E_STATE = range(7)
+STATUS_NONFINITE, STATUS_CONTACT_OVERFLOW, STATUS_COLOR_OVERFLOW = 1, 2, 4
+PLANE = 0xFFFF
+
+
+class MsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libms error {code}: {msg}")
+        self.code = code
+
+
+class ms_scene_desc(C.Structure):
+    _fields_ = [("n_envs", C.c_int32), ("env_body_off", C.c_void_p), ("bodies", C.c_void_p),
+                ("env_joint_off", C.c_void_p), ("joints", C.c_void_p)]
+
+
+class ms_state_view(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("quat", C.c_void_p), ("linvel", C.c_void_p), ("angvel", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
+class ms_plan(C.Structure):
+    _fields_ = [("lanes_per_env", C.c_int32), ("pack", C.c_int32), ("max_resident_groups", C.c_int32)]
+
+
+_P = C.c_void_p
+_I = C.c_int32
+_sig = {
+    "ms_query_batch_bytes": [_P, _P, _P, C.POINTER(C.c_size_t)],
+    "ms_create_batch": [_P, _P, _P, _P, C.c_size_t, _P, C.POINTER(_P)],
+    "ms_step": [_P, _P, _I, _P],
+    "ms_reset_envs": [_P, _P, _I, _P, _P],
+    "ms_get_state": [_P, _P, _P],
+    "ms_get_layout": [_P, _P, _P],
+    "ms_get_sizes": [_P, _P, _P, _P],
+    "ms_get_plan": [_P, _P, _P, _P, _P],
+    "ms_get_contacts": [_P, _P, _I, _P, _I, _P, _I, _P, _P, _P, _P],
+    "ms_destroy_batch": [_P],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.ms_last_error.restype = C.c_char_p
+_lib.ms_version.restype = C.c_char_p
+
+
+def _check(code):
+    if code != MS_OK:
+        raise MsError(code, _lib.ms_last_error().decode())
+
+
+def ms_version() -> str:
+    return _lib.ms_version().decode()
+
+
+def _scene_struct(scene):
+    arrs = [np.ascontiguousarray(scene.body_off, np.int32), np.ascontiguousarray(scene.bodies),
+            np.ascontiguousarray(scene.joint_off, np.int32), np.ascontiguousarray(scene.joints)]
+    assert arrs[1].dtype == scenes.BODY_DTYPE and arrs[3].dtype == scenes.JOINT_DTYPE
+    sd = ms_scene_desc(scene.n_envs, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                       arrs[3].ctypes.data if len(arrs[3]) else None)
+    return sd, arrs
+
+
+def _params(scene, params):
+    p = np.ascontiguousarray(scene.params if params is None else params)
+    assert p.dtype == scenes.PARAMS_DTYPE
+    return p
+
+
+def _plan(lanes_per_env=0, pack=1, max_resident_groups=0):
+    return ms_plan(int(lanes_per_env), int(pack), int(max_resident_groups))
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def ms_query_batch_bytes(scene, params=None, plan=None) -> int:
+    p = _params(scene, params)
+    sd, keep = _scene_struct(scene)
+    pl = plan or _plan()
+    out = C.c_size_t()
+    _check(_lib.ms_query_batch_bytes(p.ctypes.data, C.byref(sd), C.byref(pl), C.byref(out)))
+    return out.value
+
+
+class Batch:
+    """A batch of envs resident on one GPU: owns its torch workspace and the C handle."""
+
+    def __init__(self, scene, params=None, device="cuda:0", lanes_per_env=0, pack=1, max_resident_groups=0,
+                 stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.scene = scene
+        self.params = _params(scene, params)
+        self.n_envs, self.n_bodies, self.n_joints = scene.n_envs, scene.n_bodies, scene.n_joints
+        self._plan = _plan(lanes_per_env, pack, max_resident_groups)
+        sd, keep = _scene_struct(scene)
+        nbytes = C.c_size_t()
+        _check(_lib.ms_query_batch_bytes(self.params.ctypes.data, C.byref(sd), C.byref(self._plan),
+                                         C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        with torch.cuda.device(self.device):
+            # 256-byte alignment: over-allocate and offset
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
+            h = C.c_void_p()
+            _check(_lib.ms_create_batch(self.params.ctypes.data, C.byref(sd), C.byref(self._plan),
+                                        C.c_void_p(self._ws_ptr), self.workspace_bytes, _stream(stream),
+                                        C.byref(h)))
+        self._h = h
+
+    # ------------------------------------------------------------------ ABI wrappers
+    def step(self, n_steps: int = 1, targets=None, stream=None):
+        """ms_step: advance every env by n_steps steps; targets is a float32 device tensor [J]."""
+        tp = None
+        if targets is not None:
+            assert targets.dtype.is_floating_point and targets.numel() == self.n_joints and targets.is_cuda
+            assert targets.is_contiguous()
+            tp = C.c_void_p(targets.data_ptr())
+        _check(_lib.ms_step(self._h, tp, int(n_steps), _stream(stream)))
+
+    def reset_envs(self, env_ids, src=None, stream=None):
+        """ms_reset_envs: env_ids an int32 device tensor; src None (initial state) or a dict of
+        full-batch SoA device tensors pos [3, B], quat [4, B], linvel [3, B], angvel [3, B]."""
+        import torch
+        assert env_ids.dtype == torch.int32 and env_ids.is_cuda and env_ids.is_contiguous()
+        view = None
+        if src is not None:
+            for k, rows in (("pos", 3), ("quat", 4), ("linvel", 3), ("angvel", 3)):
+                t = src[k]
+                assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous() and tuple(t.shape) == (rows, self.n_bodies)
+            view = ms_state_view(src["pos"].data_ptr(), src["quat"].data_ptr(), src["linvel"].data_ptr(),
+                                 src["angvel"].data_ptr(), None)
+        _check(_lib.ms_reset_envs(self._h, C.c_void_p(env_ids.data_ptr()), int(env_ids.numel()),
+                                  C.byref(view) if view is not None else None, _stream(stream)))
+
+    def get_state(self, out=None, stream=None):
+        """ms_get_state into (new or given) device tensors; returns the dict."""
+        import torch
+        B, E = self.n_bodies, self.n_envs
+        if out is None:
+            f = dict(dtype=torch.float32, device=self.device)
+            out = dict(pos=torch.empty(3, B, **f), quat=torch.empty(4, B, **f), linvel=torch.empty(3, B, **f),
+                       angvel=torch.empty(3, B, **f), status=torch.empty(E, dtype=torch.int32, device=self.device))
+        view = ms_state_view(out["pos"].data_ptr(), out["quat"].data_ptr(), out["linvel"].data_ptr(),
+                             out["angvel"].data_ptr(), out["status"].data_ptr())
+        _check(_lib.ms_get_state(self._h, C.byref(view), _stream(stream)))
+        return out
+
+    def state_numpy(self):
+        import torch
+        st = self.get_state()
+        torch.cuda.current_stream().synchronize()
+        return {k: v.cpu().numpy() for k, v in st.items()}
+
+    def layout(self):
+        bo = np.zeros(self.n_envs + 1, np.int32)
+        jo = np.zeros(self.n_envs + 1, np.int32)
+        _check(_lib.ms_get_layout(self._h, bo.ctypes.data, jo.ctypes.data))
+        return bo, jo
+
+    def plan(self):
+        nt, grid, lds = C.c_int32(), C.c_int32(), C.c_int32()
+        lanes = np.zeros(self.n_envs, np.int32)
+        _check(_lib.ms_get_plan(self._h, C.byref(nt), C.byref(grid), C.byref(lds), lanes.ctypes.data))
+        return dict(n_tiles=nt.value, grid=grid.value, lds_bytes=lds.value, lanes=lanes)
+
+    def contacts(self, stream=None):
+        """ms_get_contacts (needs debug_export): pairs int32 [n, 5], points float32 [n, 8],
+        manifolds float32 [n, 8]."""
+        n = [C.c_int32(), C.c_int32(), C.c_int32()]
+        _check(_lib.ms_get_contacts(self._h, None, 0, None, 0, None, 0, *[C.byref(x) for x in n], _stream(stream)))
+        np_, npt, nm = (x.value for x in n)
+        pairs = np.zeros((np_, 5), np.int32)
+        pts = np.zeros((npt, 8), np.float32)
+        mans = np.zeros((nm, 8), np.float32)
+        _check(_lib.ms_get_contacts(self._h, pairs.ctypes.data, np_, pts.ctypes.data, npt, mans.ctypes.data, nm,
+                                    *[C.byref(x) for x in n], _stream(stream)))
+        return dict(pairs=pairs, points=pts, manifolds=mans)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ms_destroy_batch(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# The C names, for callers that prefer the flat ABI.
+def ms_create_batch(scene, params=None, device="cuda:0", **plan) -> Batch:
+    return Batch(scene, params, device, **plan)
+
+
+def ms_step(batch: Batch, targets=None, n_steps: int = 1, stream=None):
+    batch.step(n_steps, targets, stream)
+
+
+def ms_reset_envs(batch: Batch, env_ids, src=None, stream=None):
+    batch.reset_envs(env_ids, src, stream)
+
+
+def ms_get_state(batch: Batch, out=None, stream=None):
+    return batch.get_state(out, stream)
+
+
+def ms_get_contacts(batch: Batch, stream=None):
+    return batch.contacts(stream)
+
+
+def ms_destroy_batch(batch: Batch):
+    batch.close()

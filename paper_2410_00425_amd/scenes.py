@@ -38,9 +38,9 @@ PARAMS_DTYPE = np.dtype([
     ("plane_restitution", "<f4"), ("contact_offset", "<f4"), ("baumgarte", "<f4"),
     ("max_depen_vel", "<f4"), ("joint_baumgarte", "<f4"), ("bounce_threshold", "<f4"),
     ("lin_damping", "<f4"), ("ang_damping", "<f4"), ("max_contacts_per_env", "<i4"),
-    ("debug_export", "<i4"), ("joint_iters", "<i4"),
+    ("debug_export", "<i4"), ("joint_iters", "<i4"), ("max_manifolds_per_env", "<i4"),
 ])
-assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 76 and PARAMS_DTYPE.itemsize == 84
+assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 76 and PARAMS_DTYPE.itemsize == 88
 
 SPHERE, CAPSULE, BOX = 0, 1, 2
 STATIC = 1
@@ -54,7 +54,8 @@ def make_params(**kw) -> np.ndarray:
                     plane_z=0.0, plane_enabled=1, plane_friction=0.5, plane_restitution=0.0,
                     contact_offset=0.01, baumgarte=0.2, max_depen_vel=1.0, joint_baumgarte=0.2,
                     bounce_threshold=1.0, lin_damping=0.0, ang_damping=0.0,
-                    max_contacts_per_env=0, debug_export=0, joint_iters=4)
+                    max_contacts_per_env=0, debug_export=0, joint_iters=4,
+                    max_manifolds_per_env=0)
     defaults.update(kw)
     for k, v in defaults.items():
         p[k] = v

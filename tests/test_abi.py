@@ -1,0 +1,63 @@
+"""C ABI checks that need no GPU: the library loads, exports every function include/ms.h
+declares, passes its host self-check, and rejects invalid descriptors with the documented codes
+in the host-only ms_query_batch_bytes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2410_00425_amd import scenes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2410_00425_amd", "libms.so")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ms.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ms_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert "ms_step" in names and "ms_create_batch" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_selfcheck():
+    assert ctypes.CDLL(LIB).ms_selfcheck() == 0
+
+
+def test_query_bytes_and_validation():
+    from paper_2410_00425_amd import ms
+    sc = S.tray(8, seed=0)
+    nb = ms.ms_query_batch_bytes(sc)
+    assert nb > 8 * 24 * 13 * 4
+    bad = S.tray(2, seed=0)
+    bad.bodies["shape"][3] = 7
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_query_batch_bytes(bad)
+    assert e.value.code == ms.MS_E_INVALID_ARG
+    arm = S.arm_cube(2, seed=0)
+    arm.joints["child"][2] = 99
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_query_batch_bytes(arm)
+    assert e.value.code == ms.MS_E_INVALID_ARG
+    big = S.single([S.body(S.SPHERE, (0.01,), (0.1 * i, 0, 0.5), mass=1.0) for i in range(65)])
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_query_batch_bytes(big)
+    assert e.value.code == ms.MS_E_CAPACITY
+    p = sc.params.copy()
+    p["dt"] = -1
+    with pytest.raises(ms.MsError):
+        ms.ms_query_batch_bytes(sc, p)
+    with pytest.raises(ms.MsError):
+        ms.ms_query_batch_bytes(sc, plan=ms.ms_plan(3, 1, 0))
+    nan_t = S.arm_cube(1, seed=0)
+    nan_t.joints["target"][0] = np.nan
+    with pytest.raises(ms.MsError):
+        ms.ms_query_batch_bytes(nan_t)

@@ -148,3 +148,22 @@ def test_arm_cube_workload_is_well_behaved():
     gaps = np.concatenate([joint_state(sc, st, e)[1] for e in range(sc.n_envs)])
     assert gaps.max() < 5e-3
     assert np.abs(st["angvel"]).max() < 10 and np.abs(st["linvel"]).max() < 5
+
+
+def test_drive_arctangent_against_library():
+    # The drive angle's arctangent (half-angle reductions + Taylor series, correctly rounded
+    # operations only) against the C library's atan2, on x >= 0 (the sign-fixed quaternion).
+    import ctypes
+    from oracle.oracle import lib
+    L = lib()
+    L.or_atan2_pos64.restype = ctypes.c_double
+    L.or_atan2_pos64.argtypes = [ctypes.c_double] * 2
+    L.or_atan2_pos32.restype = ctypes.c_float
+    L.or_atan2_pos32.argtypes = [ctypes.c_float] * 2
+    rng = np.random.default_rng(0)
+    ys, xs = rng.normal(size=5000), np.abs(rng.normal(size=5000))
+    ys[:4], xs[:4] = [0.0, 1.0, -1.0, 3.0], [0.0, 0.0, 1.0, 1e-30]
+    for y, x in zip(ys, xs):
+        assert abs(L.or_atan2_pos64(y, x) - math.atan2(y, x)) < 1e-12
+        y32, x32 = float(np.float32(y)), float(np.float32(x))
+        assert abs(L.or_atan2_pos32(y32, x32) - math.atan2(y32, x32)) < 4e-7
