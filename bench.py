@@ -1,17 +1,26 @@
 """Benchmark of the batched rigid-body step on one MI355X.
 
-Workload (default): 4096 tray envs (a static tray holding 20 random boxes / spheres / capsules,
-24 bodies per env, dt = 0.005 s, 8 TGS substeps), synthetic and seeded.  A step is one call of
-ms_step advancing all envs by one dt (load, broadphase, narrowphase, rows, colouring, solve,
-integration, store).  W untimed warm-up steps, then exactly K timed steps bracketed by device
-synchronisation; per-step HIP events on the launch stream give p50 / p99 latency.
+Headline workload: 4096 tray envs (a static tray holding 20 random boxes / spheres / capsules
+dropped from random poses; 24 bodies per env; dt = 0.005 s, 8 TGS substeps), synthetic and
+seeded.  A step is one ms_step call advancing all 4096 envs by one dt: load from HBM, bounding
+boxes, candidate pairs, narrowphase, contact rows, colouring, 8 substeps of the coloured
+Gauss-Seidel solve with integration, store.  W untimed warm-up steps, then exactly K timed steps
+bracketed by device synchronisation; HIP events on the launch stream time every launch (p50 /
+p99) and the whole region.
 
-Prints one JSON line (metric, value, ...), plus the roofline of the step kernel and the CPU
-oracle timed on a bounded sample of the same workload.
+The line also carries:
+  * roofline: the step kernel against the chip's FP32 vector peak; achieved = algorithmic FLOP
+    per launch / measured launch time, the FLOP per launch from live per-env work counters
+    (candidate pairs per shape kind, contact points, manifolds, joints, bodies) times per-unit
+    FLOP counts taken from the kernel source (listed in FLOP_PER_UNIT);
+  * cpu_baseline: the float32 CPU oracle on all host threads over a bounded sample;
+  * extra: the other workloads (one box per env at 4096, the 7-link arm at 1024, the
+    heterogeneous batch against its padded form) unless --quick.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,19 +29,49 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PEAK_FP32 = 157.3e12     # MI355X FP32 vector FLOP/s (256 CUs x 2.4 GHz x 256 FLOP/clk with dual issue)
+PEAK_HBM = 8.0e12        # bytes/s
+
+# FLOP per unit (add, sub, mul, div, sqrt; compares excluded), counted in ms_step.hip.
+FLOP_PER_UNIT = {
+    "body_step": 81 + 54,       # per body per step: step-start pose + world inverse inertia + AABB
+    "static_body_step": 54,     # AABB only
+    "body_substep": 108,        # gravity, damping, integration of the offsets (dynamic bodies)
+    # narrowphase per candidate, by kind: 0 sphere-sphere, 1 sphere-capsule, 2 sphere-box,
+    # 4 capsule-capsule, 5 capsule-box, 8 box-box, 9 plane-sphere, 10 plane-capsule, 11 plane-box
+    "narrow": {0: 95, 1: 130, 2: 130, 4: 185, 5: 340, 8: 1350, 9: 45, 10: 72, 11: 222},
+    "point_prep": 104,          # normal row setup per contact point
+    "manifold_prep": 220,       # friction patch setup per manifold
+    "point_solve": 160,         # normal row per point per substep (separation, bias, impulse)
+    "manifold_solve": 250,      # two tangent rows + twist per manifold per substep
+    "point_warm": 63,           # warm start per point per substep after the first
+    "manifold_warm": 115,
+    "joint_solve": 1010,        # point block + angular block + drive per joint solve
+    "joint_warm": 300,
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ms_step.hip", "ms_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_2410_00425_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="tray")
     ap.add_argument("--envs", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time the other workloads")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
 
 
@@ -42,6 +81,7 @@ def time_batch(batch, steps, warmup, spl, targets=None):
     for _ in range(max(1, warmup // spl)):
         batch.step(spl, targets)
     torch.cuda.synchronize()
+    batch.stats(reset=True)
     n_launch = max(1, steps // spl)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch + 1)]
     torch.cuda.synchronize()
@@ -52,15 +92,58 @@ def time_batch(batch, steps, warmup, spl, targets=None):
         ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n_launch)]) / spl  # ms per step
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n_launch)])
     total_ms = ev[0].elapsed_time(ev[-1])
-    return dict(total_ms=total_ms, wall_s=wall, n_steps=n_launch * spl, p50_ms=float(np.percentile(per, 50)),
-                p99_ms=float(np.percentile(per, 99)), mean_ms=float(per.mean()))
+    st = batch.stats()
+    return dict(total_ms=total_ms, wall_s=wall, n_steps=n_launch * spl, n_launch=n_launch,
+                launch_ms=total_ms / n_launch, p50_ms=float(np.percentile(per, 50)) / spl,
+                p99_ms=float(np.percentile(per, 99)) / spl, stats=st)
+
+
+def algorithmic_flop(scene, stats, params):
+    """FLOP of the step model for the counted work (all envs, all counted steps)."""
+    import numpy as np
+    S = int(params["pos_iters"]) if int(params["solver"]) == 0 else 1
+    JI = max(1, int(params["joint_iters"]))
+    steps = stats[:, 0].astype(np.float64)
+    nb = np.diff(scene.body_off).astype(np.float64)
+    nj = np.diff(scene.joint_off).astype(np.float64)
+    static = np.add.reduceat((scene.bodies["flags"] & 1).astype(np.float64), scene.body_off[:-1])
+    dyn = nb - static
+    F = FLOP_PER_UNIT
+    f = steps * (dyn * (F["body_step"] + S * F["body_substep"]) + static * F["static_body_step"])
+    for k, c in F["narrow"].items():
+        f = f + stats[:, 1 + k] * c
+    pts, man = stats[:, 13].astype(np.float64), stats[:, 14].astype(np.float64)
+    f = f + pts * F["point_prep"] + man * F["manifold_prep"]
+    f = f + S * (pts * F["point_solve"] + man * F["manifold_solve"]) + (S - 1) * (pts * F["point_warm"] +
+                                                                                 man * F["manifold_warm"])
+    f = f + steps * nj * (S * JI * F["joint_solve"] + (S - 1) * F["joint_warm"])
+    return float(f.sum())
+
+
+def algorithmic_bytes(scene):
+    """HBM bytes per launch: state read + written (52 B per body each way), body parameters
+    (48 B), offsets (8 B per env), joints (72 B + 4 B target), status (4 B read + 4 written)."""
+    return scene.n_bodies * (52 * 2 + 48) + scene.n_envs * (8 + 8) + scene.n_joints * 76
+
+
+def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1):
+    sc = S.by_name(name, n_envs, seed=seed)
+    b = ms.Batch(sc, lanes_per_env=lanes, pack=pack)
+    r = time_batch(b, steps, warmup, spl)
+    flop = algorithmic_flop(sc, r["stats"], sc.params)
+    plan = b.plan()
+    b.close()
+    launches = r["n_launch"]
+    return sc, r, dict(workload=name, envs=n_envs, bodies=sc.n_bodies, joints=sc.n_joints,
+                       env_steps_per_s=n_envs * r["n_steps"] / (r["total_ms"] / 1e3), ms_per_step=r["total_ms"] / r["n_steps"],
+                       p50_ms=r["p50_ms"], p99_ms=r["p99_ms"], flop_per_launch=flop / launches,
+                       tflops=flop / (r["total_ms"] / 1e3) / 1e12, tiles=plan["n_tiles"], lds_bytes=plan["lds_bytes"])
 
 
 def cpu_baseline(name, seed, budget_s=15.0):
-    """The oracle (float32) on all host threads over a bounded sample of the same workload."""
-    import numpy as np
+    """The float32 oracle on all host threads over a bounded sample of the same workload."""
     from oracle.oracle import Oracle
     from paper_2410_00425_amd import scenes as S
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -68,39 +151,73 @@ def cpu_baseline(name, seed, budget_s=15.0):
     n_env = 256
     sc = S.by_name(name, n_env, seed=seed)
     o = Oracle(sc, 32)
-    o.step(5, n_threads=threads)  # warm
+    o.step(40, n_threads=threads)  # same warm-up as the GPU run
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
         o.step(5, n_threads=threads)
         steps += 5
     dt = time.perf_counter() - t0
     return dict(value=n_env * steps / dt, unit="env-steps/s", cores=threads, kind="oracle",
-                sample=f"{n_env} {name} envs x {steps} steps (float32 oracle, {threads} threads, {dt:.1f} s)")
+                sample=f"{n_env} {name} envs x {steps} steps after 40 warm-up steps (float32 oracle, "
+                       f"{threads} threads, {dt:.1f} s)")
+
+
+def traffic_from_profile(name):
+    """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("kernel_source") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU: the step has no cross-GPU work; "
-                                   "--gpus above 1 is not supported"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU (the batched step has no cross-GPU work); "
+                                   f"--gpus {args.gpus} is not supported"}), flush=True)
         sys.exit(2)
     import torch
     from paper_2410_00425_amd import ms, scenes as S
     torch.cuda.init()
-    sc = S.by_name(args.workload, args.envs, seed=args.seed)
-    b = ms.Batch(sc, lanes_per_env=args.lanes)
-    r = time_batch(b, args.steps, args.warmup, args.steps_per_launch)
-    value = sc.n_envs * r["n_steps"] / (r["total_ms"] / 1e3)
+    sc, r, head = run_workload(ms, S, args.workload, args.envs, args.steps, args.warmup, args.steps_per_launch,
+                               args.seed, args.lanes)
+    value = head["env_steps_per_s"]
+    achieved = head["flop_per_launch"] / (r["launch_ms"] / 1e3)
     out = {
         "metric": "env-steps/sec at 4096 envs (plain vs batched/served); p50/p99 step latency",
         "value": value, "unit": "env-steps/s", "n_gpus": 1, "steps": r["n_steps"], "warmup": args.warmup,
         "ms_per_step": r["total_ms"] / r["n_steps"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {sc.n_envs} envs, {sc.n_bodies // sc.n_envs} bodies/env",
-                   "steps_per_launch": args.steps_per_launch, "plan": {k: v for k, v in b.plan().items()
-                                                                        if k != "lanes"}},
+        "config": {"workload": f"{args.workload} x {sc.n_envs} envs ({sc.n_bodies // sc.n_envs} bodies/env), "
+                               f"dt {float(sc.params['dt'])}, {int(sc.params['pos_iters'])} TGS substeps, "
+                               f"{args.steps_per_launch} step(s) per launch",
+                   "envs": sc.n_envs, "bodies": sc.n_bodies, "tiles": head["tiles"], "lds_bytes": head["lds_bytes"]},
         "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": traffic_from_profile(args.workload),
+                     "flop_per_launch": head["flop_per_launch"], "launch_ms": r["launch_ms"],
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(sc),
+                     "hbm_frac": algorithmic_bytes(sc) / (r["launch_ms"] / 1e3) / PEAK_HBM,
+                     "kernel_source": kernel_source_hash()},
     }
+    if args.copy_calibration:
+        n = 64 << 20
+        x = torch.empty(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
+    if not args.quick:
+        extra = {}
+        for name, n in (("drop_boxes", 4096), ("arm_cube", 1024), ("hetero", 4096), ("hetero_padded", 4096)):
+            _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed)
+            extra[name] = res
+        extra["hetero_speedup_vs_padded"] = extra["hetero"]["env_steps_per_s"] / extra["hetero_padded"]["env_steps_per_s"]
+        out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
     print(json.dumps(out), flush=True)

@@ -198,6 +198,13 @@ ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, f
 ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds_bytes,
                       int32_t* host_env_lanes);
 
+/* Work counters accumulated by every step since the last reset, int64 [n_envs][16]: steps,
+ * candidate pairs per shape kind (12 kinds: 3 * min + max of the two shapes for body pairs,
+ * 9 + shape for plane pairs; sphere 0, capsule 1, box 2), contact points, manifolds, colours
+ * (summed over steps).  host_stats may be NULL; reset != 0 zeroes the counters.  Synchronises
+ * `hip_stream`. */
+ms_status ms_get_stats(ms_batch* b, int64_t* host_stats, int32_t reset, void* hip_stream);
+
 ms_status ms_destroy_batch(ms_batch* b);
 
 /* Fused step over several batches in one launch (the serving path): the env tiles of every

@@ -47,7 +47,13 @@ struct BatchDev {
     float* dbg_man;        // [sum mcap_e][8]: pair index, colour, lt1, lt2, ltw, mu, rt, count
     const int* dbg_man_off;
     int* dbg_counts;       // [E][4]: candidates, points, manifolds, colours
+    // work counters, accumulated over launches: [E][NSTAT] (see STAT_*)
+    int* stats;
 };
+
+// Work counters per env: steps, candidate pairs per shape kind (3 * min + max shape for body
+// pairs, 9 + shape for plane pairs), contact points, manifolds, colours.
+enum { STAT_STEPS = 0, STAT_KIND0 = 1, STAT_POINTS = 13, STAT_MANIFOLDS = 14, STAT_COLOURS = 15, NSTAT = 16 };
 
 // One env slot of a tile (host-computed).
 struct TileEnv {
@@ -110,7 +116,7 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     L.SCHED = o; o += nj + mcap + 66;
     L.JSCHED = o; o += nj + mcap + 66;
     L.CSTART = o; o += 68;
-    L.SCAL = o; o += 16;
+    L.SCAL = o; o += 32;  // 16 scalars + 16 work counters
     L.total = (o + 3) & ~3;
     return L;
 }

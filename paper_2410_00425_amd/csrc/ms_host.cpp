@@ -75,7 +75,7 @@ struct Plan {
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
     size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, status, bpar, body_off, joint_off, jrec, targets, tiles,
-        tenv, bd, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
+        tenv, bd, stats, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
 
 ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
@@ -191,6 +191,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.tiles = take(pl.tiles.size() * sizeof(Tile));
     L.tenv = take(pl.tenv.size() * sizeof(TileEnv));
     L.bd = take(sizeof(BatchDev));
+    L.stats = take(E * NSTAT * 4);
     if (p->debug_export) {
         L.dbg_pairs = take(size_t(pl.dbg_pair_off[E]) * 16);
         L.dbg_pair_off = take((E + 1) * 4);
@@ -280,6 +281,7 @@ void fill_batchdev(ms_batch* b) {
     d.plane = p.plane_enabled ? 1 : 0;
     d.beta = p.baumgarte; d.max_depen = p.max_depen_vel; d.beta_j = p.joint_baumgarte; d.bounce = p.bounce_threshold;
     d.lin_damp = p.lin_damping; d.ang_damp = p.ang_damping;
+    d.stats = at<int>(w, L.stats);
     if (p.debug_export) {
         d.dbg_pairs = at<int>(w, L.dbg_pairs); d.dbg_pair_off = at<int>(w, L.dbg_pair_off);
         d.dbg_pts = at<float>(w, L.dbg_pts); d.dbg_pt_off = at<int>(w, L.dbg_pt_off);
@@ -314,10 +316,10 @@ int ms_selfcheck(void) {
                     Lay L = make_lay(n, nj, cap, mcap);
                     int ends[] = {L.JM + 2 * n, L.JNT + 26 * nj, L.CAND + (P + 1) / 2, L.PT + 14 * cap,
                                   L.MAN + 22 * mcap, L.BCOL + (nj + mcap + 1) / 2, L.ORDER + (nj + mcap + 1) / 2,
-                                  L.SCHED + nj + mcap + 66, L.JSCHED + nj + mcap + 66, L.CSTART + 68, L.SCAL + 16};
+                                  L.SCHED + nj + mcap + 66, L.JSCHED + nj + mcap + 66, L.CSTART + 68, L.SCAL + 32};
                     for (int e : ends)
                         if (e > L.total) return 3;
-                    if (L.SCAL + 16 > L.total || (L.total & 3)) return 4;
+                    if (L.SCAL + 32 > L.total || (L.total & 3)) return 4;
                 }
     }
     return 0;
@@ -434,6 +436,8 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     if (e == hipSuccess) e = up(L.ivel, &hs[7 * B], p3);
     if (e == hipSuccess) e = up(L.iang, &hs[10 * B], p3);
     if (e == hipSuccess) e = up(L.status, zeros.data(), E * 4);
+    std::vector<int> zstats(E * NSTAT, 0);
+    if (e == hipSuccess) e = up(L.stats, zstats.data(), E * NSTAT * 4);
     if (e == hipSuccess) e = up(L.bpar, bp.data(), 3 * B * 16);
     if (e == hipSuccess) e = up(L.body_off, b->body_off.data(), (E + 1) * 4);
     if (e == hipSuccess) e = up(L.joint_off, b->joint_off.data(), (E + 1) * 4);
@@ -581,6 +585,23 @@ ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, f
     if (n_pairs) *n_pairs = np;
     if (n_points) *n_points = npt;
     if (n_manifolds) *n_manifolds = nm;
+    return MS_OK;
+}
+
+ms_status ms_get_stats(ms_batch* b, int64_t* host_stats, int32_t reset, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_OK(hipStreamSynchronize(s));
+    const size_t n = size_t(b->E) * NSTAT;
+    if (host_stats) {
+        std::vector<int> tmp(n);
+        HIP_OK(hipMemcpy(tmp.data(), b->hbd.stats, n * 4, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < n; ++k) host_stats[k] = tmp[k];
+    }
+    if (reset) {
+        std::vector<int> z(n, 0);
+        HIP_OK(hipMemcpy(b->hbd.stats, z.data(), n * 4, hipMemcpyHostToDevice));
+    }
     return MS_OK;
 }
 

@@ -1096,6 +1096,7 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
             J[J_TG] = bd.targets[c.j0 + j];
         }
         if (c.active && li == 0) SC[SC_STATUS] = bd.status[c.env];
+        for (int k = li; k < (c.active ? NSTAT : 0); k += G) SC[16 + k] = 0;
         __syncthreads();
         // jointed-partner masks (parent-child pairs never collide)
         for (int i = li; i < nA; i += G) {
@@ -1202,6 +1203,16 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
                         a = code & 0xFF;
                         b = code >> 8;
                         plane = b == n;
+                        {
+                            int sa = iptr(c.L + l.SH)[a] & 0xFF;
+                            int kind;
+                            if (plane) kind = 9 + sa;
+                            else {
+                                int sb2 = iptr(c.L + l.SH)[b] & 0xFF;
+                                kind = 3 * min(sa, sb2) + max(sa, sb2);
+                            }
+                            atomicAdd(&SC[16 + STAT_KIND0 + kind], 1);
+                        }
                         V3 xa = ld3(c.L, l.X0, n, a);
                         if (plane) {
                             Shp sb = shape_of(c, a, v3(0.0f, 0.0f, xa.z - bd.plane_z));
@@ -1304,11 +1315,17 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
                 SC[SC_NPTS] = npts;
                 SC[SC_NMAN] = nman;
                 if (overflow) SC[SC_STATUS] |= 2;
+                SC[16 + STAT_STEPS] += 1;
+                SC[16 + STAT_POINTS] += npts;
+                SC[16 + STAT_MANIFOLDS] += nman;
             }
             __syncthreads();
 
             // --------------------------------------------------------- S5 colouring
-            if (!frozen && li == 0) colour_env(c, G);
+            if (!frozen && li == 0) {
+                colour_env(c, G);
+                SC[16 + STAT_COLOURS] += SC[SC_NCOL];
+            }
             __syncthreads();
             const int ns = frozen ? 0 : SC[SC_NSCHED];
             const int njs = frozen ? 0 : SC[SC_NJSCHED];
@@ -1398,6 +1415,7 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
             for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = c.L[l.W + r * n + i];
         }
         if (c.active && li == 0) bd.status[c.env] = SC[SC_STATUS];
+        for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += SC[16 + k];
         __syncthreads();
     }
 }

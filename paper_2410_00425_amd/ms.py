@@ -60,6 +60,7 @@ _sig = {
     "ms_get_sizes": [_P, _P, _P, _P],
     "ms_get_plan": [_P, _P, _P, _P, _P],
     "ms_get_contacts": [_P, _P, _I, _P, _I, _P, _I, _P, _P, _P, _P],
+    "ms_get_stats": [_P, _P, _I, _P],
     "ms_destroy_batch": [_P],
 }
 for _name, _args in _sig.items():
@@ -208,6 +209,12 @@ class Batch:
         _check(_lib.ms_get_contacts(self._h, pairs.ctypes.data, np_, pts.ctypes.data, npt, mans.ctypes.data, nm,
                                     *[C.byref(x) for x in n], _stream(stream)))
         return dict(pairs=pairs, points=pts, manifolds=mans)
+
+    def stats(self, reset=False, stream=None):
+        """ms_get_stats: int64 [E, 16] work counters accumulated since the last reset."""
+        out = np.zeros((self.n_envs, 16), np.int64)
+        _check(_lib.ms_get_stats(self._h, out.ctypes.data, 1 if reset else 0, _stream(stream)))
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
