@@ -198,6 +198,16 @@ ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, f
 ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds_bytes,
                       int32_t* host_env_lanes);
 
+/* LDS classes of the launch plan: *n_classes and, per class, int32 {tiles, LDS bytes per
+ * workgroup, kernel variant (0 unconstrained, 1 two waves per SIMD), lanes per env, first tile}
+ * into host_classes (may be NULL). */
+ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes);
+
+/* Autotuner: for every LDS class, time each kernel variant over trial_steps launches of that
+ * class alone and keep the fastest.  The batch's state, status and work counters are saved
+ * before and restored after (the trial steps leave no trace).  Synchronises `hip_stream`. */
+ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream);
+
 /* Work counters accumulated by every step since the last reset, int64 [n_envs][16]: steps,
  * candidate pairs per shape kind (12 kinds: 3 * min + max of the two shapes for body pairs,
  * 9 + shape for plane pairs; sphere 0, capsule 1, box 2), contact points, manifolds, colours

@@ -18,6 +18,8 @@ using namespace msdev;
 
 extern "C" __global__ void ms_step_kernel(const BatchDev* batches, const Tile* tiles, int n_tiles, const TileEnv* tenv,
                                           int n_steps);
+extern "C" __global__ void ms_step_kernel_w2(const BatchDev* batches, const Tile* tiles, int n_tiles,
+                                             const TileEnv* tenv, int n_steps);
 extern "C" __global__ void ms_reset_kernel(BatchDev bd, const int* env_ids, int n_ids, const float* spos,
                                            const float* squat, const float* svel, const float* sang);
 
@@ -45,6 +47,8 @@ ms_status fail(ms_status s, const char* fmt, ...) {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
+constexpr int MAX_CLASSES = 4;
+
 // Per-env sizes used by the planner.
 struct EnvInfo {
     int n, nj, n_dyn, cap, mcap, words, lanes;
@@ -63,10 +67,21 @@ int pick_lanes(const EnvInfo& e, int forced, int tile_budget_words) {
     return G;
 }
 
+// Tiles of one LDS class run in one launch whose dynamic LDS is the class maximum.
+struct LdsClass {
+    int first_tile, n_tiles, lds_words;
+    int variant;  // 0: ms_step_kernel, 1: ms_step_kernel_w2 (two waves per SIMD)
+    int lanes;    // lanes per env of the class's first tile
+};
+
+typedef void (*StepKernel)(const BatchDev*, const Tile*, int, const TileEnv*, int);
+inline StepKernel kernel_of(int variant) { return variant == 1 ? ms_step_kernel_w2 : ms_step_kernel; }
+
 struct Plan {
     std::vector<EnvInfo> info;
-    std::vector<Tile> tiles;
+    std::vector<Tile> tiles;  // ordered by LDS class, largest first
     std::vector<TileEnv> tenv;
+    std::vector<LdsClass> classes;
     int max_tile_words = 0;
     // debug offsets
     std::vector<int> dbg_pair_off, dbg_pt_off, dbg_man_off;
@@ -74,7 +89,7 @@ struct Plan {
 
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
-    size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, status, bpar, body_off, joint_off, jrec, targets, tiles,
+    size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, save, status, bpar, body_off, joint_off, jrec, targets, tiles,
         tenv, bd, stats, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
 
@@ -163,6 +178,18 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
         cur.count++;
     }
     if (cur.count > 0) out.tiles.push_back(cur);
+    // LDS classes: tiles sorted by LDS need (largest first, stable); a new class starts when a
+    // tile needs less than 2/3 of the class maximum, at most MAX_CLASSES classes.
+    std::stable_sort(out.tiles.begin(), out.tiles.end(),
+                     [](const Tile& a, const Tile& b) { return a.lds_words > b.lds_words; });
+    out.classes.clear();
+    for (int t = 0; t < int(out.tiles.size()); ++t) {
+        const Tile& tl = out.tiles[t];
+        bool split = !out.classes.empty() && 3 * tl.lds_words < 2 * out.classes.back().lds_words &&
+                     int(out.classes.size()) < MAX_CLASSES && (plan == nullptr || plan->pack != 0);
+        if (out.classes.empty() || split) out.classes.push_back(LdsClass{t, 0, tl.lds_words, tl.lanes == 64 ? 1 : 0, tl.lanes});
+        out.classes.back().n_tiles++;
+    }
     for (const Tile& t : out.tiles) out.max_tile_words = std::max(out.max_tile_words, t.lds_words);
     out.dbg_pair_off.assign(E + 1, 0);
     out.dbg_pt_off.assign(E + 1, 0);
@@ -182,6 +209,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + std::max<size_t>(bytes, 4)); return r; };
     L.pos = take(3 * B * 4); L.quat = take(4 * B * 4); L.vel = take(3 * B * 4); L.angvel = take(3 * B * 4);
     L.ipos = take(3 * B * 4); L.iquat = take(4 * B * 4); L.ivel = take(3 * B * 4); L.iang = take(3 * B * 4);
+    L.save = take(13 * B * 4 + E * 4);
     L.status = take(E * 4);
     L.bpar = take(3 * B * 16);
     L.body_off = take((E + 1) * 4);
@@ -254,6 +282,17 @@ struct ms_batch {
     int device = 0;
     int grid = 0;
     size_t lds_bytes = 0;
+    // fork / join streams for LDS classes after the first (default priority)
+    hipStream_t side[MAX_CLASSES] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[MAX_CLASSES] = {};
+    ~ms_batch() {
+        for (int k = 0; k < MAX_CLASSES; ++k) {
+            if (side[k]) (void)hipStreamDestroy(side[k]);
+            if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+    }
 };
 
 namespace {
@@ -471,10 +510,38 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     if (dev_targets && b->J > 0)
         HIP_OK(hipMemcpyAsync(const_cast<float*>(b->hbd.targets), dev_targets, size_t(b->J) * 4, hipMemcpyDeviceToDevice, s));
-    const int n_tiles = int(b->plan.tiles.size());
-    hipLaunchKernelGGL(ms_step_kernel, dim3(b->grid), dim3(WAVE), b->lds_bytes, s, b->dbd,
-                       at<Tile>(b->ws, b->lay.tiles), n_tiles, at<TileEnv>(b->ws, b->lay.tenv), int(n_steps));
-    HIP_OK(hipGetLastError());
+    const std::vector<LdsClass>& cls = b->plan.classes;
+    const Tile* tiles = at<Tile>(b->ws, b->lay.tiles);
+    const TileEnv* tenv = at<TileEnv>(b->ws, b->lay.tenv);
+    if (cls.size() == 1) {
+        hipLaunchKernelGGL(kernel_of(cls[0].variant), dim3(b->grid), dim3(WAVE), b->lds_bytes, s, b->dbd, tiles,
+                           int(b->plan.tiles.size()), tenv, int(n_steps));
+        HIP_OK(hipGetLastError());
+        return MS_OK;
+    }
+    // one launch per LDS class: the largest class on the caller's stream, the others on side
+    // streams forked from and joined back into it
+    if (!b->ev_fork) {
+        HIP_OK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        for (size_t k = 1; k < cls.size(); ++k) {
+            HIP_OK(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+        }
+    }
+    HIP_OK(hipEventRecord(b->ev_fork, s));
+    for (size_t k = 0; k < cls.size(); ++k) {
+        hipStream_t sk = k == 0 ? s : b->side[k];
+        if (k > 0) HIP_OK(hipStreamWaitEvent(sk, b->ev_fork, 0));
+        int grid = cls[k].n_tiles;
+        if (b->grid < int(b->plan.tiles.size())) grid = std::max(1, std::min(grid, b->grid));
+        hipLaunchKernelGGL(kernel_of(cls[k].variant), dim3(grid), dim3(WAVE), size_t(cls[k].lds_words) * 4, sk, b->dbd,
+                           tiles + cls[k].first_tile, cls[k].n_tiles, tenv, int(n_steps));
+        HIP_OK(hipGetLastError());
+        if (k > 0) {
+            HIP_OK(hipEventRecord(b->ev_join[k], sk));
+            HIP_OK(hipStreamWaitEvent(s, b->ev_join[k], 0));
+        }
+    }
     return MS_OK;
 }
 
@@ -522,6 +589,18 @@ ms_status ms_get_sizes(ms_batch* b, int32_t* n_envs, int32_t* n_bodies, int32_t*
     if (n_envs) *n_envs = b->E;
     if (n_bodies) *n_bodies = b->B;
     if (n_joints) *n_joints = b->J;
+    return MS_OK;
+}
+
+ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (n_classes) *n_classes = int(b->plan.classes.size());
+    if (host_classes)
+        for (size_t k = 0; k < b->plan.classes.size(); ++k) {
+            const LdsClass& c = b->plan.classes[k];
+            int32_t* o = host_classes + 5 * k;
+            o[0] = c.n_tiles; o[1] = c.lds_words * 4; o[2] = c.variant; o[3] = c.lanes; o[4] = c.first_tile;
+        }
     return MS_OK;
 }
 
@@ -585,6 +664,59 @@ ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, f
     if (n_pairs) *n_pairs = np;
     if (n_points) *n_points = npt;
     if (n_manifolds) *n_manifolds = nm;
+    return MS_OK;
+}
+
+ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (trial_steps < 1 || trial_steps > 1000) return fail(MS_E_INVALID_ARG, "trial_steps out of range [1, 1000]");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t B = b->B, E = b->E;
+    char* w = b->ws;
+    const WsLayout& L = b->lay;
+    // save the state (and status, stats) so that tuning leaves no trace
+    const size_t st_bytes[4] = {3 * B * 4, 4 * B * 4, 3 * B * 4, 3 * B * 4};
+    const size_t st_off[4] = {L.pos, L.quat, L.vel, L.angvel};
+    size_t o = L.save;
+    for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + o, w + st_off[k], st_bytes[k], hipMemcpyDeviceToDevice, s)); o += st_bytes[k]; }
+    HIP_OK(hipMemcpyAsync(w + o, w + L.status, E * 4, hipMemcpyDeviceToDevice, s));
+    std::vector<int> stats_save(E * NSTAT);
+    HIP_OK(hipMemcpyAsync(stats_save.data(), w + L.stats, E * NSTAT * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const Tile* tiles = at<Tile>(w, L.tiles);
+    const TileEnv* tenv = at<TileEnv>(w, L.tenv);
+    for (LdsClass& c : b->plan.classes) {
+        float best = 1e30f;
+        int best_v = c.variant;
+        for (int v = 0; v < 2; ++v) {
+            // restore, one untimed launch, then trial_steps timed launches of this class alone
+            size_t oo = L.save;
+            for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + st_off[k], w + oo, st_bytes[k], hipMemcpyDeviceToDevice, s)); oo += st_bytes[k]; }
+            hipLaunchKernelGGL(kernel_of(v), dim3(c.n_tiles), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
+                               tiles + c.first_tile, c.n_tiles, tenv, 1);
+            HIP_OK(hipEventRecord(e0, s));
+            for (int t = 0; t < trial_steps; ++t)
+                hipLaunchKernelGGL(kernel_of(v), dim3(c.n_tiles), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
+                                   tiles + c.first_tile, c.n_tiles, tenv, 1);
+            HIP_OK(hipGetLastError());
+            HIP_OK(hipEventRecord(e1, s));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_v = v; }
+        }
+        c.variant = best_v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    o = L.save;
+    for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + st_off[k], w + o, st_bytes[k], hipMemcpyDeviceToDevice, s)); o += st_bytes[k]; }
+    HIP_OK(hipMemcpyAsync(w + L.status, w + o, E * 4, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(w + L.stats, stats_save.data(), E * NSTAT * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
     return MS_OK;
 }
 

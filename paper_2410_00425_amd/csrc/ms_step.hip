@@ -587,27 +587,6 @@ __device__ __forceinline__ float invm_of(const EnvCtx& c, int i) { return i < 0 
 __device__ __forceinline__ V3 v_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.V, c.lay.n, i); }
 __device__ __forceinline__ V3 w_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.W, c.lay.n, i); }
 
-// Apply impulse P at arms rA, rB: -P on A, +P on B (dynamic bodies only).
-__device__ __forceinline__ void apply_lin(const EnvCtx& c, int a, int b, V3 rA, V3 rB, V3 P) {
-    int n = c.lay.n;
-    if (is_dyn(c, a)) {
-        float im = c.L[c.lay.INVM + a];
-        S6 I = load_iw(c, a);
-        st3(c.L, c.lay.V, n, a, ld3(c.L, c.lay.V, n, a) - im * P);
-        st3(c.L, c.lay.W, n, a, ld3(c.L, c.lay.W, n, a) - muls(I, cross3(rA, P)));
-    }
-    if (is_dyn(c, b)) {
-        float im = c.L[c.lay.INVM + b];
-        S6 I = load_iw(c, b);
-        st3(c.L, c.lay.V, n, b, ld3(c.L, c.lay.V, n, b) + im * P);
-        st3(c.L, c.lay.W, n, b, ld3(c.L, c.lay.W, n, b) + muls(I, cross3(rB, P)));
-    }
-}
-__device__ __forceinline__ void apply_ang(const EnvCtx& c, int a, int b, V3 Lv) {
-    int n = c.lay.n;
-    if (is_dyn(c, a)) st3(c.L, c.lay.W, n, a, ld3(c.L, c.lay.W, n, a) - muls(load_iw(c, a), Lv));
-    if (is_dyn(c, b)) st3(c.L, c.lay.W, n, b, ld3(c.L, c.lay.W, n, b) + muls(load_iw(c, b), Lv));
-}
 __device__ __forceinline__ float eff_mass(const EnvCtx& c, int a, int b, V3 rA, V3 rB, V3 x) {
     float k = invm_of(c, a) + invm_of(c, b);
     if (a >= 0) { V3 cr = cross3(rA, x); k += dot3(cr, muls(load_iw(c, a), cr)); }
@@ -623,14 +602,6 @@ __device__ __forceinline__ Shp shape_of(const EnvCtx& c, int i, V3 centre) {
     s.R = rotm(ld4(c.L, l.Q0, l.n, i));
     s.d[0] = c.L[l.DIM + i]; s.d[1] = c.L[l.DIM + l.n + i]; s.d[2] = c.L[l.DIM + 2 * l.n + i];
     return s;
-}
-
-// Displacement of the body-fixed point x0 + r since the step start: dx + R(dq) r - r.
-__device__ __forceinline__ V3 point_disp(const EnvCtx& c, int i, V3 r) {
-    Qt d = ld4(c.L, c.lay.DQ, c.lay.n, i);
-    V3 u = v3(d.x, d.y, d.z);
-    V3 ur = cross3(u, r);
-    return ld3(c.L, c.lay.DX, c.lay.n, i) + (2.0f * d.w) * ur + 2.0f * cross3(u, ur);
 }
 
 // ----------------------------------------------------------------------------- manifold block
@@ -653,15 +624,75 @@ __device__ __forceinline__ void man_header(const EnvCtx& c, int m, int& a, int& 
     cnt = fc >> 16;
 }
 
+// A block owns its dynamic bodies for the duration of its colour, so a lane keeps the two bodies
+// of its block in registers for the whole block solve and writes them back once.
+struct BodyR {
+    V3 v, w;
+    float im;
+    S6 I;
+    bool dyn;
+};
+struct PoseR {
+    V3 dx;
+    Qt dq;
+};
+__device__ __forceinline__ BodyR load_body(const EnvCtx& c, int i) {
+    BodyR r;
+    if (i < 0) {
+        r.v = v3(0, 0, 0); r.w = v3(0, 0, 0); r.im = 0.0f; r.I = S6{0, 0, 0, 0, 0, 0}; r.dyn = false;
+        return r;
+    }
+    const int n = c.lay.n;
+    r.v = ld3(c.L, c.lay.V, n, i);
+    r.w = ld3(c.L, c.lay.W, n, i);
+    r.im = c.L[c.lay.INVM + i];
+    r.I = load_iw(c, i);
+    r.dyn = is_dyn(c, i);
+    return r;
+}
+__device__ __forceinline__ void store_body(const EnvCtx& c, int i, const BodyR& r) {
+    if (!r.dyn) return;
+    const int n = c.lay.n;
+    st3(c.L, c.lay.V, n, i, r.v);
+    st3(c.L, c.lay.W, n, i, r.w);
+}
+__device__ __forceinline__ PoseR load_pose(const EnvCtx& c, int i) {
+    if (i < 0) return PoseR{v3(0, 0, 0), Qt{1.0f, 0.0f, 0.0f, 0.0f}};
+    return PoseR{ld3(c.L, c.lay.DX, c.lay.n, i), ld4(c.L, c.lay.DQ, c.lay.n, i)};
+}
+// -P on A at arm rA, +P on B at arm rB (dynamic bodies only).
+__device__ __forceinline__ void imp_lin(BodyR& A, BodyR& B, V3 rA, V3 rB, V3 P) {
+    if (A.dyn) { A.v = A.v - A.im * P; A.w = A.w - muls(A.I, cross3(rA, P)); }
+    if (B.dyn) { B.v = B.v + B.im * P; B.w = B.w + muls(B.I, cross3(rB, P)); }
+}
+__device__ __forceinline__ void imp_ang(BodyR& A, BodyR& B, V3 L) {
+    if (A.dyn) A.w = A.w - muls(A.I, L);
+    if (B.dyn) B.w = B.w + muls(B.I, L);
+}
+__device__ __forceinline__ V3 relv(const BodyR& A, const BodyR& B, bool has_a, V3 rA, V3 rB) {
+    V3 vb = B.v + cross3(B.w, rB);
+    V3 va = has_a ? A.v + cross3(A.w, rA) : v3(0, 0, 0);
+    return vb - va;
+}
+// Displacement of the body-fixed point x0 + r since the step start: dx + R(dq) r - r.
+__device__ __forceinline__ V3 disp(const PoseR& p, V3 r) {
+    V3 u = v3(p.dq.x, p.dq.y, p.dq.z);
+    V3 ur = cross3(u, r);
+    return p.dx + (2.0f * p.dq.w) * ur + 2.0f * cross3(u, ur);
+}
+
 __device__ void manifold_warm(const EnvCtx& c, int m) {
     int a, b, first, cnt;
     man_header(c, m, a, b, first, cnt);
+    BodyR A = load_body(c, a), B = load_body(c, b);
     for (int k = first; k < first + cnt; ++k)
-        apply_lin(c, a, b, pr3(c, R_RA, k), pr3(c, R_RB, k), pr(c, R_LN, k) * pr3(c, R_N, k));
+        imp_lin(A, B, pr3(c, R_RA, k), pr3(c, R_RB, k), pr(c, R_LN, k) * pr3(c, R_N, k));
     V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m);
     V3 t2 = cross3(nb, t1);
-    apply_lin(c, a, b, mf3(c, M_RA, m), mf3(c, M_RB, m), mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * t2);
-    apply_ang(c, a, b, mf(c, M_LTW, m) * nb);
+    imp_lin(A, B, mf3(c, M_RA, m), mf3(c, M_RB, m), mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * t2);
+    imp_ang(A, B, mf(c, M_LTW, m) * nb);
+    store_body(c, a, A);
+    store_body(c, b, B);
 }
 
 __device__ __forceinline__ V3 rel_vel(const EnvCtx& c, int a, int b, V3 rA, V3 rB) {
@@ -674,64 +705,77 @@ __device__ void manifold_solve(const EnvCtx& c, int m, float h, bool vpass) {
     const BatchDev& bd = *c.bd;
     int a, b, first, cnt;
     man_header(c, m, a, b, first, cnt);
+    const bool has_a = a >= 0;
+    BodyR A = load_body(c, a), B = load_body(c, b);
+    PoseR pA = load_pose(c, a), pB = load_pose(c, b);
     float lsum = 0.0f;
     for (int k = first; k < first + cnt; ++k) {
         V3 rA = pr3(c, R_RA, k), rB = pr3(c, R_RB, k), n = pr3(c, R_N, k);
-        V3 dA = a >= 0 ? point_disp(c, a, rA) : v3(0, 0, 0);
-        V3 dB = point_disp(c, b, rB);
+        V3 dA = has_a ? disp(pA, rA) : v3(0, 0, 0);
+        V3 dB = disp(pB, rB);
         float s = pr(c, R_S0, k) + dot3(n, dB - dA);
         float bias;
         if (s > 0.0f) bias = s / h;
         else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
-        float vn = dot3(rel_vel(c, a, b, rA, rB), n);
+        float vn = dot3(relv(A, B, has_a, rA, rB), n);
         float dl = -pr(c, R_MN, k) * (vn + bias);
         float old = pr(c, R_LN, k);
         float nl = fmaxf(old + dl, 0.0f);
         pr(c, R_LN, k) = nl;
-        apply_lin(c, a, b, rA, rB, (nl - old) * n);
+        imp_lin(A, B, rA, rB, (nl - old) * n);
         lsum += nl;
     }
     float lim = mf(c, M_MU, m) * lsum;
     V3 rA = mf3(c, M_RA, m), rB = mf3(c, M_RB, m), nb = mf3(c, M_NB, m), t1 = mf3(c, M_T1, m);
     V3 t2 = cross3(nb, t1);
     {
-        float vt = dot3(rel_vel(c, a, b, rA, rB), t1);
+        float vt = dot3(relv(A, B, has_a, rA, rB), t1);
         float old = mf(c, M_LT1, m);
         float nl = fminf(fmaxf(old - mf(c, M_MT1, m) * vt, -lim), lim);
         mfr(c, M_LT1, m) = nl;
-        apply_lin(c, a, b, rA, rB, (nl - old) * t1);
+        imp_lin(A, B, rA, rB, (nl - old) * t1);
     }
     {
-        float vt = dot3(rel_vel(c, a, b, rA, rB), t2);
+        float vt = dot3(relv(A, B, has_a, rA, rB), t2);
         float old = mf(c, M_LT2, m);
         float nl = fminf(fmaxf(old - mf(c, M_MT2, m) * vt, -lim), lim);
         mfr(c, M_LT2, m) = nl;
-        apply_lin(c, a, b, rA, rB, (nl - old) * t2);
+        imp_lin(A, B, rA, rB, (nl - old) * t2);
     }
     {
         float limw = mf(c, M_RT, m) * lim;
-        float wr = dot3(nb, w_of(c, b) - w_of(c, a));
+        float wr = dot3(nb, B.w - A.w);
         float old = mf(c, M_LTW, m);
         float nl = fminf(fmaxf(old - mf(c, M_MTW, m) * wr, -limw), limw);
         mfr(c, M_LTW, m) = nl;
-        apply_ang(c, a, b, (nl - old) * nb);
+        imp_ang(A, B, (nl - old) * nb);
     }
+    store_body(c, a, A);
+    store_body(c, b, B);
 }
 
 __device__ void manifold_restitution(const EnvCtx& c, int m) {
     const BatchDev& bd = *c.bd;
     int a, b, first, cnt;
     man_header(c, m, a, b, first, cnt);
+    const bool has_a = a >= 0;
+    BodyR A = load_body(c, a), B = load_body(c, b);
+    bool any = false;
     for (int k = first; k < first + cnt; ++k) {
         float vpre = pr(c, R_VN, k);
         float old = pr(c, R_LN, k);
         if (!(vpre < -bd.bounce && old > 0.0f)) continue;
+        any = true;
         V3 rA = pr3(c, R_RA, k), rB = pr3(c, R_RB, k), n = pr3(c, R_N, k);
-        float vn = dot3(rel_vel(c, a, b, rA, rB), n);
+        float vn = dot3(relv(A, B, has_a, rA, rB), n);
         float dl = -pr(c, R_MN, k) * (vn + pr(c, R_E, k) * vpre);
         float nl = fmaxf(old + dl, 0.0f);
         pr(c, R_LN, k) = nl;
-        apply_lin(c, a, b, rA, rB, (nl - old) * n);
+        imp_lin(A, B, rA, rB, (nl - old) * n);
+    }
+    if (any) {
+        store_body(c, a, A);
+        store_body(c, b, B);
     }
 }
 
@@ -762,7 +806,7 @@ __device__ __forceinline__ float atan2_w(float y, float w) {
     return y < 0.0f ? -a : a;
 }
 
-struct JFrame { int a, b; V3 rA, rB, zA, b1, b2; };
+struct JFrame { int a, b; V3 rA, rB, zA, b1, b2; Qt qa, qb; };
 __device__ __forceinline__ float* jrec(const EnvCtx& c, int j) { return c.L + c.lay.JNT + J_WORDS * j; }
 __device__ __forceinline__ V3 x_of(const EnvCtx& c, int i) {
     return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.X0, c.lay.n, i) + ld3(c.L, c.lay.DX, c.lay.n, i);
@@ -776,10 +820,11 @@ __device__ JFrame joint_frame(const EnvCtx& c, int j) {
     JFrame f;
     f.a = reinterpret_cast<const int*>(J)[J_PA];
     f.b = reinterpret_cast<const int*>(J)[J_CH];
-    Qt qa = qc_of(c, f.a), qb = qc_of(c, f.b);
-    f.rA = mulv(rotm(qa), v3(J[J_AA], J[J_AA + 1], J[J_AA + 2]));
-    f.rB = mulv(rotm(qb), v3(J[J_AB], J[J_AB + 1], J[J_AB + 2]));
-    M3 Ra = rotm(qmul(qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]}));
+    f.qa = qc_of(c, f.a);
+    f.qb = qc_of(c, f.b);
+    f.rA = mulv(rotm(f.qa), v3(J[J_AA], J[J_AA + 1], J[J_AA + 2]));
+    f.rB = mulv(rotm(f.qb), v3(J[J_AB], J[J_AB + 1], J[J_AB + 2]));
+    M3 Ra = rotm(qmul(f.qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]}));
     f.zA = colm(Ra, 2); f.b1 = colm(Ra, 0); f.b2 = colm(Ra, 1);
     return f;
 }
@@ -787,9 +832,12 @@ __device__ JFrame joint_frame(const EnvCtx& c, int j) {
 __device__ void joint_warm(const EnvCtx& c, int j) {
     JFrame f = joint_frame(c, j);
     float* J = jrec(c, j);
-    apply_lin(c, f.a, f.b, f.rA, f.rB, v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]));
-    apply_ang(c, f.a, f.b, J[J_LA] * f.b1 + J[J_LA + 1] * f.b2);
-    apply_ang(c, f.a, f.b, J[J_LD] * f.zA);
+    BodyR A = load_body(c, f.a), B = load_body(c, f.b);
+    imp_lin(A, B, f.rA, f.rB, v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]));
+    imp_ang(A, B, J[J_LA] * f.b1 + J[J_LA + 1] * f.b2);
+    imp_ang(A, B, J[J_LD] * f.zA);
+    store_body(c, f.a, A);
+    store_body(c, f.b, B);
 }
 
 __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
@@ -798,11 +846,12 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
     float* J = jrec(c, j);
     const int a = f.a, b = f.b;
     const float brate = vpass ? 0.0f : bd.beta_j / bd.dt;
-    S6 Ia = a >= 0 ? load_iw(c, a) : S6{0, 0, 0, 0, 0, 0};
-    S6 Ib = load_iw(c, b);
+    BodyR A = load_body(c, a), B = load_body(c, b);
+    const S6& Ia = A.I;
+    const S6& Ib = B.I;
     // point block: K = (mA^-1 + mB^-1) I - [rA]x IA [rA]x - [rB]x IB [rB]x
     {
-        float im = invm_of(c, a) + invm_of(c, b);
+        float im = A.im + B.im;
         float K[3][3] = {{im, 0, 0}, {0, im, 0}, {0, 0, im}};
         for (int side = 0; side < 2; ++side) {
             if (side == 0 && a < 0) continue;
@@ -817,7 +866,7 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
                 for (int q = 0; q < 3; ++q) K[p][q] -= SI[p][0] * Sx[0][q] + SI[p][1] * Sx[1][q] + SI[p][2] * Sx[2][q];
         }
         V3 C = (x_of(c, b) + f.rB) - (x_of(c, a) + f.rA);
-        V3 Cd = (v_of(c, b) + cross3(w_of(c, b), f.rB)) - (v_of(c, a) + cross3(w_of(c, a), f.rA));
+        V3 Cd = (B.v + cross3(B.w, f.rB)) - (A.v + cross3(A.w, f.rA));
         V3 rhs = Cd + brate * C;
         float c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
         float c01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
@@ -834,16 +883,16 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
             V3 lam = v3(-(c00 * rhs.x + c01 * rhs.y + c02 * rhs.z) * id, -(c10 * rhs.x + c11 * rhs.y + c12 * rhs.z) * id,
                         -(c20 * rhs.x + c21 * rhs.y + c22 * rhs.z) * id);
             J[J_LP] += lam.x; J[J_LP + 1] += lam.y; J[J_LP + 2] += lam.z;
-            apply_lin(c, a, b, f.rA, f.rB, lam);
+            imp_lin(A, B, f.rA, f.rB, lam);
         }
     }
     // angular block: keep the joint axes aligned (2 rows)
     {
-        Qt qb = qmul(qc_of(c, b), Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
-        V3 zB = colm(rotm(qb), 2);
+        Qt qbf = qmul(f.qb, Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
+        V3 zB = colm(rotm(qbf), 2);
         V3 zc = cross3(f.zA, zB);
         float C1 = dot3(f.b1, zc), C2 = dot3(f.b2, zc);
-        V3 dw = w_of(c, b) - w_of(c, a);
+        V3 dw = B.w - A.w;
         float Cd1 = dot3(f.b1, dw), Cd2 = dot3(f.b2, dw);
         S6 Is{Ia.xx + Ib.xx, Ia.yy + Ib.yy, Ia.zz + Ib.zz, Ia.xy + Ib.xy, Ia.xz + Ib.xz, Ia.yz + Ib.yz};
         float k11 = dot3(f.b1, muls(Is, f.b1)), k12 = dot3(f.b1, muls(Is, f.b2)), k22 = dot3(f.b2, muls(Is, f.b2));
@@ -854,7 +903,7 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
             float l1 = -(k22 * r1 - k12 * r2) * id;
             float l2 = -(-k12 * r1 + k11 * r2) * id;
             J[J_LA] += l1; J[J_LA + 1] += l2;
-            apply_ang(c, a, b, l1 * f.b1 + l2 * f.b2);
+            imp_ang(A, B, l1 * f.b1 + l2 * f.b2);
         }
     }
     // PD drive: soft row about the joint axis
@@ -865,8 +914,8 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
         float den = kd + h * kp;
         float gamma = 1.0f / (h * den);
         float beta_d = h * kp / den;
-        Qt qa = qmul(qc_of(c, a), Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]});
-        Qt qbf = qmul(qc_of(c, b), Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
+        Qt qa = qmul(f.qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]});
+        Qt qbf = qmul(f.qb, Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
         Qt rel = qmul(Qt{qa.w, -qa.x, -qa.y, -qa.z}, qbf);
         if (rel.w < 0.0f) rel = Qt{-rel.w, -rel.x, -rel.y, -rel.z};
         float th = 2.0f * atan2_w(rel.z, rel.w);
@@ -875,11 +924,13 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
         const float pi = 3.14159265358979323846f;
         C = remainderf(C, 2.0f * pi);
         if (C <= -pi) C += 2.0f * pi;
-        float Cd = dot3(ax, w_of(c, b) - w_of(c, a));
+        float Cd = dot3(ax, B.w - A.w);
         float dl = -(Cd + beta_d * C / h + gamma * J[J_LD]) / (k + gamma);
         J[J_LD] += dl;
-        apply_ang(c, a, b, dl * ax);
+        imp_ang(A, B, dl * ax);
     }
+    store_body(c, a, A);
+    store_body(c, b, B);
 }
 
 // ----------------------------------------------------------------------------- S1 AABB (exact)
@@ -1038,13 +1089,120 @@ __device__ void colour_env(const EnvCtx& c, int G) {
     SC[SC_NJSCHED] = njs;
 }
 
+// S3 for one candidate: decode the pair, run the narrowphase in a frame centred on body A (or
+// on the ground below the body) and reduce to <= 4 points; code < 0 means no candidate.
+__device__ void np_candidate(const EnvCtx& c, int code, NOut& o, int& a, int& b, bool& plane, V3& base,
+                                          V3& offB) {
+    o.n = 0;
+    o.decision = 0;
+    base = v3(0, 0, 0);
+    offB = v3(0, 0, 0);
+    if (code < 0) return;
+    const Lay& l = c.lay;
+    const BatchDev& bd = *c.bd;
+    const int n = l.n;
+    a = code & 0xFF;
+    b = code >> 8;
+    plane = b == n;
+    {
+        int* SC = iptr(c.L + l.SCAL);
+        int sa = iptr(c.L + l.SH)[a] & 0xFF;
+        int kind;
+        if (plane) kind = 9 + sa;
+        else {
+            int sb2 = iptr(c.L + l.SH)[b] & 0xFF;
+            kind = 3 * min(sa, sb2) + max(sa, sb2);
+        }
+        atomicAdd(&SC[16 + STAT_KIND0 + kind], 1);
+    }
+    V3 xa = ld3(c.L, l.X0, n, a);
+    if (plane) {
+        Shp sb = shape_of(c, a, v3(0.0f, 0.0f, xa.z - bd.plane_z));
+        base = v3(xa.x, xa.y, bd.plane_z);
+        offB = sb.c;
+        np_plane(o, sb, bd.delta);
+    } else {
+        Shp sa = shape_of(c, a, v3(0, 0, 0));
+        Shp sb = shape_of(c, b, ld3(c.L, l.X0, n, b) - xa);
+        base = xa;
+        offB = sb.c;
+        np_pair(o, sa, sb, bd.delta);
+    }
+    reduce4(o);
+}
+
+// S4 for one kept pair: a normal row per kept point (arms from the step-start centres, pre-step
+// normal velocity, effective mass) and the manifold's friction patch at the points' centroid.
+__device__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, bool plane, V3 base,
+                                        V3 offB, int keep, int first, int m, bool dbg, int dpo, int dmo) {
+    const Lay& l = c.lay;
+    const BatchDev& bd = *c.bd;
+    int ia = plane ? -1 : a, ib = plane ? a : b;
+    float mu, e;
+    if (plane) { mu = (bd.plane_mu + c.L[l.MU + a]) / 2.0f; e = fmaxf(bd.plane_e, c.L[l.EE + a]); }
+    else { mu = (c.L[l.MU + a] + c.L[l.MU + b]) / 2.0f; e = fmaxf(c.L[l.EE + a], c.L[l.EE + b]); }
+    V3 csum = v3(0, 0, 0), nsum = v3(0, 0, 0);
+    for (int q = 0; q < keep; ++q) {
+        int kk = first + q;
+        V3 p = o.pt[q].p, nv = o.pt[q].n;
+        V3 rA = ia >= 0 ? p : v3(0, 0, 0);
+        V3 rB = p - offB;
+        V3 vrel = rel_vel(c, ia, ib, rA, rB);
+        pr(c, R_RA, kk) = rA.x; pr(c, R_RA + 1, kk) = rA.y; pr(c, R_RA + 2, kk) = rA.z;
+        pr(c, R_RB, kk) = rB.x; pr(c, R_RB + 1, kk) = rB.y; pr(c, R_RB + 2, kk) = rB.z;
+        pr(c, R_N, kk) = nv.x; pr(c, R_N + 1, kk) = nv.y; pr(c, R_N + 2, kk) = nv.z;
+        pr(c, R_MN, kk) = eff_mass(c, ia, ib, rA, rB, nv);
+        pr(c, R_S0, kk) = o.pt[q].s;
+        pr(c, R_E, kk) = e;
+        pr(c, R_VN, kk) = dot3(vrel, nv);
+        pr(c, R_LN, kk) = 0.0f;
+        csum = csum + p;
+        nsum = nsum + nv;
+        if (dbg) {
+            float* dq = bd.dbg_pts + 8 * size_t(dpo + kk);
+            V3 pw = base + p;
+            dq[0] = pw.x; dq[1] = pw.y; dq[2] = pw.z; dq[3] = nv.x; dq[4] = nv.y; dq[5] = nv.z;
+            dq[6] = o.pt[q].s; dq[7] = 0.0f;
+        }
+    }
+    V3 cc = (1.0f / float(keep)) * csum;
+    V3 nb = (1.0f / len3(nsum)) * nsum;
+    V3 rA = ia >= 0 ? cc : v3(0, 0, 0);
+    V3 rB = cc - offB;
+    V3 vrel = rel_vel(c, ia, ib, rA, rB);
+    V3 vt = vrel - dot3(vrel, nb) * nb;
+    float vtl = len3(vt);
+    V3 t1 = vtl >= 1e-3f ? (1.0f / vtl) * vt : onb_t1(nb);
+    V3 t2 = cross3(nb, t1);
+    float kw = (ia >= 0 ? dot3(nb, muls(load_iw(c, ia), nb)) : 0.0f) + dot3(nb, muls(load_iw(c, ib), nb));
+    float rsum = 0.0f;
+    for (int q = 0; q < keep; ++q) rsum += len3(o.pt[q].p - cc);
+    iptr(c.L + l.MAN + M_AB * l.mcap)[m] = (ia < 0 ? 0xFF : ia) | (ib << 8);
+    iptr(c.L + l.MAN + M_FC * l.mcap)[m] = first | (keep << 16);
+    mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
+    mfr(c, M_RB, m) = rB.x; mfr(c, M_RB + 1, m) = rB.y; mfr(c, M_RB + 2, m) = rB.z;
+    mfr(c, M_NB, m) = nb.x; mfr(c, M_NB + 1, m) = nb.y; mfr(c, M_NB + 2, m) = nb.z;
+    mfr(c, M_T1, m) = t1.x; mfr(c, M_T1 + 1, m) = t1.y; mfr(c, M_T1 + 2, m) = t1.z;
+    mfr(c, M_MT1, m) = eff_mass(c, ia, ib, rA, rB, t1);
+    mfr(c, M_MT2, m) = eff_mass(c, ia, ib, rA, rB, t2);
+    mfr(c, M_MTW, m) = kw > 0.0f ? 1.0f / kw : 0.0f;
+    mfr(c, M_MU, m) = mu;
+    mfr(c, M_RT, m) = rsum / float(keep);
+    mfr(c, M_LT1, m) = 0.0f; mfr(c, M_LT2, m) = 0.0f; mfr(c, M_LTW, m) = 0.0f;
+    if (dbg) {
+        float* dm = bd.dbg_man + 8 * size_t(dmo + m);
+        dm[0] = __int_as_float(k);
+        dm[7] = __int_as_float(keep);
+    }
+}
+
 }  // namespace
 
 // ============================================================================= step kernel
-extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* __restrict__ batches,
-                                                              const Tile* __restrict__ tiles, int n_tiles,
-                                                              const TileEnv* __restrict__ tenv, int n_steps) {
-    extern __shared__ float lds[];
+// The step of every tile of the work list; `lds` is the workgroup's dynamic LDS.
+__device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restrict__ batches,
+                                           const Tile* __restrict__ tiles, int n_tiles,
+                                           const TileEnv* __restrict__ tenv, int n_steps) {
     const int lane = threadIdx.x;
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
@@ -1193,41 +1351,10 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
                 for (int ch = 0; ch < nch; ++ch) {
                     int k = ch * G + li;
                     NOut o;
-                    o.n = 0;
-                    o.decision = 0;
                     int a = 0, b = 0;
                     bool plane = false;
-                    V3 base = v3(0, 0, 0), offB = v3(0, 0, 0);
-                    if (k < ncand) {
-                        int code = CAND[k];
-                        a = code & 0xFF;
-                        b = code >> 8;
-                        plane = b == n;
-                        {
-                            int sa = iptr(c.L + l.SH)[a] & 0xFF;
-                            int kind;
-                            if (plane) kind = 9 + sa;
-                            else {
-                                int sb2 = iptr(c.L + l.SH)[b] & 0xFF;
-                                kind = 3 * min(sa, sb2) + max(sa, sb2);
-                            }
-                            atomicAdd(&SC[16 + STAT_KIND0 + kind], 1);
-                        }
-                        V3 xa = ld3(c.L, l.X0, n, a);
-                        if (plane) {
-                            Shp sb = shape_of(c, a, v3(0.0f, 0.0f, xa.z - bd.plane_z));
-                            base = v3(xa.x, xa.y, bd.plane_z);
-                            offB = sb.c;
-                            np_plane(o, sb, delta);
-                        } else {
-                            Shp sa = shape_of(c, a, v3(0, 0, 0));
-                            Shp sb = shape_of(c, b, ld3(c.L, l.X0, n, b) - xa);
-                            base = xa;
-                            offB = sb.c;
-                            np_pair(o, sa, sb, delta);
-                        }
-                        reduce4(o);
-                    }
+                    V3 base, offB;
+                    np_candidate(c, k < ncand ? int(CAND[k]) : -1, o, a, b, plane, base, offB);
                     int tot;
                     int pre = group_scan(o.n, li, G, tot);
                     int keep = min(max(l.cap - (npts + pre), 0), o.n);
@@ -1244,66 +1371,7 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
                         int* dp = bd.dbg_pairs + 4 * size_t(dpp + k);
                         dp[0] = a; dp[1] = plane ? PLANE : b; dp[2] = keep; dp[3] = o.decision;
                     }
-                    if (keep > 0) {
-                        int ia = plane ? -1 : a, ib = plane ? a : b;
-                        float mu, e;
-                        if (plane) { mu = (bd.plane_mu + c.L[l.MU + a]) / 2.0f; e = fmaxf(bd.plane_e, c.L[l.EE + a]); }
-                        else { mu = (c.L[l.MU + a] + c.L[l.MU + b]) / 2.0f; e = fmaxf(c.L[l.EE + a], c.L[l.EE + b]); }
-                        V3 csum = v3(0, 0, 0), nsum = v3(0, 0, 0);
-                        for (int q = 0; q < keep; ++q) {
-                            int kk = first + q;
-                            V3 p = o.pt[q].p, nv = o.pt[q].n;
-                            V3 rA = ia >= 0 ? p : v3(0, 0, 0);
-                            V3 rB = p - offB;
-                            V3 vrel = rel_vel(c, ia, ib, rA, rB);
-                            pr(c, R_RA, kk) = rA.x; pr(c, R_RA + 1, kk) = rA.y; pr(c, R_RA + 2, kk) = rA.z;
-                            pr(c, R_RB, kk) = rB.x; pr(c, R_RB + 1, kk) = rB.y; pr(c, R_RB + 2, kk) = rB.z;
-                            pr(c, R_N, kk) = nv.x; pr(c, R_N + 1, kk) = nv.y; pr(c, R_N + 2, kk) = nv.z;
-                            pr(c, R_MN, kk) = eff_mass(c, ia, ib, rA, rB, nv);
-                            pr(c, R_S0, kk) = o.pt[q].s;
-                            pr(c, R_E, kk) = e;
-                            pr(c, R_VN, kk) = dot3(vrel, nv);
-                            pr(c, R_LN, kk) = 0.0f;
-                            csum = csum + p;
-                            nsum = nsum + nv;
-                            if (dbg) {
-                                float* dq = bd.dbg_pts + 8 * size_t(dpo + kk);
-                                V3 pw = base + p;
-                                dq[0] = pw.x; dq[1] = pw.y; dq[2] = pw.z; dq[3] = nv.x; dq[4] = nv.y; dq[5] = nv.z;
-                                dq[6] = o.pt[q].s; dq[7] = 0.0f;
-                            }
-                        }
-                        V3 cc = (1.0f / float(keep)) * csum;
-                        V3 nb = (1.0f / len3(nsum)) * nsum;
-                        V3 rA = ia >= 0 ? cc : v3(0, 0, 0);
-                        V3 rB = cc - offB;
-                        V3 vrel = rel_vel(c, ia, ib, rA, rB);
-                        V3 vt = vrel - dot3(vrel, nb) * nb;
-                        float vtl = len3(vt);
-                        V3 t1 = vtl >= 1e-3f ? (1.0f / vtl) * vt : onb_t1(nb);
-                        V3 t2 = cross3(nb, t1);
-                        float kw = (ia >= 0 ? dot3(nb, muls(load_iw(c, ia), nb)) : 0.0f) + dot3(nb, muls(load_iw(c, ib), nb));
-                        float rsum = 0.0f;
-                        for (int q = 0; q < keep; ++q) rsum += len3(o.pt[q].p - cc);
-                        int m = m_idx;
-                        iptr(c.L + l.MAN + M_AB * l.mcap)[m] = (ia < 0 ? 0xFF : ia) | (ib << 8);
-                        iptr(c.L + l.MAN + M_FC * l.mcap)[m] = first | (keep << 16);
-                        mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
-                        mfr(c, M_RB, m) = rB.x; mfr(c, M_RB + 1, m) = rB.y; mfr(c, M_RB + 2, m) = rB.z;
-                        mfr(c, M_NB, m) = nb.x; mfr(c, M_NB + 1, m) = nb.y; mfr(c, M_NB + 2, m) = nb.z;
-                        mfr(c, M_T1, m) = t1.x; mfr(c, M_T1 + 1, m) = t1.y; mfr(c, M_T1 + 2, m) = t1.z;
-                        mfr(c, M_MT1, m) = eff_mass(c, ia, ib, rA, rB, t1);
-                        mfr(c, M_MT2, m) = eff_mass(c, ia, ib, rA, rB, t2);
-                        mfr(c, M_MTW, m) = kw > 0.0f ? 1.0f / kw : 0.0f;
-                        mfr(c, M_MU, m) = mu;
-                        mfr(c, M_RT, m) = rsum / float(keep);
-                        mfr(c, M_LT1, m) = 0.0f; mfr(c, M_LT2, m) = 0.0f; mfr(c, M_LTW, m) = 0.0f;
-                        if (dbg) {
-                            float* dm = bd.dbg_man + 8 * size_t(dmo + m);
-                            dm[0] = __int_as_float(k);
-                            dm[7] = __int_as_float(keep);
-                        }
-                    }
+                    if (keep > 0) write_rows(c, o, k, a, b, plane, base, offB, keep, first, m_idx, dbg, dpo, dmo);
                     npts += ktot;
                     int mkept;
                     group_scan(keep > 0 ? 1 : 0, li, G, mkept);
@@ -1418,6 +1486,22 @@ extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* 
         for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += SC[16 + k];
         __syncthreads();
     }
+}
+
+// Two builds of the same step: unconstrained register allocation (small envs, where the
+// wave count is bounded by LDS anyway) and a cap of 256 registers per lane (two waves per SIMD)
+// for large envs whose solve is latency bound.  The planner / tuner picks one per LDS class.
+extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* __restrict__ batches,
+                                                              const Tile* __restrict__ tiles, int n_tiles,
+                                                              const TileEnv* __restrict__ tenv, int n_steps) {
+    extern __shared__ float lds[];
+    step_tiles(lds, batches, tiles, n_tiles, tenv, n_steps);
+}
+extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+ms_step_kernel_w2(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, int n_tiles,
+                  const TileEnv* __restrict__ tenv, int n_steps) {
+    extern __shared__ float lds[];
+    step_tiles(lds, batches, tiles, n_tiles, tenv, n_steps);
 }
 
 // ============================================================================= reset kernel

@@ -61,6 +61,8 @@ _sig = {
     "ms_get_plan": [_P, _P, _P, _P, _P],
     "ms_get_contacts": [_P, _P, _I, _P, _I, _P, _I, _P, _P, _P, _P],
     "ms_get_stats": [_P, _P, _I, _P],
+    "ms_get_classes": [_P, _P, _P],
+    "ms_tune_batch": [_P, _I, _P],
     "ms_destroy_batch": [_P],
 }
 for _name, _args in _sig.items():
@@ -209,6 +211,19 @@ class Batch:
         _check(_lib.ms_get_contacts(self._h, pairs.ctypes.data, np_, pts.ctypes.data, npt, mans.ctypes.data, nm,
                                     *[C.byref(x) for x in n], _stream(stream)))
         return dict(pairs=pairs, points=pts, manifolds=mans)
+
+    def classes(self):
+        """ms_get_classes: per LDS class {tiles, lds_bytes, variant, lanes, first_tile}."""
+        n = C.c_int32()
+        _check(_lib.ms_get_classes(self._h, C.byref(n), None))
+        out = np.zeros((n.value, 5), np.int32)
+        _check(_lib.ms_get_classes(self._h, C.byref(n), out.ctypes.data))
+        return [dict(tiles=int(r[0]), lds_bytes=int(r[1]), variant=int(r[2]), lanes=int(r[3])) for r in out]
+
+    def tune(self, trial_steps=3, stream=None):
+        """ms_tune_batch: pick the fastest kernel variant per LDS class (state is restored)."""
+        _check(_lib.ms_tune_batch(self._h, int(trial_steps), _stream(stream)))
+        return self.classes()
 
     def stats(self, reset=False, stream=None):
         """ms_get_stats: int64 [E, 16] work counters accumulated since the last reset."""

@@ -275,3 +275,25 @@ def test_full_size_tray_sampled_envs():
                                                                                        "angvel")}
     bad, excused = compare_states(sub, gs, os_, margin)
     assert not bad and len(excused) <= 1
+
+
+def test_tuning_leaves_state_and_bits_unchanged():
+    # The autotuner runs trial steps of every kernel variant and restores the state; both
+    # kernel variants compute the same bits, so a tuned batch matches an untuned one exactly.
+    sc = S.hetero(256, seed=13)
+    st = to_dev(oracle_state(sc, 20))
+    ids = torch.arange(sc.n_envs, dtype=torch.int32, device="cuda")
+    a, b = gpu_batch(sc, debug=False), gpu_batch(sc, debug=False)
+    a.reset_envs(ids, st)
+    b.reset_envs(ids, st)
+    before = a.state_numpy()
+    a.tune(2)
+    after = a.state_numpy()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    assert np.all(a.stats() == 0)
+    a.step(5)
+    b.step(5)
+    sa, sb = a.state_numpy(), b.state_numpy()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
