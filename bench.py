@@ -213,8 +213,10 @@ def main():
         out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
     if not args.quick:
         extra = {}
-        for name, n in (("drop_boxes", 4096), ("arm_cube", 1024), ("hetero", 4096), ("hetero_padded", 4096)):
-            _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed)
+        # the padded baseline is the plain launch: one tile per env, one LDS size for all (pack=0)
+        for name, n, pack in (("drop_boxes", 4096, 1), ("arm_cube", 1024, 1), ("hetero", 4096, 1),
+                              ("hetero_padded", 4096, 0)):
+            _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed, pack=pack)
             extra[name] = res
         extra["hetero_speedup_vs_padded"] = extra["hetero"]["env_steps_per_s"] / extra["hetero_padded"]["env_steps_per_s"]
         out["extra"] = extra

@@ -217,6 +217,21 @@ ms_status ms_get_stats(ms_batch* b, int64_t* host_stats, int32_t reset, void* hi
 
 ms_status ms_destroy_batch(ms_batch* b);
 
+/* Captured step sequences (Sec. "GPU Parallelized Simulation and Rendering": the step stays on
+ * the GPU with minimal host overhead per step).  ms_graph_create records
+ * n_launches consecutive ms_step(b, dev_targets, steps_per_launch) calls, including the fork /
+ * join of LDS classes on side streams, into a HIP graph by stream capture on a private stream
+ * and instantiates it; ms_graph_launch replays it on `hip_stream` (stream-ordered, no host
+ * synchronisation).  The graph reads dev_targets (J floats, may be NULL) at replay time, so the
+ * caller may rewrite that buffer between replays; it must stay valid while the graph exists.
+ * The graph holds no memset nodes.  A graph belongs to its batch: destroy it before the batch.
+ * Errors: invalid arguments or a failed capture return a status and leave nothing behind. */
+typedef struct ms_graph ms_graph;
+ms_status ms_graph_create(ms_batch* b, const float* dev_targets, int32_t steps_per_launch, int32_t n_launches,
+                          ms_graph** out);
+ms_status ms_graph_launch(ms_graph* g, void* hip_stream);
+ms_status ms_graph_destroy(ms_graph* g);
+
 /* Fused step over several batches in one launch (the serving path): the env tiles of every
  * batch are concatenated into one work list.  dev_targets (may be NULL) holds per-batch target
  * pointers as in ms_step.  dev_scratch is caller device memory of at least
@@ -226,6 +241,53 @@ ms_status ms_destroy_batch(ms_batch* b);
 ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, size_t* bytes);
 ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches,
                        int32_t n_steps, void* dev_scratch, size_t scratch_bytes, void* hip_stream);
+
+/* Serving (Sec. "GPU Parallelized Simulation and Rendering": all state stays on one GPU; Sec.
+ * "Heterogeneous GPU Simulation": envs of different sizes share the GPU).  A server owns a
+ * worker thread and a stream on the current device, and a caller-owned device arena of
+ * arena_bytes (256-byte aligned) from which it carves, first fit, each admitted session's
+ * workspace (ms_query_batch_bytes + its targets buffer) and a scratch reserve of scratch_bytes
+ * for the fused work list (0: arena / 16, at most 16 MiB).
+ *   ms_server_open    queues a session (a batch of envs, descriptors copied) for admission and
+ *                     returns its id; sessions are admitted in arrival order as soon as their
+ *                     block fits (HBM-budget admission; one that can never fit the arena is
+ *                     rejected here with MS_E_BUDGET).
+ *   ms_server_submit  queues a request of n_steps steps (host_targets: J floats or NULL =
+ *                     keep); a session's requests run in submission order.
+ *   ms_server_wait    blocks until the request is done, fills *info (may be NULL) and forgets
+ *                     the request: wait on each request exactly once.
+ *   ms_server_close   retires the session after its queued requests; its block is freed.
+ *   ms_server_get_state  waits until the session is admitted and idle, then copies its state
+ *                     on hip_stream as ms_get_state does.
+ *   ms_server_drain   waits until every queued request has run and closed sessions are gone.
+ *   ms_server_stats   int64 [8]: fused launches, batches summed over launches, env-steps, requests
+ *                     done, sessions admitted, busy microseconds, peak arena bytes, sessions
+ *                     rejected at admission.
+ *   ms_server_destroy runs what is queued, stops the worker and frees everything.
+ * Continuous batching: each worker iteration advances the head request of every admitted
+ * session by the smallest remaining step count in one ms_step_many launch; requests arriving
+ * meanwhile join the next iteration.  Times are seconds on ms_server_clock (monotonic).
+ * The arena must stay valid until ms_server_destroy returns.  All calls are thread safe. */
+typedef struct ms_server ms_server;
+typedef struct {
+    int64_t request, session;
+    int32_t status, n_steps;
+    double t_submit, t_start, t_done;   /* queued, first launch, completion observed */
+    int32_t fused_batches;              /* sessions in the launch that completed it */
+    int32_t pad;
+} ms_request_info;
+ms_status ms_server_create(void* dev_arena, size_t arena_bytes, size_t scratch_bytes, ms_server** out);
+ms_status ms_server_open(ms_server* s, const ms_sim_params* params, const ms_scene_desc* scene, const ms_plan* plan,
+                         int64_t* session);
+ms_status ms_server_submit(ms_server* s, int64_t session, int32_t n_steps, const float* host_targets,
+                           int64_t* request);
+ms_status ms_server_wait(ms_server* s, int64_t request, ms_request_info* info);
+ms_status ms_server_close(ms_server* s, int64_t session);
+ms_status ms_server_get_state(ms_server* s, int64_t session, const ms_state_view* dst, void* hip_stream);
+ms_status ms_server_drain(ms_server* s);
+ms_status ms_server_stats(ms_server* s, int64_t* host_stats);
+ms_status ms_server_destroy(ms_server* s);
+double ms_server_clock(void);
 
 /* Thread-local message of the last non-OK status returned on this thread. */
 const char* ms_last_error(void);

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "ms.h"
@@ -504,6 +505,17 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     return MS_OK;
 }
 
+// Side streams and events of the LDS-class fork / join, created once per batch.
+static ms_status ensure_side_streams(ms_batch* b) {
+    if (b->ev_fork || b->plan.classes.size() < 2) return MS_OK;
+    HIP_OK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    for (size_t k = 1; k < b->plan.classes.size(); ++k) {
+        HIP_OK(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+    }
+    return MS_OK;
+}
+
 ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* hip_stream) {
     if (!b) return fail(MS_E_INVALID_ARG, "null batch");
     if (n_steps < 1) return fail(MS_E_INVALID_ARG, "n_steps must be >= 1 (got %d)", n_steps);
@@ -521,13 +533,7 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     }
     // one launch per LDS class: the largest class on the caller's stream, the others on side
     // streams forked from and joined back into it
-    if (!b->ev_fork) {
-        HIP_OK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-        for (size_t k = 1; k < cls.size(); ++k) {
-            HIP_OK(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
-            HIP_OK(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
-        }
-    }
+    if (ms_status st = ensure_side_streams(b); st != MS_OK) return st;
     HIP_OK(hipEventRecord(b->ev_fork, s));
     for (size_t k = 0; k < cls.size(); ++k) {
         hipStream_t sk = k == 0 ? s : b->side[k];
@@ -743,6 +749,59 @@ ms_status ms_destroy_batch(ms_batch* b) {
 }
 
 // ----------------------------------------------------------------------------- fused multi-batch step
+struct ms_graph {
+    ms_batch* b = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~ms_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+ms_status ms_graph_create(ms_batch* b, const float* dev_targets, int32_t steps_per_launch, int32_t n_launches,
+                          ms_graph** out) {
+    if (!b || !out) return fail(MS_E_INVALID_ARG, "null batch or output handle");
+    *out = nullptr;
+    if (steps_per_launch < 1 || n_launches < 1 || n_launches > 100000)
+        return fail(MS_E_INVALID_ARG, "steps_per_launch must be >= 1 and n_launches in [1, 100000] (got %d, %d)",
+                    steps_per_launch, n_launches);
+    HIP_OK(hipSetDevice(b->device));
+    if (ms_status st = ensure_side_streams(b); st != MS_OK) return st;
+    hipStream_t cap = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    std::unique_ptr<ms_graph> g(new ms_graph());
+    g->b = b;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    ms_status st = e == hipSuccess ? MS_OK : fail(MS_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    if (st == MS_OK) {
+        for (int k = 0; k < n_launches && st == MS_OK; ++k) st = ms_step(b, dev_targets, steps_per_launch, cap);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap, &graph);   // always end the capture, also after a failed step
+        g->graph = graph;
+        if (st == MS_OK && e != hipSuccess) st = fail(MS_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    if (st == MS_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = fail(MS_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cap);
+    if (st != MS_OK) return st;
+    *out = g.release();
+    return MS_OK;
+}
+
+ms_status ms_graph_launch(ms_graph* g, void* hip_stream) {
+    if (!g || !g->exec) return fail(MS_E_INVALID_ARG, "null graph");
+    HIP_OK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream)));
+    return MS_OK;
+}
+
+ms_status ms_graph_destroy(ms_graph* g) {
+    delete g;
+    return MS_OK;
+}
+
 static size_t many_bytes(ms_batch* const* batches, int32_t n) {
     size_t tiles = 0, tenv = 0;
     for (int i = 0; i < n; ++i) { tiles += batches[i]->plan.tiles.size(); tenv += batches[i]->plan.tenv.size(); }
@@ -758,15 +817,23 @@ ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, 
 }
 
 namespace {
-// Pinned host staging for the combined work list, reused once the previous upload completed.
+// Pinned host staging for the combined work list, reused once the previous upload completed,
+// and the side streams of the LDS-class fork / join (one set per host thread and device).
 struct Staging {
     void* host = nullptr;
     size_t cap = 0;
     hipEvent_t ev = nullptr;
     int device = -1;
     bool pending = false;
+    hipStream_t side[MAX_CLASSES] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[MAX_CLASSES] = {};
 };
 thread_local Staging g_stage;
+
+struct ManyTile {
+    int lds_words, batch, tile;
+};
 }  // namespace
 
 ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches, int32_t n_steps,
@@ -781,10 +848,17 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     if (reinterpret_cast<uintptr_t>(dev_scratch) % ALIGN) return fail(MS_E_INVALID_ARG, "scratch must be 256-byte aligned");
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
+    for (int i = 0; i < n_batches; ++i)
+        if (batches[i]->device != dev) return fail(MS_E_INVALID_ARG, "batch %d lives on device %d, not %d", i, batches[i]->device, dev);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Staging& st = g_stage;
     if (st.device != dev) {
         if (st.ev) { (void)hipEventSynchronize(st.ev); (void)hipEventDestroy(st.ev); st.ev = nullptr; }
+        for (int k = 0; k < MAX_CLASSES; ++k) {
+            if (st.side[k]) { (void)hipStreamSynchronize(st.side[k]); (void)hipStreamDestroy(st.side[k]); st.side[k] = nullptr; }
+            if (st.ev_join[k]) { (void)hipEventDestroy(st.ev_join[k]); st.ev_join[k] = nullptr; }
+        }
+        if (st.ev_fork) { (void)hipEventDestroy(st.ev_fork); st.ev_fork = nullptr; }
         st.device = dev;
         st.pending = false;
         HIP_OK(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
@@ -800,27 +874,37 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     char* h = static_cast<char*>(st.host);
     BatchDev* tb = reinterpret_cast<BatchDev*>(h);
     Tile* tt = reinterpret_cast<Tile*>(h + align_up(size_t(n_batches) * sizeof(BatchDev)));
-    size_t n_tiles = 0, n_tenv = 0;
+    size_t n_tiles = 0;
     for (int i = 0; i < n_batches; ++i) n_tiles += batches[i]->plan.tiles.size();
     TileEnv* te = reinterpret_cast<TileEnv*>(reinterpret_cast<char*>(tt) + align_up(n_tiles * sizeof(Tile)));
-    size_t max_lds = 0, kt = 0;
+    // env slots batch by batch; tiles of all batches merged and ordered by LDS need (largest
+    // first), then cut into LDS classes by the rule of the single-batch plan
+    std::vector<int> tenv_base(n_batches + 1, 0);
+    std::vector<ManyTile> order;
+    order.reserve(n_tiles);
     for (int i = 0; i < n_batches; ++i) {
         ms_batch* b = batches[i];
         tb[i] = b->hbd;
-        for (const Tile& t : b->plan.tiles) {
-            Tile u = t;
-            u.first += int(n_tenv);
-            tt[kt++] = u;
-        }
-        for (const TileEnv& e : b->plan.tenv) {
-            TileEnv f = e;
+        tenv_base[i + 1] = tenv_base[i] + int(b->plan.tenv.size());
+        for (size_t k = 0; k < b->plan.tenv.size(); ++k) {
+            TileEnv f = b->plan.tenv[k];
             f.batch = i;
-            te[n_tenv++] = f;
+            te[tenv_base[i] + k] = f;
         }
-        max_lds = std::max(max_lds, b->lds_bytes);
+        for (size_t t = 0; t < b->plan.tiles.size(); ++t) order.push_back(ManyTile{b->plan.tiles[t].lds_words, i, int(t)});
         if (dev_targets && dev_targets[i] && b->J > 0)
             HIP_OK(hipMemcpyAsync(const_cast<float*>(b->hbd.targets), dev_targets[i], size_t(b->J) * 4,
                                   hipMemcpyDeviceToDevice, s));
+    }
+    std::stable_sort(order.begin(), order.end(), [](const ManyTile& a, const ManyTile& b) { return a.lds_words > b.lds_words; });
+    std::vector<LdsClass> cls;
+    for (size_t k = 0; k < order.size(); ++k) {
+        Tile u = batches[order[k].batch]->plan.tiles[order[k].tile];
+        u.first += tenv_base[order[k].batch];
+        tt[k] = u;
+        bool split = !cls.empty() && 3 * u.lds_words < 2 * cls.back().lds_words && int(cls.size()) < MAX_CLASSES;
+        if (cls.empty() || split) cls.push_back(LdsClass{int(k), 0, u.lds_words, u.lanes == 64 ? 1 : 0, u.lanes});
+        cls.back().n_tiles++;
     }
     HIP_OK(hipMemcpyAsync(dev_scratch, st.host, need, hipMemcpyHostToDevice, s));
     HIP_OK(hipEventRecord(st.ev, s));
@@ -829,9 +913,26 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     const BatchDev* dtb = reinterpret_cast<const BatchDev*>(d);
     const Tile* dtt = reinterpret_cast<const Tile*>(d + (reinterpret_cast<char*>(tt) - h));
     const TileEnv* dte = reinterpret_cast<const TileEnv*>(d + (reinterpret_cast<char*>(te) - h));
-    hipLaunchKernelGGL(ms_step_kernel, dim3(unsigned(n_tiles)), dim3(WAVE), max_lds, s, dtb, dtt, int(n_tiles), dte,
-                       int(n_steps));
-    HIP_OK(hipGetLastError());
+    if (cls.size() > 1 && !st.ev_fork) {
+        HIP_OK(hipEventCreateWithFlags(&st.ev_fork, hipEventDisableTiming));
+        for (int k = 1; k < MAX_CLASSES; ++k) {
+            HIP_OK(hipStreamCreateWithFlags(&st.side[k], hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&st.ev_join[k], hipEventDisableTiming));
+        }
+    }
+    if (cls.size() > 1) HIP_OK(hipEventRecord(st.ev_fork, s));
+    for (size_t k = 0; k < cls.size(); ++k) {
+        hipStream_t sk = k == 0 ? s : st.side[k];
+        if (k > 0) HIP_OK(hipStreamWaitEvent(sk, st.ev_fork, 0));
+        hipLaunchKernelGGL(kernel_of(cls[k].variant), dim3(unsigned(cls[k].n_tiles)), dim3(WAVE),
+                           size_t(cls[k].lds_words) * 4, sk, dtb, dtt + cls[k].first_tile, cls[k].n_tiles, dte,
+                           int(n_steps));
+        HIP_OK(hipGetLastError());
+        if (k > 0) {
+            HIP_OK(hipEventRecord(st.ev_join[k], sk));
+            HIP_OK(hipStreamWaitEvent(s, st.ev_join[k], 0));
+        }
+    }
     return MS_OK;
 }
 

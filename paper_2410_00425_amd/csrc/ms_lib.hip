@@ -1,3 +1,4 @@
 // ms_lib.hip — single translation unit of libms: the device kernels and the host runtime.
 #include "ms_step.hip"
 #include "ms_host.cpp"
+#include "ms_server.cpp"

@@ -41,6 +41,8 @@ __device__ __forceinline__ V3 cross3(V3 a, V3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 __device__ __forceinline__ float len3(V3 a) { return sqrtf(dot3(a, a)); }
+// c ? a : b on values (component selects; no address of either operand is taken).
+__device__ __forceinline__ V3 vsel(bool c, V3 a, V3 b) { return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z}; }
 __device__ __forceinline__ float comp(V3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
 __device__ __forceinline__ void setc(V3& a, int i, float v) {
     if (i == 0) a.x = v; else if (i == 1) a.y = v; else a.z = v;
@@ -75,7 +77,12 @@ __device__ __forceinline__ V3 mulTv(const M3& a, V3 v) {
     return {a.m[0][0] * v.x + a.m[1][0] * v.y + a.m[2][0] * v.z, a.m[0][1] * v.x + a.m[1][1] * v.y + a.m[2][1] * v.z,
             a.m[0][2] * v.x + a.m[1][2] * v.y + a.m[2][2] * v.z};
 }
-__device__ __forceinline__ V3 colm(const M3& a, int j) { return {a.m[0][j], a.m[1][j], a.m[2][j]}; }
+// Column j; every element is read at a constant offset (a run-time j selects between values),
+// so matrices stay in registers.
+__device__ __forceinline__ V3 colm(const M3& a, int j) {
+    V3 c0 = {a.m[0][0], a.m[1][0], a.m[2][0]}, c1 = {a.m[0][1], a.m[1][1], a.m[2][1]}, c2 = {a.m[0][2], a.m[1][2], a.m[2][2]};
+    return j == 0 ? c0 : (j == 1 ? c1 : c2);
+}
 
 // Symmetric 3x3 stored as xx, yy, zz, xy, xz, yz.
 struct S6 { float xx, yy, zz, xy, xz, yz; };
@@ -125,6 +132,15 @@ __device__ __forceinline__ void st4(float* L, int off, int n, int i, Qt q) {
 }
 
 // ----------------------------------------------------------------------------- wave helpers
+// Every workgroup is exactly one wavefront (64 lanes).  LDS operations of one wavefront are
+// performed in program order, so lanes that exchange data through LDS between phases need only
+// a wavefront-scope fence, which keeps the compiler from moving memory operations across the
+// phase boundary and costs no wait on the hardware.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
@@ -165,10 +181,14 @@ __device__ __forceinline__ S6 load_iw(const EnvCtx& c, int i) {
 }
 
 // ----------------------------------------------------------------------------- narrowphase
+// Every array below is indexed by compile-time constants only (loops are unrolled and run-time
+// choices become selects), so the narrowphase lives in registers, not in scratch memory.
 struct Pt { V3 p, n; float s; };
+// Contact points of one pair: up to 8 slots; the pair's point list is the valid slots (mask)
+// in slot order.  Each generator writes its k-th candidate point into slot k.
 struct NOut {
     Pt pt[8];
-    int n;
+    uint32_t mask;
     int decision;
 };
 struct Shp {
@@ -179,20 +199,40 @@ struct Shp {
     __device__ V3 p0() const { return c - d[1] * colm(R, 2); }
     __device__ V3 p1() const { return c + d[1] * colm(R, 2); }
 };
+__device__ __forceinline__ float dim(const Shp& s, int i) { return i == 0 ? s.d[0] : (i == 1 ? s.d[1] : s.d[2]); }
+__device__ __forceinline__ V3 axis(const Shp& s, int i) {
+    return i == 0 ? colm(s.R, 0) : (i == 1 ? colm(s.R, 1) : colm(s.R, 2));
+}
+// c ? a : b, field by field (a value select keeps both shapes in registers).
+__device__ __forceinline__ Shp pick(bool c, const Shp& a, const Shp& b) {
+    Shp r;
+    r.type = c ? a.type : b.type;
+    r.c = v3(c ? a.c.x : b.c.x, c ? a.c.y : b.c.y, c ? a.c.z : b.c.z);
+    r.d[0] = c ? a.d[0] : b.d[0]; r.d[1] = c ? a.d[1] : b.d[1]; r.d[2] = c ? a.d[2] : b.d[2];
+    r.R.m[0][0] = c ? a.R.m[0][0] : b.R.m[0][0]; r.R.m[0][1] = c ? a.R.m[0][1] : b.R.m[0][1];
+    r.R.m[0][2] = c ? a.R.m[0][2] : b.R.m[0][2]; r.R.m[1][0] = c ? a.R.m[1][0] : b.R.m[1][0];
+    r.R.m[1][1] = c ? a.R.m[1][1] : b.R.m[1][1]; r.R.m[1][2] = c ? a.R.m[1][2] : b.R.m[1][2];
+    r.R.m[2][0] = c ? a.R.m[2][0] : b.R.m[2][0]; r.R.m[2][1] = c ? a.R.m[2][1] : b.R.m[2][1];
+    r.R.m[2][2] = c ? a.R.m[2][2] : b.R.m[2][2];
+    return r;
+}
+__device__ __forceinline__ int n_points(const NOut& o) { return __popc(o.mask); }
 
+template <int K>
 __device__ __forceinline__ void emit(NOut& o, V3 pa, V3 pb, V3 n, float s, float delta) {
-    if (s < delta && o.n < 8) {
-        o.pt[o.n].p = 0.5f * (pa + pb);
-        o.pt[o.n].n = n;
-        o.pt[o.n].s = s;
-        o.n++;
+    static_assert(K >= 0 && K < 8, "slot");
+    if (s < delta) {
+        o.pt[K].p = 0.5f * (pa + pb);
+        o.pt[K].n = n;
+        o.pt[K].s = s;
+        o.mask |= 1u << K;
     }
 }
 
 __device__ __forceinline__ float clamp01(float v) { return v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v); }
 
 // Segment-segment closest parameters (clamped-parameter method, Ericson RTCD 5.1.9).
-__device__ void seg_seg(V3 p1, V3 q1, V3 p2, V3 q2, float& s, float& t) {
+__device__ __forceinline__ void seg_seg(V3 p1, V3 q1, V3 p2, V3 q2, float& s, float& t) {
     V3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
     float a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
     const float eps = 1e-12f;
@@ -214,31 +254,39 @@ __device__ __forceinline__ float seg_point(V3 p0, V3 p1, V3 x) {
     return clamp01(dot3(x - p0, d) / dd);
 }
 
-__device__ void np_sphere_sphere(NOut& o, V3 ca, float ra, V3 cb, float rb, float delta) {
+template <int K>
+__device__ __forceinline__ void np_sphere_sphere(NOut& o, V3 ca, float ra, V3 cb, float rb, float delta) {
     V3 d = cb - ca;
     float dist = len3(d);
     V3 n = dist < 1e-9f ? v3(0.0f, 0.0f, 1.0f) : (1.0f / dist) * d;
-    emit(o, ca + ra * n, cb - rb * n, n, dist - ra - rb, delta);
+    emit<K>(o, ca + ra * n, cb - rb * n, n, dist - ra - rb, delta);
 }
 
-__device__ void np_plane_sphere(NOut& o, V3 c, float r, float delta) {
+template <int K>
+__device__ __forceinline__ void np_plane_sphere(NOut& o, V3 c, float r, float delta) {
     V3 n = v3(0.0f, 0.0f, 1.0f);
-    emit(o, v3(c.x, c.y, 0.0f), c - r * n, n, c.z - r, delta);
+    emit<K>(o, v3(c.x, c.y, 0.0f), c - r * n, n, c.z - r, delta);
 }
 
-__device__ void np_plane_box(NOut& o, const Shp& b, float delta) {
-    for (int k = 0; k < 8; ++k) {
-        V3 l = v3((k & 1) ? b.d[0] : -b.d[0], (k & 2) ? b.d[1] : -b.d[1], (k & 4) ? b.d[2] : -b.d[2]);
-        V3 c = b.c + mulv(b.R, l);
-        emit(o, v3(c.x, c.y, 0.0f), c, v3(0.0f, 0.0f, 1.0f), c.z, delta);
-    }
+template <int K>
+__device__ __forceinline__ void plane_box_corner(NOut& o, const Shp& b, float delta) {
+    V3 l = v3((K & 1) ? b.d[0] : -b.d[0], (K & 2) ? b.d[1] : -b.d[1], (K & 4) ? b.d[2] : -b.d[2]);
+    V3 c = b.c + mulv(b.R, l);
+    emit<K>(o, v3(c.x, c.y, 0.0f), c, v3(0.0f, 0.0f, 1.0f), c.z, delta);
+}
+__device__ __forceinline__ void np_plane_box(NOut& o, const Shp& b, float delta) {
+    plane_box_corner<0>(o, b, delta); plane_box_corner<1>(o, b, delta);
+    plane_box_corner<2>(o, b, delta); plane_box_corner<3>(o, b, delta);
+    plane_box_corner<4>(o, b, delta); plane_box_corner<5>(o, b, delta);
+    plane_box_corner<6>(o, b, delta); plane_box_corner<7>(o, b, delta);
 }
 
-__device__ void np_box_sphere(NOut& o, const Shp& bx, V3 c, float r, float delta) {
+__device__ __forceinline__ void np_box_sphere(NOut& o, const Shp& bx, V3 c, float r, float delta) {
     V3 l = mulTv(bx.R, c - bx.c);
     V3 q = l;
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
-        float v = comp(l, i), h = bx.d[i];
+        float v = comp(l, i), h = dim(bx, i);
         setc(q, i, v < -h ? -h : (v > h ? h : v));
     }
     V3 dl = l - q;
@@ -247,12 +295,13 @@ __device__ void np_box_sphere(NOut& o, const Shp& bx, V3 c, float r, float delta
         o.decision = 0;
         float dist = sqrtf(d2);
         V3 n = mulv(bx.R, (1.0f / dist) * dl);
-        emit(o, bx.c + mulv(bx.R, q), c - r * n, n, dist - r, delta);
+        emit<0>(o, bx.c + mulv(bx.R, q), c - r * n, n, dist - r, delta);
     } else {
         int best = 0;
         float bd = bx.d[0] - fabsf(l.x);
+#pragma unroll
         for (int i = 1; i < 3; ++i) {
-            float di = bx.d[i] - fabsf(comp(l, i));
+            float di = dim(bx, i) - fabsf(comp(l, i));
             if (di < bd) { bd = di; best = i; }
         }
         float sg = comp(l, best) >= 0.0f ? 1.0f : -1.0f;
@@ -260,9 +309,9 @@ __device__ void np_box_sphere(NOut& o, const Shp& bx, V3 c, float r, float delta
         setc(nl, best, sg);
         V3 n = mulv(bx.R, nl);
         V3 face = l;
-        setc(face, best, sg * bx.d[best]);
+        setc(face, best, sg * dim(bx, best));
         o.decision = 1 + best;
-        emit(o, bx.c + mulv(bx.R, face), c - r * n, n, -bd - r, delta);
+        emit<0>(o, bx.c + mulv(bx.R, face), c - r * n, n, -bd - r, delta);
     }
 }
 
@@ -272,7 +321,7 @@ __device__ __forceinline__ float box_ext(const Shp& b, V3 L) {
 }
 __device__ __forceinline__ float tie_tol(float s, float hmin) { return 0.05f * fabsf(s) + 0.01f * hmin; }
 
-__device__ void clip_slab(V3 p0, V3 p1, V3 c, V3 a, float h, float& t0, float& t1) {
+__device__ __forceinline__ void clip_slab(V3 p0, V3 p1, V3 c, V3 a, float h, float& t0, float& t1) {
     float u0 = dot3(p0 - c, a), du = dot3(p1 - p0, a);
     if (fabsf(du) < 1e-12f) {
         if (u0 > h || u0 < -h) { t0 = 1.0f; t1 = 0.0f; }
@@ -284,65 +333,80 @@ __device__ void clip_slab(V3 p0, V3 p1, V3 c, V3 a, float h, float& t0, float& t
     if (tb < t1) t1 = tb;
 }
 
-__device__ void np_box_capsule(NOut& o, const Shp& bx, const Shp& cp, float delta) {
+// A separating-axis candidate kept while scanning the axes in order: first strictly larger
+// separation wins, exactly as an argmax over the axis list.
+struct AxisBest {
+    int k;
+    float s;
+    V3 L;
+};
+
+__device__ __forceinline__ void np_box_capsule(NOut& o, const Shp& bx, const Shp& cp, float delta) {
     V3 P0 = cp.p0(), P1 = cp.p1(), u = colm(cp.R, 2);
     float rc = cp.d[0], hl = cp.d[1];
     V3 dc = cp.c - bx.c;
-    float sep[6];
-    V3 ax[6];
-    bool valid[6];
+    // face axes 0..2 and axis x edge axes 3..5; track the best face, the best valid edge and
+    // the largest valid separation
+    AxisBest bf{0, 0.0f, v3(0, 0, 0)}, be{-1, 0.0f, v3(0, 0, 0)};
+    float smax = 0.0f;
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         V3 L = colm(bx.R, i);
         if (dot3(L, dc) < 0.0f) L = -L;
-        ax[i] = L; valid[i] = true;
-        sep[i] = dot3(dc, L) - hl * fabsf(dot3(u, L)) - bx.d[i] - rc;
+        float sep = dot3(dc, L) - hl * fabsf(dot3(u, L)) - dim(bx, i) - rc;
+        if (i == 0 || sep > bf.s) bf = AxisBest{i, sep, L};
+        if (i == 0 || sep > smax) smax = sep;
     }
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         V3 L = cross3(u, colm(bx.R, i));
         float l = len3(L);
-        valid[3 + i] = l >= 1e-6f;
-        if (!valid[3 + i]) { sep[3 + i] = -1e30f; ax[3 + i] = v3(0.0f, 0.0f, 0.0f); continue; }
-        L = (1.0f / l) * L;
-        if (dot3(L, dc) < 0.0f) L = -L;
-        ax[3 + i] = L;
-        sep[3 + i] = dot3(dc, L) - hl * fabsf(dot3(u, L)) - box_ext(bx, L) - rc;
+        if (l >= 1e-6f) {
+            L = (1.0f / l) * L;
+            if (dot3(L, dc) < 0.0f) L = -L;
+            float sep = dot3(dc, L) - hl * fabsf(dot3(u, L)) - box_ext(bx, L) - rc;
+            if (be.k < 0 || sep > be.s) be = AxisBest{3 + i, sep, L};
+            if (sep > smax) smax = sep;
+        }
     }
     float hmin = fminf(fminf(bx.d[0], bx.d[1]), fminf(bx.d[2], rc));
-    int bf = 0;
-    for (int i = 1; i < 3; ++i) if (sep[i] > sep[bf]) bf = i;
-    int be = -1;
-    for (int i = 3; i < 6; ++i) if (valid[i] && (be < 0 || sep[i] > sep[be])) be = i;
-    int best = bf;
-    if (be >= 0 && sep[be] > sep[bf] + tie_tol(sep[bf], hmin)) best = be;
-    float smax = sep[0];
-    for (int i = 1; i < 6; ++i) if (valid[i] && sep[i] > smax) smax = sep[i];
-    o.decision = best;
+    AxisBest best = bf;
+    if (be.k >= 0 && be.s > bf.s + tie_tol(bf.s, hmin)) best = be;
+    o.decision = best.k;
     if (smax >= delta) return;
-    if (best < 3) {
-        int i = best;
-        V3 nr = ax[i];
+    if (best.k < 3) {
+        int i = best.k;
+        V3 nr = best.L;
         int j1 = (i + 1) % 3, j2 = (i + 2) % 3;
         float t0 = 0.0f, t1 = 1.0f;
-        clip_slab(P0, P1, bx.c, colm(bx.R, j1), bx.d[j1], t0, t1);
-        clip_slab(P0, P1, bx.c, colm(bx.R, j2), bx.d[j2], t0, t1);
+        clip_slab(P0, P1, bx.c, axis(bx, j1), dim(bx, j1), t0, t1);
+        clip_slab(P0, P1, bx.c, axis(bx, j2), dim(bx, j2), t0, t1);
+        const float di = dim(bx, i);
         if (t0 <= t1) {
-            int np = t1 > t0 ? 2 : 1;
-            for (int k = 0; k < np; ++k) {
-                float tk = k == 0 ? t0 : t1;
-                V3 C = P0 + tk * (P1 - P0);
-                float above = dot3(C - bx.c, nr) - bx.d[i];
-                emit(o, C - above * nr, C - rc * nr, nr, above - rc, delta);
+            {
+                V3 C = P0 + t0 * (P1 - P0);
+                float above = dot3(C - bx.c, nr) - di;
+                emit<0>(o, C - above * nr, C - rc * nr, nr, above - rc, delta);
+            }
+            if (t1 > t0) {
+                V3 C = P0 + t1 * (P1 - P0);
+                float above = dot3(C - bx.c, nr) - di;
+                emit<1>(o, C - above * nr, C - rc * nr, nr, above - rc, delta);
             }
         } else {
             o.decision = 6 + i;
             float bestd = 1e30f;
             V3 bs = v3(0.0f, 0.0f, 0.0f), be2 = v3(0.0f, 0.0f, 0.0f);
-            V3 fc = bx.c + bx.d[i] * nr;
+            V3 fc = bx.c + di * nr;
+            const V3 a1 = axis(bx, j1), a2 = axis(bx, j2);
+            const float h1 = dim(bx, j1), h2 = dim(bx, j2);
+#pragma unroll
             for (int k = 0; k < 4; ++k) {
-                int along = (k < 2) ? j1 : j2, other = (k < 2) ? j2 : j1;
+                V3 ca = vsel(k < 2, a1, a2), co = vsel(k < 2, a2, a1);     // along, other
+                float ha = k < 2 ? h1 : h2, ho = k < 2 ? h2 : h1;
                 float sg = (k & 1) ? 1.0f : -1.0f;
-                V3 ec = fc + (sg * bx.d[other]) * colm(bx.R, other);
-                V3 e0 = ec - bx.d[along] * colm(bx.R, along), e1 = ec + bx.d[along] * colm(bx.R, along);
+                V3 ec = fc + (sg * ho) * co;
+                V3 e0 = ec - ha * ca, e1 = ec + ha * ca;
                 float s, t;
                 seg_seg(P0, P1, e0, e1, s, t);
                 V3 cs = P0 + s * (P1 - P0), ce = e0 + t * (e1 - e0);
@@ -352,123 +416,191 @@ __device__ void np_box_capsule(NOut& o, const Shp& bx, const Shp& cp, float delt
             }
             float dist = sqrtf(bestd);
             V3 n = dist > 1e-9f ? (1.0f / dist) * (bs - be2) : nr;
-            emit(o, be2, bs - rc * n, n, dist - rc, delta);
+            emit<0>(o, be2, bs - rc * n, n, dist - rc, delta);
         }
     } else {
-        int i = best - 3;
-        V3 L = ax[best];
+        int i = best.k - 3;
+        V3 L = best.L;
         V3 ec = bx.c;
+#pragma unroll
         for (int j = 0; j < 3; ++j) {
             if (j == i) continue;
             float dj = dot3(colm(bx.R, j), L);
-            ec = ec + ((dj >= 0.0f ? 1.0f : -1.0f) * bx.d[j]) * colm(bx.R, j);
+            ec = ec + ((dj >= 0.0f ? 1.0f : -1.0f) * dim(bx, j)) * colm(bx.R, j);
         }
-        V3 e0 = ec - bx.d[i] * colm(bx.R, i), e1 = ec + bx.d[i] * colm(bx.R, i);
+        V3 e0 = ec - dim(bx, i) * axis(bx, i), e1 = ec + dim(bx, i) * axis(bx, i);
         float s, t;
         seg_seg(P0, P1, e0, e1, s, t);
         V3 cs = P0 + s * (P1 - P0), ce = e0 + t * (e1 - e0);
-        emit(o, ce, cs - rc * L, L, dot3(cs - ce, L) - rc, delta);
+        emit<0>(o, ce, cs - rc * L, L, dot3(cs - ce, L) - rc, delta);
     }
 }
 
-// Keep the part of polygon `in` (n vertices) with dot(x, a) <= off (at most 8 vertices out).
-__device__ int clip_poly(const V3* in, int n, V3 a, float off, V3* out) {
-    int m = 0;
-    for (int k = 0; k < n; ++k) {
-        V3 p = in[k], q = in[(k + 1) % n];
-        float dp = dot3(p, a) - off, dq = dot3(q, a) - off;
-        if (dp <= 0.0f && m < 8) out[m++] = p;
-        if (((dp < 0.0f && dq > 0.0f) || (dp > 0.0f && dq < 0.0f)) && m < 8) {
-            float t = dp / (dp - dq);
-            out[m++] = p + t * (q - p);
+// Polygon of at most N vertices held in registers.
+template <int N>
+struct Poly {
+    V3 v[N];
+    int n;
+};
+// Write x at position `at` of a register polygon (a select per slot).
+template <int N>
+__device__ __forceinline__ void poly_put(Poly<N>& P, int at, V3 x) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (j == at) P.v[j] = x;
+}
+// Sutherland-Hodgman step: keep the part of `in` with dot(x, a) <= off.  Walking the edges in
+// order, a vertex inside is kept and an edge crossing the plane adds its crossing point (the
+// output is capped at 8 vertices).  `ok` turns false if the output would outgrow NO slots, in
+// which case the caller redoes the clip with 8-vertex polygons.
+template <int NI, int NO>
+__device__ __forceinline__ void clip_step(const Poly<NI>& in, V3 a, float off, Poly<NO>& out, bool& ok) {
+    out.n = 0;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        if (k < in.n) {
+            V3 p = in.v[k];
+            V3 q = vsel(k + 1 < in.n, in.v[k + 1 < NI ? k + 1 : 0], in.v[0]);
+            float dp = dot3(p, a) - off, dq = dot3(q, a) - off;
+            if (dp <= 0.0f && out.n < 8) {
+                if (out.n < NO) poly_put(out, out.n, p); else ok = false;
+                out.n++;
+            }
+            if (((dp < 0.0f && dq > 0.0f) || (dp > 0.0f && dq < 0.0f)) && out.n < 8) {
+                float t = dp / (dp - dq);
+                if (out.n < NO) poly_put(out, out.n, p + t * (q - p)); else ok = false;
+                out.n++;
+            }
         }
     }
-    return m;
+    if (out.n > NO) out.n = NO;
 }
 
-__device__ void np_box_box(NOut& o, const Shp& A, const Shp& B, float delta) {
+// The incident face (4 vertices) clipped against the reference face's four side planes; first
+// with slots for a convex input (one more vertex per plane), and only if a clip would outgrow
+// them (a degenerate, numerically non-convex case) again with 8 slots throughout.
+__device__ __forceinline__ void clip_face(const V3 q[4], V3 a1, float o1p, float o1m, V3 a2, float o2p, float o2m,
+                                          Poly<8>& res) {
+    bool ok = true;
+    Poly<4> p4;
+    p4.v[0] = q[0]; p4.v[1] = q[1]; p4.v[2] = q[2]; p4.v[3] = q[3]; p4.n = 4;
+    Poly<5> p5; Poly<6> p6; Poly<7> p7;
+    clip_step(p4, a1, o1p, p5, ok);
+    clip_step(p5, -a1, o1m, p6, ok);
+    clip_step(p6, a2, o2p, p7, ok);
+    clip_step(p7, -a2, o2m, res, ok);
+    if (!ok) {
+        Poly<8> x, y;
+        x.n = 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x.v[j] = q[j];
+#pragma unroll
+        for (int j = 4; j < 8; ++j) x.v[j] = v3(0, 0, 0);
+        bool dummy = true;
+        clip_step(x, a1, o1p, y, dummy);
+        clip_step(y, -a1, o1m, x, dummy);
+        clip_step(x, a2, o2p, y, dummy);
+        clip_step(y, -a2, o2m, res, dummy);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void emit_face_point(NOut& o, const Poly<8>& P, const Shp& Rf, V3 nref, float dri, V3 nAB,
+                                                bool refA, float delta) {
+    if (K < P.n) {
+        V3 p = P.v[K];
+        float s = dot3(p - Rf.c, nref) - dri;
+        V3 onref = p - s * nref;
+        if (refA) emit<K>(o, onref, p, nAB, s, delta);
+        else emit<K>(o, p, onref, nAB, s, delta);
+    }
+}
+
+__device__ __forceinline__ void np_box_box(NOut& o, const Shp& A, const Shp& B, float delta) {
     V3 d = B.c - A.c;
-    float sep[15];
-    V3 ax[15];
-    bool valid[15];
+    // axes: A faces 0..2, B faces 3..5, edge crosses 6..14 (skipped when degenerate)
+    AxisBest fa{0, 0.0f, v3(0, 0, 0)}, fb{3, 0.0f, v3(0, 0, 0)}, fe{-1, 0.0f, v3(0, 0, 0)};
+    float smax = 0.0f;
+#pragma unroll
     for (int k = 0; k < 15; ++k) {
         V3 L;
+        bool valid = true;
         if (k < 3) L = colm(A.R, k);
         else if (k < 6) L = colm(B.R, k - 3);
         else {
             L = cross3(colm(A.R, (k - 6) / 3), colm(B.R, (k - 6) % 3));
             float l = len3(L);
-            if (l < 1e-6f) { valid[k] = false; sep[k] = -1e30f; ax[k] = v3(0.0f, 0.0f, 0.0f); continue; }
+            valid = l >= 1e-6f;
             L = (1.0f / l) * L;
         }
-        if (dot3(L, d) < 0.0f) L = -L;
-        valid[k] = true;
-        ax[k] = L;
-        sep[k] = dot3(d, L) - box_ext(A, L) - box_ext(B, L);
+        if (valid) {
+            if (dot3(L, d) < 0.0f) L = -L;
+            float sep = dot3(d, L) - box_ext(A, L) - box_ext(B, L);
+            if (k < 3) { if (k == 0 || sep > fa.s) fa = AxisBest{k, sep, L}; }
+            else if (k < 6) { if (k == 3 || sep > fb.s) fb = AxisBest{k, sep, L}; }
+            else if (fe.k < 0 || sep > fe.s) fe = AxisBest{k, sep, L};
+            if (k == 0 || sep > smax) smax = sep;
+        }
     }
     float hmin = fminf(fminf(fminf(A.d[0], A.d[1]), fminf(A.d[2], B.d[0])), fminf(B.d[1], B.d[2]));
-    int fa = 0, fb = 3, fe = -1;
-    for (int k = 1; k < 3; ++k) if (sep[k] > sep[fa]) fa = k;
-    for (int k = 4; k < 6; ++k) if (sep[k] > sep[fb]) fb = k;
-    for (int k = 6; k < 15; ++k) if (valid[k] && (fe < 0 || sep[k] > sep[fe])) fe = k;
-    int best = fb;
-    if (sep[fa] > sep[fb] + tie_tol(sep[fb], hmin)) best = fa;
-    if (fe >= 0 && sep[fe] > sep[best] + tie_tol(sep[best], hmin)) best = fe;
-    float smax = sep[0];
-    for (int k = 1; k < 15; ++k) if (valid[k] && sep[k] > smax) smax = sep[k];
-    o.decision = best;
+    AxisBest best = fb;
+    if (fa.s > fb.s + tie_tol(fb.s, hmin)) best = fa;
+    if (fe.k >= 0 && fe.s > best.s + tie_tol(best.s, hmin)) best = fe;
+    o.decision = best.k;
     if (smax >= delta) return;
-    if (best < 6) {
-        bool refA = best < 3;
-        const Shp& Rf = refA ? A : B;
-        const Shp& In = refA ? B : A;
-        int ri = refA ? best : best - 3;
-        V3 nref = refA ? ax[best] : -ax[best];
+    if (best.k < 6) {
+        const bool refA = best.k < 3;
+        const Shp Rf = pick(refA, A, B);
+        const Shp In = pick(refA, B, A);
+        const int ri = refA ? best.k : best.k - 3;
+        V3 nref = vsel(refA, best.L, -best.L);
         int ii = 0;
         float bd = fabsf(dot3(colm(In.R, 0), nref));
+#pragma unroll
         for (int j = 1; j < 3; ++j) {
             float dj = fabsf(dot3(colm(In.R, j), nref));
             if (dj > bd) { bd = dj; ii = j; }
         }
-        float sgn = dot3(colm(In.R, ii), nref) >= 0.0f ? -1.0f : 1.0f;
-        V3 fcen = In.c + (sgn * In.d[ii]) * colm(In.R, ii);
+        const V3 ai = axis(In, ii);
+        float sgn = dot3(ai, nref) >= 0.0f ? -1.0f : 1.0f;
+        V3 fcen = In.c + (sgn * dim(In, ii)) * ai;
         int u = (ii + 1) % 3, v = (ii + 2) % 3;
-        V3 U = In.d[u] * colm(In.R, u), Wv = In.d[v] * colm(In.R, v);
-        V3 poly[8], tmp[8];
-        poly[0] = fcen + U + Wv; poly[1] = fcen - U + Wv; poly[2] = fcen - U - Wv; poly[3] = fcen + U - Wv;
-        int n = 4;
+        V3 U = dim(In, u) * axis(In, u), Wv = dim(In, v) * axis(In, v);
+        V3 q[4] = {fcen + U + Wv, fcen - U + Wv, fcen - U - Wv, fcen + U - Wv};
         int r1 = (ri + 1) % 3, r2 = (ri + 2) % 3;
-        V3 a1 = colm(Rf.R, r1), a2 = colm(Rf.R, r2);
-        n = clip_poly(poly, n, a1, dot3(Rf.c, a1) + Rf.d[r1], tmp);
-        n = clip_poly(tmp, n, -a1, -dot3(Rf.c, a1) + Rf.d[r1], poly);
-        n = clip_poly(poly, n, a2, dot3(Rf.c, a2) + Rf.d[r2], tmp);
-        n = clip_poly(tmp, n, -a2, -dot3(Rf.c, a2) + Rf.d[r2], poly);
-        V3 nAB = refA ? nref : -nref;
-        for (int k = 0; k < n; ++k) {
-            V3 p = poly[k];
-            float s = dot3(p - Rf.c, nref) - Rf.d[ri];
-            V3 onref = p - s * nref;
-            if (refA) emit(o, onref, p, nAB, s, delta);
-            else emit(o, p, onref, nAB, s, delta);
-        }
+        V3 a1 = axis(Rf, r1), a2 = axis(Rf, r2);
+        const float h1 = dim(Rf, r1), h2 = dim(Rf, r2);
+        Poly<8> P;
+        clip_face(q, a1, dot3(Rf.c, a1) + h1, -dot3(Rf.c, a1) + h1, a2, dot3(Rf.c, a2) + h2, -dot3(Rf.c, a2) + h2, P);
+        V3 nAB = vsel(refA, nref, -nref);
+        const float dri = dim(Rf, ri);
+        emit_face_point<0>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<1>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<2>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<3>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<4>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<5>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<6>(o, P, Rf, nref, dri, nAB, refA, delta);
+        emit_face_point<7>(o, P, Rf, nref, dri, nAB, refA, delta);
     } else {
-        int ia = (best - 6) / 3, ib = (best - 6) % 3;
-        V3 L = ax[best];
+        int ia = (best.k - 6) / 3, ib = (best.k - 6) % 3;
+        V3 L = best.L;
         V3 ca = A.c, cb = B.c;
+#pragma unroll
         for (int j = 0; j < 3; ++j) {
-            if (j != ia) { float dj = dot3(colm(A.R, j), L); ca = ca + ((dj >= 0.0f ? 1.0f : -1.0f) * A.d[j]) * colm(A.R, j); }
-            if (j != ib) { float dj = dot3(colm(B.R, j), L); cb = cb + ((dj >= 0.0f ? -1.0f : 1.0f) * B.d[j]) * colm(B.R, j); }
+            if (j != ia) { float dj = dot3(colm(A.R, j), L); ca = ca + ((dj >= 0.0f ? 1.0f : -1.0f) * dim(A, j)) * colm(A.R, j); }
+            if (j != ib) { float dj = dot3(colm(B.R, j), L); cb = cb + ((dj >= 0.0f ? -1.0f : 1.0f) * dim(B, j)) * colm(B.R, j); }
         }
-        V3 a0 = ca - A.d[ia] * colm(A.R, ia), a1 = ca + A.d[ia] * colm(A.R, ia);
-        V3 b0 = cb - B.d[ib] * colm(B.R, ib), b1 = cb + B.d[ib] * colm(B.R, ib);
+        V3 a0 = ca - dim(A, ia) * axis(A, ia), a1 = ca + dim(A, ia) * axis(A, ia);
+        V3 b0 = cb - dim(B, ib) * axis(B, ib), b1 = cb + dim(B, ib) * axis(B, ib);
         float s, t;
         seg_seg(a0, a1, b0, b1, s, t);
         V3 pa = a0 + s * (a1 - a0), pb = b0 + t * (b1 - b0);
-        emit(o, pa, pb, L, dot3(pb - pa, L), delta);
+        emit<0>(o, pa, pb, L, dot3(pb - pa, L), delta);
     }
 }
 
-__device__ void np_capsule_capsule(NOut& o, const Shp& A, const Shp& B, float delta) {
+__device__ __forceinline__ void np_capsule_capsule(NOut& o, const Shp& A, const Shp& B, float delta) {
     V3 a0 = A.p0(), a1 = A.p1(), b0 = B.p0(), b1 = B.p1();
     V3 d1 = a1 - a0, d2 = b1 - b0;
     V3 cr = cross3(d1, d2);
@@ -478,10 +610,15 @@ __device__ void np_capsule_capsule(NOut& o, const Shp& A, const Shp& B, float de
         float lo = fmaxf(0.0f, fminf(s0, s1)), hi = fminf(1.0f, fmaxf(s0, s1));
         if (lo < hi) {
             o.decision = 1;
-            for (int k = 0; k < 2; ++k) {
-                V3 pa = a0 + (k == 0 ? lo : hi) * d1;
+            {
+                V3 pa = a0 + lo * d1;
                 float t = seg_point(b0, b1, pa);
-                np_sphere_sphere(o, pa, A.d[0], b0 + t * d2, B.d[0], delta);
+                np_sphere_sphere<0>(o, pa, A.d[0], b0 + t * d2, B.d[0], delta);
+            }
+            {
+                V3 pa = a0 + hi * d1;
+                float t = seg_point(b0, b1, pa);
+                np_sphere_sphere<1>(o, pa, A.d[0], b0 + t * d2, B.d[0], delta);
             }
             return;
         }
@@ -489,24 +626,25 @@ __device__ void np_capsule_capsule(NOut& o, const Shp& A, const Shp& B, float de
     o.decision = 0;
     float s, t;
     seg_seg(a0, a1, b0, b1, s, t);
-    np_sphere_sphere(o, a0 + s * d1, A.d[0], b0 + t * d2, B.d[0], delta);
+    np_sphere_sphere<0>(o, a0 + s * d1, A.d[0], b0 + t * d2, B.d[0], delta);
 }
 
-__device__ void np_flip(NOut& o) {
-    for (int k = 0; k < o.n; ++k) o.pt[k].n = -o.pt[k].n;
+__device__ __forceinline__ void np_flip(NOut& o) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) o.pt[k].n = -o.pt[k].n;   // the flipped generators fill slots 0..1
 }
 
-__device__ void np_pair(NOut& o, const Shp& A, const Shp& B, float delta) {
+__device__ __forceinline__ void np_pair(NOut& o, const Shp& A, const Shp& B, float delta) {
     int ta = A.type, tb = B.type;
-    if (ta == 0 && tb == 0) { np_sphere_sphere(o, A.c, A.d[0], B.c, B.d[0], delta); return; }
+    if (ta == 0 && tb == 0) { np_sphere_sphere<0>(o, A.c, A.d[0], B.c, B.d[0], delta); return; }
     if (ta == 0 && tb == 1) {
         float t = seg_point(B.p0(), B.p1(), A.c);
-        np_sphere_sphere(o, A.c, A.d[0], B.p0() + t * (B.p1() - B.p0()), B.d[0], delta);
+        np_sphere_sphere<0>(o, A.c, A.d[0], B.p0() + t * (B.p1() - B.p0()), B.d[0], delta);
         return;
     }
     if (ta == 1 && tb == 0) {
         float t = seg_point(A.p0(), A.p1(), B.c);
-        np_sphere_sphere(o, A.p0() + t * (A.p1() - A.p0()), A.d[0], B.c, B.d[0], delta);
+        np_sphere_sphere<0>(o, A.p0() + t * (A.p1() - A.p0()), A.d[0], B.c, B.d[0], delta);
         return;
     }
     if (ta == 1 && tb == 1) { np_capsule_capsule(o, A, B, delta); return; }
@@ -517,61 +655,84 @@ __device__ void np_pair(NOut& o, const Shp& A, const Shp& B, float delta) {
     np_box_box(o, A, B, delta);
 }
 
-__device__ void np_plane(NOut& o, const Shp& B, float delta) {
-    if (B.type == 0) np_plane_sphere(o, B.c, B.d[0], delta);
-    else if (B.type == 1) { np_plane_sphere(o, B.p0(), B.d[0], delta); np_plane_sphere(o, B.p1(), B.d[0], delta); }
+__device__ __forceinline__ void np_plane(NOut& o, const Shp& B, float delta) {
+    if (B.type == 0) np_plane_sphere<0>(o, B.c, B.d[0], delta);
+    else if (B.type == 1) { np_plane_sphere<0>(o, B.p0(), B.d[0], delta); np_plane_sphere<1>(o, B.p1(), B.d[0], delta); }
     else np_plane_box(o, B, delta);
 }
 
 // <= 4 points: deepest; farthest from it; largest triangle; most area added outside the
-// triangle; lowest index on ties; kept points in their original order.
-__device__ void reduce4(NOut& o) {
-    if (o.n <= 4) return;
-    int n = o.n;
-    unsigned used = 0;
-    int k0 = 0;
-    for (int k = 1; k < n; ++k) if (o.pt[k].s < o.pt[k0].s) k0 = k;
-    used |= 1u << k0;
-    // each selection starts from the first unused point, so an index is always valid
-    int k1 = k0 == 0 ? 1 : 0; float b1 = -1.0f;
-    for (int k = 0; k < n; ++k) {
-        if (used >> k & 1) continue;
-        V3 d = o.pt[k].p - o.pt[k0].p;
-        float v = dot3(d, d);
-        if (v > b1) { b1 = v; k1 = k; }
+// triangle; first point of the list on ties; kept points in their original order.  The list is
+// the valid slots in slot order; `used` marks slots.
+__device__ __forceinline__ void reduce4(NOut& o) {
+    if (n_points(o) <= 4) return;
+    const uint32_t valid = o.mask;
+    // deepest
+    int k0 = __ffs(valid) - 1;
+    float s0 = 0.0f;
+    V3 p0 = v3(0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k == k0) { s0 = o.pt[k].s; p0 = o.pt[k].p; }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (((valid >> k) & 1) && o.pt[k].s < s0) { k0 = k; s0 = o.pt[k].s; p0 = o.pt[k].p; }
+    uint32_t used = 1u << k0;
+    // farthest from the deepest (starting from the first unused point)
+    int k1 = __ffs(valid & ~used) - 1;
+    float b1 = -1.0f;
+    V3 p1 = v3(0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k == k1) p1 = o.pt[k].p;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!((valid & ~used) >> k & 1)) continue;
+        V3 dd = o.pt[k].p - p0;
+        float v = dot3(dd, dd);
+        if (v > b1) { b1 = v; k1 = k; p1 = o.pt[k].p; }
     }
     used |= 1u << k1;
-    int k2 = 0;
-    while (used >> k2 & 1) ++k2;
+    // largest triangle with the first two
+    int k2 = __ffs(valid & ~used) - 1;
     float b2 = -1.0f;
-    V3 e01 = o.pt[k1].p - o.pt[k0].p;
-    for (int k = 0; k < n; ++k) {
-        if (used >> k & 1) continue;
-        V3 c = cross3(e01, o.pt[k].p - o.pt[k0].p);
-        float v = dot3(c, c);
-        if (v > b2) { b2 = v; k2 = k; }
+    V3 p2 = v3(0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k == k2) p2 = o.pt[k].p;
+    V3 e01 = p1 - p0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!((valid & ~used) >> k & 1)) continue;
+        V3 cc = cross3(e01, o.pt[k].p - p0);
+        float v = dot3(cc, cc);
+        if (v > b2) { b2 = v; k2 = k; p2 = o.pt[k].p; }
     }
     used |= 1u << k2;
-    V3 nt = cross3(e01, o.pt[k2].p - o.pt[k0].p);
-    int tri[3] = {k0, k1, k2};
-    int k3 = 0;
-    while (used >> k3 & 1) ++k3;
+    V3 nt = cross3(e01, p2 - p0);
+    // most area added outside the triangle
+    int k3 = __ffs(valid & ~used) - 1;
     float b3 = -1e30f;
-    for (int k = 0; k < n; ++k) {
-        if (used >> k & 1) continue;
-        float best = -1e30f;
-        for (int e = 0; e < 3; ++e) {
-            V3 pa = o.pt[tri[e]].p, pb = o.pt[tri[(e + 1) % 3]].p;
-            float v = -dot3(cross3(pb - pa, o.pt[k].p - pa), nt);
-            if (v > best) best = v;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!((valid & ~used) >> k & 1)) continue;
+        float bestv = -1e30f;
+        {
+            float v = -dot3(cross3(p1 - p0, o.pt[k].p - p0), nt);
+            if (v > bestv) bestv = v;
         }
-        if (best > b3) { b3 = best; k3 = k; }
+        {
+            float v = -dot3(cross3(p2 - p1, o.pt[k].p - p1), nt);
+            if (v > bestv) bestv = v;
+        }
+        {
+            float v = -dot3(cross3(p0 - p2, o.pt[k].p - p2), nt);
+            if (v > bestv) bestv = v;
+        }
+        if (bestv > b3) { b3 = bestv; k3 = k; }
     }
     used |= 1u << k3;
-    int m = 0;
-    for (int k = 0; k < n; ++k)
-        if (used >> k & 1) o.pt[m++] = o.pt[k];
-    o.n = m;
+    o.mask = used;
 }
 
 // Duff et al. 2017 orthonormal basis: t1 for unit n (t2 = n x t1).
@@ -681,80 +842,13 @@ __device__ __forceinline__ V3 disp(const PoseR& p, V3 r) {
     return p.dx + (2.0f * p.dq.w) * ur + 2.0f * cross3(u, ur);
 }
 
-__device__ void manifold_warm(const EnvCtx& c, int m) {
-    int a, b, first, cnt;
-    man_header(c, m, a, b, first, cnt);
-    BodyR A = load_body(c, a), B = load_body(c, b);
-    for (int k = first; k < first + cnt; ++k)
-        imp_lin(A, B, pr3(c, R_RA, k), pr3(c, R_RB, k), pr(c, R_LN, k) * pr3(c, R_N, k));
-    V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m);
-    V3 t2 = cross3(nb, t1);
-    imp_lin(A, B, mf3(c, M_RA, m), mf3(c, M_RB, m), mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * t2);
-    imp_ang(A, B, mf(c, M_LTW, m) * nb);
-    store_body(c, a, A);
-    store_body(c, b, B);
-}
-
 __device__ __forceinline__ V3 rel_vel(const EnvCtx& c, int a, int b, V3 rA, V3 rB) {
     V3 vb = v_of(c, b) + cross3(w_of(c, b), rB);
     V3 va = a >= 0 ? v_of(c, a) + cross3(w_of(c, a), rA) : v3(0, 0, 0);
     return vb - va;
 }
 
-__device__ void manifold_solve(const EnvCtx& c, int m, float h, bool vpass) {
-    const BatchDev& bd = *c.bd;
-    int a, b, first, cnt;
-    man_header(c, m, a, b, first, cnt);
-    const bool has_a = a >= 0;
-    BodyR A = load_body(c, a), B = load_body(c, b);
-    PoseR pA = load_pose(c, a), pB = load_pose(c, b);
-    float lsum = 0.0f;
-    for (int k = first; k < first + cnt; ++k) {
-        V3 rA = pr3(c, R_RA, k), rB = pr3(c, R_RB, k), n = pr3(c, R_N, k);
-        V3 dA = has_a ? disp(pA, rA) : v3(0, 0, 0);
-        V3 dB = disp(pB, rB);
-        float s = pr(c, R_S0, k) + dot3(n, dB - dA);
-        float bias;
-        if (s > 0.0f) bias = s / h;
-        else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
-        float vn = dot3(relv(A, B, has_a, rA, rB), n);
-        float dl = -pr(c, R_MN, k) * (vn + bias);
-        float old = pr(c, R_LN, k);
-        float nl = fmaxf(old + dl, 0.0f);
-        pr(c, R_LN, k) = nl;
-        imp_lin(A, B, rA, rB, (nl - old) * n);
-        lsum += nl;
-    }
-    float lim = mf(c, M_MU, m) * lsum;
-    V3 rA = mf3(c, M_RA, m), rB = mf3(c, M_RB, m), nb = mf3(c, M_NB, m), t1 = mf3(c, M_T1, m);
-    V3 t2 = cross3(nb, t1);
-    {
-        float vt = dot3(relv(A, B, has_a, rA, rB), t1);
-        float old = mf(c, M_LT1, m);
-        float nl = fminf(fmaxf(old - mf(c, M_MT1, m) * vt, -lim), lim);
-        mfr(c, M_LT1, m) = nl;
-        imp_lin(A, B, rA, rB, (nl - old) * t1);
-    }
-    {
-        float vt = dot3(relv(A, B, has_a, rA, rB), t2);
-        float old = mf(c, M_LT2, m);
-        float nl = fminf(fmaxf(old - mf(c, M_MT2, m) * vt, -lim), lim);
-        mfr(c, M_LT2, m) = nl;
-        imp_lin(A, B, rA, rB, (nl - old) * t2);
-    }
-    {
-        float limw = mf(c, M_RT, m) * lim;
-        float wr = dot3(nb, B.w - A.w);
-        float old = mf(c, M_LTW, m);
-        float nl = fminf(fmaxf(old - mf(c, M_MTW, m) * wr, -limw), limw);
-        mfr(c, M_LTW, m) = nl;
-        imp_ang(A, B, (nl - old) * nb);
-    }
-    store_body(c, a, A);
-    store_body(c, b, B);
-}
-
-__device__ void manifold_restitution(const EnvCtx& c, int m) {
+__device__ __forceinline__ void manifold_restitution(const EnvCtx& c, int m) {
     const BatchDev& bd = *c.bd;
     int a, b, first, cnt;
     man_header(c, m, a, b, first, cnt);
@@ -815,7 +909,7 @@ __device__ __forceinline__ Qt qc_of(const EnvCtx& c, int i) {
     return i < 0 ? Qt{1.0f, 0.0f, 0.0f, 0.0f} : ld4(c.L, c.lay.QC, c.lay.n, i);
 }
 
-__device__ JFrame joint_frame(const EnvCtx& c, int j) {
+__device__ __forceinline__ JFrame joint_frame(const EnvCtx& c, int j) {
     const float* J = jrec(c, j);
     JFrame f;
     f.a = reinterpret_cast<const int*>(J)[J_PA];
@@ -829,7 +923,7 @@ __device__ JFrame joint_frame(const EnvCtx& c, int j) {
     return f;
 }
 
-__device__ void joint_warm(const EnvCtx& c, int j) {
+__device__ __forceinline__ void joint_warm(const EnvCtx& c, int j) {
     JFrame f = joint_frame(c, j);
     float* J = jrec(c, j);
     BodyR A = load_body(c, f.a), B = load_body(c, f.b);
@@ -840,7 +934,7 @@ __device__ void joint_warm(const EnvCtx& c, int j) {
     store_body(c, f.b, B);
 }
 
-__device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
+__device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
     const BatchDev& bd = *c.bd;
     JFrame f = joint_frame(c, j);
     float* J = jrec(c, j);
@@ -855,7 +949,7 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
         float K[3][3] = {{im, 0, 0}, {0, im, 0}, {0, 0, im}};
         for (int side = 0; side < 2; ++side) {
             if (side == 0 && a < 0) continue;
-            V3 r = side == 0 ? f.rA : f.rB;
+            V3 r = vsel(side == 0, f.rA, f.rB);
             const S6& I = side == 0 ? Ia : Ib;
             float Im[3][3] = {{I.xx, I.xy, I.xz}, {I.xy, I.yy, I.yz}, {I.xz, I.yz, I.zz}};
             float Sx[3][3] = {{0, -r.z, r.y}, {r.z, 0, -r.x}, {-r.y, r.x, 0}};
@@ -934,7 +1028,7 @@ __device__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
 }
 
 // ----------------------------------------------------------------------------- S1 AABB (exact)
-__device__ void body_aabb(const EnvCtx& c, int i) {
+__device__ __forceinline__ void body_aabb(const EnvCtx& c, int i) {
 #pragma clang fp contract(off)
     const Lay& l = c.lay;
     const int n = l.n;
@@ -980,35 +1074,185 @@ __device__ __forceinline__ bool aabb_overlap(const EnvCtx& c, int a, int b) {
 // (pair_of lives in ms_dev.h)
 
 // ----------------------------------------------------------------------------- schedule runner
-enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
 
 // Walk a schedule: entry e = (start | count << 16) into the colour order; blocks of one entry
 // touch disjoint dynamic bodies, so the lanes of the group run them concurrently.  `emax` is
 // the wave-wide maximum number of entries (every lane reaches every barrier).
-__device__ void run_schedule(const EnvCtx& c, int sched_off, int nsched, int emax, int op, float h, int li) {
+// Rows of one manifold block that stay fixed during a colour sweep (the block's own impulses
+// change only in its own phase; body masses, inertias and pose offsets change only between
+// sweeps).  A lane loads them for its next block at the end of the current phase, so a phase
+// waits on one round of LDS loads (the two bodies' velocities) instead of a chain of them.
+struct ManPre {
+    int a, b, cnt;
+    float ima, imb;
+    S6 Ia, Ib;
+    bool da, db;
+    PoseR pa, pb;
+    V3 rA[4], rB[4], n[4];
+    float s0[4], mn[4], ln[4];
+    V3 mrA, mrB, nb, t1;
+    float mt1, mt2, mtw, mu, rt, lt1, lt2, ltw;
+    int first;
+};
+
+template <bool SOLVE>
+__device__ __forceinline__ void man_prefetch(const EnvCtx& c, int m, ManPre& p) {
+    man_header(c, m, p.a, p.b, p.first, p.cnt);
+    const int n = c.lay.n;
+    p.da = is_dyn(c, p.a);
+    p.db = is_dyn(c, p.b);
+    p.ima = p.a >= 0 ? c.L[c.lay.INVM + p.a] : 0.0f;
+    p.imb = c.L[c.lay.INVM + p.b];
+    p.Ia = p.a >= 0 ? load_iw(c, p.a) : S6{0, 0, 0, 0, 0, 0};
+    p.Ib = load_iw(c, p.b);
+    if (SOLVE) {
+        p.pa = load_pose(c, p.a);
+        p.pb = load_pose(c, p.b);
+    }
+    (void)n;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < p.cnt) {
+            const int q = p.first + k;
+            p.rA[k] = pr3(c, R_RA, q);
+            p.rB[k] = pr3(c, R_RB, q);
+            p.n[k] = pr3(c, R_N, q);
+            p.ln[k] = pr(c, R_LN, q);
+            if (SOLVE) { p.s0[k] = pr(c, R_S0, q); p.mn[k] = pr(c, R_MN, q); }
+        }
+    }
+    p.mrA = mf3(c, M_RA, m);
+    p.mrB = mf3(c, M_RB, m);
+    p.nb = mf3(c, M_NB, m);
+    p.t1 = mf3(c, M_T1, m);
+    p.lt1 = mf(c, M_LT1, m);
+    p.lt2 = mf(c, M_LT2, m);
+    p.ltw = mf(c, M_LTW, m);
+    if (SOLVE) {
+        p.mt1 = mf(c, M_MT1, m); p.mt2 = mf(c, M_MT2, m); p.mtw = mf(c, M_MTW, m);
+        p.mu = mf(c, M_MU, m); p.rt = mf(c, M_RT, m);
+    }
+}
+
+__device__ __forceinline__ void man_bodies(const EnvCtx& c, const ManPre& p, BodyR& A, BodyR& B) {
+    const int n = c.lay.n;
+    if (p.a >= 0) { A.v = ld3(c.L, c.lay.V, n, p.a); A.w = ld3(c.L, c.lay.W, n, p.a); }
+    else { A.v = v3(0, 0, 0); A.w = v3(0, 0, 0); }
+    B.v = ld3(c.L, c.lay.V, n, p.b);
+    B.w = ld3(c.L, c.lay.W, n, p.b);
+    A.im = p.ima; A.I = p.Ia; A.dyn = p.da;
+    B.im = p.imb; B.I = p.Ib; B.dyn = p.db;
+}
+
+// Warm start of a manifold block: re-apply its accumulated impulses (normal rows in point order,
+// then the two tangent rows and the twist row).
+__device__ __forceinline__ void man_warm_pre(const EnvCtx& c, const ManPre& p) {
+    BodyR A, B;
+    man_bodies(c, p, A, B);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < p.cnt) imp_lin(A, B, p.rA[k], p.rB[k], p.ln[k] * p.n[k]);
+    V3 t2 = cross3(p.nb, p.t1);
+    imp_lin(A, B, p.mrA, p.mrB, p.lt1 * p.t1 + p.lt2 * t2);
+    imp_ang(A, B, p.ltw * p.nb);
+    store_body(c, p.a, A);
+    store_body(c, p.b, B);
+}
+
+// One Gauss-Seidel visit of a manifold block: normal rows in point order (separation from the
+// pose offsets, speculative / Baumgarte bias, clamped accumulated impulse), then the friction
+// patch: two tangent rows and the twist row, clamped by mu and mu * r_t times the normal sum.
+__device__ __forceinline__ void man_solve_pre(const EnvCtx& c, int m, const ManPre& p, float h, bool vpass) {
+    const BatchDev& bd = *c.bd;
+    const bool has_a = p.a >= 0;
+    BodyR A, B;
+    man_bodies(c, p, A, B);
+    float lsum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < p.cnt) {
+            const V3 rA = p.rA[k], rB = p.rB[k], n = p.n[k];
+            V3 dA = has_a ? disp(p.pa, rA) : v3(0, 0, 0);
+            V3 dB = disp(p.pb, rB);
+            float s = p.s0[k] + dot3(n, dB - dA);
+            float bias;
+            if (s > 0.0f) bias = s / h;
+            else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
+            float vn = dot3(relv(A, B, has_a, rA, rB), n);
+            float dl = -p.mn[k] * (vn + bias);
+            float old = p.ln[k];
+            float nl = fmaxf(old + dl, 0.0f);
+            pr(c, R_LN, p.first + k) = nl;
+            imp_lin(A, B, rA, rB, (nl - old) * n);
+            lsum += nl;
+        }
+    }
+    float lim = p.mu * lsum;
+    V3 t2 = cross3(p.nb, p.t1);
+    {
+        float vt = dot3(relv(A, B, has_a, p.mrA, p.mrB), p.t1);
+        float nl = fminf(fmaxf(p.lt1 - p.mt1 * vt, -lim), lim);
+        mfr(c, M_LT1, m) = nl;
+        imp_lin(A, B, p.mrA, p.mrB, (nl - p.lt1) * p.t1);
+    }
+    {
+        float vt = dot3(relv(A, B, has_a, p.mrA, p.mrB), t2);
+        float nl = fminf(fmaxf(p.lt2 - p.mt2 * vt, -lim), lim);
+        mfr(c, M_LT2, m) = nl;
+        imp_lin(A, B, p.mrA, p.mrB, (nl - p.lt2) * t2);
+    }
+    {
+        float limw = p.rt * lim;
+        float wr = dot3(p.nb, B.w - A.w);
+        float nl = fminf(fmaxf(p.ltw - p.mtw * wr, -limw), limw);
+        mfr(c, M_LTW, m) = nl;
+        imp_ang(A, B, (nl - p.ltw) * p.nb);
+    }
+    store_body(c, p.a, A);
+    store_body(c, p.b, B);
+}
+
+enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
+
+// Block of this lane at schedule entry e (-1: none).
+__device__ __forceinline__ int sched_block(const EnvCtx& c, int sched_off, int nsched, int e, int li) {
+    if (e >= nsched) return -1;
+    const int ent = reinterpret_cast<const int*>(c.L + sched_off)[e];
+    const int start = ent & 0xFFFF, cnt = ent >> 16;
+    if (li >= cnt) return -1;
+    return reinterpret_cast<const uint16_t*>(c.L + c.lay.ORDER)[start + li];
+}
+
+// One sweep over a schedule: entry by entry (colour order), each lane visiting its block of the
+// entry, a wavefront sync between entries.  A manifold block of a warm or solve sweep runs from
+// its rows loaded in one batch; when no env of the wave has joints (PIPE) the rows of a lane's
+// next block are loaded at the end of the current entry, behind the compute of this one.
+template <int OP, bool PIPE>
+__device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int nsched, int emax, float h, int li) {
     const Lay& l = c.lay;
-    const int* SCH = reinterpret_cast<const int*>(c.L + sched_off);
-    const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
+    constexpr bool PRE = OP == OP_WARM || OP == OP_SOLVE || OP == OP_VSOLVE;
+    constexpr bool SOLVE = OP == OP_SOLVE || OP == OP_VSOLVE;
+    int blk = sched_block(c, sched_off, nsched, 0, li);
+    ManPre pre;
+    if (PIPE && PRE && blk >= 0) man_prefetch<SOLVE>(c, blk - l.nj, pre);
     for (int e = 0; e < emax; ++e) {
-        if (e < nsched) {
-            int ent = SCH[e];
-            int start = ent & 0xFFFF, cnt = ent >> 16;
-            if (li < cnt) {
-                int blk = ORD[start + li];
-                if (blk < l.nj) {
-                    if (op == OP_WARM) joint_warm(c, blk);
-                    else if (op == OP_SOLVE || op == OP_JOINT) joint_solve(c, blk, h, false);
-                    else if (op == OP_VSOLVE) joint_solve(c, blk, h, true);
-                } else {
-                    int m = blk - l.nj;
-                    if (op == OP_WARM) manifold_warm(c, m);
-                    else if (op == OP_SOLVE) manifold_solve(c, m, h, false);
-                    else if (op == OP_VSOLVE) manifold_solve(c, m, h, true);
-                    else if (op == OP_REST) manifold_restitution(c, m);
-                }
+        if (blk >= 0) {
+            if (!PIPE && blk < l.nj) {
+                if (OP == OP_WARM) joint_warm(c, blk);
+                else if (OP == OP_SOLVE || OP == OP_JOINT) joint_solve(c, blk, h, false);
+                else if (OP == OP_VSOLVE) joint_solve(c, blk, h, true);
+            } else {
+                const int m = blk - l.nj;
+                if (!PIPE && PRE) man_prefetch<SOLVE>(c, m, pre);
+                if (OP == OP_WARM) man_warm_pre(c, pre);
+                else if (OP == OP_SOLVE) man_solve_pre(c, m, pre, h, false);
+                else if (OP == OP_VSOLVE) man_solve_pre(c, m, pre, h, true);
+                else if (OP == OP_REST) manifold_restitution(c, m);
             }
         }
-        __syncthreads();
+        blk = sched_block(c, sched_off, nsched, e + 1, li);
+        if (PIPE && PRE && blk >= 0) man_prefetch<SOLVE>(c, blk - l.nj, pre);
+        wave_sync();
     }
 }
 
@@ -1016,7 +1260,7 @@ __device__ void run_schedule(const EnvCtx& c, int sched_off, int nsched, int ema
 // Serial greedy colouring by the group leader: blocks = joints (index order) then manifolds
 // (canonical order); each block takes the smallest colour unused by its dynamic bodies.  Then a
 // stable counting sort by colour and the two schedules (all blocks; joints only).
-__device__ void colour_env(const EnvCtx& c, int G) {
+__device__ __forceinline__ void colour_env(const EnvCtx& c, int G) {
     const Lay& l = c.lay;
     int* SC = iptr(c.L + l.SCAL);
     const int nman = SC[SC_NMAN];
@@ -1089,11 +1333,122 @@ __device__ void colour_env(const EnvCtx& c, int G) {
     SC[SC_NJSCHED] = njs;
 }
 
+// The same greedy colouring and stable sort for an env that owns the whole wave (64 lanes): the
+// colour masks of the bodies live in registers (body i in lane i) and the greedy loop runs on
+// uniform values read across lanes, so a block costs a few scalar instructions instead of a
+// chain of LDS round trips.  Block order, colours and schedules equal those of colour_env.
+__device__ __forceinline__ void colour_env_wave(const EnvCtx& c) {
+    const Lay& l = c.lay;
+    const int li = threadIdx.x;
+    int* SC = iptr(c.L + l.SCAL);
+    const int nman = SC[SC_NMAN];
+    const int nb = l.nj + nman;
+    uint16_t* BC = reinterpret_cast<uint16_t*>(c.L + l.BCOL);
+    uint16_t* ORD = reinterpret_cast<uint16_t*>(c.L + l.ORDER);
+    const uint64_t dynm = __ballot(li < l.n && is_dyn(c, li));
+    uint32_t mlo = 0, mhi = 0;   // colours used by body li
+    int ccnt = 0, jcnt = 0;      // blocks / joint blocks of colour li
+    int c64 = 0, j64 = 0;        // the same for the overflow colour
+    int ncol = 0;
+    bool overflow = false;
+    for (int r = 0; r * WAVE < nb; ++r) {
+        const int blk = r * WAVE + li;
+        int pk = 0xFFFFFFFF;
+        if (blk < nb) {
+            int a, b;
+            if (blk < l.nj) {
+                const int* J = reinterpret_cast<const int*>(jrec(c, blk));
+                a = J[J_PA]; b = J[J_CH];
+            } else {
+                int f, cnt;
+                man_header(c, blk - l.nj, a, b, f, cnt);
+            }
+            pk = (a & 0xFFFF) | (b << 16);
+        }
+        const int kend = min(WAVE, nb - r * WAVE);
+        int mycol = 0;
+        for (int k = 0; k < kend; ++k) {
+            const int w = __builtin_amdgcn_readlane(pk, k);
+            const int a = int(int16_t(w & 0xFFFF)), b = w >> 16;
+            const bool da = a >= 0 && ((dynm >> a) & 1), db = b >= 0 && ((dynm >> b) & 1);
+            uint64_t u = 0;
+            if (da) u |= uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mlo), a))) |
+                         (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mhi), a))) << 32);
+            if (db) u |= uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mlo), b))) |
+                         (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mhi), b))) << 32);
+            int col;
+            const bool joint = r * WAVE + k < l.nj;
+            if (~u == 0) {
+                col = N_COLOURS;
+                overflow = true;
+                c64 += 1;
+                j64 += joint ? 1 : 0;
+            } else {
+                col = __ffsll((unsigned long long)(~u)) - 1;
+                const uint32_t blo = col < 32 ? (1u << col) : 0u, bhi = col < 32 ? 0u : (1u << (col - 32));
+                if ((da && li == a) || (db && li == b)) { mlo |= blo; mhi |= bhi; }
+                if (li == col) { ccnt += 1; jcnt += joint ? 1 : 0; }
+            }
+            if (li == k) mycol = col;
+            ncol = max(ncol, col + 1);
+        }
+        if (blk < nb) BC[blk] = uint16_t(mycol);
+    }
+    if (overflow && li == 0) SC[SC_STATUS] |= 4;
+    // colour starts: inclusive prefix of the per-colour counts over the lanes
+    int incl = ccnt;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int y = __shfl_up(incl, d);
+        if (li >= d) incl += y;
+    }
+    const int start = incl - ccnt;                         // first slot of colour li
+    const int start64 = __builtin_amdgcn_readlane(incl, WAVE - 1);
+    // stable scatter by colour: rank = earlier blocks of the same colour
+    int seen = 0;      // blocks of colour li placed so far
+    int seen64 = 0;
+    for (int r = 0; r * WAVE < nb; ++r) {
+        const int blk = r * WAVE + li;
+        const bool valid = blk < nb;
+        const int col = valid ? int(BC[blk]) : -1;
+        for (int k = 0; k < ncol; ++k) {
+            const uint64_t m = __ballot(col == k);
+            if (m == 0) continue;
+            const int base = k < N_COLOURS ? __builtin_amdgcn_readlane(start, k) + __builtin_amdgcn_readlane(seen, k)
+                                           : start64 + seen64;
+            if (col == k) ORD[base + __popcll(m & ((uint64_t(1) << li) - 1))] = uint16_t(blk);
+            if (k < N_COLOURS) { if (li == k) seen += __popcll(m); }
+            else seen64 += __popcll(m);
+        }
+    }
+    // schedules: entries of <= 64 blocks per parallel colour, one entry per overflow block
+    if (li == 0) {
+        int* SCH = iptr(c.L + l.SCHED);
+        int* JS = iptr(c.L + l.JSCHED);
+        int ns = 0, njs = 0;
+        for (int col = 0; col < ncol; ++col) {
+            const int s0 = col < N_COLOURS ? __builtin_amdgcn_readlane(start, col) : start64;
+            const int cnt = col < N_COLOURS ? __builtin_amdgcn_readlane(ccnt, col) : c64;
+            const int jc = col < N_COLOURS ? __builtin_amdgcn_readlane(jcnt, col) : j64;
+            if (col < N_COLOURS) {
+                for (int o = 0; o < cnt; o += WAVE) SCH[ns++] = (s0 + o) | (min(WAVE, cnt - o) << 16);
+                for (int o = 0; o < jc; o += WAVE) JS[njs++] = (s0 + o) | (min(WAVE, jc - o) << 16);
+            } else {
+                for (int o = 0; o < cnt; ++o) SCH[ns++] = (s0 + o) | (1 << 16);
+                for (int o = 0; o < jc; ++o) JS[njs++] = (s0 + o) | (1 << 16);
+            }
+        }
+        SC[SC_NCOL] = ncol;
+        SC[SC_NSCHED] = ns;
+        SC[SC_NJSCHED] = l.nj > 0 ? njs : 0;
+    }
+}
+
 // S3 for one candidate: decode the pair, run the narrowphase in a frame centred on body A (or
 // on the ground below the body) and reduce to <= 4 points; code < 0 means no candidate.
-__device__ void np_candidate(const EnvCtx& c, int code, NOut& o, int& a, int& b, bool& plane, V3& base,
+__device__ __forceinline__ void np_candidate(const EnvCtx& c, int code, NOut& o, int& a, int& b, bool& plane, V3& base,
                                           V3& offB) {
-    o.n = 0;
+    o.mask = 0;
     o.decision = 0;
     base = v3(0, 0, 0);
     offB = v3(0, 0, 0);
@@ -1133,7 +1488,7 @@ __device__ void np_candidate(const EnvCtx& c, int code, NOut& o, int& a, int& b,
 
 // S4 for one kept pair: a normal row per kept point (arms from the step-start centres, pre-step
 // normal velocity, effective mass) and the manifold's friction patch at the points' centroid.
-__device__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, bool plane, V3 base,
+__device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, bool plane, V3 base,
                                         V3 offB, int keep, int first, int m, bool dbg, int dpo, int dmo) {
     const Lay& l = c.lay;
     const BatchDev& bd = *c.bd;
@@ -1142,9 +1497,12 @@ __device__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, 
     if (plane) { mu = (bd.plane_mu + c.L[l.MU + a]) / 2.0f; e = fmaxf(bd.plane_e, c.L[l.EE + a]); }
     else { mu = (c.L[l.MU + a] + c.L[l.MU + b]) / 2.0f; e = fmaxf(c.L[l.EE + a], c.L[l.EE + b]); }
     V3 csum = v3(0, 0, 0), nsum = v3(0, 0, 0);
-    for (int q = 0; q < keep; ++q) {
+    int q = 0;   // position in the kept list (the first `keep` valid slots)
+#pragma unroll
+    for (int K = 0; K < 8; ++K) {
+        if (!((o.mask >> K) & 1) || q >= keep) continue;
         int kk = first + q;
-        V3 p = o.pt[q].p, nv = o.pt[q].n;
+        V3 p = o.pt[K].p, nv = o.pt[K].n;
         V3 rA = ia >= 0 ? p : v3(0, 0, 0);
         V3 rB = p - offB;
         V3 vrel = rel_vel(c, ia, ib, rA, rB);
@@ -1152,7 +1510,7 @@ __device__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, 
         pr(c, R_RB, kk) = rB.x; pr(c, R_RB + 1, kk) = rB.y; pr(c, R_RB + 2, kk) = rB.z;
         pr(c, R_N, kk) = nv.x; pr(c, R_N + 1, kk) = nv.y; pr(c, R_N + 2, kk) = nv.z;
         pr(c, R_MN, kk) = eff_mass(c, ia, ib, rA, rB, nv);
-        pr(c, R_S0, kk) = o.pt[q].s;
+        pr(c, R_S0, kk) = o.pt[K].s;
         pr(c, R_E, kk) = e;
         pr(c, R_VN, kk) = dot3(vrel, nv);
         pr(c, R_LN, kk) = 0.0f;
@@ -1162,8 +1520,9 @@ __device__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, 
             float* dq = bd.dbg_pts + 8 * size_t(dpo + kk);
             V3 pw = base + p;
             dq[0] = pw.x; dq[1] = pw.y; dq[2] = pw.z; dq[3] = nv.x; dq[4] = nv.y; dq[5] = nv.z;
-            dq[6] = o.pt[q].s; dq[7] = 0.0f;
+            dq[6] = o.pt[K].s; dq[7] = 0.0f;
         }
+        ++q;
     }
     V3 cc = (1.0f / float(keep)) * csum;
     V3 nb = (1.0f / len3(nsum)) * nsum;
@@ -1176,7 +1535,13 @@ __device__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, 
     V3 t2 = cross3(nb, t1);
     float kw = (ia >= 0 ? dot3(nb, muls(load_iw(c, ia), nb)) : 0.0f) + dot3(nb, muls(load_iw(c, ib), nb));
     float rsum = 0.0f;
-    for (int q = 0; q < keep; ++q) rsum += len3(o.pt[q].p - cc);
+    q = 0;
+#pragma unroll
+    for (int K = 0; K < 8; ++K) {
+        if (!((o.mask >> K) & 1) || q >= keep) continue;
+        rsum += len3(o.pt[K].p - cc);
+        ++q;
+    }
     iptr(c.L + l.MAN + M_AB * l.mcap)[m] = (ia < 0 ? 0xFF : ia) | (ib << 8);
     iptr(c.L + l.MAN + M_FC * l.mcap)[m] = first | (keep << 16);
     mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
@@ -1255,7 +1620,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
         }
         if (c.active && li == 0) SC[SC_STATUS] = bd.status[c.env];
         for (int k = li; k < (c.active ? NSTAT : 0); k += G) SC[16 + k] = 0;
-        __syncthreads();
+        wave_sync();
         // jointed-partner masks (parent-child pairs never collide)
         for (int i = li; i < nA; i += G) {
             uint64_t m = 0;
@@ -1269,7 +1634,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             iptr(c.L + l.JM)[2 * i] = int(uint32_t(m));
             iptr(c.L + l.JM)[2 * i + 1] = int(uint32_t(m >> 32));
         }
-        __syncthreads();
+        wave_sync();
 
         for (int step = 0; step < n_steps; ++step) {
             const bool frozen = !c.active || (SC[SC_STATUS] & 1);
@@ -1281,7 +1646,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 int* dc = bd.dbg_counts + 4 * c.env;
                 dc[0] = 0; dc[1] = 0; dc[2] = 0; dc[3] = 0;
             }
-            __syncthreads();
+            wave_sync();
 
             // --------------------------------------------------------- S0 + S1
             for (int i = li; i < nn; i += G) {
@@ -1310,7 +1675,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 float* J = jrec(c, j);
                 for (int w = J_LP; w <= J_LD; ++w) J[w] = 0.0f;
             }
-            __syncthreads();
+            wave_sync();
 
             // --------------------------------------------------------- S2 candidate pairs
             const int P = frozen ? 0 : l.P;
@@ -1337,7 +1702,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     ncand += __popcll(gb);
                 }
             }
-            __syncthreads();
+            wave_sync();
 
             // --------------------------------------------------------- S3 + S4 narrowphase, rows
             int npts = 0, nman = 0;
@@ -1356,9 +1721,10 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     V3 base, offB;
                     np_candidate(c, k < ncand ? int(CAND[k]) : -1, o, a, b, plane, base, offB);
                     int tot;
-                    int pre = group_scan(o.n, li, G, tot);
-                    int keep = min(max(l.cap - (npts + pre), 0), o.n);
-                    bool ovf = keep < o.n;
+                    const int on = n_points(o);
+                    int pre = group_scan(on, li, G, tot);
+                    int keep = min(max(l.cap - (npts + pre), 0), on);
+                    bool ovf = keep < on;
                     int mtot;
                     int mpre = group_scan(keep > 0 ? 1 : 0, li, G, mtot);
                     if (keep > 0 && nman + mpre >= l.mcap) { keep = 0; ovf = true; }
@@ -1387,18 +1753,22 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 SC[16 + STAT_POINTS] += npts;
                 SC[16 + STAT_MANIFOLDS] += nman;
             }
-            __syncthreads();
+            wave_sync();
 
             // --------------------------------------------------------- S5 colouring
-            if (!frozen && li == 0) {
+            if (G == WAVE) {
+                if (!frozen) colour_env_wave(c);
+            } else if (!frozen && li == 0) {
                 colour_env(c, G);
-                SC[16 + STAT_COLOURS] += SC[SC_NCOL];
             }
-            __syncthreads();
+            wave_sync();
+            if (!frozen && li == 0) SC[16 + STAT_COLOURS] += SC[SC_NCOL];
+            wave_sync();
             const int ns = frozen ? 0 : SC[SC_NSCHED];
             const int njs = frozen ? 0 : SC[SC_NJSCHED];
             const int ns_max = wave_max(ns), njs_max = wave_max(njs);
             const int JI = bd.JI;
+            const bool pipe = __ballot(c.active && nj > 0) == 0;   // no joints anywhere in the wave
 
             // --------------------------------------------------------- S6 substeps
             const float ldmp = 1.0f / (1.0f + h * bd.lin_damp);
@@ -1411,11 +1781,11 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     st3(c.L, l.V, n, i, v);
                     st3(c.L, l.W, n, i, admp * ld3(c.L, l.W, n, i));
                 }
-                __syncthreads();
-                if (s > 0) run_schedule(c, l.SCHED, ns, ns_max, OP_WARM, h, li);
+                wave_sync();
+                if (s > 0) (pipe ? run_schedule<OP_WARM, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li));
                 for (int it = 0; it < K; ++it) {
-                    for (int jx = 1; jx < JI; ++jx) run_schedule(c, l.JSCHED, njs, njs_max, OP_JOINT, h, li);
-                    run_schedule(c, l.SCHED, ns, ns_max, OP_SOLVE, h, li);
+                    for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
+                    (pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
                 }
                 // integrate the offsets from the step-start pose
                 for (int i = li; i < nn; i += G) {
@@ -1429,11 +1799,11 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     st4(c.L, l.DQ, n, i, d);
                     st4(c.L, l.QC, n, i, qnorm(qmul(d, ld4(c.L, l.Q0, n, i))));
                 }
-                __syncthreads();
+                wave_sync();
             }
             // --------------------------------------------------------- S7
-            for (int it = 0; it < bd.V; ++it) run_schedule(c, l.SCHED, ns, ns_max, OP_VSOLVE, h, li);
-            run_schedule(c, l.SCHED, ns, ns_max, OP_REST, h, li);
+            for (int it = 0; it < bd.V; ++it) (pipe ? run_schedule<OP_VSOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_VSOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
+            run_schedule<OP_REST, false>(c, l.SCHED, ns, ns_max, h, li);
 
             // --------------------------------------------------------- S8 non-finite guard
             bool bad = false;
@@ -1454,7 +1824,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 }
                 if (li == 0) SC[SC_STATUS] |= 1;
             }
-            __syncthreads();
+            wave_sync();
             // --------------------------------------------------------- debug export
             if (dbg) {
                 int dpo = bd.dbg_pt_off[c.env], dmo = bd.dbg_man_off[c.env];
@@ -1472,7 +1842,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         // ------------------------------------------------------------- store
         for (int i = li; i < nA; i += G) {
             int gi = c.b0 + i;
@@ -1484,7 +1854,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
         }
         if (c.active && li == 0) bd.status[c.env] = SC[SC_STATUS];
         for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += SC[16 + k];
-        __syncthreads();
+        wave_sync();
     }
 }
 

@@ -64,11 +64,24 @@ _sig = {
     "ms_get_classes": [_P, _P, _P],
     "ms_tune_batch": [_P, _I, _P],
     "ms_destroy_batch": [_P],
+    "ms_graph_create": [_P, _P, _I, _I, C.POINTER(_P)],
+    "ms_graph_launch": [_P, _P],
+    "ms_graph_destroy": [_P],
+    "ms_server_create": [_P, C.c_size_t, C.c_size_t, C.POINTER(_P)],
+    "ms_server_open": [_P, _P, _P, _P, C.POINTER(C.c_int64)],
+    "ms_server_submit": [_P, C.c_int64, _I, _P, C.POINTER(C.c_int64)],
+    "ms_server_wait": [_P, C.c_int64, _P],
+    "ms_server_close": [_P, C.c_int64],
+    "ms_server_get_state": [_P, C.c_int64, _P, _P],
+    "ms_server_drain": [_P],
+    "ms_server_stats": [_P, _P],
+    "ms_server_destroy": [_P],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = C.c_int
+_lib.ms_server_clock.restype = C.c_double
 _lib.ms_last_error.restype = C.c_char_p
 _lib.ms_version.restype = C.c_char_p
 
@@ -231,11 +244,136 @@ class Batch:
         _check(_lib.ms_get_stats(self._h, out.ctypes.data, 1 if reset else 0, _stream(stream)))
         return out
 
+    def graph(self, steps_per_launch=1, n_launches=1, targets=None):
+        """ms_graph_create: n_launches ms_step calls captured into a replayable HIP graph."""
+        return Graph(self, steps_per_launch, n_launches, targets)
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.ms_destroy_batch(self._h)
             self._h = None
             self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured sequence of steps of one batch (ms_graph_*); replay with launch()."""
+
+    def __init__(self, batch, steps_per_launch, n_launches, targets=None):
+        self.batch = batch
+        self.steps = int(steps_per_launch) * int(n_launches)
+        self._targets = targets   # the graph reads this buffer at replay: keep it alive
+        tp = None
+        if targets is not None:
+            assert targets.is_cuda and targets.is_contiguous() and targets.numel() == batch.n_joints
+            tp = C.c_void_p(targets.data_ptr())
+        h = C.c_void_p()
+        _check(_lib.ms_graph_create(batch._h, tp, int(steps_per_launch), int(n_launches), C.byref(h)))
+        self._g = h
+
+    def launch(self, stream=None):
+        _check(_lib.ms_graph_launch(self._g, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_g", None):
+            _lib.ms_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ms_request_info(C.Structure):
+    _fields_ = [("request", C.c_int64), ("session", C.c_int64), ("status", C.c_int32), ("n_steps", C.c_int32),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("fused_batches", C.c_int32), ("pad", C.c_int32)]
+
+
+def server_clock() -> float:
+    return _lib.ms_server_clock()
+
+
+class Server:
+    """ms_server_*: sessions admitted against an HBM arena and continuous batching of their step
+    requests.  The arena is a torch uint8 tensor owned by this object; every call is thread safe
+    (ctypes releases the GIL while the library waits)."""
+
+    def __init__(self, arena_bytes: int, scratch_bytes: int = 0, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self._arena.data_ptr() + 255) & ~255
+            h = C.c_void_p()
+            _check(_lib.ms_server_create(C.c_void_p(ptr), int(arena_bytes), int(scratch_bytes), C.byref(h)))
+        self._h = h
+        self._scenes = {}
+
+    def open(self, scene, params=None, lanes_per_env=0, pack=1) -> int:
+        p = _params(scene, params)
+        sd, keep = _scene_struct(scene)
+        pl = _plan(lanes_per_env, pack, 0)
+        sid = C.c_int64()
+        _check(_lib.ms_server_open(self._h, p.ctypes.data, C.byref(sd), C.byref(pl), C.byref(sid)))
+        self._scenes[sid.value] = scene
+        return sid.value
+
+    def submit(self, session: int, n_steps: int, targets=None) -> int:
+        rid = C.c_int64()
+        tp = None
+        if targets is not None:
+            t = np.ascontiguousarray(targets, dtype=np.float32)
+            assert t.size == self._scenes[session].n_joints
+            tp = t.ctypes.data
+        _check(_lib.ms_server_submit(self._h, int(session), int(n_steps), tp, C.byref(rid)))
+        return rid.value
+
+    def wait(self, request: int) -> dict:
+        info = ms_request_info()
+        _check(_lib.ms_server_wait(self._h, int(request), C.byref(info)))
+        return dict(request=info.request, session=info.session, status=info.status, n_steps=info.n_steps,
+                    t_submit=info.t_submit, t_start=info.t_start, t_done=info.t_done, fused=info.fused_batches)
+
+    def close_session(self, session: int):
+        _check(_lib.ms_server_close(self._h, int(session)))
+
+    def get_state(self, session: int) -> dict:
+        import torch
+        sc = self._scenes[session]
+        B, E = sc.n_bodies, sc.n_envs
+        f = dict(dtype=torch.float32, device=self.device)
+        out = dict(pos=torch.empty(3, B, **f), quat=torch.empty(4, B, **f), linvel=torch.empty(3, B, **f),
+                   angvel=torch.empty(3, B, **f), status=torch.empty(E, dtype=torch.int32, device=self.device))
+        view = ms_state_view(out["pos"].data_ptr(), out["quat"].data_ptr(), out["linvel"].data_ptr(),
+                             out["angvel"].data_ptr(), out["status"].data_ptr())
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.ms_server_get_state(self._h, int(session), C.byref(view), C.c_void_p(s.cuda_stream)))
+        s.synchronize()
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+    def drain(self):
+        _check(_lib.ms_server_drain(self._h))
+
+    def stats(self) -> dict:
+        out = np.zeros(8, np.int64)
+        _check(_lib.ms_server_stats(self._h, out.ctypes.data))
+        keys = ("launches", "fused_batches", "env_steps", "requests_done", "sessions_admitted", "busy_us",
+                "peak_arena_bytes", "sessions_rejected")
+        return dict(zip(keys, (int(x) for x in out)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ms_server_destroy(self._h)
+            self._h = None
+            self._arena = None
 
     def __del__(self):
         try:
