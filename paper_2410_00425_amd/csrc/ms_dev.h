@@ -110,11 +110,11 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     L.JNT = o; o += 26 * nj;
     L.CAND = o; o += (L.P + 1) / 2;
     L.PT = o; o += 14 * cap;
-    L.MAN = o; o += 22 * mcap;
+    L.MAN = o; o += 23 * mcap;
     L.BCOL = o; o += (nj + mcap + 1) / 2;
     L.ORDER = o; o += (nj + mcap + 1) / 2;
     L.SCHED = o; o += nj + mcap + 66;
-    L.JSCHED = o; o += nj + mcap + 66;
+    L.JSCHED = o; o += nj > 0 ? nj + mcap + 66 : 66;  // without joints: cursors of the serial colouring only
     L.CSTART = o; o += 68;
     L.SCAL = o; o += 32;  // 16 scalars + 16 work counters
     L.total = (o + 3) & ~3;

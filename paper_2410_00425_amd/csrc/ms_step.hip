@@ -93,12 +93,14 @@ __device__ __forceinline__ V3 muls(const S6& s, V3 v) {
 
 // ----------------------------------------------------------------------------- LDS layout
 // (Lay / make_lay live in ms_dev.h: one definition for the kernel and the host planner)
-// Contact-row planes (length cap): rA 0..2, rB 3..5, n 6..8, mn 9, s0 10, e 11, vnpre 12, ln 13.
-enum { R_RA = 0, R_RB = 3, R_N = 6, R_MN = 9, R_S0 = 10, R_E = 11, R_VN = 12, R_LN = 13 };
+// Contact-row planes (length cap): rA 0..2, rB 3..5, n 6..8, mn 9, s0 10, vnpre 11, ln 12,
+// bias of the current substep 13.
+enum { R_RA = 0, R_RB = 3, R_N = 6, R_MN = 9, R_S0 = 10, R_VN = 11, R_LN = 12, R_BIAS = 13 };
 // Manifold planes (length mcap): header 0 (a | b << 8 as int), 1 (first | count << 16),
-// rA 2..4, rB 5..7, nb 8..10, t1 11..13, mt1 14, mt2 15, mtw 16, mu 17, rt 18, lt1 19, lt2 20, ltw 21.
+// rA 2..4, rB 5..7, nb 8..10, t1 11..13, mt1 14, mt2 15, mtw 16, mu 17, rt 18, lt1 19, lt2 20, ltw 21,
+// restitution 22.
 enum { M_AB = 0, M_FC = 1, M_RA = 2, M_RB = 5, M_NB = 8, M_T1 = 11, M_MT1 = 14, M_MT2 = 15, M_MTW = 16,
-       M_MU = 17, M_RT = 18, M_LT1 = 19, M_LT2 = 20, M_LTW = 21 };
+       M_MU = 17, M_RT = 18, M_LT1 = 19, M_LT2 = 20, M_LTW = 21, M_REST = 22 };
 // Joint record in LDS (26 words): parent, child, aA 2..4, QA 5..8, aB 9..11, QB 12..15, kp 16,
 // kd 17, target 18, lp 19..21, la 22..23, ld 24.
 enum { J_PA = 0, J_CH = 1, J_AA = 2, J_QA = 5, J_AB = 9, J_QB = 12, J_KP = 16, J_KD = 17, J_TG = 18,
@@ -152,17 +154,19 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int g, int G) {
 __device__ __forceinline__ int prefix_in_group(uint64_t gb, int li) {
     return __popcll(gb & ((uint64_t(1) << li) - 1));
 }
-// Exclusive prefix sum of v over the lanes of a group (G a power of two <= 64) and the total.
-__device__ __forceinline__ int group_scan(int v, int li, int G, int& total) {
-    int x = v;
+// Exclusive prefix sum over the lanes of a group (G a power of two <= 64) and the group total,
+// for 0 <= v < 2^BITS, from one ballot per bit (no cross-lane data movement).
+template <int BITS>
+__device__ __forceinline__ int group_scan_small(int v, int li, int g, int G, int& total) {
+    int pre = 0, tot = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(x, d);
-        if (d < G && li >= d) x += y;
+    for (int b = 0; b < BITS; ++b) {
+        const uint64_t m = group_bits(__ballot((v >> b) & 1), g, G);
+        pre += prefix_in_group(m, li) << b;
+        tot += __popcll(m) << b;
     }
-    int lane = threadIdx.x;
-    total = __shfl(x, (lane / G) * G + G - 1);
-    return x - v;
+    total = tot;
+    return pre;
 }
 
 // ----------------------------------------------------------------------------- body access
@@ -735,6 +739,23 @@ __device__ __forceinline__ void reduce4(NOut& o) {
     o.mask = used;
 }
 
+// Move the (at most 4 after reduce4) points of the list into slots 0.. in list order.
+__device__ __forceinline__ void compact4(NOut& o) {
+    Pt out[4] = {o.pt[0], o.pt[1], o.pt[2], o.pt[3]};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!((o.mask >> k) & 1)) continue;
+        const int r = __popc(o.mask & ((1u << k) - 1));
+#pragma unroll
+        for (int j = 0; j < 4 && j <= k; ++j)
+            if (r == j) out[j] = o.pt[k];
+    }
+    const int n = min(__popc(o.mask), 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o.pt[j] = out[j];
+    o.mask = (1u << n) - 1;
+}
+
 // Duff et al. 2017 orthonormal basis: t1 for unit n (t2 = n x t1).
 __device__ __forceinline__ V3 onb_t1(V3 n) {
     float sg = copysignf(1.0f, n.z);
@@ -862,7 +883,7 @@ __device__ __forceinline__ void manifold_restitution(const EnvCtx& c, int m) {
         any = true;
         V3 rA = pr3(c, R_RA, k), rB = pr3(c, R_RB, k), n = pr3(c, R_N, k);
         float vn = dot3(relv(A, B, has_a, rA, rB), n);
-        float dl = -pr(c, R_MN, k) * (vn + pr(c, R_E, k) * vpre);
+        float dl = -pr(c, R_MN, k) * (vn + mf(c, M_REST, m) * vpre);
         float nl = fmaxf(old + dl, 0.0f);
         pr(c, R_LN, k) = nl;
         imp_lin(A, B, rA, rB, (nl - old) * n);
@@ -1087,9 +1108,8 @@ struct ManPre {
     float ima, imb;
     S6 Ia, Ib;
     bool da, db;
-    PoseR pa, pb;
     V3 rA[4], rB[4], n[4];
-    float s0[4], mn[4], ln[4];
+    float bias[4], mn[4], ln[4];
     V3 mrA, mrB, nb, t1;
     float mt1, mt2, mtw, mu, rt, lt1, lt2, ltw;
     int first;
@@ -1105,10 +1125,6 @@ __device__ __forceinline__ void man_prefetch(const EnvCtx& c, int m, ManPre& p) 
     p.imb = c.L[c.lay.INVM + p.b];
     p.Ia = p.a >= 0 ? load_iw(c, p.a) : S6{0, 0, 0, 0, 0, 0};
     p.Ib = load_iw(c, p.b);
-    if (SOLVE) {
-        p.pa = load_pose(c, p.a);
-        p.pb = load_pose(c, p.b);
-    }
     (void)n;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1118,7 +1134,7 @@ __device__ __forceinline__ void man_prefetch(const EnvCtx& c, int m, ManPre& p) 
             p.rB[k] = pr3(c, R_RB, q);
             p.n[k] = pr3(c, R_N, q);
             p.ln[k] = pr(c, R_LN, q);
-            if (SOLVE) { p.s0[k] = pr(c, R_S0, q); p.mn[k] = pr(c, R_MN, q); }
+            if (SOLVE) { p.bias[k] = pr(c, R_BIAS, q); p.mn[k] = pr(c, R_MN, q); }
         }
     }
     p.mrA = mf3(c, M_RA, m);
@@ -1159,11 +1175,10 @@ __device__ __forceinline__ void man_warm_pre(const EnvCtx& c, const ManPre& p) {
     store_body(c, p.b, B);
 }
 
-// One Gauss-Seidel visit of a manifold block: normal rows in point order (separation from the
-// pose offsets, speculative / Baumgarte bias, clamped accumulated impulse), then the friction
+// One Gauss-Seidel visit of a manifold block: normal rows in point order (bias of the substep,
+// clamped accumulated impulse), then the friction
 // patch: two tangent rows and the twist row, clamped by mu and mu * r_t times the normal sum.
-__device__ __forceinline__ void man_solve_pre(const EnvCtx& c, int m, const ManPre& p, float h, bool vpass) {
-    const BatchDev& bd = *c.bd;
+__device__ __forceinline__ void man_solve_pre(const EnvCtx& c, int m, const ManPre& p) {
     const bool has_a = p.a >= 0;
     BodyR A, B;
     man_bodies(c, p, A, B);
@@ -1172,14 +1187,8 @@ __device__ __forceinline__ void man_solve_pre(const EnvCtx& c, int m, const ManP
     for (int k = 0; k < 4; ++k) {
         if (k < p.cnt) {
             const V3 rA = p.rA[k], rB = p.rB[k], n = p.n[k];
-            V3 dA = has_a ? disp(p.pa, rA) : v3(0, 0, 0);
-            V3 dB = disp(p.pb, rB);
-            float s = p.s0[k] + dot3(n, dB - dA);
-            float bias;
-            if (s > 0.0f) bias = s / h;
-            else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
             float vn = dot3(relv(A, B, has_a, rA, rB), n);
-            float dl = -p.mn[k] * (vn + bias);
+            float dl = -p.mn[k] * (vn + p.bias[k]);
             float old = p.ln[k];
             float nl = fmaxf(old + dl, 0.0f);
             pr(c, R_LN, p.first + k) = nl;
@@ -1210,6 +1219,32 @@ __device__ __forceinline__ void man_solve_pre(const EnvCtx& c, int m, const ManP
     }
     store_body(c, p.a, A);
     store_body(c, p.b, B);
+}
+
+// Bias of every contact point for the sweeps of one substep.  The pose offsets change only
+// when a substep integrates, so the current separation s = s0 + n . (dB - dA) of each point (the
+// displacement of its body-fixed arms since the step start) and its bias (speculative s / h for
+// a gap; Baumgarte beta s / h capped at the maximum depenetration velocity for a penetration, or
+// none in a velocity pass) are the same in every colour of the substep: one pass, a lane per
+// manifold, computes them before the sweeps.
+__device__ __forceinline__ void bias_pass(const EnvCtx& c, int nman, float h, bool vpass, int li, int G) {
+    const BatchDev& bd = *c.bd;
+    for (int m = li; m < nman; m += G) {
+        int a, b, first, cnt;
+        man_header(c, m, a, b, first, cnt);
+        const bool has_a = a >= 0;
+        const PoseR pa = load_pose(c, a), pb = load_pose(c, b);
+        for (int q = first; q < first + cnt; ++q) {
+            const V3 rA = pr3(c, R_RA, q), rB = pr3(c, R_RB, q), n = pr3(c, R_N, q);
+            V3 dA = has_a ? disp(pa, rA) : v3(0, 0, 0);
+            V3 dB = disp(pb, rB);
+            float s = pr(c, R_S0, q) + dot3(n, dB - dA);
+            float bias;
+            if (s > 0.0f) bias = s / h;
+            else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
+            pr(c, R_BIAS, q) = bias;
+        }
+    }
 }
 
 enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
@@ -1245,8 +1280,7 @@ __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int
                 const int m = blk - l.nj;
                 if (!PIPE && PRE) man_prefetch<SOLVE>(c, m, pre);
                 if (OP == OP_WARM) man_warm_pre(c, pre);
-                else if (OP == OP_SOLVE) man_solve_pre(c, m, pre, h, false);
-                else if (OP == OP_VSOLVE) man_solve_pre(c, m, pre, h, true);
+                else if (OP == OP_SOLVE || OP == OP_VSOLVE) man_solve_pre(c, m, pre);
                 else if (OP == OP_REST) manifold_restitution(c, m);
             }
         }
@@ -1484,6 +1518,7 @@ __device__ __forceinline__ void np_candidate(const EnvCtx& c, int code, NOut& o,
         np_pair(o, sa, sb, bd.delta);
     }
     reduce4(o);
+    compact4(o);
 }
 
 // S4 for one kept pair: a normal row per kept point (arms from the step-start centres, pre-step
@@ -1497,11 +1532,10 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
     if (plane) { mu = (bd.plane_mu + c.L[l.MU + a]) / 2.0f; e = fmaxf(bd.plane_e, c.L[l.EE + a]); }
     else { mu = (c.L[l.MU + a] + c.L[l.MU + b]) / 2.0f; e = fmaxf(c.L[l.EE + a], c.L[l.EE + b]); }
     V3 csum = v3(0, 0, 0), nsum = v3(0, 0, 0);
-    int q = 0;   // position in the kept list (the first `keep` valid slots)
 #pragma unroll
-    for (int K = 0; K < 8; ++K) {
-        if (!((o.mask >> K) & 1) || q >= keep) continue;
-        int kk = first + q;
+    for (int K = 0; K < 4; ++K) {
+        if (K >= keep) continue;   // the kept points are slots 0 .. keep - 1
+        int kk = first + K;
         V3 p = o.pt[K].p, nv = o.pt[K].n;
         V3 rA = ia >= 0 ? p : v3(0, 0, 0);
         V3 rB = p - offB;
@@ -1511,7 +1545,6 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
         pr(c, R_N, kk) = nv.x; pr(c, R_N + 1, kk) = nv.y; pr(c, R_N + 2, kk) = nv.z;
         pr(c, R_MN, kk) = eff_mass(c, ia, ib, rA, rB, nv);
         pr(c, R_S0, kk) = o.pt[K].s;
-        pr(c, R_E, kk) = e;
         pr(c, R_VN, kk) = dot3(vrel, nv);
         pr(c, R_LN, kk) = 0.0f;
         csum = csum + p;
@@ -1522,7 +1555,6 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
             dq[0] = pw.x; dq[1] = pw.y; dq[2] = pw.z; dq[3] = nv.x; dq[4] = nv.y; dq[5] = nv.z;
             dq[6] = o.pt[K].s; dq[7] = 0.0f;
         }
-        ++q;
     }
     V3 cc = (1.0f / float(keep)) * csum;
     V3 nb = (1.0f / len3(nsum)) * nsum;
@@ -1535,13 +1567,9 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
     V3 t2 = cross3(nb, t1);
     float kw = (ia >= 0 ? dot3(nb, muls(load_iw(c, ia), nb)) : 0.0f) + dot3(nb, muls(load_iw(c, ib), nb));
     float rsum = 0.0f;
-    q = 0;
 #pragma unroll
-    for (int K = 0; K < 8; ++K) {
-        if (!((o.mask >> K) & 1) || q >= keep) continue;
-        rsum += len3(o.pt[K].p - cc);
-        ++q;
-    }
+    for (int K = 0; K < 4; ++K)
+        if (K < keep) rsum += len3(o.pt[K].p - cc);
     iptr(c.L + l.MAN + M_AB * l.mcap)[m] = (ia < 0 ? 0xFF : ia) | (ib << 8);
     iptr(c.L + l.MAN + M_FC * l.mcap)[m] = first | (keep << 16);
     mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
@@ -1553,6 +1581,7 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
     mfr(c, M_MTW, m) = kw > 0.0f ? 1.0f / kw : 0.0f;
     mfr(c, M_MU, m) = mu;
     mfr(c, M_RT, m) = rsum / float(keep);
+    mfr(c, M_REST, m) = e;
     mfr(c, M_LT1, m) = 0.0f; mfr(c, M_LT2, m) = 0.0f; mfr(c, M_LTW, m) = 0.0f;
     if (dbg) {
         float* dm = bd.dbg_man + 8 * size_t(dmo + m);
@@ -1721,15 +1750,15 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     V3 base, offB;
                     np_candidate(c, k < ncand ? int(CAND[k]) : -1, o, a, b, plane, base, offB);
                     int tot;
-                    const int on = n_points(o);
-                    int pre = group_scan(on, li, G, tot);
+                    const int on = n_points(o);   // 0..4
+                    int pre = group_scan_small<3>(on, li, g, G, tot);
                     int keep = min(max(l.cap - (npts + pre), 0), on);
                     bool ovf = keep < on;
                     int mtot;
-                    int mpre = group_scan(keep > 0 ? 1 : 0, li, G, mtot);
+                    int mpre = group_scan_small<1>(keep > 0 ? 1 : 0, li, g, G, mtot);
                     if (keep > 0 && nman + mpre >= l.mcap) { keep = 0; ovf = true; }
                     int ktot;
-                    int kpre = group_scan(keep, li, G, ktot);
+                    int kpre = group_scan_small<3>(keep, li, g, G, ktot);
                     int m_idx = nman + mpre;
                     int first = npts + kpre;
                     overflow |= group_bits(__ballot(ovf), g, G) != 0;
@@ -1740,7 +1769,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     if (keep > 0) write_rows(c, o, k, a, b, plane, base, offB, keep, first, m_idx, dbg, dpo, dmo);
                     npts += ktot;
                     int mkept;
-                    group_scan(keep > 0 ? 1 : 0, li, G, mkept);
+                    group_scan_small<1>(keep > 0 ? 1 : 0, li, g, G, mkept);
                     nman += mkept;
                 }
             }
@@ -1769,6 +1798,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             const int ns_max = wave_max(ns), njs_max = wave_max(njs);
             const int JI = bd.JI;
             const bool pipe = __ballot(c.active && nj > 0) == 0;   // no joints anywhere in the wave
+            const int nmanA = frozen ? 0 : SC[SC_NMAN];
 
             // --------------------------------------------------------- S6 substeps
             const float ldmp = 1.0f / (1.0f + h * bd.lin_damp);
@@ -1781,6 +1811,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                     st3(c.L, l.V, n, i, v);
                     st3(c.L, l.W, n, i, admp * ld3(c.L, l.W, n, i));
                 }
+                bias_pass(c, nmanA, h, false, li, G);
                 wave_sync();
                 if (s > 0) (pipe ? run_schedule<OP_WARM, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li));
                 for (int it = 0; it < K; ++it) {
@@ -1802,6 +1833,10 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 wave_sync();
             }
             // --------------------------------------------------------- S7
+            if (bd.V > 0) {
+                bias_pass(c, nmanA, h, true, li, G);
+                wave_sync();
+            }
             for (int it = 0; it < bd.V; ++it) (pipe ? run_schedule<OP_VSOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_VSOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
             run_schedule<OP_REST, false>(c, l.SCHED, ns, ns_max, h, li);
 
