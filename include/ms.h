@@ -102,7 +102,9 @@ typedef struct {
 /* Step parameters.  One step advances dt; TGS runs pos_iters substeps of one iteration each,
  * PGS runs one substep of pos_iters iterations; vel_iters velocity-only sweeps follow.  The
  * ground is the half-space z <= plane_z when plane_enabled != 0.  max_contacts_per_env <= 0
- * selects the default 8 * n_bodies + 16.  debug_export != 0 makes the step also write the last
+ * selects the default min(6 * n_dyn + 8, 384) contact points per env, max_manifolds_per_env <= 0
+ * min(3 * n_dyn + 4, 192) manifolds (n_dyn: dynamic bodies of the env); pairs beyond them lose
+ * their points and the env's status gets bit 2.  debug_export != 0 makes the step also write the last
  * step's pair list, contact points and colours (read with ms_get_contacts). */
 typedef struct {
     float dt;

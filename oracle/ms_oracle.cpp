@@ -827,12 +827,13 @@ template <class T> struct Stepper {
         for (const Joint<T>& j : E.joints)
             if (j.parent >= 0) { jmask[j.parent] |= uint64_t(1) << j.child; jmask[j.child] |= uint64_t(1) << j.parent; }
 
-        // Capacities from the dynamic body count: points min(8 n_dyn + 16, 384), manifolds
-        // min(4 n_dyn + 16, 192), unless the parameters set them.
+        // Capacities from the dynamic body count: points min(6 n_dyn + 8, 384), manifolds
+        // min(3 n_dyn + 4, 192), unless the parameters set them.  Beyond them, the pairs that
+        // come later in canonical order lose their points and the env is flagged (status 2).
         int n_dyn = 0;
         for (int i = 0; i < n; ++i) n_dyn += E.bodies[i].dyn() ? 1 : 0;
-        const int cap = P.max_contacts_per_env > 0 ? P.max_contacts_per_env : std::min(8 * n_dyn + 16, 384);
-        const int mcap = P.max_manifolds_per_env > 0 ? P.max_manifolds_per_env : std::min(4 * n_dyn + 16, 192);
+        const int cap = P.max_contacts_per_env > 0 ? P.max_contacts_per_env : std::min(6 * n_dyn + 8, 384);
+        const int mcap = P.max_manifolds_per_env > 0 ? P.max_manifolds_per_env : std::min(3 * n_dyn + 4, 192);
         rows.clear(); mans.clear();
         // S2 + S3 in canonical order: for each a, partners b = a+1 .. n-1, then the plane.
         for (int a = 0; a < n; ++a) {

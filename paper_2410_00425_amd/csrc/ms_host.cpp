@@ -61,7 +61,7 @@ int pick_lanes(const EnvInfo& e, int forced, int tile_budget_words) {
     if (forced > 0) return forced;
     int G;
     if (e.n <= 2 && e.nj == 0) G = 8;
-    else if (e.n <= 6) G = 16;
+    else if (e.n <= 10) G = 16;
     else if (e.n <= 14) G = 32;
     else G = 64;
     while (G < 64 && (WAVE / G) * e.words > tile_budget_words) G *= 2;
@@ -141,7 +141,7 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
     const int E = s->n_envs;
     const int forced = plan ? plan->lanes_per_env : 0;
     const bool pack = plan ? plan->pack != 0 : true;
-    const int budget = 8192;  // tile LDS budget in words (32 KiB) unless one env needs more
+    const int budget = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
     out.info.resize(E);
     for (int e = 0; e < E; ++e) {
         EnvInfo& I = out.info[e];
@@ -149,8 +149,8 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
         I.nj = s->env_joint_off[e + 1] - s->env_joint_off[e];
         I.n_dyn = 0;
         for (int i = 0; i < I.n; ++i) I.n_dyn += (s->bodies[s->env_body_off[e] + i].flags & MS_BODY_STATIC) ? 0 : 1;
-        I.cap = p->max_contacts_per_env > 0 ? p->max_contacts_per_env : std::min(8 * I.n_dyn + 16, 384);
-        I.mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(4 * I.n_dyn + 16, 192);
+        I.cap = p->max_contacts_per_env > 0 ? p->max_contacts_per_env : std::min(6 * I.n_dyn + 8, 384);
+        I.mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(3 * I.n_dyn + 4, 192);
         I.words = env_lds_words(I.n, I.nj, I.cap, I.mcap);
         I.lanes = pick_lanes(I, forced, budget);
     }
