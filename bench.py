@@ -15,7 +15,9 @@ The line also carries:
     FLOP counts taken from the kernel source (listed in FLOP_PER_UNIT);
   * cpu_baseline: the float32 CPU oracle on all host threads over a bounded sample;
   * extra: the other workloads (one box per env at 4096, the 7-link arm at 1024, the
-    heterogeneous batch against its padded form) unless --quick.
+    heterogeneous batch against its padded form) and the serving run (8 clients, continuous
+    batching under an HBM budget: saturation throughput, p50 / p99 request latency under Poisson
+    arrivals, and the same requests run without the server) unless --quick.
 """
 from __future__ import annotations
 
@@ -70,6 +72,8 @@ def parse():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving sweep: arrival rates 0.1 .. 1.25 x saturation, budgets 128 MB / 256 MB / 1 GB")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
@@ -162,6 +166,36 @@ def cpu_baseline(name, seed, budget_s=15.0):
                        f"{threads} threads, {dt:.1f} s)")
 
 
+def serving(ms, full=False, seed=0):
+    """Continuous batching of step requests from 8 clients (2-step requests on sessions of one of
+    the three scene families with 2**U{6..12} envs): saturation throughput (closed loop), latency
+    under Poisson arrivals at a fraction of it, and the same requests run plainly (one batch per
+    session, one synchronised ms_step per request, no server)."""
+    from paper_2410_00425_amd import serve_load as L
+    pool = L.ScenePool(seed)
+    spc, rps = (63, 20) if full else (2, 20)   # full: 8 x 63 x 20 = 10,080 requests per arrival rate
+    out = {}
+    budgets = (128 << 20, 256 << 20, 1 << 30) if full else (256 << 20,)
+    for budget in budgets:
+        srv = ms.Server(budget)
+        recs, wall = L.run_clients(ms, srv, pool, float("inf"), n_clients=8, sessions_per_client=spc,
+                                   reqs_per_session=rps, seed=seed)
+        sat = L.summarize(recs, wall)
+        st = srv.stats()
+        res = {"saturation": sat, "server": st}
+        fracs = (0.1, 0.25, 0.5, 0.75, 1.0, 1.25) if full else (0.75,)
+        for f in fracs:
+            recs, wall = L.run_clients(ms, srv, pool, f * sat["requests_per_s"], n_clients=8, sessions_per_client=spc,
+                                       reqs_per_session=rps, seed=seed + 1)
+            res[f"poisson_{f}"] = L.summarize(recs, wall)
+        srv.close()
+        out[f"budget_{budget >> 20}MB"] = res
+    out["plain"] = L.run_plain(ms, pool, n_clients=8, sessions_per_client=spc, reqs_per_session=rps, seed=seed)
+    key = f"budget_{256}MB"
+    out["served_vs_plain"] = out[key]["saturation"]["env_steps_per_s"] / out["plain"]["env_steps_per_s"]
+    return out
+
+
 def traffic_from_profile(name):
     """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
     p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
@@ -219,6 +253,7 @@ def main():
             _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed, pack=pack)
             extra[name] = res
         extra["hetero_speedup_vs_padded"] = extra["hetero"]["env_steps_per_s"] / extra["hetero_padded"]["env_steps_per_s"]
+        extra["serving"] = serving(ms, full=args.serve_full, seed=args.seed)
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)

@@ -108,7 +108,9 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     L.JM = o; o += 2 * n;  // jointed-partner masks (u64)
     // 55 n words so far
     L.JNT = o; o += 26 * nj;
-    L.CAND = o; o += (L.P + 1) / 2;
+    // candidate pairs (u16) during S2-S4; afterwards the per-body block lists (offsets [n + 1],
+    // entries u16 [2 (nj + mcap)])
+    L.CAND = o; o += (L.P + 1) / 2 > n + 1 + nj + mcap ? (L.P + 1) / 2 : n + 1 + nj + mcap;
     L.PT = o; o += 14 * cap;
     L.MAN = o; o += 23 * mcap;
     L.BCOL = o; o += (nj + mcap + 1) / 2;

@@ -354,13 +354,14 @@ int ms_selfcheck(void) {
             for (int cap = 1; cap <= 512; cap = cap * 2 + 1)
                 for (int mcap = 1; mcap <= cap; mcap = mcap * 2 + 1) {
                     Lay L = make_lay(n, nj, cap, mcap);
-                    // every region at least as large as the kernel's use of it, in order, no overlap:
+                    // every region at least as large as the kernel's use of it, in order, no overlap
+                    // (the candidate area later holds the per-body block lists):
                     // contact rows 14 words per point, manifold rows 23 per manifold, schedules of
                     // up to nj + mcap + 66 entries (the joint schedule holds the 65 colouring
                     // cursors when there are no joints)
                     const int start[] = {L.JM, L.JNT, L.CAND, L.PT, L.MAN, L.BCOL, L.ORDER, L.SCHED, L.JSCHED,
                                          L.CSTART, L.SCAL};
-                    const int size[] = {2 * n, 26 * nj, (P + 1) / 2, 14 * cap, 23 * mcap, (nj + mcap + 1) / 2,
+                    const int size[] = {2 * n, 26 * nj, std::max((P + 1) / 2, n + 1 + nj + mcap), 14 * cap, 23 * mcap, (nj + mcap + 1) / 2,
                                         (nj + mcap + 1) / 2, nj + mcap + 66, nj > 0 ? nj + mcap + 66 : N_COLOURS + 1,
                                         N_COLOURS + 2, 32};
                     for (int r = 0; r < 11; ++r) {

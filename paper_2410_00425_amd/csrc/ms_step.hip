@@ -1247,6 +1247,97 @@ __device__ __forceinline__ void bias_pass(const EnvCtx& c, int nman, float h, bo
     }
 }
 
+// Per-body block lists for the warm start (envs without joints): for every dynamic body, the
+// manifolds touching it in colour order with the body's side.  A body sits in at most one block
+// per colour, and a warm-start impulse does not depend on any velocity, so applying a body's
+// blocks in this order reproduces, bit for bit, what the coloured warm sweep does to that body.
+// Built once per step (after colouring) in the candidate area: offsets [n + 1] ints, then u16
+// entries (manifold | side << 15).
+// nn: the env's body count, 0 for a frozen env or an empty slot of the tile (which must not
+// touch the LDS it aliases).
+__device__ __forceinline__ void build_body_lists(const EnvCtx& c, int nn, int nman, int li, int G) {
+    const Lay& l = c.lay;
+    const int n = nn;
+    int* OFF = iptr(c.L + l.CAND);
+    uint16_t* ENT = reinterpret_cast<uint16_t*>(OFF + l.n + 1);
+    const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
+    // degree of every body: lane per body, blocks in colour order
+    for (int i = li; i < n; i += G) {
+        int deg = 0;
+        if (is_dyn(c, i)) {
+            for (int p = 0; p < nman; ++p) {
+                int a, b, f, cnt;
+                man_header(c, int(ORD[p]), a, b, f, cnt);
+                deg += (a == i ? 1 : 0) + (b == i ? 1 : 0);
+            }
+        }
+        OFF[i + 1] = deg;
+    }
+    wave_sync();
+    if (li == 0 && n > 0) {
+        OFF[0] = 0;
+        for (int i = 0; i < n; ++i) OFF[i + 1] += OFF[i];
+    }
+    wave_sync();
+    for (int i = li; i < n; i += G) {
+        if (!is_dyn(c, i)) continue;
+        int o = OFF[i];
+        for (int p = 0; p < nman; ++p) {
+            const int m = int(ORD[p]);
+            int a, b, f, cnt;
+            man_header(c, m, a, b, f, cnt);
+            if (a == i) ENT[o++] = uint16_t(m);
+            if (b == i) ENT[o++] = uint16_t(m | 0x8000);
+        }
+    }
+}
+
+// Gravity and damping of one dynamic body for a substep, then (after the first substep) its
+// warm start: the accumulated impulses of its blocks in colour order, as imp_lin / imp_ang apply
+// them to this body (side A subtracts, side B adds).
+__device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float h, float ldmp, float admp, bool warm) {
+    const BatchDev& bd = *c.bd;
+    const Lay& l = c.lay;
+    const int n = l.n;
+    V3 v = ld3(c.L, l.V, n, i);
+    v = ldmp * (v + h * v3(bd.gx, bd.gy, bd.gz));
+    V3 w = admp * ld3(c.L, l.W, n, i);
+    if (warm) {
+        const float im = c.L[l.INVM + i];
+        const S6 I = load_iw(c, i);
+        const int* OFF = iptr(c.L + l.CAND);
+        const uint16_t* ENT = reinterpret_cast<const uint16_t*>(OFF + n + 1);
+        for (int e = OFF[i]; e < OFF[i + 1]; ++e) {
+            const int ent = ENT[e];
+            const int m = ent & 0x7FFF;
+            const bool sideB = (ent >> 15) != 0;
+            int a, b, first, cnt;
+            man_header(c, m, a, b, first, cnt);
+            const int rrow = sideB ? R_RB : R_RA;
+            const int mrow = sideB ? M_RB : M_RA;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < cnt) {
+                    const int q = first + k;
+                    const V3 P = pr(c, R_LN, q) * pr3(c, R_N, q);
+                    const V3 r = pr3(c, rrow, q);
+                    if (sideB) { v = v + im * P; w = w + muls(I, cross3(r, P)); }
+                    else { v = v - im * P; w = w - muls(I, cross3(r, P)); }
+                }
+            }
+            const V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m);
+            const V3 t2 = cross3(nb, t1);
+            const V3 P = mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * t2;
+            const V3 r = mf3(c, mrow, m);
+            const V3 L = mf(c, M_LTW, m) * nb;
+            if (sideB) { v = v + im * P; w = w + muls(I, cross3(r, P)); w = w + muls(I, L); }
+            else { v = v - im * P; w = w - muls(I, cross3(r, P)); w = w - muls(I, L); }
+        }
+    }
+    st3(c.L, l.V, n, i, v);
+    st3(c.L, l.W, n, i, w);
+}
+
 enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
 
 // Block of this lane at schedule entry e (-1: none).
@@ -1803,17 +1894,18 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             // --------------------------------------------------------- S6 substeps
             const float ldmp = 1.0f / (1.0f + h * bd.lin_damp);
             const float admp = 1.0f / (1.0f + h * bd.ang_damp);
+            // joint-free waves warm-start body by body (fused with gravity); others sweep colours
+            if (pipe && S > 1) {
+                build_body_lists(c, nn, nmanA, li, G);
+                wave_sync();
+            }
             for (int s = 0; s < S; ++s) {
-                for (int i = li; i < nn; i += G) {
-                    if (!is_dyn(c, i)) continue;
-                    V3 v = ld3(c.L, l.V, n, i);
-                    v = ldmp * (v + h * v3(bd.gx, bd.gy, bd.gz));
-                    st3(c.L, l.V, n, i, v);
-                    st3(c.L, l.W, n, i, admp * ld3(c.L, l.W, n, i));
-                }
+                const bool gather = pipe && s > 0;
+                for (int i = li; i < nn; i += G)
+                    if (is_dyn(c, i)) body_substep_start(c, i, h, ldmp, admp, gather);
                 bias_pass(c, nmanA, h, false, li, G);
                 wave_sync();
-                if (s > 0) (pipe ? run_schedule<OP_WARM, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li));
+                if (s > 0 && !pipe) run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li);
                 for (int it = 0; it < K; ++it) {
                     for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
                     (pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));

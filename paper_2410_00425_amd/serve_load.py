@@ -38,10 +38,11 @@ class ScenePool:
                 self._cache[key] = S.by_name(family, n, seed=self.seed)
             return self._cache[key]
 
-    def warm(self):
-        for f in FAMILIES:
-            for k in range(6, 13):
-                self.get(f, 1 << k)
+    def prepare(self, seed, n_clients, sessions_per_client):
+        """Generate ahead of time the scenes the clients will open."""
+        for ci in range(n_clients):
+            for family, n in session_plan(seed, ci, sessions_per_client):
+                self.get(family, n)
 
 
 def session_plan(seed, client, n_sessions):
@@ -55,6 +56,7 @@ def session_plan(seed, client, n_sessions):
 def run_clients(ms, server, pool, lam, n_clients=8, sessions_per_client=2, reqs_per_session=20, steps=2, seed=0):
     """Drive the server from n_clients threads; returns per-request records and the wall time."""
     clock = ms.server_clock
+    pool.prepare(seed, n_clients, sessions_per_client)
     recs, errors = [], []
     lock = threading.Lock()
     t_begin = clock() + 0.05
@@ -121,6 +123,7 @@ def run_plain(ms, pool, n_clients=8, sessions_per_client=2, reqs_per_session=20,
     request, synchronised after each (no fusion, no overlap); returns env-steps/s and latencies."""
     import torch
     clock = ms.server_clock
+    pool.prepare(seed, n_clients, sessions_per_client)
     lat, es = [], 0
     t0 = clock()
     for ci in range(n_clients):
