@@ -132,10 +132,40 @@ def algorithmic_bytes(scene):
     return scene.n_bodies * (52 * 2 + 48) + scene.n_envs * (8 + 8) + scene.n_joints * 76
 
 
-def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1):
+def time_graph(batch, steps, warmup, per_graph=10):
+    """Steps replayed from a captured graph of per_graph single-step launches."""
+    import numpy as np
+    import torch
+    for _ in range(max(1, warmup)):
+        batch.step(1)
+    g = batch.graph(1, per_graph)
+    g.launch()
+    torch.cuda.synchronize()
+    batch.stats(reset=True)
+    n_rep = max(1, steps // per_graph)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_rep + 1)]
+    ev[0].record()
+    for i in range(n_rep):
+        g.launch()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n_rep)]) / per_graph
+    total_ms = ev[0].elapsed_time(ev[-1])
+    g.close()
+    st = batch.stats()
+    n_steps = n_rep * per_graph
+    return dict(total_ms=total_ms, n_steps=n_steps, n_launch=n_steps, launch_ms=total_ms / n_steps,
+                p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), stats=st)
+
+
+def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False):
     sc = S.by_name(name, n_envs, seed=seed)
     b = ms.Batch(sc, lanes_per_env=lanes, pack=pack)
-    r = time_batch(b, steps, warmup, spl)
+    if tune:
+        for _ in range(max(1, warmup)):
+            b.step(1)
+        b.tune(3)
+    r = time_graph(b, steps, warmup) if graph else time_batch(b, steps, warmup, spl)
     flop = algorithmic_flop(sc, r["stats"], sc.params)
     plan = b.plan()
     b.close()
@@ -252,7 +282,12 @@ def main():
                               ("hetero_padded", 4096, 0)):
             _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed, pack=pack)
             extra[name] = res
+        # the batched form with the autotuned tiling, its steps replayed from a captured graph
+        _, _, res = run_workload(ms, S, "hetero", 4096, 100, 20, 1, args.seed, tune=True, graph=True)
+        extra["hetero_tuned_graph"] = res
         extra["hetero_speedup_vs_padded"] = extra["hetero"]["env_steps_per_s"] / extra["hetero_padded"]["env_steps_per_s"]
+        extra["hetero_tuned_graph_speedup_vs_padded"] = (extra["hetero_tuned_graph"]["env_steps_per_s"] /
+                                                         extra["hetero_padded"]["env_steps_per_s"])
         extra["serving"] = serving(ms, full=args.serve_full, seed=args.seed)
         out["extra"] = extra
     if not args.no_cpu:

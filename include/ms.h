@@ -205,9 +205,13 @@ ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds
  * into host_classes (may be NULL). */
 ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes);
 
-/* Autotuner: for every LDS class, time each kernel variant over trial_steps launches of that
- * class alone and keep the fastest.  The batch's state, status and work counters are saved
- * before and restored after (the trial steps leave no trace).  Synchronises `hip_stream`. */
+/* Autotuner.  First the env tiling: for every group of envs that the planner gave the same
+ * lanes per env (so 64 / lanes envs per wavefront), the whole batch is timed over trial_steps
+ * steps with half and with twice as many lanes for that group, and a change is kept if it is
+ * at least 2 % faster.  Then, for every LDS class, each kernel variant is timed over
+ * trial_steps launches of that class alone and the fastest kept.  The tiling never changes a
+ * result.  The batch's state, status and work counters are saved before and restored after
+ * (the trial steps leave no trace).  Synchronises `hip_stream`. */
 ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream);
 
 /* Work counters accumulated by every step since the last reset, int64 [n_envs][16]: steps,

@@ -137,23 +137,12 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     return MS_OK;
 }
 
-void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* plan, Plan& out) {
-    const int E = s->n_envs;
-    const int forced = plan ? plan->lanes_per_env : 0;
-    const bool pack = plan ? plan->pack != 0 : true;
-    const int budget = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
-    out.info.resize(E);
-    for (int e = 0; e < E; ++e) {
-        EnvInfo& I = out.info[e];
-        I.n = s->env_body_off[e + 1] - s->env_body_off[e];
-        I.nj = s->env_joint_off[e + 1] - s->env_joint_off[e];
-        I.n_dyn = 0;
-        for (int i = 0; i < I.n; ++i) I.n_dyn += (s->bodies[s->env_body_off[e] + i].flags & MS_BODY_STATIC) ? 0 : 1;
-        I.cap = p->max_contacts_per_env > 0 ? p->max_contacts_per_env : std::min(6 * I.n_dyn + 8, 384);
-        I.mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(3 * I.n_dyn + 4, 192);
-        I.words = env_lds_words(I.n, I.nj, I.cap, I.mcap);
-        I.lanes = pick_lanes(I, forced, budget);
-    }
+constexpr int TILE_BUDGET = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
+
+// Tiles, env slots and LDS classes from the per-env sizes and lanes (info[e].lanes): envs sorted
+// by (lanes, LDS words) when packing, consecutive envs of equal lanes share a tile while it fits.
+void make_tiles(Plan& out, bool pack) {
+    const int E = int(out.info.size());
     std::vector<int> order(E);
     for (int e = 0; e < E; ++e) order[e] = e;
     if (pack)
@@ -169,7 +158,7 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
         int e = order[k];
         const EnvInfo& I = out.info[e];
         bool fits = cur.count > 0 && cur.lanes == I.lanes && cur.count < WAVE / I.lanes &&
-                    cur.lds_words + I.words <= std::max(budget, I.words);
+                    cur.lds_words + I.words <= std::max(TILE_BUDGET, I.words);
         if (!fits) {
             if (cur.count > 0) out.tiles.push_back(cur);
             cur = Tile{int(out.tenv.size()), 0, I.lanes, 0};
@@ -187,11 +176,30 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
     for (int t = 0; t < int(out.tiles.size()); ++t) {
         const Tile& tl = out.tiles[t];
         bool split = !out.classes.empty() && 3 * tl.lds_words < 2 * out.classes.back().lds_words &&
-                     int(out.classes.size()) < MAX_CLASSES && (plan == nullptr || plan->pack != 0);
+                     int(out.classes.size()) < MAX_CLASSES && pack;
         if (out.classes.empty() || split) out.classes.push_back(LdsClass{t, 0, tl.lds_words, tl.lanes == 64 ? 1 : 0, tl.lanes});
         out.classes.back().n_tiles++;
     }
     for (const Tile& t : out.tiles) out.max_tile_words = std::max(out.max_tile_words, t.lds_words);
+}
+
+void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* plan, Plan& out) {
+    const int E = s->n_envs;
+    const int forced = plan ? plan->lanes_per_env : 0;
+    const bool pack = plan ? plan->pack != 0 : true;
+    out.info.resize(E);
+    for (int e = 0; e < E; ++e) {
+        EnvInfo& I = out.info[e];
+        I.n = s->env_body_off[e + 1] - s->env_body_off[e];
+        I.nj = s->env_joint_off[e + 1] - s->env_joint_off[e];
+        I.n_dyn = 0;
+        for (int i = 0; i < I.n; ++i) I.n_dyn += (s->bodies[s->env_body_off[e] + i].flags & MS_BODY_STATIC) ? 0 : 1;
+        I.cap = p->max_contacts_per_env > 0 ? p->max_contacts_per_env : std::min(6 * I.n_dyn + 8, 384);
+        I.mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(3 * I.n_dyn + 4, 192);
+        I.words = env_lds_words(I.n, I.nj, I.cap, I.mcap);
+        I.lanes = pick_lanes(I, forced, TILE_BUDGET);
+    }
+    make_tiles(out, pack);
     out.dbg_pair_off.assign(E + 1, 0);
     out.dbg_pt_off.assign(E + 1, 0);
     out.dbg_man_off.assign(E + 1, 0);
@@ -217,7 +225,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.joint_off = take((E + 1) * 4);
     L.jrec = take(J * JREC * 4);
     L.targets = take(J * 4);
-    L.tiles = take(pl.tiles.size() * sizeof(Tile));
+    L.tiles = take(E * sizeof(Tile));   // room for any tiling (one env per tile at most)
     L.tenv = take(pl.tenv.size() * sizeof(TileEnv));
     L.bd = take(sizeof(BatchDev));
     L.stats = take(E * NSTAT * 4);
@@ -283,6 +291,8 @@ struct ms_batch {
     int device = 0;
     int grid = 0;
     size_t lds_bytes = 0;
+    bool pack = true;
+    int max_resident_groups = 0;
     // fork / join streams for LDS classes after the first (default priority)
     hipStream_t side[MAX_CLASSES] = {};
     hipEvent_t ev_fork = nullptr;
@@ -429,9 +439,11 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
         delete b;
         return fail(MS_E_CAPACITY, "an env tile needs %zu bytes of LDS; the device allows %d", need, max_lds);
     }
+    b->pack = plan ? plan->pack != 0 : true;
+    b->max_resident_groups = plan ? plan->max_resident_groups : 0;
     const int n_tiles = int(b->plan.tiles.size());
     b->grid = n_tiles;
-    if (plan && plan->max_resident_groups > 0) b->grid = std::min(n_tiles, plan->max_resident_groups);
+    if (b->max_resident_groups > 0) b->grid = std::min(n_tiles, b->max_resident_groups);
 
     // host staging
     const size_t B = b->B, E = b->E, J = b->J;
@@ -516,13 +528,35 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
 
 // Side streams and events of the LDS-class fork / join, created once per batch.
 static ms_status ensure_side_streams(ms_batch* b) {
-    if (b->ev_fork || b->plan.classes.size() < 2) return MS_OK;
-    HIP_OK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    if (b->plan.classes.size() < 2) return MS_OK;
+    if (!b->ev_fork) HIP_OK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     for (size_t k = 1; k < b->plan.classes.size(); ++k) {
-        HIP_OK(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
-        HIP_OK(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+        if (!b->side[k]) HIP_OK(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
+        if (!b->ev_join[k]) HIP_OK(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
     }
     return MS_OK;
+}
+
+// Rebuild the tiles for new per-env lanes and upload them (the workspace has room for any
+// tiling).  Synchronises `s`.  The result of a step does not depend on the tiling.
+static ms_status retile(ms_batch* b, const std::vector<int>& lanes, hipStream_t s) {
+    Plan np = b->plan;   // the batch keeps its plan unless the new one is valid
+    for (size_t e = 0; e < lanes.size(); ++e) np.info[e].lanes = lanes[e];
+    make_tiles(np, b->pack);
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess) max_lds = 65536;
+    if (size_t(np.max_tile_words) * 4 > size_t(max_lds))
+        return fail(MS_E_CAPACITY, "a tile would need %d bytes of LDS", np.max_tile_words * 4);
+    b->plan = std::move(np);
+    b->lds_bytes = size_t(b->plan.max_tile_words) * 4;
+    const int n_tiles = int(b->plan.tiles.size());
+    b->grid = b->max_resident_groups > 0 ? std::min(n_tiles, b->max_resident_groups) : n_tiles;
+    HIP_OK(hipMemcpyAsync(b->ws + b->lay.tiles, b->plan.tiles.data(), b->plan.tiles.size() * sizeof(Tile),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(b->ws + b->lay.tenv, b->plan.tenv.data(), b->plan.tenv.size() * sizeof(TileEnv),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return ensure_side_streams(b);
 }
 
 ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* hip_stream) {
@@ -698,18 +732,62 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
     std::vector<int> stats_save(E * NSTAT);
     HIP_OK(hipMemcpyAsync(stats_save.data(), w + L.stats, E * NSTAT * 4, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    auto restore = [&]() -> ms_status {
+        size_t oo = L.save;
+        for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + st_off[k], w + oo, st_bytes[k], hipMemcpyDeviceToDevice, s)); oo += st_bytes[k]; }
+        HIP_OK(hipMemcpyAsync(w + L.status, w + oo, E * 4, hipMemcpyDeviceToDevice, s));
+        return MS_OK;
+    };
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
+    ms_status st = MS_OK;
+    // whole-batch step time of the current plan: restore, one untimed step, trial_steps timed
+    auto time_batch = [&](float& ms) -> ms_status {
+        if (ms_status r = restore(); r != MS_OK) return r;
+        if (ms_status r = ms_step(b, nullptr, 1, s); r != MS_OK) return r;
+        HIP_OK(hipEventRecord(e0, s));
+        for (int t = 0; t < trial_steps; ++t)
+            if (ms_status r = ms_step(b, nullptr, 1, s); r != MS_OK) return r;
+        HIP_OK(hipEventRecord(e1, s));
+        HIP_OK(hipEventSynchronize(e1));
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        return MS_OK;
+    };
+    // 1. lanes per env (64 / lanes envs per wavefront): for each group of envs that the planner
+    //    gave the same lanes, try half and twice as many; keep a change only if the whole batch
+    //    steps at least 2 % faster
+    std::vector<int> orig(E), lanes(E);
+    for (size_t e = 0; e < E; ++e) orig[e] = lanes[e] = b->plan.info[e].lanes;
+    float best = 0.0f;
+    st = time_batch(best);
+    std::vector<int> groups(orig);
+    std::sort(groups.begin(), groups.end());
+    groups.erase(std::unique(groups.begin(), groups.end()), groups.end());
+    for (int G : groups) {
+        if (st != MS_OK) break;
+        for (int alt : {G / 2, G * 2}) {
+            if (alt < 1 || alt > WAVE || st != MS_OK) continue;
+            std::vector<int> trial(lanes);
+            for (size_t e = 0; e < E; ++e)
+                if (orig[e] == G) trial[e] = alt;
+            if (retile(b, trial, s) != MS_OK) continue;   // e.g. a tile too large: skip this option
+            float t = 0.0f;
+            st = time_batch(t);
+            if (st == MS_OK && t < 0.98f * best) { best = t; lanes = trial; }
+        }
+        if (st == MS_OK) st = retile(b, lanes, s);
+    }
+    // 2. kernel variant per LDS class, each class timed alone
     const Tile* tiles = at<Tile>(w, L.tiles);
     const TileEnv* tenv = at<TileEnv>(w, L.tenv);
     for (LdsClass& c : b->plan.classes) {
-        float best = 1e30f;
+        if (st != MS_OK) break;
+        float bestc = 1e30f;
         int best_v = c.variant;
-        for (int v = 0; v < 2; ++v) {
-            // restore, one untimed launch, then trial_steps timed launches of this class alone
-            size_t oo = L.save;
-            for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + st_off[k], w + oo, st_bytes[k], hipMemcpyDeviceToDevice, s)); oo += st_bytes[k]; }
+        for (int v = 0; v < 2 && st == MS_OK; ++v) {
+            st = restore();
+            if (st != MS_OK) break;
             hipLaunchKernelGGL(kernel_of(v), dim3(c.n_tiles), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
                                tiles + c.first_tile, c.n_tiles, tenv, 1);
             HIP_OK(hipEventRecord(e0, s));
@@ -721,18 +799,16 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
             HIP_OK(hipEventSynchronize(e1));
             float ms = 0.0f;
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; best_v = v; }
+            if (ms < bestc) { bestc = ms; best_v = v; }
         }
         c.variant = best_v;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    o = L.save;
-    for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + st_off[k], w + o, st_bytes[k], hipMemcpyDeviceToDevice, s)); o += st_bytes[k]; }
-    HIP_OK(hipMemcpyAsync(w + L.status, w + o, E * 4, hipMemcpyDeviceToDevice, s));
+    ms_status rs = restore();
     HIP_OK(hipMemcpyAsync(w + L.stats, stats_save.data(), E * NSTAT * 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
-    return MS_OK;
+    return st != MS_OK ? st : rs;
 }
 
 ms_status ms_get_stats(ms_batch* b, int64_t* host_stats, int32_t reset, void* hip_stream) {

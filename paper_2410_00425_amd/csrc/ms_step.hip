@@ -1466,8 +1466,10 @@ __device__ __forceinline__ void colour_env_wave(const EnvCtx& c) {
     const Lay& l = c.lay;
     const int li = threadIdx.x;
     int* SC = iptr(c.L + l.SCAL);
-    const int nman = SC[SC_NMAN];
-    const int nb = l.nj + nman;
+    // one env per wave: its sizes are wave-uniform (scalar loop bounds)
+    const int nj = __builtin_amdgcn_readfirstlane(l.nj);
+    const int nman = __builtin_amdgcn_readfirstlane(SC[SC_NMAN]);
+    const int nb = nj + nman;
     uint16_t* BC = reinterpret_cast<uint16_t*>(c.L + l.BCOL);
     uint16_t* ORD = reinterpret_cast<uint16_t*>(c.L + l.ORDER);
     const uint64_t dynm = __ballot(li < l.n && is_dyn(c, li));
@@ -1481,12 +1483,12 @@ __device__ __forceinline__ void colour_env_wave(const EnvCtx& c) {
         int pk = 0xFFFFFFFF;
         if (blk < nb) {
             int a, b;
-            if (blk < l.nj) {
+            if (blk < nj) {
                 const int* J = reinterpret_cast<const int*>(jrec(c, blk));
                 a = J[J_PA]; b = J[J_CH];
             } else {
                 int f, cnt;
-                man_header(c, blk - l.nj, a, b, f, cnt);
+                man_header(c, blk - nj, a, b, f, cnt);
             }
             pk = (a & 0xFFFF) | (b << 16);
         }
@@ -1502,7 +1504,7 @@ __device__ __forceinline__ void colour_env_wave(const EnvCtx& c) {
             if (db) u |= uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mlo), b))) |
                          (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(mhi), b))) << 32);
             int col;
-            const bool joint = r * WAVE + k < l.nj;
+            const bool joint = r * WAVE + k < nj;
             if (~u == 0) {
                 col = N_COLOURS;
                 overflow = true;
@@ -1565,7 +1567,7 @@ __device__ __forceinline__ void colour_env_wave(const EnvCtx& c) {
         }
         SC[SC_NCOL] = ncol;
         SC[SC_NSCHED] = ns;
-        SC[SC_NJSCHED] = l.nj > 0 ? njs : 0;
+        SC[SC_NJSCHED] = nj > 0 ? njs : 0;
     }
 }
 
@@ -1800,7 +1802,47 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             // --------------------------------------------------------- S2 candidate pairs
             const int P = frozen ? 0 : l.P;
             int ncand = 0;
-            {
+            if (G == WAVE) {
+                // one env per wave: lane a tests a against every later body b (b's box read by
+                // all lanes at once) into a bit mask, then writes its pairs b ascending and the
+                // plane last at its offset in a scan over lanes: canonical order
+                uint16_t* CAND = reinterpret_cast<uint16_t*>(c.L + l.CAND);
+                const int nw = __builtin_amdgcn_readfirstlane(nn);
+                const int a = li;
+                const bool act = a < nw;
+                const float* AB = c.L + l.AABB;
+                V3 amin = v3(0, 0, 0), amax = v3(0, 0, 0);
+                uint64_t jm = 0;
+                bool dyn_a = false;
+                if (act) {
+                    amin = v3(AB[a], AB[n + a], AB[2 * n + a]);
+                    amax = v3(AB[3 * n + a], AB[4 * n + a], AB[5 * n + a]);
+                    const int* JMi = iptr(c.L + l.JM);
+                    jm = uint64_t(uint32_t(JMi[2 * a])) | (uint64_t(uint32_t(JMi[2 * a + 1])) << 32);
+                    dyn_a = is_dyn(c, a);
+                }
+                const uint64_t dynm = __ballot(dyn_a);
+                uint64_t mask = 0;
+                for (int b = 1; b < nw; ++b) {
+                    const V3 bmin = v3(AB[b], AB[n + b], AB[2 * n + b]);
+                    const V3 bmax = v3(AB[3 * n + b], AB[4 * n + b], AB[5 * n + b]);
+                    const bool ov = b > a && (dyn_a || ((dynm >> b) & 1)) && !((jm >> b) & 1) &&
+                                    (amin.x <= bmax.x && bmin.x <= amax.x) && (amin.y <= bmax.y && bmin.y <= amax.y) &&
+                                    (amin.z <= bmax.z && bmin.z <= amax.z);
+                    if (ov) mask |= uint64_t(1) << b;
+                }
+                const bool pl = act && bd.plane && dyn_a && amin.z <= bd.plane_z;
+                const int cnt = __popcll(mask) + (pl ? 1 : 0);
+                int tot;
+                int o = group_scan_small<7>(cnt, li, 0, WAVE, tot);
+                while (mask) {
+                    const int b = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    CAND[o++] = uint16_t(a | (b << 8));
+                }
+                if (pl) CAND[o] = uint16_t(a | (n << 8));
+                ncand = tot;
+            } else {
                 const int nch = wave_max((P + G - 1) / G);
                 uint16_t* CAND = reinterpret_cast<uint16_t*>(c.L + l.CAND);
                 const int* JMi = iptr(c.L + l.JM);
