@@ -201,7 +201,9 @@ ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds
                       int32_t* host_env_lanes);
 
 /* LDS classes of the launch plan: *n_classes and, per class, int32 {tiles, LDS bytes per
- * workgroup, kernel variant (0 unconstrained, 1 two waves per SIMD), lanes per env, first tile}
+ * workgroup, kernel variant (0 unconstrained, 1 two waves per SIMD, 2 and 3 the same two built
+ * for tiles that hold one env on all 64 lanes; a class runs its one-env tiles with 2 or 3 and its
+ * other tiles with 0 or 1, and the value reported is the first), lanes per env, first tile}
  * into host_classes (may be NULL). */
 ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes);
 

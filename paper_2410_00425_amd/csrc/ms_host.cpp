@@ -21,6 +21,10 @@ extern "C" __global__ void ms_step_kernel(const BatchDev* batches, const Tile* t
                                           int n_steps);
 extern "C" __global__ void ms_step_kernel_w2(const BatchDev* batches, const Tile* tiles, int n_tiles,
                                              const TileEnv* tenv, int n_steps);
+extern "C" __global__ void ms_step_kernel_one(const BatchDev* batches, const Tile* tiles, int n_tiles,
+                                              const TileEnv* tenv, int n_steps);
+extern "C" __global__ void ms_step_kernel_one_w2(const BatchDev* batches, const Tile* tiles, int n_tiles,
+                                                 const TileEnv* tenv, int n_steps);
 extern "C" __global__ void ms_reset_kernel(BatchDev bd, const int* env_ids, int n_ids, const float* spos,
                                            const float* squat, const float* svel, const float* sang);
 
@@ -48,7 +52,7 @@ ms_status fail(ms_status s, const char* fmt, ...) {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
-constexpr int MAX_CLASSES = 4;
+constexpr int MAX_CLASSES = 4;  // one stream per class; the default four hardware queues
 
 // Per-env sizes used by the planner.
 struct EnvInfo {
@@ -69,14 +73,66 @@ int pick_lanes(const EnvInfo& e, int forced, int tile_budget_words) {
 }
 
 // Tiles of one LDS class run in one launch whose dynamic LDS is the class maximum.
+// A class is launched on its own stream as up to two kernels in sequence: its one-env, 64-lane
+// tiles (the first n_one) with a scalar-env build, the other tiles with a general build.
 struct LdsClass {
     int first_tile, n_tiles, lds_words;
-    int variant;  // 0: ms_step_kernel, 1: ms_step_kernel_w2 (two waves per SIMD)
+    int variant;  // of the one-env part: 2 ms_step_kernel_one, 3 ms_step_kernel_one_w2
     int lanes;    // lanes per env of the class's first tile
+    int n_one;    // leading one-env tiles
+    int variant_gen;  // of the rest: 0 ms_step_kernel, 1 ms_step_kernel_w2 (two waves per SIMD)
 };
 
 typedef void (*StepKernel)(const BatchDev*, const Tile*, int, const TileEnv*, int);
-inline StepKernel kernel_of(int variant) { return variant == 1 ? ms_step_kernel_w2 : ms_step_kernel; }
+inline StepKernel kernel_of(int variant) {
+    switch (variant) {
+        case 1: return ms_step_kernel_w2;
+        case 2: return ms_step_kernel_one;
+        case 3: return ms_step_kernel_one_w2;
+        default: return ms_step_kernel;
+    }
+}
+inline bool one_env_tile(const Tile& t) { return t.lanes == WAVE && t.count == 1; }
+
+// Cut tiles sorted by LDS need (largest first) into launch classes — a new class when a tile
+// needs less than 2/3 of the class maximum, at most MAX_CLASSES.  Default kernels: two waves per SIMD for the one-env part; for
+// the rest, two waves per SIMD in a class that starts with 64-lane tiles (large envs), else the
+// unconstrained build.
+template <class TileRef>
+void cut_classes(int n, TileRef tile_ref, bool split_ok, std::vector<LdsClass>& cls) {
+    cls.clear();
+    for (int t = 0; t < n; ++t) {
+        const Tile& tl = tile_ref(t);
+        bool split = !cls.empty() && split_ok && int(cls.size()) < MAX_CLASSES &&
+                     3 * tl.lds_words < 2 * cls.back().lds_words;
+        if (cls.empty() || split) cls.push_back(LdsClass{t, 0, tl.lds_words, 3, tl.lanes, 0, tl.lanes == WAVE ? 1 : 0});
+        cls.back().n_tiles++;
+        cls.back().lds_words = std::max(cls.back().lds_words, tl.lds_words);
+    }
+    // a class made only of one-env tiles runs the scalar-env build; a mixed class runs the
+    // general build on all its tiles (two launches in sequence on one stream cost more tail
+    // than the scalar-env build saves)
+    for (LdsClass& c : cls) {
+        bool all_one = true;
+        for (int t = c.first_tile; t < c.first_tile + c.n_tiles; ++t) all_one = all_one && one_env_tile(tile_ref(t));
+        c.n_one = all_one ? c.n_tiles : 0;
+    }
+}
+
+// Launch one class on stream s: the one-env part, then the general part.
+ms_status launch_class(const LdsClass& c, const BatchDev* dbd, const Tile* tiles, const TileEnv* tenv, int n_steps,
+                       int grid_cap, hipStream_t s) {
+    const size_t lds = size_t(c.lds_words) * 4;
+    const int parts[2][3] = {{c.first_tile, c.n_one, c.variant},
+                             {c.first_tile + c.n_one, c.n_tiles - c.n_one, c.variant_gen}};
+    for (const auto& pt : parts) {
+        if (pt[1] <= 0) continue;
+        const int grid = grid_cap > 0 ? std::max(1, std::min(pt[1], grid_cap)) : pt[1];
+        hipLaunchKernelGGL(kernel_of(pt[2]), dim3(grid), dim3(WAVE), lds, s, dbd, tiles + pt[0], pt[1], tenv, n_steps);
+        HIP_OK(hipGetLastError());
+    }
+    return MS_OK;
+}
 
 struct Plan {
     std::vector<EnvInfo> info;
@@ -168,18 +224,10 @@ void make_tiles(Plan& out, bool pack) {
         cur.count++;
     }
     if (cur.count > 0) out.tiles.push_back(cur);
-    // LDS classes: tiles sorted by LDS need (largest first, stable); a new class starts when a
-    // tile needs less than 2/3 of the class maximum, at most MAX_CLASSES classes.
+    // LDS classes: tiles sorted by LDS need (largest first, stable), then cut (cut_classes).
     std::stable_sort(out.tiles.begin(), out.tiles.end(),
                      [](const Tile& a, const Tile& b) { return a.lds_words > b.lds_words; });
-    out.classes.clear();
-    for (int t = 0; t < int(out.tiles.size()); ++t) {
-        const Tile& tl = out.tiles[t];
-        bool split = !out.classes.empty() && 3 * tl.lds_words < 2 * out.classes.back().lds_words &&
-                     int(out.classes.size()) < MAX_CLASSES && pack;
-        if (out.classes.empty() || split) out.classes.push_back(LdsClass{t, 0, tl.lds_words, tl.lanes == 64 ? 1 : 0, tl.lanes});
-        out.classes.back().n_tiles++;
-    }
+    cut_classes(int(out.tiles.size()), [&](int t) -> Tile& { return out.tiles[t]; }, pack, out.classes);
     for (const Tile& t : out.tiles) out.max_tile_words = std::max(out.max_tile_words, t.lds_words);
 }
 
@@ -568,12 +616,8 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     const std::vector<LdsClass>& cls = b->plan.classes;
     const Tile* tiles = at<Tile>(b->ws, b->lay.tiles);
     const TileEnv* tenv = at<TileEnv>(b->ws, b->lay.tenv);
-    if (cls.size() == 1) {
-        hipLaunchKernelGGL(kernel_of(cls[0].variant), dim3(b->grid), dim3(WAVE), b->lds_bytes, s, b->dbd, tiles,
-                           int(b->plan.tiles.size()), tenv, int(n_steps));
-        HIP_OK(hipGetLastError());
-        return MS_OK;
-    }
+    const int grid_cap = b->max_resident_groups;
+    if (cls.size() == 1) return launch_class(cls[0], b->dbd, tiles, tenv, int(n_steps), grid_cap, s);
     // one launch per LDS class: the largest class on the caller's stream, the others on side
     // streams forked from and joined back into it
     if (ms_status st = ensure_side_streams(b); st != MS_OK) return st;
@@ -581,11 +625,7 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     for (size_t k = 0; k < cls.size(); ++k) {
         hipStream_t sk = k == 0 ? s : b->side[k];
         if (k > 0) HIP_OK(hipStreamWaitEvent(sk, b->ev_fork, 0));
-        int grid = cls[k].n_tiles;
-        if (b->grid < int(b->plan.tiles.size())) grid = std::max(1, std::min(grid, b->grid));
-        hipLaunchKernelGGL(kernel_of(cls[k].variant), dim3(grid), dim3(WAVE), size_t(cls[k].lds_words) * 4, sk, b->dbd,
-                           tiles + cls[k].first_tile, cls[k].n_tiles, tenv, int(n_steps));
-        HIP_OK(hipGetLastError());
+        if (ms_status st = launch_class(cls[k], b->dbd, tiles, tenv, int(n_steps), grid_cap, sk); st != MS_OK) return st;
         if (k > 0) {
             HIP_OK(hipEventRecord(b->ev_join[k], sk));
             HIP_OK(hipStreamWaitEvent(s, b->ev_join[k], 0));
@@ -648,7 +688,8 @@ ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes)
         for (size_t k = 0; k < b->plan.classes.size(); ++k) {
             const LdsClass& c = b->plan.classes[k];
             int32_t* o = host_classes + 5 * k;
-            o[0] = c.n_tiles; o[1] = c.lds_words * 4; o[2] = c.variant; o[3] = c.lanes; o[4] = c.first_tile;
+            o[0] = c.n_tiles; o[1] = c.lds_words * 4; o[2] = c.n_one > 0 ? c.variant : c.variant_gen;
+            o[3] = c.lanes; o[4] = c.first_tile;
         }
     return MS_OK;
 }
@@ -778,30 +819,35 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
         }
         if (st == MS_OK) st = retile(b, lanes, s);
     }
-    // 2. kernel variant per LDS class, each class timed alone
+    // 2. kernel variant per part of each LDS class (one-env part: 2 / 3, general part: 0 / 1),
+    //    each part timed alone
     const Tile* tiles = at<Tile>(w, L.tiles);
     const TileEnv* tenv = at<TileEnv>(w, L.tenv);
     for (LdsClass& c : b->plan.classes) {
-        if (st != MS_OK) break;
-        float bestc = 1e30f;
-        int best_v = c.variant;
-        for (int v = 0; v < 2 && st == MS_OK; ++v) {
-            st = restore();
-            if (st != MS_OK) break;
-            hipLaunchKernelGGL(kernel_of(v), dim3(c.n_tiles), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
-                               tiles + c.first_tile, c.n_tiles, tenv, 1);
-            HIP_OK(hipEventRecord(e0, s));
-            for (int t = 0; t < trial_steps; ++t)
-                hipLaunchKernelGGL(kernel_of(v), dim3(c.n_tiles), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
-                                   tiles + c.first_tile, c.n_tiles, tenv, 1);
-            HIP_OK(hipGetLastError());
-            HIP_OK(hipEventRecord(e1, s));
-            HIP_OK(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < bestc) { bestc = ms; best_v = v; }
+        for (int part = 0; part < 2 && st == MS_OK; ++part) {
+            const int first = part == 0 ? c.first_tile : c.first_tile + c.n_one;
+            const int count = part == 0 ? c.n_one : c.n_tiles - c.n_one;
+            if (count <= 0) continue;
+            float bestc = 1e30f;
+            int best_v = part == 0 ? c.variant : c.variant_gen;
+            for (int v = part == 0 ? 2 : 0; v < (part == 0 ? 4 : 2) && st == MS_OK; ++v) {
+                st = restore();
+                if (st != MS_OK) break;
+                hipLaunchKernelGGL(kernel_of(v), dim3(count), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
+                                   tiles + first, count, tenv, 1);
+                HIP_OK(hipEventRecord(e0, s));
+                for (int t = 0; t < trial_steps; ++t)
+                    hipLaunchKernelGGL(kernel_of(v), dim3(count), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
+                                       tiles + first, count, tenv, 1);
+                HIP_OK(hipGetLastError());
+                HIP_OK(hipEventRecord(e1, s));
+                HIP_OK(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < bestc) { bestc = ms; best_v = v; }
+            }
+            (part == 0 ? c.variant : c.variant_gen) = best_v;
         }
-        c.variant = best_v;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -918,6 +964,7 @@ thread_local Staging g_stage;
 
 struct ManyTile {
     int lds_words, batch, tile;
+    bool one;
 };
 }  // namespace
 
@@ -976,7 +1023,10 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
             f.batch = i;
             te[tenv_base[i] + k] = f;
         }
-        for (size_t t = 0; t < b->plan.tiles.size(); ++t) order.push_back(ManyTile{b->plan.tiles[t].lds_words, i, int(t)});
+        for (size_t t = 0; t < b->plan.tiles.size(); ++t) {
+            const Tile& u = b->plan.tiles[t];
+            order.push_back(ManyTile{u.lds_words, i, int(t), u.lanes == WAVE && u.count == 1});
+        }
         if (dev_targets && dev_targets[i] && b->J > 0)
             HIP_OK(hipMemcpyAsync(const_cast<float*>(b->hbd.targets), dev_targets[i], size_t(b->J) * 4,
                                   hipMemcpyDeviceToDevice, s));
@@ -987,10 +1037,8 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
         Tile u = batches[order[k].batch]->plan.tiles[order[k].tile];
         u.first += tenv_base[order[k].batch];
         tt[k] = u;
-        bool split = !cls.empty() && 3 * u.lds_words < 2 * cls.back().lds_words && int(cls.size()) < MAX_CLASSES;
-        if (cls.empty() || split) cls.push_back(LdsClass{int(k), 0, u.lds_words, u.lanes == 64 ? 1 : 0, u.lanes});
-        cls.back().n_tiles++;
     }
+    cut_classes(int(order.size()), [&](int k) -> Tile& { return tt[k]; }, true, cls);
     HIP_OK(hipMemcpyAsync(dev_scratch, st.host, need, hipMemcpyHostToDevice, s));
     HIP_OK(hipEventRecord(st.ev, s));
     st.pending = true;
@@ -1009,10 +1057,7 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     for (size_t k = 0; k < cls.size(); ++k) {
         hipStream_t sk = k == 0 ? s : st.side[k];
         if (k > 0) HIP_OK(hipStreamWaitEvent(sk, st.ev_fork, 0));
-        hipLaunchKernelGGL(kernel_of(cls[k].variant), dim3(unsigned(cls[k].n_tiles)), dim3(WAVE),
-                           size_t(cls[k].lds_words) * 4, sk, dtb, dtt + cls[k].first_tile, cls[k].n_tiles, dte,
-                           int(n_steps));
-        HIP_OK(hipGetLastError());
+if (ms_status r = launch_class(cls[k], dtb, dtt, dte, int(n_steps), 0, sk); r != MS_OK) return r;
         if (k > 0) {
             HIP_OK(hipEventRecord(st.ev_join[k], sk));
             HIP_OK(hipStreamWaitEvent(s, st.ev_join[k], 0));

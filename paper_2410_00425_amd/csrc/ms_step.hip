@@ -1687,6 +1687,9 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
 
 // ============================================================================= step kernel
 // The step of every tile of the work list; `lds` is the workgroup's dynamic LDS.
+// ONE: every tile of the launch holds a single env served by all 64 lanes, so the env's sizes
+// and offsets are wavefront-uniform (scalar registers) and the group arithmetic folds away.
+template <bool ONE>
 __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restrict__ batches,
                                            const Tile* __restrict__ tiles, int n_tiles,
                                            const TileEnv* __restrict__ tenv, int n_steps) {
@@ -1694,11 +1697,11 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
 
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const Tile tile = tiles[t];
-        const int G = tile.lanes;
-        const int g = lane / G, li = lane % G;
+        const int G = ONE ? WAVE : tile.lanes;
+        const int g = ONE ? 0 : lane / G, li = ONE ? lane : lane % G;
         EnvCtx c;
-        c.active = g < tile.count;
-        TileEnv te = c.active ? tenv[tile.first + g] : tenv[tile.first];
+        c.active = ONE ? true : g < tile.count;
+        TileEnv te = ONE ? tenv[tile.first] : (c.active ? tenv[tile.first + g] : tenv[tile.first]);
         c.bd = &batches[te.batch];
         c.env = te.env;
         c.L = lds + te.lds_off;
@@ -2027,20 +2030,33 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
     }
 }
 
-// Two builds of the same step: unconstrained register allocation (small envs, where the
-// wave count is bounded by LDS anyway) and a cap of 256 registers per lane (two waves per SIMD)
-// for large envs whose solve is latency bound.  The planner / tuner picks one per LDS class.
+// Builds of the same step: any tiling with unconstrained register allocation (small envs, where
+// the wave count is bounded by LDS anyway) or capped at 256 registers per lane (two waves per
+// SIMD); and the same two for launches whose tiles all hold one env served by the whole
+// wavefront.  The planner / tuner picks one per LDS class.
 extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* __restrict__ batches,
                                                               const Tile* __restrict__ tiles, int n_tiles,
                                                               const TileEnv* __restrict__ tenv, int n_steps) {
     extern __shared__ float lds[];
-    step_tiles(lds, batches, tiles, n_tiles, tenv, n_steps);
+    step_tiles<false>(lds, batches, tiles, n_tiles, tenv, n_steps);
 }
 extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 ms_step_kernel_w2(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, int n_tiles,
                   const TileEnv* __restrict__ tenv, int n_steps) {
     extern __shared__ float lds[];
-    step_tiles(lds, batches, tiles, n_tiles, tenv, n_steps);
+    step_tiles<false>(lds, batches, tiles, n_tiles, tenv, n_steps);
+}
+extern "C" __global__ void __launch_bounds__(64) ms_step_kernel_one(const BatchDev* __restrict__ batches,
+                                                                  const Tile* __restrict__ tiles, int n_tiles,
+                                                                  const TileEnv* __restrict__ tenv, int n_steps) {
+    extern __shared__ float lds[];
+    step_tiles<true>(lds, batches, tiles, n_tiles, tenv, n_steps);
+}
+extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+ms_step_kernel_one_w2(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, int n_tiles,
+                      const TileEnv* __restrict__ tenv, int n_steps) {
+    extern __shared__ float lds[];
+    step_tiles<true>(lds, batches, tiles, n_tiles, tenv, n_steps);
 }
 
 // ============================================================================= reset kernel
