@@ -80,7 +80,7 @@ struct Lay {
     int n, nj, cap, mcap, P;
     // bodies
     int X0, Q0, DX, DQ, QC, V, W, V0, W0, INVM, IB, IW, AABB, SH, DIM, MU, EE, CM, JM;
-    int JNT, CAND, PT, MAN, BCOL, ORDER, SCHED, JSCHED, CSTART, SCAL;
+    int JNT, JINV, CAND, PT, MAN, BCOL, ORDER, SCHED, JSCHED, CSTART, SCAL;
     int total;  // words, a multiple of 4
 };
 __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
@@ -108,6 +108,8 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     L.JM = o; o += 2 * n;  // jointed-partner masks (u64)
     // 55 n words so far
     L.JNT = o; o += 26 * nj;
+    L.JINV = o; o += 39 * nj;   // per-joint quantities fixed within a substep
+
     // candidate pairs (u16) during S2-S4; afterwards the per-body block lists (offsets [n + 1],
     // entries u16 [2 (nj + mcap)])
     L.CAND = o; o += (L.P + 1) / 2 > n + 1 + nj + mcap ? (L.P + 1) / 2 : n + 1 + nj + mcap;

@@ -417,13 +417,13 @@ int ms_selfcheck(void) {
                     // contact rows 14 words per point, manifold rows 23 per manifold, schedules of
                     // up to nj + mcap + 66 entries (the joint schedule holds the 65 colouring
                     // cursors when there are no joints)
-                    const int start[] = {L.JM, L.JNT, L.CAND, L.PT, L.MAN, L.BCOL, L.ORDER, L.SCHED, L.JSCHED,
-                                         L.CSTART, L.SCAL};
-                    const int size[] = {2 * n, 26 * nj, std::max((P + 1) / 2, n + 1 + nj + mcap), 14 * cap, 23 * mcap, (nj + mcap + 1) / 2,
+                    const int start[] = {L.JM, L.JNT, L.JINV, L.CAND, L.PT, L.MAN, L.BCOL, L.ORDER, L.SCHED,
+                                         L.JSCHED, L.CSTART, L.SCAL};
+                    const int size[] = {2 * n, 26 * nj, 39 * nj, std::max((P + 1) / 2, n + 1 + nj + mcap), 14 * cap, 23 * mcap, (nj + mcap + 1) / 2,
                                         (nj + mcap + 1) / 2, nj + mcap + 66, nj > 0 ? nj + mcap + 66 : N_COLOURS + 1,
                                         N_COLOURS + 2, 32};
-                    for (int r = 0; r < 11; ++r) {
-                        const int next = r + 1 < 11 ? start[r + 1] : L.total;
+                    for (int r = 0; r < 12; ++r) {
+                        const int next = r + 1 < 12 ? start[r + 1] : L.total;
                         if (start[r] + size[r] > next) return 3;
                     }
                     if (L.SCAL + 32 > L.total || (L.total & 3)) return 4;

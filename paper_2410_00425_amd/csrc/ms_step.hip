@@ -944,30 +944,33 @@ __device__ __forceinline__ JFrame joint_frame(const EnvCtx& c, int j) {
     return f;
 }
 
-__device__ __forceinline__ void joint_warm(const EnvCtx& c, int j) {
-    JFrame f = joint_frame(c, j);
-    float* J = jrec(c, j);
-    BodyR A = load_body(c, f.a), B = load_body(c, f.b);
-    imp_lin(A, B, f.rA, f.rB, v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]));
-    imp_ang(A, B, J[J_LA] * f.b1 + J[J_LA + 1] * f.b2);
-    imp_ang(A, B, J[J_LD] * f.zA);
-    store_body(c, f.a, A);
-    store_body(c, f.b, B);
-}
+// Quantities of a joint that depend only on the poses, the frozen inertias and the joint
+// record, so they stay fixed through the colour sweeps of a substep (poses change only when the
+// substep integrates): anchors and frame axes, the adjugate and determinant of the point block,
+// the position error, the angular block and its errors, the drive's softness terms.  joint_prep
+// stores them once per substep; joint_warm / joint_solve read them.  Same operations in the same
+// order as computing them inside every visit.
+enum { JI_RA = 0, JI_RB = 3, JI_ZA = 6, JI_B1 = 9, JI_B2 = 12, JI_ADJ = 15, JI_DET = 24, JI_CP = 25, JI_C1 = 28,
+       JI_C2 = 29, JI_K11 = 30, JI_K12 = 31, JI_K22 = 32, JI_DET2 = 33, JI_GAM = 34, JI_KG = 35, JI_BCH = 36,
+       JI_WORDS = 39 };
+__device__ __forceinline__ float* jinv(const EnvCtx& c, int j) { return c.L + c.lay.JINV + JI_WORDS * j; }
+__device__ __forceinline__ V3 jv3(const float* P, int o) { return v3(P[o], P[o + 1], P[o + 2]); }
+__device__ __forceinline__ void jst3(float* P, int o, V3 v) { P[o] = v.x; P[o + 1] = v.y; P[o + 2] = v.z; }
 
-__device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
-    const BatchDev& bd = *c.bd;
+__device__ __forceinline__ void joint_prep(const EnvCtx& c, int j, float h) {
     JFrame f = joint_frame(c, j);
-    float* J = jrec(c, j);
+    const float* J = jrec(c, j);
+    float* P = jinv(c, j);
     const int a = f.a, b = f.b;
-    const float brate = vpass ? 0.0f : bd.beta_j / bd.dt;
-    BodyR A = load_body(c, a), B = load_body(c, b);
-    const S6& Ia = A.I;
-    const S6& Ib = B.I;
-    // point block: K = (mA^-1 + mB^-1) I - [rA]x IA [rA]x - [rB]x IB [rB]x
+    const S6 Ia = a >= 0 ? load_iw(c, a) : S6{0, 0, 0, 0, 0, 0};
+    const S6 Ib = load_iw(c, b);
+    const float ima = invm_of(c, a), imb = invm_of(c, b);
+    jst3(P, JI_RA, f.rA); jst3(P, JI_RB, f.rB); jst3(P, JI_ZA, f.zA); jst3(P, JI_B1, f.b1); jst3(P, JI_B2, f.b2);
+    // point block: K = (mA^-1 + mB^-1) I - [rA]x IA [rA]x - [rB]x IB [rB]x, its adjugate and determinant
     {
-        float im = A.im + B.im;
+        float im = ima + imb;
         float K[3][3] = {{im, 0, 0}, {0, im, 0}, {0, 0, im}};
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
             if (side == 0 && a < 0) continue;
             V3 r = vsel(side == 0, f.rA, f.rB);
@@ -975,53 +978,41 @@ __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, boo
             float Im[3][3] = {{I.xx, I.xy, I.xz}, {I.xy, I.yy, I.yz}, {I.xz, I.yz, I.zz}};
             float Sx[3][3] = {{0, -r.z, r.y}, {r.z, 0, -r.x}, {-r.y, r.x, 0}};
             float SI[3][3];
+#pragma unroll
             for (int p = 0; p < 3; ++p)
+#pragma unroll
                 for (int q = 0; q < 3; ++q) SI[p][q] = Sx[p][0] * Im[0][q] + Sx[p][1] * Im[1][q] + Sx[p][2] * Im[2][q];
+#pragma unroll
             for (int p = 0; p < 3; ++p)
+#pragma unroll
                 for (int q = 0; q < 3; ++q) K[p][q] -= SI[p][0] * Sx[0][q] + SI[p][1] * Sx[1][q] + SI[p][2] * Sx[2][q];
         }
-        V3 C = (x_of(c, b) + f.rB) - (x_of(c, a) + f.rA);
-        V3 Cd = (B.v + cross3(B.w, f.rB)) - (A.v + cross3(A.w, f.rA));
-        V3 rhs = Cd + brate * C;
-        float c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
-        float c01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
-        float c02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-        float c10 = K[1][2] * K[2][0] - K[1][0] * K[2][2];
-        float c11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
-        float c12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
-        float c20 = K[1][0] * K[2][1] - K[1][1] * K[2][0];
-        float c21 = K[0][1] * K[2][0] - K[0][0] * K[2][1];
-        float c22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-        float det = K[0][0] * c00 + K[0][1] * c10 + K[0][2] * c20;
-        if (det != 0.0f) {
-            float id = 1.0f / det;
-            V3 lam = v3(-(c00 * rhs.x + c01 * rhs.y + c02 * rhs.z) * id, -(c10 * rhs.x + c11 * rhs.y + c12 * rhs.z) * id,
-                        -(c20 * rhs.x + c21 * rhs.y + c22 * rhs.z) * id);
-            J[J_LP] += lam.x; J[J_LP + 1] += lam.y; J[J_LP + 2] += lam.z;
-            imp_lin(A, B, f.rA, f.rB, lam);
-        }
+        float* A9 = P + JI_ADJ;
+        A9[0] = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+        A9[1] = K[0][2] * K[2][1] - K[0][1] * K[2][2];
+        A9[2] = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+        A9[3] = K[1][2] * K[2][0] - K[1][0] * K[2][2];
+        A9[4] = K[0][0] * K[2][2] - K[0][2] * K[2][0];
+        A9[5] = K[0][2] * K[1][0] - K[0][0] * K[1][2];
+        A9[6] = K[1][0] * K[2][1] - K[1][1] * K[2][0];
+        A9[7] = K[0][1] * K[2][0] - K[0][0] * K[2][1];
+        A9[8] = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+        P[JI_DET] = K[0][0] * A9[0] + K[0][1] * A9[3] + K[0][2] * A9[6];
+        jst3(P, JI_CP, (x_of(c, b) + f.rB) - (x_of(c, a) + f.rA));
     }
-    // angular block: keep the joint axes aligned (2 rows)
+    // angular block: axis misalignment and the 2x2 block
     {
         Qt qbf = qmul(f.qb, Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
         V3 zB = colm(rotm(qbf), 2);
         V3 zc = cross3(f.zA, zB);
-        float C1 = dot3(f.b1, zc), C2 = dot3(f.b2, zc);
-        V3 dw = B.w - A.w;
-        float Cd1 = dot3(f.b1, dw), Cd2 = dot3(f.b2, dw);
+        P[JI_C1] = dot3(f.b1, zc);
+        P[JI_C2] = dot3(f.b2, zc);
         S6 Is{Ia.xx + Ib.xx, Ia.yy + Ib.yy, Ia.zz + Ib.zz, Ia.xy + Ib.xy, Ia.xz + Ib.xz, Ia.yz + Ib.yz};
         float k11 = dot3(f.b1, muls(Is, f.b1)), k12 = dot3(f.b1, muls(Is, f.b2)), k22 = dot3(f.b2, muls(Is, f.b2));
-        float r1 = Cd1 + brate * C1, r2 = Cd2 + brate * C2;
-        float det = k11 * k22 - k12 * k12;
-        if (det != 0.0f) {
-            float id = 1.0f / det;
-            float l1 = -(k22 * r1 - k12 * r2) * id;
-            float l2 = -(-k12 * r1 + k11 * r2) * id;
-            J[J_LA] += l1; J[J_LA + 1] += l2;
-            imp_ang(A, B, l1 * f.b1 + l2 * f.b2);
-        }
+        P[JI_K11] = k11; P[JI_K12] = k12; P[JI_K22] = k22;
+        P[JI_DET2] = k11 * k22 - k12 * k12;
     }
-    // PD drive: soft row about the joint axis
+    // drive: soft-row terms and the twist error wrapped into (-pi, pi]
     float kp = J[J_KP], kd = J[J_KD];
     if (kp != 0.0f || kd != 0.0f) {
         V3 ax = f.zA;
@@ -1039,8 +1030,70 @@ __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, boo
         const float pi = 3.14159265358979323846f;
         C = remainderf(C, 2.0f * pi);
         if (C <= -pi) C += 2.0f * pi;
+        P[JI_GAM] = gamma;
+        P[JI_KG] = k + gamma;
+        P[JI_BCH] = beta_d * C / h;
+    }
+}
+
+__device__ __forceinline__ void joint_warm(const EnvCtx& c, int j) {
+    const float* P = jinv(c, j);
+    const float* J = jrec(c, j);
+    const int a = reinterpret_cast<const int*>(J)[J_PA], b = reinterpret_cast<const int*>(J)[J_CH];
+    const V3 rA = jv3(P, JI_RA), rB = jv3(P, JI_RB), zA = jv3(P, JI_ZA), b1 = jv3(P, JI_B1), b2 = jv3(P, JI_B2);
+    BodyR A = load_body(c, a), B = load_body(c, b);
+    imp_lin(A, B, rA, rB, v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]));
+    imp_ang(A, B, J[J_LA] * b1 + J[J_LA + 1] * b2);
+    imp_ang(A, B, J[J_LD] * zA);
+    store_body(c, a, A);
+    store_body(c, b, B);
+}
+
+__device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
+    const BatchDev& bd = *c.bd;
+    const float* P = jinv(c, j);
+    float* J = jrec(c, j);
+    const int a = reinterpret_cast<const int*>(J)[J_PA], b = reinterpret_cast<const int*>(J)[J_CH];
+    const V3 rA = jv3(P, JI_RA), rB = jv3(P, JI_RB);
+    const float brate = vpass ? 0.0f : bd.beta_j / bd.dt;
+    BodyR A = load_body(c, a), B = load_body(c, b);
+    // point block
+    {
+        V3 C = jv3(P, JI_CP);
+        V3 Cd = (B.v + cross3(B.w, rB)) - (A.v + cross3(A.w, rA));
+        V3 rhs = Cd + brate * C;
+        const float det = P[JI_DET];
+        if (det != 0.0f) {
+            const float* A9 = P + JI_ADJ;
+            float id = 1.0f / det;
+            V3 lam = v3(-(A9[0] * rhs.x + A9[1] * rhs.y + A9[2] * rhs.z) * id, -(A9[3] * rhs.x + A9[4] * rhs.y + A9[5] * rhs.z) * id,
+                        -(A9[6] * rhs.x + A9[7] * rhs.y + A9[8] * rhs.z) * id);
+            J[J_LP] += lam.x; J[J_LP + 1] += lam.y; J[J_LP + 2] += lam.z;
+            imp_lin(A, B, rA, rB, lam);
+        }
+    }
+    // angular block: keep the joint axes aligned (2 rows)
+    {
+        const V3 b1 = jv3(P, JI_B1), b2 = jv3(P, JI_B2);
+        V3 dw = B.w - A.w;
+        float Cd1 = dot3(b1, dw), Cd2 = dot3(b2, dw);
+        const float k11 = P[JI_K11], k12 = P[JI_K12], k22 = P[JI_K22];
+        float r1 = Cd1 + brate * P[JI_C1], r2 = Cd2 + brate * P[JI_C2];
+        float det = P[JI_DET2];
+        if (det != 0.0f) {
+            float id = 1.0f / det;
+            float l1 = -(k22 * r1 - k12 * r2) * id;
+            float l2 = -(-k12 * r1 + k11 * r2) * id;
+            J[J_LA] += l1; J[J_LA + 1] += l2;
+            imp_ang(A, B, l1 * b1 + l2 * b2);
+        }
+    }
+    // PD drive: soft row about the joint axis
+    float kp = J[J_KP], kd = J[J_KD];
+    if (kp != 0.0f || kd != 0.0f) {
+        V3 ax = jv3(P, JI_ZA);
         float Cd = dot3(ax, B.w - A.w);
-        float dl = -(Cd + beta_d * C / h + gamma * J[J_LD]) / (k + gamma);
+        float dl = -(Cd + P[JI_BCH] + P[JI_GAM] * J[J_LD]) / P[JI_KG];
         J[J_LD] += dl;
         imp_ang(A, B, dl * ax);
     }
@@ -1949,6 +2002,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 for (int i = li; i < nn; i += G)
                     if (is_dyn(c, i)) body_substep_start(c, i, h, ldmp, admp, gather);
                 bias_pass(c, nmanA, h, false, li, G);
+                for (int j = li; j < (frozen ? 0 : nj); j += G) joint_prep(c, j, h);
                 wave_sync();
                 if (s > 0 && !pipe) run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li);
                 for (int it = 0; it < K; ++it) {
@@ -1972,6 +2026,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             // --------------------------------------------------------- S7
             if (bd.V > 0) {
                 bias_pass(c, nmanA, h, true, li, G);
+                for (int j = li; j < (frozen ? 0 : nj); j += G) joint_prep(c, j, h);
                 wave_sync();
             }
             for (int it = 0; it < bd.V; ++it) (pipe ? run_schedule<OP_VSOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_VSOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
