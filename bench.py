@@ -162,9 +162,9 @@ def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1,
     sc = S.by_name(name, n_envs, seed=seed)
     b = ms.Batch(sc, lanes_per_env=lanes, pack=pack)
     if tune:
-        for _ in range(max(1, warmup)):
+        for _ in range(60):   # tune on a settled state (contacts formed), trials of 10 steps
             b.step(1)
-        b.tune(3)
+        b.tune(10)
     r = time_graph(b, steps, warmup) if graph else time_batch(b, steps, warmup, spl)
     flop = algorithmic_flop(sc, r["stats"], sc.params)
     plan = b.plan()

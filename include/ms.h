@@ -210,7 +210,7 @@ ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes)
 /* Autotuner.  First the env tiling: for every group of envs that the planner gave the same
  * lanes per env (so 64 / lanes envs per wavefront), the whole batch is timed over trial_steps
  * steps with half and with twice as many lanes for that group, and a change is kept if it is
- * at least 2 % faster.  Then, for every LDS class, each kernel variant is timed over
+ * at least 3 % faster.  Then, for every LDS class, each kernel variant is timed over
  * trial_steps launches of that class alone and the fastest kept.  The tiling never changes a
  * result.  The batch's state, status and work counters are saved before and restored after
  * (the trial steps leave no trace).  Synchronises `hip_stream`. */

@@ -797,7 +797,7 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
     };
     // 1. lanes per env (64 / lanes envs per wavefront): for each group of envs that the planner
     //    gave the same lanes, try half and twice as many; keep a change only if the whole batch
-    //    steps at least 2 % faster
+    //    steps at least 3 % faster
     std::vector<int> orig(E), lanes(E);
     for (size_t e = 0; e < E; ++e) orig[e] = lanes[e] = b->plan.info[e].lanes;
     float best = 0.0f;
@@ -815,7 +815,7 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
             if (retile(b, trial, s) != MS_OK) continue;   // e.g. a tile too large: skip this option
             float t = 0.0f;
             st = time_batch(t);
-            if (st == MS_OK && t < 0.98f * best) { best = t; lanes = trial; }
+            if (st == MS_OK && t < 0.97f * best) { best = t; lanes = trial; }
         }
         if (st == MS_OK) st = retile(b, lanes, s);
     }

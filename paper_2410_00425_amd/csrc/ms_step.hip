@@ -1101,6 +1101,83 @@ __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, boo
     store_body(c, b, B);
 }
 
+// A joint visit from values loaded ahead: everything joint_solve reads except the two bodies'
+// velocities (the block's own accumulated impulses change only in its own visit, the rest only
+// between substeps).  Used by the joint-only sweeps, where a lane's next joint is loaded at the
+// end of the current entry.
+struct JointPre {
+    int a, b;
+    V3 rA, rB, zA, b1, b2, CP, lp;
+    float adj[9];
+    float det, C1, C2, k11, k12, k22, det2, gam, kg, bch, kp, kd, la0, la1, ld;
+    float ima, imb;
+    S6 Ia, Ib;
+    bool da, db;
+};
+__device__ __forceinline__ void joint_prefetch(const EnvCtx& c, int j, JointPre& q) {
+    const float* P = jinv(c, j);
+    const float* J = jrec(c, j);
+    q.a = reinterpret_cast<const int*>(J)[J_PA];
+    q.b = reinterpret_cast<const int*>(J)[J_CH];
+    q.rA = jv3(P, JI_RA); q.rB = jv3(P, JI_RB); q.zA = jv3(P, JI_ZA); q.b1 = jv3(P, JI_B1); q.b2 = jv3(P, JI_B2);
+    q.CP = jv3(P, JI_CP);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q.adj[k] = P[JI_ADJ + k];
+    q.det = P[JI_DET]; q.C1 = P[JI_C1]; q.C2 = P[JI_C2];
+    q.k11 = P[JI_K11]; q.k12 = P[JI_K12]; q.k22 = P[JI_K22]; q.det2 = P[JI_DET2];
+    q.gam = P[JI_GAM]; q.kg = P[JI_KG]; q.bch = P[JI_BCH];
+    q.kp = J[J_KP]; q.kd = J[J_KD];
+    q.lp = v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]); q.la0 = J[J_LA]; q.la1 = J[J_LA + 1]; q.ld = J[J_LD];
+    q.da = is_dyn(c, q.a); q.db = is_dyn(c, q.b);
+    q.ima = invm_of(c, q.a); q.imb = invm_of(c, q.b);
+    q.Ia = q.a >= 0 ? load_iw(c, q.a) : S6{0, 0, 0, 0, 0, 0};
+    q.Ib = load_iw(c, q.b);
+}
+__device__ __forceinline__ void joint_solve_pre(const EnvCtx& c, int j, const JointPre& q, float brate) {
+    float* J = jrec(c, j);
+    const int n = c.lay.n;
+    BodyR A, B;
+    if (q.a >= 0) { A.v = ld3(c.L, c.lay.V, n, q.a); A.w = ld3(c.L, c.lay.W, n, q.a); }
+    else { A.v = v3(0, 0, 0); A.w = v3(0, 0, 0); }
+    B.v = ld3(c.L, c.lay.V, n, q.b);
+    B.w = ld3(c.L, c.lay.W, n, q.b);
+    A.im = q.ima; A.I = q.Ia; A.dyn = q.da;
+    B.im = q.imb; B.I = q.Ib; B.dyn = q.db;
+    {
+        V3 Cd = (B.v + cross3(B.w, q.rB)) - (A.v + cross3(A.w, q.rA));
+        V3 rhs = Cd + brate * q.CP;
+        if (q.det != 0.0f) {
+            float id = 1.0f / q.det;
+            V3 lam = v3(-(q.adj[0] * rhs.x + q.adj[1] * rhs.y + q.adj[2] * rhs.z) * id,
+                        -(q.adj[3] * rhs.x + q.adj[4] * rhs.y + q.adj[5] * rhs.z) * id,
+                        -(q.adj[6] * rhs.x + q.adj[7] * rhs.y + q.adj[8] * rhs.z) * id);
+            J[J_LP] = q.lp.x + lam.x; J[J_LP + 1] = q.lp.y + lam.y; J[J_LP + 2] = q.lp.z + lam.z;
+            imp_lin(A, B, q.rA, q.rB, lam);
+        }
+    }
+    {
+        V3 dw = B.w - A.w;
+        float Cd1 = dot3(q.b1, dw), Cd2 = dot3(q.b2, dw);
+        float r1 = Cd1 + brate * q.C1, r2 = Cd2 + brate * q.C2;
+        if (q.det2 != 0.0f) {
+            float id = 1.0f / q.det2;
+            float l1 = -(q.k22 * r1 - q.k12 * r2) * id;
+            float l2 = -(-q.k12 * r1 + q.k11 * r2) * id;
+            J[J_LA] = q.la0 + l1; J[J_LA + 1] = q.la1 + l2;
+            imp_ang(A, B, l1 * q.b1 + l2 * q.b2);
+        }
+    }
+    if (q.kp != 0.0f || q.kd != 0.0f) {
+        V3 ax = q.zA;
+        float Cd = dot3(ax, B.w - A.w);
+        float dl = -(Cd + q.bch + q.gam * q.ld) / q.kg;
+        J[J_LD] = q.ld + dl;
+        imp_ang(A, B, dl * ax);
+    }
+    store_body(c, q.a, A);
+    store_body(c, q.b, B);
+}
+
 // ----------------------------------------------------------------------------- S1 AABB (exact)
 __device__ __forceinline__ void body_aabb(const EnvCtx& c, int i) {
 #pragma clang fp contract(off)
@@ -1409,6 +1486,19 @@ __device__ __forceinline__ int sched_block(const EnvCtx& c, int sched_off, int n
 template <int OP, bool PIPE>
 __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int nsched, int emax, float h, int li) {
     const Lay& l = c.lay;
+    if (OP == OP_JOINT) {   // joint-only schedule: every block is a joint
+        const float brate = c.bd->beta_j / c.bd->dt;
+        int blk = sched_block(c, sched_off, nsched, 0, li);
+        JointPre jp;
+        if (blk >= 0) joint_prefetch(c, blk, jp);
+        for (int e = 0; e < emax; ++e) {
+            if (blk >= 0) joint_solve_pre(c, blk, jp, brate);
+            blk = sched_block(c, sched_off, nsched, e + 1, li);
+            if (blk >= 0) joint_prefetch(c, blk, jp);
+            wave_sync();
+        }
+        return;
+    }
     constexpr bool PRE = OP == OP_WARM || OP == OP_SOLVE || OP == OP_VSOLVE;
     constexpr bool SOLVE = OP == OP_SOLVE || OP == OP_VSOLVE;
     int blk = sched_block(c, sched_off, nsched, 0, li);
