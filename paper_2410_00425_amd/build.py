@@ -13,9 +13,11 @@ LIB = os.path.join(HERE, "libms.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every HIP object of this project.  No FP contraction:
 # every float operation of the step is a separately rounded IEEE binary32 operation, in the
-# order the step model writes it.
+# order the step model writes it.  Common-code sinking is off: merging the narrowphase's
+# per-shape slot writes behind pointer phis would put its register-slot arrays in scratch
+# memory.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-simplifycfg-sink-common=false",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
