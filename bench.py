@@ -54,9 +54,10 @@ FLOP_PER_UNIT = {
 
 
 def kernel_source_hash():
+    """Hash of what determines the step kernel's code: its sources and the build flags."""
     h = hashlib.sha256()
-    for f in ("ms_step.hip", "ms_dev.h"):
-        h.update(open(os.path.join(ROOT, "paper_2410_00425_amd", "csrc", f), "rb").read())
+    for f in ("csrc/ms_step.hip", "csrc/ms_dev.h", "build.py"):
+        h.update(open(os.path.join(ROOT, "paper_2410_00425_amd", f), "rb").read())
     return h.hexdigest()[:16]
 
 
