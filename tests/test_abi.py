@@ -61,3 +61,16 @@ def test_query_bytes_and_validation():
     nan_t.joints["target"][0] = np.nan
     with pytest.raises(ms.MsError):
         ms.ms_query_batch_bytes(nan_t)
+
+
+def test_empty_batch_and_size_limits_are_rejected():
+    """An empty batch, and an env above 64 bodies or 64 joints, are invalid arguments / capacity
+    errors from the host-only query (nothing is enqueued)."""
+    from paper_2410_00425_amd import ms
+    empty = S.tray(4, seed=0).subset([])
+    with pytest.raises(ms.MsError) as e:
+        ms.ms_query_batch_bytes(empty)
+    assert e.value.code == ms.MS_E_INVALID_ARG
+    # exactly 64 bodies is accepted
+    sixty_four = S.single([S.body(S.SPHERE, (0.01,), (0.03 * i, 0, 0.5), mass=1.0) for i in range(64)])
+    assert ms.ms_query_batch_bytes(sixty_four) > 0
