@@ -93,10 +93,10 @@ __device__ __forceinline__ V3 muls(const S6& s, V3 v) {
 
 // ----------------------------------------------------------------------------- LDS layout
 // (Lay / make_lay live in ms_dev.h: one definition for the kernel and the host planner)
-// Contact-row planes (length cap): rA 0..2, rB 3..5, n 6..8, mn 9, s0 10, vnpre 11, ln 12,
+// Contact-row words (one record per point): rA 0..2, rB 3..5, n 6..8, mn 9, s0 10, vnpre 11, ln 12,
 // bias of the current substep 13.
 enum { R_RA = 0, R_RB = 3, R_N = 6, R_MN = 9, R_S0 = 10, R_VN = 11, R_LN = 12, R_BIAS = 13 };
-// Manifold planes (length mcap): header 0 (a | b << 8 as int), 1 (first | count << 16),
+// Manifold words (one record per manifold): header 0 (a | b << 8 as int), 1 (first | count << 16),
 // rA 2..4, rB 5..7, nb 8..10, t1 11..13, mt1 14, mt2 15, mtw 16, mu 17, rt 18, lt1 19, lt2 20, ltw 21,
 // restitution 22.
 enum { M_AB = 0, M_FC = 1, M_RA = 2, M_RB = 5, M_NB = 8, M_T1 = 11, M_MT1 = 14, M_MT2 = 15, M_MTW = 16,
@@ -787,19 +787,22 @@ __device__ __forceinline__ Shp shape_of(const EnvCtx& c, int i, V3 centre) {
 }
 
 // ----------------------------------------------------------------------------- manifold block
-__device__ __forceinline__ float mf(const EnvCtx& c, int plane, int m) { return c.L[c.lay.MAN + plane * c.lay.mcap + m]; }
-__device__ __forceinline__ float& mfr(const EnvCtx& c, int plane, int m) { return c.L[c.lay.MAN + plane * c.lay.mcap + m]; }
+// Rows are records (array of structures): a manifold's 23 words and a point's 14 words are
+// contiguous, so a lane's row loads share one address and pair up into wide LDS reads.
+constexpr int M_WORDS = 23, R_WORDS = 14;
+__device__ __forceinline__ float mf(const EnvCtx& c, int plane, int m) { return c.L[c.lay.MAN + m * M_WORDS + plane]; }
+__device__ __forceinline__ float& mfr(const EnvCtx& c, int plane, int m) { return c.L[c.lay.MAN + m * M_WORDS + plane]; }
 __device__ __forceinline__ V3 mf3(const EnvCtx& c, int plane, int m) {
     return v3(mf(c, plane, m), mf(c, plane + 1, m), mf(c, plane + 2, m));
 }
-__device__ __forceinline__ float& pr(const EnvCtx& c, int plane, int k) { return c.L[c.lay.PT + plane * c.lay.cap + k]; }
+__device__ __forceinline__ float& pr(const EnvCtx& c, int plane, int k) { return c.L[c.lay.PT + k * R_WORDS + plane]; }
 __device__ __forceinline__ V3 pr3(const EnvCtx& c, int plane, int k) {
     return v3(pr(c, plane, k), pr(c, plane + 1, k), pr(c, plane + 2, k));
 }
 
 __device__ __forceinline__ void man_header(const EnvCtx& c, int m, int& a, int& b, int& first, int& cnt) {
-    int ab = iptr(c.L + c.lay.MAN + M_AB * c.lay.mcap)[m];
-    int fc = iptr(c.L + c.lay.MAN + M_FC * c.lay.mcap)[m];
+    int ab = iptr(c.L + c.lay.MAN + m * M_WORDS)[M_AB];
+    int fc = iptr(c.L + c.lay.MAN + m * M_WORDS)[M_FC];
     a = (ab & 0xFF) == 0xFF ? -1 : (ab & 0xFF);
     b = (ab >> 8) & 0xFF;
     first = fc & 0xFFFF;
@@ -1806,8 +1809,8 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
 #pragma unroll
     for (int K = 0; K < 4; ++K)
         if (K < keep) rsum += len3(o.pt[K].p - cc);
-    iptr(c.L + l.MAN + M_AB * l.mcap)[m] = (ia < 0 ? 0xFF : ia) | (ib << 8);
-    iptr(c.L + l.MAN + M_FC * l.mcap)[m] = first | (keep << 16);
+    iptr(c.L + l.MAN + m * M_WORDS)[M_AB] = (ia < 0 ? 0xFF : ia) | (ib << 8);
+    iptr(c.L + l.MAN + m * M_WORDS)[M_FC] = first | (keep << 16);
     mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
     mfr(c, M_RB, m) = rB.x; mfr(c, M_RB + 1, m) = rB.y; mfr(c, M_RB + 2, m) = rB.z;
     mfr(c, M_NB, m) = nb.x; mfr(c, M_NB + 1, m) = nb.y; mfr(c, M_NB + 2, m) = nb.z;
