@@ -75,11 +75,13 @@ struct Tile {
     int lds_words;
 };
 
-// Word offsets of one env's arrays (component-major planes of length n / cap / mcap).
+// Word offsets of one env's arrays: component-major planes of length n, except the per-body
+// solver records and the contact, manifold and joint rows, which are records.
+enum { B_V = 0, B_W = 3, B_IM = 6, B_IW = 7, BODY_WORDS = 13 };
 struct Lay {
     int n, nj, cap, mcap, P;
     // bodies
-    int X0, Q0, DX, DQ, QC, V, W, V0, W0, INVM, IB, IW, AABB, SH, DIM, MU, EE, CM, JM;
+    int X0, Q0, DX, DQ, QC, BODY, V0, W0, IB, AABB, SH, DIM, MU, EE, CM, JM;
     int JNT, JINV, CAND, PT, MAN, BCOL, ORDER, SCHED, JSCHED, CSTART, SCAL;
     int total;  // words, a multiple of 4
 };
@@ -92,13 +94,12 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     L.DX = o; o += 3 * n;
     L.DQ = o; o += 4 * n;
     L.QC = o; o += 4 * n;
-    L.V = o; o += 3 * n;
-    L.W = o; o += 3 * n;
+    // solver record of a body, BODY_WORDS per body: v (3), w (3), inverse mass, world inverse
+    // inertia frozen for the step (xx, yy, zz, xy, xz, yz)
+    L.BODY = o; o += BODY_WORDS * n;
     L.V0 = o; o += 3 * n;
     L.W0 = o; o += 3 * n;
-    L.INVM = o; o += n;
     L.IB = o; o += 3 * n;  // principal inverse inertia (body frame)
-    L.IW = o; o += 6 * n;  // world inverse inertia, frozen for the step
     L.AABB = o; o += 6 * n;
     L.SH = o; o += n;
     L.DIM = o; o += 3 * n;

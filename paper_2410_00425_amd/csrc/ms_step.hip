@@ -178,11 +178,15 @@ struct BodyRef {
 __device__ __forceinline__ bool is_dyn(const EnvCtx& c, int i) {
     return i >= 0 && !((iptr(c.L + c.lay.SH)[i] >> 8) & 1);
 }
+__device__ __forceinline__ float* body_rec(const EnvCtx& c, int i) { return c.L + c.lay.BODY + i * BODY_WORDS; }
 __device__ __forceinline__ S6 load_iw(const EnvCtx& c, int i) {
-    const float* L = c.L + c.lay.IW;
-    int n = c.lay.n;
-    return S6{L[i], L[n + i], L[2 * n + i], L[3 * n + i], L[4 * n + i], L[5 * n + i]};
+    const float* R = body_rec(c, i) + B_IW;
+    return S6{R[0], R[1], R[2], R[3], R[4], R[5]};
 }
+__device__ __forceinline__ V3 ldv(const EnvCtx& c, int i) { const float* R = body_rec(c, i) + B_V; return v3(R[0], R[1], R[2]); }
+__device__ __forceinline__ V3 ldw(const EnvCtx& c, int i) { const float* R = body_rec(c, i) + B_W; return v3(R[0], R[1], R[2]); }
+__device__ __forceinline__ void stv(const EnvCtx& c, int i, V3 v) { float* R = body_rec(c, i) + B_V; R[0] = v.x; R[1] = v.y; R[2] = v.z; }
+__device__ __forceinline__ void stw(const EnvCtx& c, int i, V3 v) { float* R = body_rec(c, i) + B_W; R[0] = v.x; R[1] = v.y; R[2] = v.z; }
 
 // ----------------------------------------------------------------------------- narrowphase
 // Every array below is indexed by compile-time constants only (loops are unrolled and run-time
@@ -765,9 +769,9 @@ __device__ __forceinline__ V3 onb_t1(V3 n) {
 }
 
 // ----------------------------------------------------------------------------- LDS body helpers
-__device__ __forceinline__ float invm_of(const EnvCtx& c, int i) { return i < 0 ? 0.0f : c.L[c.lay.INVM + i]; }
-__device__ __forceinline__ V3 v_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.V, c.lay.n, i); }
-__device__ __forceinline__ V3 w_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.W, c.lay.n, i); }
+__device__ __forceinline__ float invm_of(const EnvCtx& c, int i) { return i < 0 ? 0.0f : body_rec(c, i)[B_IM]; }
+__device__ __forceinline__ V3 v_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ldv(c, i); }
+__device__ __forceinline__ V3 w_of(const EnvCtx& c, int i) { return i < 0 ? v3(0, 0, 0) : ldw(c, i); }
 
 __device__ __forceinline__ float eff_mass(const EnvCtx& c, int a, int b, V3 rA, V3 rB, V3 x) {
     float k = invm_of(c, a) + invm_of(c, b);
@@ -828,9 +832,9 @@ __device__ __forceinline__ BodyR load_body(const EnvCtx& c, int i) {
         return r;
     }
     const int n = c.lay.n;
-    r.v = ld3(c.L, c.lay.V, n, i);
-    r.w = ld3(c.L, c.lay.W, n, i);
-    r.im = c.L[c.lay.INVM + i];
+    r.v = ldv(c, i);
+    r.w = ldw(c, i);
+    r.im = body_rec(c, i)[B_IM];
     r.I = load_iw(c, i);
     r.dyn = is_dyn(c, i);
     return r;
@@ -838,8 +842,8 @@ __device__ __forceinline__ BodyR load_body(const EnvCtx& c, int i) {
 __device__ __forceinline__ void store_body(const EnvCtx& c, int i, const BodyR& r) {
     if (!r.dyn) return;
     const int n = c.lay.n;
-    st3(c.L, c.lay.V, n, i, r.v);
-    st3(c.L, c.lay.W, n, i, r.w);
+    stv(c, i, r.v);
+    stw(c, i, r.w);
 }
 __device__ __forceinline__ PoseR load_pose(const EnvCtx& c, int i) {
     if (i < 0) return PoseR{v3(0, 0, 0), Qt{1.0f, 0.0f, 0.0f, 0.0f}};
@@ -1140,10 +1144,10 @@ __device__ __forceinline__ void joint_solve_pre(const EnvCtx& c, int j, const Jo
     float* J = jrec(c, j);
     const int n = c.lay.n;
     BodyR A, B;
-    if (q.a >= 0) { A.v = ld3(c.L, c.lay.V, n, q.a); A.w = ld3(c.L, c.lay.W, n, q.a); }
+    if (q.a >= 0) { A.v = ldv(c, q.a); A.w = ldw(c, q.a); }
     else { A.v = v3(0, 0, 0); A.w = v3(0, 0, 0); }
-    B.v = ld3(c.L, c.lay.V, n, q.b);
-    B.w = ld3(c.L, c.lay.W, n, q.b);
+    B.v = ldv(c, q.b);
+    B.w = ldw(c, q.b);
     A.im = q.ima; A.I = q.Ia; A.dyn = q.da;
     B.im = q.imb; B.I = q.Ib; B.dyn = q.db;
     {
@@ -1254,8 +1258,8 @@ __device__ __forceinline__ void man_prefetch(const EnvCtx& c, int m, ManPre& p) 
     const int n = c.lay.n;
     p.da = is_dyn(c, p.a);
     p.db = is_dyn(c, p.b);
-    p.ima = p.a >= 0 ? c.L[c.lay.INVM + p.a] : 0.0f;
-    p.imb = c.L[c.lay.INVM + p.b];
+    p.ima = p.a >= 0 ? body_rec(c, p.a)[B_IM] : 0.0f;
+    p.imb = body_rec(c, p.b)[B_IM];
     p.Ia = p.a >= 0 ? load_iw(c, p.a) : S6{0, 0, 0, 0, 0, 0};
     p.Ib = load_iw(c, p.b);
     (void)n;
@@ -1285,10 +1289,10 @@ __device__ __forceinline__ void man_prefetch(const EnvCtx& c, int m, ManPre& p) 
 
 __device__ __forceinline__ void man_bodies(const EnvCtx& c, const ManPre& p, BodyR& A, BodyR& B) {
     const int n = c.lay.n;
-    if (p.a >= 0) { A.v = ld3(c.L, c.lay.V, n, p.a); A.w = ld3(c.L, c.lay.W, n, p.a); }
+    if (p.a >= 0) { A.v = ldv(c, p.a); A.w = ldw(c, p.a); }
     else { A.v = v3(0, 0, 0); A.w = v3(0, 0, 0); }
-    B.v = ld3(c.L, c.lay.V, n, p.b);
-    B.w = ld3(c.L, c.lay.W, n, p.b);
+    B.v = ldv(c, p.b);
+    B.w = ldw(c, p.b);
     A.im = p.ima; A.I = p.Ia; A.dyn = p.da;
     B.im = p.imb; B.I = p.Ib; B.dyn = p.db;
 }
@@ -1432,11 +1436,11 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
     const BatchDev& bd = *c.bd;
     const Lay& l = c.lay;
     const int n = l.n;
-    V3 v = ld3(c.L, l.V, n, i);
+    V3 v = ldv(c, i);
     v = ldmp * (v + h * v3(bd.gx, bd.gy, bd.gz));
-    V3 w = admp * ld3(c.L, l.W, n, i);
+    V3 w = admp * ldw(c, i);
     if (warm) {
-        const float im = c.L[l.INVM + i];
+        const float im = body_rec(c, i)[B_IM];
         const S6 I = load_iw(c, i);
         const int* OFF = iptr(c.L + l.CAND);
         const uint16_t* ENT = reinterpret_cast<const uint16_t*>(OFF + n + 1);
@@ -1467,8 +1471,8 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
             else { v = v - im * P; w = w - muls(I, cross3(r, P)); w = w - muls(I, L); }
         }
     }
-    st3(c.L, l.V, n, i, v);
-    st3(c.L, l.W, n, i, w);
+    stv(c, i, v);
+    stw(c, i, w);
 }
 
 enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
@@ -1868,13 +1872,13 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             int gi = c.b0 + i;
             for (int r = 0; r < 3; ++r) c.L[l.X0 + r * n + i] = bd.pos[r * B + gi];
             for (int r = 0; r < 4; ++r) c.L[l.QC + r * n + i] = bd.quat[r * B + gi];
-            for (int r = 0; r < 3; ++r) c.L[l.V + r * n + i] = bd.vel[r * B + gi];
-            for (int r = 0; r < 3; ++r) c.L[l.W + r * n + i] = bd.angvel[r * B + gi];
+            for (int r = 0; r < 3; ++r) body_rec(c, i)[B_V + r] = bd.vel[r * B + gi];
+            for (int r = 0; r < 3; ++r) body_rec(c, i)[B_W + r] = bd.angvel[r * B + gi];
             float4 p0 = bd.bpar[gi], p1 = bd.bpar[B + gi], p2 = bd.bpar[2 * B + gi];
             int sh = __float_as_int(p0.x);
             iptr(c.L + l.SH)[i] = sh;
             bool dyn = !((sh >> 8) & 1);
-            c.L[l.INVM + i] = dyn ? p0.y : 0.0f;
+            body_rec(c, i)[B_IM] = dyn ? p0.y : 0.0f;
             c.L[l.MU + i] = p0.z;
             c.L[l.EE + i] = p0.w;
             c.L[l.DIM + i] = p1.x; c.L[l.DIM + n + i] = p1.y; c.L[l.DIM + 2 * n + i] = p1.z;
@@ -1926,8 +1930,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 st4(c.L, l.Q0, n, i, ld4(c.L, l.QC, n, i));
                 st3(c.L, l.DX, n, i, v3(0, 0, 0));
                 st4(c.L, l.DQ, n, i, Qt{1.0f, 0.0f, 0.0f, 0.0f});
-                st3(c.L, l.V0, n, i, ld3(c.L, l.V, n, i));
-                st3(c.L, l.W0, n, i, ld3(c.L, l.W, n, i));
+                st3(c.L, l.V0, n, i, ldv(c, i));
+                st3(c.L, l.W0, n, i, ldw(c, i));
                 // world inverse inertia R diag(I^-1) R^T from the step-start orientation
                 M3 R = rotm(ld4(c.L, l.Q0, n, i));
                 float d0 = c.L[l.IB + i], d1 = c.L[l.IB + n + i], d2 = c.L[l.IB + 2 * n + i];
@@ -1935,8 +1939,9 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 for (int p = 0; p < 3; ++p)
                     for (int q = p; q < 3; ++q)
                         Iw[p][q] = R.m[p][0] * d0 * R.m[q][0] + R.m[p][1] * d1 * R.m[q][1] + R.m[p][2] * d2 * R.m[q][2];
-                c.L[l.IW + i] = Iw[0][0]; c.L[l.IW + n + i] = Iw[1][1]; c.L[l.IW + 2 * n + i] = Iw[2][2];
-                c.L[l.IW + 3 * n + i] = Iw[0][1]; c.L[l.IW + 4 * n + i] = Iw[0][2]; c.L[l.IW + 5 * n + i] = Iw[1][2];
+                float* Iwr = body_rec(c, i) + B_IW;
+                Iwr[0] = Iw[0][0]; Iwr[1] = Iw[1][1]; Iwr[2] = Iw[2][2];
+                Iwr[3] = Iw[0][1]; Iwr[4] = Iw[0][2]; Iwr[5] = Iw[1][2];
                 body_aabb(c, i);
                 iptr(c.L + l.CM)[2 * i] = 0;
                 iptr(c.L + l.CM)[2 * i + 1] = 0;
@@ -2105,7 +2110,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 // integrate the offsets from the step-start pose
                 for (int i = li; i < nn; i += G) {
                     if (!is_dyn(c, i)) continue;
-                    V3 v = ld3(c.L, l.V, n, i), w = ld3(c.L, l.W, n, i);
+                    V3 v = ldv(c, i), w = ldw(c, i);
                     st3(c.L, l.DX, n, i, ld3(c.L, l.DX, n, i) + h * v);
                     Qt d = ld4(c.L, l.DQ, n, i);
                     Qt e = qmul(Qt{0.0f, w.x, w.y, w.z}, d);
@@ -2130,7 +2135,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             for (int i = li; i < nn; i += G) {
                 V3 x = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
                 Qt q = ld4(c.L, l.QC, n, i);
-                V3 v = ld3(c.L, l.V, n, i), w = ld3(c.L, l.W, n, i);
+                V3 v = ldv(c, i), w = ldw(c, i);
                 float vals[13] = {x.x, x.y, x.z, q.w, q.x, q.y, q.z, v.x, v.y, v.z, w.x, w.y, w.z};
                 for (int r = 0; r < 13; ++r) bad |= !isfinite(vals[r]);
             }
@@ -2139,8 +2144,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 for (int i = li; i < nn; i += G) {
                     st3(c.L, l.DX, n, i, v3(0, 0, 0));
                     st4(c.L, l.QC, n, i, ld4(c.L, l.Q0, n, i));
-                    st3(c.L, l.V, n, i, ld3(c.L, l.V0, n, i));
-                    st3(c.L, l.W, n, i, ld3(c.L, l.W0, n, i));
+                    stv(c, i, ld3(c.L, l.V0, n, i));
+                    stw(c, i, ld3(c.L, l.W0, n, i));
                 }
                 if (li == 0) SC[SC_STATUS] |= 1;
             }
@@ -2169,8 +2174,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             V3 x = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
             bd.pos[gi] = x.x; bd.pos[B + gi] = x.y; bd.pos[2 * B + gi] = x.z;
             for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = c.L[l.QC + r * n + i];
-            for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = c.L[l.V + r * n + i];
-            for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = c.L[l.W + r * n + i];
+            for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = body_rec(c, i)[B_V + r];
+            for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = body_rec(c, i)[B_W + r];
         }
         if (c.active && li == 0) bd.status[c.env] = SC[SC_STATUS];
         for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += SC[16 + k];
