@@ -78,10 +78,11 @@ struct Tile {
 // Word offsets of one env's arrays: component-major planes of length n, except the per-body
 // solver records and the contact, manifold and joint rows, which are records.
 enum { B_V = 0, B_W = 3, B_IM = 6, B_IW = 7, BODY_WORDS = 13 };
+enum { P_DX = 0, P_DQ = 3, P_X0 = 7, P_QC = 10, P_Q0 = 14, POSE_WORDS = 18 };
 struct Lay {
     int n, nj, cap, mcap, P;
     // bodies
-    int X0, Q0, DX, DQ, QC, BODY, V0, W0, IB, AABB, SH, DIM, MU, EE, CM, JM;
+    int POSE, BODY, V0, W0, IB, AABB, SH, DIM, MU, EE, CM, JM;
     int JNT, JINV, CAND, PT, MAN, BCOL, ORDER, SCHED, JSCHED, CSTART, SCAL;
     int total;  // words, a multiple of 4
 };
@@ -89,11 +90,9 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     Lay L;
     L.n = n; L.nj = nj; L.cap = cap; L.mcap = mcap; L.P = n * (n + 1) / 2;
     int o = 0;
-    L.X0 = o; o += 3 * n;
-    L.Q0 = o; o += 4 * n;
-    L.DX = o; o += 3 * n;
-    L.DQ = o; o += 4 * n;
-    L.QC = o; o += 4 * n;
+    // pose record of a body, POSE_WORDS per body: substep offsets dx (3), dq (4), step-start
+    // position (3), current orientation (4), step-start orientation (4)
+    L.POSE = o; o += POSE_WORDS * n;
     // solver record of a body, BODY_WORDS per body: v (3), w (3), inverse mass, world inverse
     // inertia frozen for the step (xx, yy, zz, xy, xz, yz)
     L.BODY = o; o += BODY_WORDS * n;

@@ -179,6 +179,11 @@ __device__ __forceinline__ bool is_dyn(const EnvCtx& c, int i) {
     return i >= 0 && !((iptr(c.L + c.lay.SH)[i] >> 8) & 1);
 }
 __device__ __forceinline__ float* body_rec(const EnvCtx& c, int i) { return c.L + c.lay.BODY + i * BODY_WORDS; }
+__device__ __forceinline__ float* pose_rec(const EnvCtx& c, int i) { return c.L + c.lay.POSE + i * POSE_WORDS; }
+__device__ __forceinline__ V3 ldp3(const EnvCtx& c, int i, int w) { const float* R = pose_rec(c, i) + w; return v3(R[0], R[1], R[2]); }
+__device__ __forceinline__ Qt ldp4(const EnvCtx& c, int i, int w) { const float* R = pose_rec(c, i) + w; return Qt{R[0], R[1], R[2], R[3]}; }
+__device__ __forceinline__ void stp3(const EnvCtx& c, int i, int w, V3 v) { float* R = pose_rec(c, i) + w; R[0] = v.x; R[1] = v.y; R[2] = v.z; }
+__device__ __forceinline__ void stp4(const EnvCtx& c, int i, int w, Qt q) { float* R = pose_rec(c, i) + w; R[0] = q.w; R[1] = q.x; R[2] = q.y; R[3] = q.z; }
 __device__ __forceinline__ S6 load_iw(const EnvCtx& c, int i) {
     const float* R = body_rec(c, i) + B_IW;
     return S6{R[0], R[1], R[2], R[3], R[4], R[5]};
@@ -785,7 +790,7 @@ __device__ __forceinline__ Shp shape_of(const EnvCtx& c, int i, V3 centre) {
     const Lay& l = c.lay;
     s.type = iptr(c.L + l.SH)[i] & 0xFF;
     s.c = centre;
-    s.R = rotm(ld4(c.L, l.Q0, l.n, i));
+    s.R = rotm(ldp4(c, i, P_Q0));
     s.d[0] = c.L[l.DIM + i]; s.d[1] = c.L[l.DIM + l.n + i]; s.d[2] = c.L[l.DIM + 2 * l.n + i];
     return s;
 }
@@ -847,7 +852,7 @@ __device__ __forceinline__ void store_body(const EnvCtx& c, int i, const BodyR& 
 }
 __device__ __forceinline__ PoseR load_pose(const EnvCtx& c, int i) {
     if (i < 0) return PoseR{v3(0, 0, 0), Qt{1.0f, 0.0f, 0.0f, 0.0f}};
-    return PoseR{ld3(c.L, c.lay.DX, c.lay.n, i), ld4(c.L, c.lay.DQ, c.lay.n, i)};
+    return PoseR{ldp3(c, i, P_DX), ldp4(c, i, P_DQ)};
 }
 // -P on A at arm rA, +P on B at arm rB (dynamic bodies only).
 __device__ __forceinline__ void imp_lin(BodyR& A, BodyR& B, V3 rA, V3 rB, V3 P) {
@@ -931,10 +936,10 @@ __device__ __forceinline__ float atan2_w(float y, float w) {
 struct JFrame { int a, b; V3 rA, rB, zA, b1, b2; Qt qa, qb; };
 __device__ __forceinline__ float* jrec(const EnvCtx& c, int j) { return c.L + c.lay.JNT + J_WORDS * j; }
 __device__ __forceinline__ V3 x_of(const EnvCtx& c, int i) {
-    return i < 0 ? v3(0, 0, 0) : ld3(c.L, c.lay.X0, c.lay.n, i) + ld3(c.L, c.lay.DX, c.lay.n, i);
+    return i < 0 ? v3(0, 0, 0) : ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
 }
 __device__ __forceinline__ Qt qc_of(const EnvCtx& c, int i) {
-    return i < 0 ? Qt{1.0f, 0.0f, 0.0f, 0.0f} : ld4(c.L, c.lay.QC, c.lay.n, i);
+    return i < 0 ? Qt{1.0f, 0.0f, 0.0f, 0.0f} : ldp4(c, i, P_QC);
 }
 
 __device__ __forceinline__ JFrame joint_frame(const EnvCtx& c, int j) {
@@ -1190,7 +1195,7 @@ __device__ __forceinline__ void body_aabb(const EnvCtx& c, int i) {
 #pragma clang fp contract(off)
     const Lay& l = c.lay;
     const int n = l.n;
-    Qt q = ld4(c.L, l.Q0, n, i);
+    Qt q = ldp4(c, i, P_Q0);
     float xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
     float xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
     float wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z;
@@ -1215,7 +1220,7 @@ __device__ __forceinline__ void body_aabb(const EnvCtx& c, int i) {
             hv = t + d0;
         }
         float half = hv + delta;
-        float x = c.L[l.X0 + r * n + i];
+        float x = pose_rec(c, i)[P_X0 + r];
         c.L[l.AABB + r * n + i] = x - half;
         c.L[l.AABB + (3 + r) * n + i] = x + half;
     }
@@ -1747,7 +1752,7 @@ __device__ __forceinline__ void np_candidate(const EnvCtx& c, int code, NOut& o,
         }
         atomicAdd(&SC[16 + STAT_KIND0 + kind], 1);
     }
-    V3 xa = ld3(c.L, l.X0, n, a);
+    V3 xa = ldp3(c, a, P_X0);
     if (plane) {
         Shp sb = shape_of(c, a, v3(0.0f, 0.0f, xa.z - bd.plane_z));
         base = v3(xa.x, xa.y, bd.plane_z);
@@ -1755,7 +1760,7 @@ __device__ __forceinline__ void np_candidate(const EnvCtx& c, int code, NOut& o,
         np_plane(o, sb, bd.delta);
     } else {
         Shp sa = shape_of(c, a, v3(0, 0, 0));
-        Shp sb = shape_of(c, b, ld3(c.L, l.X0, n, b) - xa);
+        Shp sb = shape_of(c, b, ldp3(c, b, P_X0) - xa);
         base = xa;
         offB = sb.c;
         np_pair(o, sa, sb, bd.delta);
@@ -1870,8 +1875,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
         // ------------------------------------------------------------- load (once per launch)
         for (int i = li; i < nA; i += G) {
             int gi = c.b0 + i;
-            for (int r = 0; r < 3; ++r) c.L[l.X0 + r * n + i] = bd.pos[r * B + gi];
-            for (int r = 0; r < 4; ++r) c.L[l.QC + r * n + i] = bd.quat[r * B + gi];
+            for (int r = 0; r < 3; ++r) pose_rec(c, i)[P_X0 + r] = bd.pos[r * B + gi];
+            for (int r = 0; r < 4; ++r) pose_rec(c, i)[P_QC + r] = bd.quat[r * B + gi];
             for (int r = 0; r < 3; ++r) body_rec(c, i)[B_V + r] = bd.vel[r * B + gi];
             for (int r = 0; r < 3; ++r) body_rec(c, i)[B_W + r] = bd.angvel[r * B + gi];
             float4 p0 = bd.bpar[gi], p1 = bd.bpar[B + gi], p2 = bd.bpar[2 * B + gi];
@@ -1885,7 +1890,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             c.L[l.IB + i] = dyn ? p2.x : 0.0f;
             c.L[l.IB + n + i] = dyn ? p2.y : 0.0f;
             c.L[l.IB + 2 * n + i] = dyn ? p2.z : 0.0f;
-            st3(c.L, l.DX, n, i, v3(0, 0, 0));
+            stp3(c, i, P_DX, v3(0, 0, 0));
         }
         for (int j = li; j < njA; j += G) {
             const float* src = bd.jrec + size_t(c.j0 + j) * JREC;
@@ -1925,15 +1930,15 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
 
             // --------------------------------------------------------- S0 + S1
             for (int i = li; i < nn; i += G) {
-                V3 x0 = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
-                st3(c.L, l.X0, n, i, x0);
-                st4(c.L, l.Q0, n, i, ld4(c.L, l.QC, n, i));
-                st3(c.L, l.DX, n, i, v3(0, 0, 0));
-                st4(c.L, l.DQ, n, i, Qt{1.0f, 0.0f, 0.0f, 0.0f});
+                V3 x0 = ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
+                stp3(c, i, P_X0, x0);
+                stp4(c, i, P_Q0, ldp4(c, i, P_QC));
+                stp3(c, i, P_DX, v3(0, 0, 0));
+                stp4(c, i, P_DQ, Qt{1.0f, 0.0f, 0.0f, 0.0f});
                 st3(c.L, l.V0, n, i, ldv(c, i));
                 st3(c.L, l.W0, n, i, ldw(c, i));
                 // world inverse inertia R diag(I^-1) R^T from the step-start orientation
-                M3 R = rotm(ld4(c.L, l.Q0, n, i));
+                M3 R = rotm(ldp4(c, i, P_Q0));
                 float d0 = c.L[l.IB + i], d1 = c.L[l.IB + n + i], d2 = c.L[l.IB + 2 * n + i];
                 float Iw[3][3];
                 for (int p = 0; p < 3; ++p)
@@ -2111,13 +2116,13 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 for (int i = li; i < nn; i += G) {
                     if (!is_dyn(c, i)) continue;
                     V3 v = ldv(c, i), w = ldw(c, i);
-                    st3(c.L, l.DX, n, i, ld3(c.L, l.DX, n, i) + h * v);
-                    Qt d = ld4(c.L, l.DQ, n, i);
+                    stp3(c, i, P_DX, ldp3(c, i, P_DX) + h * v);
+                    Qt d = ldp4(c, i, P_DQ);
                     Qt e = qmul(Qt{0.0f, w.x, w.y, w.z}, d);
                     float hh = 0.5f * h;
                     d = qnorm(Qt{d.w + hh * e.w, d.x + hh * e.x, d.y + hh * e.y, d.z + hh * e.z});
-                    st4(c.L, l.DQ, n, i, d);
-                    st4(c.L, l.QC, n, i, qnorm(qmul(d, ld4(c.L, l.Q0, n, i))));
+                    stp4(c, i, P_DQ, d);
+                    stp4(c, i, P_QC, qnorm(qmul(d, ldp4(c, i, P_Q0))));
                 }
                 wave_sync();
             }
@@ -2133,8 +2138,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             // --------------------------------------------------------- S8 non-finite guard
             bool bad = false;
             for (int i = li; i < nn; i += G) {
-                V3 x = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
-                Qt q = ld4(c.L, l.QC, n, i);
+                V3 x = ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
+                Qt q = ldp4(c, i, P_QC);
                 V3 v = ldv(c, i), w = ldw(c, i);
                 float vals[13] = {x.x, x.y, x.z, q.w, q.x, q.y, q.z, v.x, v.y, v.z, w.x, w.y, w.z};
                 for (int r = 0; r < 13; ++r) bad |= !isfinite(vals[r]);
@@ -2142,8 +2147,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             bool anybad = group_bits(__ballot(bad), g, G) != 0;
             if (anybad) {
                 for (int i = li; i < nn; i += G) {
-                    st3(c.L, l.DX, n, i, v3(0, 0, 0));
-                    st4(c.L, l.QC, n, i, ld4(c.L, l.Q0, n, i));
+                    stp3(c, i, P_DX, v3(0, 0, 0));
+                    stp4(c, i, P_QC, ldp4(c, i, P_Q0));
                     stv(c, i, ld3(c.L, l.V0, n, i));
                     stw(c, i, ld3(c.L, l.W0, n, i));
                 }
@@ -2171,9 +2176,9 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
         // ------------------------------------------------------------- store
         for (int i = li; i < nA; i += G) {
             int gi = c.b0 + i;
-            V3 x = ld3(c.L, l.X0, n, i) + ld3(c.L, l.DX, n, i);
+            V3 x = ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
             bd.pos[gi] = x.x; bd.pos[B + gi] = x.y; bd.pos[2 * B + gi] = x.z;
-            for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = c.L[l.QC + r * n + i];
+            for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = pose_rec(c, i)[P_QC + r];
             for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = body_rec(c, i)[B_V + r];
             for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = body_rec(c, i)[B_W + r];
         }
