@@ -1457,23 +1457,35 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
             man_header(c, m, a, b, first, cnt);
             const int rrow = sideB ? R_RB : R_RA;
             const int mrow = sideB ? M_RB : M_RA;
+            // every row of the block is read before any arithmetic (one LDS round trip); the
+            // rows past the block's count lie inside the env's region and are not used
+            float ln[4];
+            V3 nq[4], rq[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int q = first + k;
+                ln[k] = pr(c, R_LN, q);
+                nq[k] = pr3(c, R_N, q);
+                rq[k] = pr3(c, rrow, q);
+            }
+            const V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m), mr = mf3(c, mrow, m);
+            const float lt1 = mf(c, M_LT1, m), lt2 = mf(c, M_LT2, m), ltw = mf(c, M_LTW, m);
+            // side A receives the negated impulses; negating the multiplier negates every product
+            // and sum below exactly, so adding them equals subtracting the unnegated ones
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k < cnt) {
-                    const int q = first + k;
-                    const V3 P = pr(c, R_LN, q) * pr3(c, R_N, q);
-                    const V3 r = pr3(c, rrow, q);
-                    if (sideB) { v = v + im * P; w = w + muls(I, cross3(r, P)); }
-                    else { v = v - im * P; w = w - muls(I, cross3(r, P)); }
+                    const V3 P = (sideB ? ln[k] : -ln[k]) * nq[k];
+                    v = v + im * P;
+                    w = w + muls(I, cross3(rq[k], P));
                 }
             }
-            const V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m);
             const V3 t2 = cross3(nb, t1);
-            const V3 P = mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * t2;
-            const V3 r = mf3(c, mrow, m);
-            const V3 L = mf(c, M_LTW, m) * nb;
-            if (sideB) { v = v + im * P; w = w + muls(I, cross3(r, P)); w = w + muls(I, L); }
-            else { v = v - im * P; w = w - muls(I, cross3(r, P)); w = w - muls(I, L); }
+            const V3 P = (sideB ? lt1 : -lt1) * t1 + (sideB ? lt2 : -lt2) * t2;
+            const V3 L = (sideB ? ltw : -ltw) * nb;
+            v = v + im * P;
+            w = w + muls(I, cross3(mr, P));
+            w = w + muls(I, L);
         }
     }
     stv(c, i, v);
