@@ -1449,12 +1449,16 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
         const S6 I = load_iw(c, i);
         const int* OFF = iptr(c.L + l.CAND);
         const uint16_t* ENT = reinterpret_cast<const uint16_t*>(OFF + n + 1);
-        for (int e = OFF[i]; e < OFF[i + 1]; ++e) {
-            const int ent = ENT[e];
+        // the next block's entry and header are read while this block's rows are in use
+        const int e0 = OFF[i], e1 = OFF[i + 1];
+        int ent = e0 < e1 ? ENT[e0] : 0;   // manifold 0 always exists: the header read stays in range
+        int fc = iptr(c.L + l.MAN + (ent & 0x7FFF) * M_WORDS)[M_FC];
+        for (int e = e0; e < e1; ++e) {
             const int m = ent & 0x7FFF;
             const bool sideB = (ent >> 15) != 0;
-            int a, b, first, cnt;
-            man_header(c, m, a, b, first, cnt);
+            const int first = fc & 0xFFFF, cnt = fc >> 16;
+            const int ent_next = ENT[e + 1 < e1 ? e + 1 : e];
+            const int fc_next = iptr(c.L + l.MAN + (ent_next & 0x7FFF) * M_WORDS)[M_FC];
             const int rrow = sideB ? R_RB : R_RA;
             const int mrow = sideB ? M_RB : M_RA;
             // every row of the block is read before any arithmetic (one LDS round trip); the
@@ -1486,6 +1490,8 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
             v = v + im * P;
             w = w + muls(I, cross3(mr, P));
             w = w + muls(I, L);
+            ent = ent_next;
+            fc = fc_next;
         }
     }
     stv(c, i, v);
