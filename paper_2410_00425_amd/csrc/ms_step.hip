@@ -1363,6 +1363,113 @@ __device__ __forceinline__ void man_solve_pre(const EnvCtx& c, int m, const ManP
     store_body(c, p.b, B);
 }
 
+// ----------------------------------------------------------------------------- paired solve
+// A manifold block visited by two lanes of a pair (lanes 2k, 2k + 1): the even lane holds body A,
+// the odd lane body B.  Each lane forms its own body's velocity at its arm and gets the
+// partner's over a cross-lane move; the relative velocity, the multiplier update and the clamps
+// are then computed by both lanes alike, and each lane applies the impulse to its own body.
+// Side A works with negated relative velocities and impulses: negation is exact and every
+// product and sum here is symmetric under it, so both lanes see bit for bit the values of the
+// one-lane visit (man_solve_pre), and A's update v + im (-P) equals v - im P.
+__device__ __forceinline__ float pair_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+}
+__device__ __forceinline__ V3 pair_swap3(V3 v) { return v3(pair_swap(v.x), pair_swap(v.y), pair_swap(v.z)); }
+
+struct ManHalf {
+    int first, cnt;
+    bool has, dyn;
+    float im;
+    S6 I;
+    V3 r[4], n[4];
+    float bias[4], mn[4], ln[4];
+    V3 mr, nb, t1;
+    float mt1, mt2, mtw, mu, rt, lt1, lt2, ltw;
+    int body;
+};
+
+// Rows of manifold m for the lane holding side `sideB` (the arms of that side only).
+__device__ __forceinline__ void man_prefetch_half(const EnvCtx& c, int m, bool sideB, ManHalf& p) {
+    int a, b;
+    man_header(c, m, a, b, p.first, p.cnt);
+    p.body = sideB ? b : a;
+    p.has = p.body >= 0;
+    p.dyn = is_dyn(c, p.body);
+    p.im = p.has ? body_rec(c, p.body)[B_IM] : 0.0f;
+    p.I = p.has ? load_iw(c, p.body) : S6{0, 0, 0, 0, 0, 0};
+    const int rrow = sideB ? R_RB : R_RA;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < p.cnt) {
+            const int q = p.first + k;
+            p.r[k] = pr3(c, rrow, q);
+            p.n[k] = pr3(c, R_N, q);
+            p.ln[k] = pr(c, R_LN, q);
+            p.bias[k] = pr(c, R_BIAS, q);
+            p.mn[k] = pr(c, R_MN, q);
+        }
+    }
+    p.mr = mf3(c, sideB ? M_RB : M_RA, m);
+    p.nb = mf3(c, M_NB, m);
+    p.t1 = mf3(c, M_T1, m);
+    p.lt1 = mf(c, M_LT1, m); p.lt2 = mf(c, M_LT2, m); p.ltw = mf(c, M_LTW, m);
+    p.mt1 = mf(c, M_MT1, m); p.mt2 = mf(c, M_MT2, m); p.mtw = mf(c, M_MTW, m);
+    p.mu = mf(c, M_MU, m); p.rt = mf(c, M_RT, m);
+}
+
+// The paired counterpart of man_solve_pre; both lanes of the pair must be active.
+__device__ __forceinline__ void man_solve_half(const EnvCtx& c, int m, bool sideB, const ManHalf& p) {
+    V3 v = p.has ? ldv(c, p.body) : v3(0, 0, 0);
+    V3 w = p.has ? ldw(c, p.body) : v3(0, 0, 0);
+    float lsum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < p.cnt) {
+            const V3 r = p.r[k], n = p.n[k];
+            const V3 u = p.has ? v + cross3(w, r) : v3(0, 0, 0);
+            const float d = dot3(u - pair_swap3(u), n);
+            const float vn = sideB ? d : -d;
+            const float dl = -p.mn[k] * (vn + p.bias[k]);
+            const float old = p.ln[k];
+            const float nl = fmaxf(old + dl, 0.0f);
+            if (sideB) pr(c, R_LN, p.first + k) = nl;
+            const V3 P = (sideB ? nl - old : -(nl - old)) * n;
+            if (p.dyn) { v = v + p.im * P; w = w + muls(p.I, cross3(r, P)); }
+            lsum += nl;
+        }
+    }
+    const float lim = p.mu * lsum;
+    const V3 t2 = cross3(p.nb, p.t1);
+    {
+        const V3 u = p.has ? v + cross3(w, p.mr) : v3(0, 0, 0);
+        const float d = dot3(u - pair_swap3(u), p.t1);
+        const float vt = sideB ? d : -d;
+        const float nl = fminf(fmaxf(p.lt1 - p.mt1 * vt, -lim), lim);
+        if (sideB) mfr(c, M_LT1, m) = nl;
+        const V3 P = (sideB ? nl - p.lt1 : -(nl - p.lt1)) * p.t1;
+        if (p.dyn) { v = v + p.im * P; w = w + muls(p.I, cross3(p.mr, P)); }
+    }
+    {
+        const V3 u = p.has ? v + cross3(w, p.mr) : v3(0, 0, 0);
+        const float d = dot3(u - pair_swap3(u), t2);
+        const float vt = sideB ? d : -d;
+        const float nl = fminf(fmaxf(p.lt2 - p.mt2 * vt, -lim), lim);
+        if (sideB) mfr(c, M_LT2, m) = nl;
+        const V3 P = (sideB ? nl - p.lt2 : -(nl - p.lt2)) * t2;
+        if (p.dyn) { v = v + p.im * P; w = w + muls(p.I, cross3(p.mr, P)); }
+    }
+    {
+        const float limw = p.rt * lim;
+        const float d = dot3(p.nb, w - pair_swap3(w));
+        const float wr = sideB ? d : -d;
+        const float nl = fminf(fmaxf(p.ltw - p.mtw * wr, -limw), limw);
+        if (sideB) mfr(c, M_LTW, m) = nl;
+        const V3 L = (sideB ? nl - p.ltw : -(nl - p.ltw)) * p.nb;
+        if (p.dyn) w = w + muls(p.I, L);
+    }
+    if (p.dyn) { stv(c, p.body, v); stw(c, p.body, w); }
+}
+
 // Bias of every contact point for the sweeps of one substep.  The pose offsets change only
 // when a substep integrates, so the current separation s = s0 + n . (dB - dA) of each point (the
 // displacement of its body-fixed arms since the step start) and its bias (speculative s / h for
@@ -1550,6 +1657,36 @@ __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int
         }
         blk = sched_block(c, sched_off, nsched, e + 1, li);
         if (PIPE && PRE && blk >= 0) man_prefetch<SOLVE>(c, blk - l.nj, pre);
+        wave_sync();
+    }
+}
+
+// The solve sweep of a joint-free env with paired lanes: lane pair k (lanes 2k, 2k + 1 of the
+// group) visits blocks k, k + G / 2, ... of each entry (the blocks of one colour share no dynamic
+// body, so any split of a colour is the same sweep), the rows of its next block loaded behind
+// the compute of the current one.
+__device__ __forceinline__ void run_schedule_pairs(const EnvCtx& c, int sched_off, int nsched, int emax, int li, int G) {
+    const Lay& l = c.lay;
+    const int hg = G >> 1, slot = li >> 1;
+    const bool sideB = (li & 1) != 0;
+    const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
+    const int* SCH = reinterpret_cast<const int*>(c.L + sched_off);
+    int ent = nsched > 0 ? SCH[0] : 0;
+    int idx = slot;
+    int blk = idx < (ent >> 16) ? int(ORD[(ent & 0xFFFF) + idx]) : -1;
+    ManHalf pre;
+    if (blk >= 0) man_prefetch_half(c, blk - l.nj, sideB, pre);
+    for (int e = 0; e < emax; ++e) {
+        while (blk >= 0) {
+            man_solve_half(c, blk - l.nj, sideB, pre);
+            idx += hg;
+            blk = idx < (ent >> 16) ? int(ORD[(ent & 0xFFFF) + idx]) : -1;
+            if (blk >= 0) man_prefetch_half(c, blk - l.nj, sideB, pre);
+        }
+        ent = e + 1 < nsched ? SCH[e + 1] : 0;
+        idx = slot;
+        blk = idx < (ent >> 16) ? int(ORD[(ent & 0xFFFF) + idx]) : -1;
+        if (blk >= 0) man_prefetch_half(c, blk - l.nj, sideB, pre);
         wave_sync();
     }
 }
@@ -2128,7 +2265,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 if (s > 0 && !pipe) run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li);
                 for (int it = 0; it < K; ++it) {
                     for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
-                    (pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
+                    (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
                 }
                 // integrate the offsets from the step-start pose
                 for (int i = li; i < nn; i += G) {
@@ -2150,7 +2287,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                 for (int j = li; j < (frozen ? 0 : nj); j += G) joint_prep(c, j, h);
                 wave_sync();
             }
-            for (int it = 0; it < bd.V; ++it) (pipe ? run_schedule<OP_VSOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_VSOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
+            for (int it = 0; it < bd.V; ++it) (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_VSOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_VSOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
             run_schedule<OP_REST, false>(c, l.SCHED, ns, ns_max, h, li);
 
             // --------------------------------------------------------- S8 non-finite guard
