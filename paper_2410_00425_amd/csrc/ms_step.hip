@@ -1483,15 +1483,26 @@ __device__ __forceinline__ void bias_pass(const EnvCtx& c, int nman, float h, bo
         man_header(c, m, a, b, first, cnt);
         const bool has_a = a >= 0;
         const PoseR pa = load_pose(c, a), pb = load_pose(c, b);
-        for (int q = first; q < first + cnt; ++q) {
-            const V3 rA = pr3(c, R_RA, q), rB = pr3(c, R_RB, q), n = pr3(c, R_N, q);
-            V3 dA = has_a ? disp(pa, rA) : v3(0, 0, 0);
-            V3 dB = disp(pb, rB);
-            float s = pr(c, R_S0, q) + dot3(n, dB - dA);
-            float bias;
-            if (s > 0.0f) bias = s / h;
-            else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
-            pr(c, R_BIAS, q) = bias;
+        // the rows of all four slots are read before any arithmetic (one LDS round trip); the
+        // rows past the block's count lie inside the env's region and are not used
+        V3 rA[4], rB[4], nq[4];
+        float s0[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = first + k;
+            rA[k] = pr3(c, R_RA, q); rB[k] = pr3(c, R_RB, q); nq[k] = pr3(c, R_N, q); s0[k] = pr(c, R_S0, q);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < cnt) {
+                V3 dA = has_a ? disp(pa, rA[k]) : v3(0, 0, 0);
+                V3 dB = disp(pb, rB[k]);
+                float s = s0[k] + dot3(nq[k], dB - dA);
+                float bias;
+                if (s > 0.0f) bias = s / h;
+                else bias = vpass ? 0.0f : fmaxf(bd.beta * s / h, -bd.max_depen);
+                pr(c, R_BIAS, first + k) = bias;
+            }
         }
     }
 }
