@@ -149,7 +149,9 @@ def test_multi_step_launch_is_bit_identical():
         assert np.array_equal(sa[k], sb[k]), k
 
 
-@pytest.mark.parametrize("name,n,lanes", [("tray", 32, (16, 32, 64)), ("drop_boxes", 64, (1, 4, 8, 16, 64)),
+# narrow groups also exercise colours split over several passes of the lane pairs (a colour of a
+# tray env holds more blocks than 2 or 8 pairs) and the one-lane sweep (G = 1)
+@pytest.mark.parametrize("name,n,lanes", [("tray", 32, (4, 16, 32, 64)), ("drop_boxes", 64, (1, 2, 4, 8, 16, 64)),
                                           ("arm_cube", 32, (8, 32, 64))])
 def test_lanes_per_env_does_not_change_bits(name, n, lanes):
     sc = S.by_name(name, n, seed=8)
