@@ -197,6 +197,67 @@ def cpu_baseline(name, seed, budget_s=15.0):
                        f"{threads} threads, {dt:.1f} s)")
 
 
+def cpu_variants(name, seed, budget_s=4.0):
+    """The oracle at both precisions on one thread and on all host threads (short samples of the
+    same workload), and the host CPU's model name."""
+    from oracle.oracle import Oracle
+    from paper_2410_00425_amd import scenes as S
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, 64))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    out = {"cpu_model": model, "runs": []}
+    for prec in (32, 64):
+        for th in (1, threads):
+            n_env = 256 if th > 1 else 32
+            sc = S.by_name(name, n_env, seed=seed)
+            o = Oracle(sc, prec)
+            o.step(40, n_threads=th)
+            steps, t0 = 0, time.perf_counter()
+            while time.perf_counter() - t0 < budget_s:
+                o.step(2, n_threads=th)
+                steps += 2
+            dt = time.perf_counter() - t0
+            o.close()
+            out["runs"].append({"precision": f"f{prec}", "threads": th, "env_steps_per_s": n_env * steps / dt,
+                                "sample": f"{n_env} {name} envs x {steps} steps after 40 warm-up steps, {dt:.1f} s"})
+    return out
+
+
+def measured_peaks(ms):
+    """Rates this device reaches for the step's kinds of work: FP32 multiply-then-add issue on
+    independent chains (ms_peak_fp32, 8 wavefronts per SIMD) and a 512 MiB device copy."""
+    import torch
+    n_waves, iters = 8192, 4096
+    buf = torch.empty(n_waves * 64, dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms.peak_fp32(buf, n_waves, iters)
+    torch.cuda.synchronize()
+    ev[0].record()
+    flop = sum(ms.peak_fp32(buf, n_waves, iters) for _ in range(5))
+    ev[1].record()
+    torch.cuda.synchronize()
+    tflops = flop / (ev[0].elapsed_time(ev[1]) / 1e3) / 1e12
+    n = 128 << 20
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(5):
+        y.copy_(x)
+    ev[1].record()
+    torch.cuda.synchronize()
+    gbps = 5 * 2 * 4 * n / (ev[0].elapsed_time(ev[1]) / 1e3) / 1e9
+    return {"fp32_mul_add_tflops": tflops, "hbm_copy_GBps": gbps,
+            "how": "ms_peak_fp32: 8192 wavefronts x 4096 rounds x 8 chains of one multiply and one add; "
+                   "copy: 512 MiB read + 512 MiB written per copy, 5 copies"}
+
+
 def serving(ms, full=False, seed=0):
     """Continuous batching of step requests from 8 clients (2-step requests on sessions of one of
     the three scene families with 2**U{6..12} envs): saturation throughput (closed loop), latency
@@ -290,9 +351,16 @@ def main():
         extra["hetero_tuned_graph_speedup_vs_padded"] = (extra["hetero_tuned_graph"]["env_steps_per_s"] /
                                                          extra["hetero_padded"]["env_steps_per_s"])
         extra["serving"] = serving(ms, full=args.serve_full, seed=args.seed)
+        pk = measured_peaks(ms)
+        extra["measured_peaks"] = pk
+        # the headline's FLOP rate against the rate its instruction kinds can reach on this device
+        out["roofline"]["peak_measured_mul_add"] = pk["fp32_mul_add_tflops"]
+        out["roofline"]["frac_measured"] = out["roofline"]["achieved"] / pk["fp32_mul_add_tflops"]
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
+        if not args.quick:
+            out.setdefault("extra", {})["cpu_oracle_variants"] = cpu_variants(args.workload, args.seed)
     print(json.dumps(out), flush=True)
 
 

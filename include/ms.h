@@ -297,6 +297,14 @@ ms_status ms_server_stats(ms_server* s, int64_t* host_stats);
 ms_status ms_server_destroy(ms_server* s);
 double ms_server_clock(void);
 
+/* Measurement helper, not part of the step: launches n_waves 64-lane wavefronts on hip_stream
+ * that run `iters` rounds of 8 independent float32 chains, each round one multiply and one add
+ * per chain (no fused or packed forms, the instruction kinds of the step's arithmetic), and
+ * write one float per lane to dev_out [n_waves * 64] (device memory, caller-owned).  FLOP per
+ * launch = 16 * iters * 64 * n_waves; timing the launch gives the FP32 vector rate that code
+ * of this kind can reach.  MS_E_INVALID_ARG for a null pointer or a non-positive size. */
+ms_status ms_peak_fp32(float* dev_out, int n_waves, int iters, void* hip_stream);
+
 /* Thread-local message of the last non-OK status returned on this thread. */
 const char* ms_last_error(void);
 

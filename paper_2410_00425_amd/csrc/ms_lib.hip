@@ -2,3 +2,4 @@
 #include "ms_step.hip"
 #include "ms_host.cpp"
 #include "ms_server.cpp"
+#include "ms_peak.hip"

@@ -76,6 +76,7 @@ _sig = {
     "ms_server_drain": [_P],
     "ms_server_stats": [_P, _P],
     "ms_server_destroy": [_P],
+    "ms_peak_fp32": [_P, _I, _I, _P],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -299,6 +300,15 @@ class ms_request_info(C.Structure):
 
 def server_clock() -> float:
     return _lib.ms_server_clock()
+
+
+def peak_fp32(out, n_waves: int, iters: int, stream=None):
+    """Launch the FP32 issue-rate kernel (ms_peak_fp32) writing into the float32 CUDA tensor `out`
+    (at least n_waves * 64 elements); returns the FLOP count of the launch."""
+    if out.dtype.itemsize != 4 or not out.is_cuda or out.numel() < n_waves * 64:
+        raise ValueError("out must be a float32 CUDA tensor of at least n_waves * 64 elements")
+    _check(_lib.ms_peak_fp32(C.c_void_p(out.data_ptr()), int(n_waves), int(iters), _stream(stream)))
+    return 16 * int(iters) * 64 * int(n_waves)
 
 
 class Server:
