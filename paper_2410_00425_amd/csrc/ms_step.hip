@@ -1552,6 +1552,61 @@ __device__ __forceinline__ void build_body_lists(const EnvCtx& c, int nn, int nm
     }
 }
 
+// The same lists for a wavefront holding one env (G = 64): the headers of the blocks in colour
+// order sit in registers (lane p holds position p, p + 64, p + 128), and every body lane walks
+// them with scalar reads of those registers instead of a chain of dependent LDS loads.
+__device__ __forceinline__ void build_body_lists_wave(const EnvCtx& c, int nn, int nman_in, int li) {
+    const Lay& l = c.lay;
+    const int n = __builtin_amdgcn_readfirstlane(nn);
+    const int nman = __builtin_amdgcn_readfirstlane(nman_in);
+    int* OFF = iptr(c.L + l.CAND);
+    uint16_t* ENT = reinterpret_cast<uint16_t*>(OFF + l.n + 1);
+    const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
+    // (manifold << 16) | a | b << 8 of colour position r * 64 + li; 0xFFFF never matches a body
+    int hd[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int p = r * WAVE + li;
+        int w = 0xFFFF;
+        if (p < nman) {
+            const int m = int(ORD[p]);
+            w = (iptr(c.L + l.MAN + m * M_WORDS)[M_AB] & 0xFFFF) | (m << 16);
+        }
+        hd[r] = w;
+    }
+    const bool mine = li < n && is_dyn(c, li);
+    int deg = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int kend = min(WAVE, nman - r * WAVE);
+        for (int k = 0; k < kend; ++k) {
+            const int w = __builtin_amdgcn_readlane(hd[r], k);
+            deg += ((w & 0xFF) == li ? 1 : 0) + (((w >> 8) & 0xFF) == li ? 1 : 0);
+        }
+    }
+    if (!mine) deg = 0;
+    // exclusive prefix of the degrees over the body lanes
+    int incl = deg;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (li >= d) incl += y;
+    }
+    if (li < n) OFF[li + 1] = incl;
+    if (li == 0 && n > 0) OFF[0] = 0;
+    int o = incl - deg;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int kend = min(WAVE, nman - r * WAVE);
+        for (int k = 0; k < kend; ++k) {
+            const int w = __builtin_amdgcn_readlane(hd[r], k);
+            const int m = w >> 16;
+            if (mine && (w & 0xFF) == li) ENT[o++] = uint16_t(m);
+            if (mine && ((w >> 8) & 0xFF) == li) ENT[o++] = uint16_t(m | 0x8000);
+        }
+    }
+}
+
 // Gravity and damping of one dynamic body for a substep, then (after the first substep) its
 // warm start: the accumulated impulses of its blocks in colour order, as imp_lin / imp_ang apply
 // them to this body (side A subtracts, side B adds).
@@ -2263,7 +2318,8 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
             const float admp = 1.0f / (1.0f + h * bd.ang_damp);
             // joint-free waves warm-start body by body (fused with gravity); others sweep colours
             if (pipe && S > 1) {
-                build_body_lists(c, nn, nmanA, li, G);
+                if (G == WAVE) build_body_lists_wave(c, nn, nmanA, li);
+                else build_body_lists(c, nn, nmanA, li, G);
                 wave_sync();
             }
             for (int s = 0; s < S; ++s) {
