@@ -133,13 +133,13 @@ def algorithmic_bytes(scene):
     return scene.n_bodies * (52 * 2 + 48) + scene.n_envs * (8 + 8) + scene.n_joints * 76
 
 
-def time_graph(batch, steps, warmup, per_graph=10):
-    """Steps replayed from a captured graph of per_graph single-step launches."""
+def time_graph(batch, steps, warmup, per_graph=10, spl=1):
+    """Steps replayed from a captured graph of per_graph steps in launches of spl steps each."""
     import numpy as np
     import torch
     for _ in range(max(1, warmup)):
         batch.step(1)
-    g = batch.graph(1, per_graph)
+    g = batch.graph(spl, per_graph // spl)
     g.launch()
     torch.cuda.synchronize()
     batch.stats(reset=True)
@@ -155,7 +155,7 @@ def time_graph(batch, steps, warmup, per_graph=10):
     g.close()
     st = batch.stats()
     n_steps = n_rep * per_graph
-    return dict(total_ms=total_ms, n_steps=n_steps, n_launch=n_steps, launch_ms=total_ms / n_steps,
+    return dict(total_ms=total_ms, n_steps=n_steps, n_launch=n_steps // spl, launch_ms=total_ms / (n_steps // spl),
                 p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), stats=st)
 
 
@@ -166,7 +166,7 @@ def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1,
         for _ in range(60):   # tune on a settled state (contacts formed), trials of 10 steps
             b.step(1)
         b.tune(10)
-    r = time_graph(b, steps, warmup) if graph else time_batch(b, steps, warmup, spl)
+    r = time_graph(b, steps, warmup, spl=spl) if graph else time_batch(b, steps, warmup, spl)
     flop = algorithmic_flop(sc, r["stats"], sc.params)
     plan = b.plan()
     b.close()
@@ -350,6 +350,16 @@ def main():
         extra["hetero_speedup_vs_padded"] = extra["hetero"]["env_steps_per_s"] / extra["hetero_padded"]["env_steps_per_s"]
         extra["hetero_tuned_graph_speedup_vs_padded"] = (extra["hetero_tuned_graph"]["env_steps_per_s"] /
                                                          extra["hetero_padded"]["env_steps_per_s"])
+        # persistent launches of one 60 Hz control step (2 steps of the 120 Hz simulation) each,
+        # replayed from a graph: the batched form and, like for like, the padded form
+        _, _, res = run_workload(ms, S, "hetero", 4096, 100, 20, 2, args.seed, tune=True, graph=True)
+        extra["hetero_tuned_graph_2spl"] = res
+        _, _, res = run_workload(ms, S, "hetero_padded", 4096, 100, 20, 2, args.seed, pack=0, graph=True)
+        extra["hetero_padded_graph_2spl"] = res
+        extra["hetero_2spl_speedup_vs_padded_plain"] = (extra["hetero_tuned_graph_2spl"]["env_steps_per_s"] /
+                                                                extra["hetero_padded"]["env_steps_per_s"])
+        extra["hetero_2spl_speedup_vs_padded_2spl"] = (extra["hetero_tuned_graph_2spl"]["env_steps_per_s"] /
+                                                       extra["hetero_padded_graph_2spl"]["env_steps_per_s"])
         extra["serving"] = serving(ms, full=args.serve_full, seed=args.seed)
         pk = measured_peaks(ms)
         extra["measured_peaks"] = pk
