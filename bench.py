@@ -139,6 +139,7 @@ def time_graph(batch, steps, warmup, per_graph=10, spl=1):
     import torch
     for _ in range(max(1, warmup)):
         batch.step(1)
+    per_graph = max(1, per_graph // spl) * spl   # whole launches per replay
     g = batch.graph(spl, per_graph // spl)
     g.launch()
     torch.cuda.synchronize()
