@@ -75,6 +75,15 @@ struct Tile {
     int lds_words;
 };
 
+// A bin: up to BIN_WAVES tiles run by the wavefronts of one workgroup, tile k at word offset
+// off[k] of the workgroup's LDS (the single-launch form of a batch with tiles of several sizes).
+constexpr int BIN_WAVES = 8;
+struct Bin {
+    int count;
+    int tile[BIN_WAVES];
+    int off[BIN_WAVES];
+};
+
 // Word offsets of one env's arrays: component-major planes of length n, except the per-body
 // solver records and the contact, manifold and joint rows, which are records.
 enum { B_V = 0, B_W = 3, B_IM = 6, B_IW = 7, BODY_WORDS = 13 };

@@ -140,6 +140,11 @@ struct Plan {
     std::vector<TileEnv> tenv;
     std::vector<LdsClass> classes;
     int max_tile_words = 0;
+    // single-launch form (batches whose tiles fall into several LDS classes): bins of up to
+    // BIN_WAVES tiles packed first-fit by decreasing size into one workgroup's LDS
+    std::vector<Bin> bins;
+    int bin_words = 0;
+    int launch_mode = 0;   // 0: bins when several LDS classes, 1: always class launches
     // debug offsets
     std::vector<int> dbg_pair_off, dbg_pt_off, dbg_man_off;
 };
@@ -147,7 +152,7 @@ struct Plan {
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
     size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, save, status, bpar, body_off, joint_off, jrec, targets, tiles,
-        tenv, bd, stats, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
+        bins, tenv, bd, stats, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
 
 ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
@@ -193,6 +198,33 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     return MS_OK;
 }
 
+constexpr int BIN_BUDGET = 40960;   // bin LDS budget in words: a CU's 160 KiB, one bin per CU
+
+// Bins for the single-launch form: tiles (sorted by LDS need, largest first) placed first-fit
+// into bins of at most BIN_WAVES tiles and BIN_BUDGET words.  Only for batches with more than
+// one LDS class; otherwise the class launch is already a single launch.
+void make_bins(Plan& out) {
+    out.bins.clear();
+    out.bin_words = 0;
+    if (out.classes.size() < 2 || out.launch_mode == 1) return;
+    std::vector<int> used;
+    for (int t = 0; t < int(out.tiles.size()); ++t) {
+        const int w = out.tiles[t].lds_words;
+        int k = 0;
+        while (k < int(out.bins.size()) && (out.bins[k].count == BIN_WAVES || used[k] + w > BIN_BUDGET)) ++k;
+        if (k == int(out.bins.size())) {
+            out.bins.push_back(Bin{});
+            used.push_back(0);
+        }
+        Bin& bn = out.bins[k];
+        bn.tile[bn.count] = t;
+        bn.off[bn.count] = used[k];
+        bn.count++;
+        used[k] += w;
+        out.bin_words = std::max(out.bin_words, used[k]);
+    }
+}
+
 constexpr int TILE_BUDGET = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
 
 // Tiles, env slots and LDS classes from the per-env sizes and lanes (info[e].lanes): envs sorted
@@ -229,12 +261,14 @@ void make_tiles(Plan& out, bool pack) {
                      [](const Tile& a, const Tile& b) { return a.lds_words > b.lds_words; });
     cut_classes(int(out.tiles.size()), [&](int t) -> Tile& { return out.tiles[t]; }, pack, out.classes);
     for (const Tile& t : out.tiles) out.max_tile_words = std::max(out.max_tile_words, t.lds_words);
+    make_bins(out);
 }
 
 void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* plan, Plan& out) {
     const int E = s->n_envs;
     const int forced = plan ? plan->lanes_per_env : 0;
     const bool pack = plan ? plan->pack != 0 : true;
+    out.launch_mode = plan ? plan->launch_mode : 0;
     out.info.resize(E);
     for (int e = 0; e < E; ++e) {
         EnvInfo& I = out.info[e];
@@ -274,6 +308,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.jrec = take(J * JREC * 4);
     L.targets = take(J * 4);
     L.tiles = take(E * sizeof(Tile));   // room for any tiling (one env per tile at most)
+    L.bins = take(E * sizeof(Bin));     // and for its bins
     L.tenv = take(pl.tenv.size() * sizeof(TileEnv));
     L.bd = take(sizeof(BatchDev));
     L.stats = take(E * NSTAT * 4);
@@ -554,6 +589,7 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     if (e == hipSuccess) e = up(L.targets, tg.data(), J * 4);
     if (e == hipSuccess) e = up(L.tiles, b->plan.tiles.data(), b->plan.tiles.size() * sizeof(Tile));
     if (e == hipSuccess) e = up(L.tenv, b->plan.tenv.data(), b->plan.tenv.size() * sizeof(TileEnv));
+    if (e == hipSuccess && !b->plan.bins.empty()) e = up(L.bins, b->plan.bins.data(), b->plan.bins.size() * sizeof(Bin));
     if (e == hipSuccess) e = up(L.bd, &b->hbd, sizeof(BatchDev));
     if (params->debug_export) {
         if (e == hipSuccess) e = up(L.dbg_pair_off, b->plan.dbg_pair_off.data(), (E + 1) * 4);
@@ -603,6 +639,9 @@ static ms_status retile(ms_batch* b, const std::vector<int>& lanes, hipStream_t 
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(b->ws + b->lay.tenv, b->plan.tenv.data(), b->plan.tenv.size() * sizeof(TileEnv),
                           hipMemcpyHostToDevice, s));
+    if (!b->plan.bins.empty())
+        HIP_OK(hipMemcpyAsync(b->ws + b->lay.bins, b->plan.bins.data(), b->plan.bins.size() * sizeof(Bin),
+                              hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
     return ensure_side_streams(b);
 }
@@ -618,6 +657,13 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     const TileEnv* tenv = at<TileEnv>(b->ws, b->lay.tenv);
     const int grid_cap = b->max_resident_groups;
     if (cls.size() == 1) return launch_class(cls[0], b->dbd, tiles, tenv, int(n_steps), grid_cap, s);
+    if (!b->plan.bins.empty()) {   // every tile in one launch, a bin per workgroup
+        const int nb = int(b->plan.bins.size());
+        hipLaunchKernelGGL(ms_step_kernel_bins, dim3(nb), dim3(WAVE * BIN_WAVES), size_t(b->plan.bin_words) * 4, s, b->dbd,
+                           tiles, at<Bin>(b->ws, b->lay.bins), nb, tenv, int(n_steps));
+        HIP_OK(hipGetLastError());
+        return MS_OK;
+    }
     // one launch per LDS class: the largest class on the caller's stream, the others on side
     // streams forked from and joined back into it
     if (ms_status st = ensure_side_streams(b); st != MS_OK) return st;
@@ -696,9 +742,10 @@ ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes)
 
 ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds_bytes, int32_t* host_env_lanes) {
     if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    const bool bins = !b->plan.bins.empty();
     if (n_tiles) *n_tiles = int(b->plan.tiles.size());
-    if (grid) *grid = b->grid;
-    if (lds_bytes) *lds_bytes = int(b->lds_bytes);
+    if (grid) *grid = bins ? int(b->plan.bins.size()) : b->grid;
+    if (lds_bytes) *lds_bytes = bins ? b->plan.bin_words * 4 : int(b->lds_bytes);
     if (host_env_lanes)
         for (int e = 0; e < b->E; ++e) host_env_lanes[e] = b->plan.info[e].lanes;
     return MS_OK;

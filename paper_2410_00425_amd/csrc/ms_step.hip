@@ -1840,7 +1840,7 @@ __device__ __forceinline__ void colour_env(const EnvCtx& c, int G) {
 // chain of LDS round trips.  Block order, colours and schedules equal those of colour_env.
 __device__ __forceinline__ void colour_env_wave(const EnvCtx& c) {
     const Lay& l = c.lay;
-    const int li = threadIdx.x;
+    const int li = int(threadIdx.x) & (WAVE - 1);
     int* SC = iptr(c.L + l.SCAL);
     // one env per wave: its sizes are wave-uniform (scalar loop bounds)
     const int nj = __builtin_amdgcn_readfirstlane(l.nj);
@@ -2066,13 +2066,9 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
 // ONE: every tile of the launch holds a single env served by all 64 lanes, so the env's sizes
 // and offsets are wavefront-uniform (scalar registers) and the group arithmetic folds away.
 template <bool ONE>
-__device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restrict__ batches,
-                                           const Tile* __restrict__ tiles, int n_tiles,
-                                           const TileEnv* __restrict__ tenv, int n_steps) {
-    const int lane = threadIdx.x;
-
-    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const Tile tile = tiles[t];
+__device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict__ batches, const Tile tile,
+                                          const TileEnv* __restrict__ tenv, int n_steps, int lane) {
+    {
         const int G = ONE ? WAVE : tile.lanes;
         const int g = ONE ? 0 : lane / G, li = ONE ? lane : lane % G;
         EnvCtx c;
@@ -2410,6 +2406,15 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
     }
 }
 
+// Workgroups of one wavefront walking the tile list.
+template <bool ONE>
+__device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restrict__ batches,
+                                           const Tile* __restrict__ tiles, int n_tiles,
+                                           const TileEnv* __restrict__ tenv, int n_steps) {
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x)
+        step_tile<ONE>(lds, batches, tiles[t], tenv, n_steps, int(threadIdx.x));
+}
+
 // Builds of the same step: any tiling with unconstrained register allocation (small envs, where
 // the wave count is bounded by LDS anyway) or capped at 256 registers per lane (two waves per
 // SIMD); and the same two for launches whose tiles all hold one env served by the whole
@@ -2437,6 +2442,21 @@ ms_step_kernel_one_w2(const BatchDev* __restrict__ batches, const Tile* __restri
                       const TileEnv* __restrict__ tenv, int n_steps) {
     extern __shared__ float lds[];
     step_tiles<true>(lds, batches, tiles, n_tiles, tenv, n_steps);
+}
+
+// One launch for every tile of a batch: workgroups of BIN_WAVES wavefronts, one bin each; wave w
+// runs tile w of its bin in the bin's LDS at that tile's offset.  Waves of a bin share nothing
+// but the allocation (every env lives in one wave), so they need no barrier.
+extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) __attribute__((amdgpu_waves_per_eu(2)))
+ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles,
+                    const Bin* __restrict__ bins, int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
+    extern __shared__ float lds[];
+    const int wave = int(threadIdx.x) / WAVE;
+    const int b = int(blockIdx.x);
+    if (b >= n_bins) return;
+    const Bin& bin = bins[b];
+    if (wave >= bin.count) return;
+    step_tile<false>(lds + bin.off[wave], batches, tiles[bin.tile[wave]], tenv, n_steps, int(threadIdx.x) & (WAVE - 1));
 }
 
 // ============================================================================= reset kernel

@@ -45,7 +45,8 @@ class ms_state_view(C.Structure):
 
 
 class ms_plan(C.Structure):
-    _fields_ = [("lanes_per_env", C.c_int32), ("pack", C.c_int32), ("max_resident_groups", C.c_int32)]
+    _fields_ = [("lanes_per_env", C.c_int32), ("pack", C.c_int32), ("max_resident_groups", C.c_int32),
+                ("launch_mode", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -111,8 +112,8 @@ def _params(scene, params):
     return p
 
 
-def _plan(lanes_per_env=0, pack=1, max_resident_groups=0):
-    return ms_plan(int(lanes_per_env), int(pack), int(max_resident_groups))
+def _plan(lanes_per_env=0, pack=1, max_resident_groups=0, launch_mode=0):
+    return ms_plan(int(lanes_per_env), int(pack), int(max_resident_groups), int(launch_mode))
 
 
 def _stream(stream):
@@ -134,13 +135,13 @@ class Batch:
     """A batch of envs resident on one GPU: owns its torch workspace and the C handle."""
 
     def __init__(self, scene, params=None, device="cuda:0", lanes_per_env=0, pack=1, max_resident_groups=0,
-                 stream=None):
+                 stream=None, launch_mode=0):
         import torch
         self.device = torch.device(device)
         self.scene = scene
         self.params = _params(scene, params)
         self.n_envs, self.n_bodies, self.n_joints = scene.n_envs, scene.n_bodies, scene.n_joints
-        self._plan = _plan(lanes_per_env, pack, max_resident_groups)
+        self._plan = _plan(lanes_per_env, pack, max_resident_groups, launch_mode)
         sd, keep = _scene_struct(scene)
         nbytes = C.c_size_t()
         _check(_lib.ms_query_batch_bytes(self.params.ctypes.data, C.byref(sd), C.byref(self._plan),

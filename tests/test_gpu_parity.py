@@ -176,13 +176,17 @@ def test_hetero_packed_matches_unpacked_and_alone():
     st = oracle_state(sc, 30)
     ids = torch.arange(sc.n_envs, dtype=torch.int32, device="cuda")
     res = []
-    for pack in (1, 0):
-        b = gpu_batch(sc, debug=False, pack=pack)
+    # packed in one launch of bins, packed in per-class launches, unpacked
+    for pack, mode in ((1, 0), (1, 1), (0, 0)):
+        b = gpu_batch(sc, debug=False, pack=pack, launch_mode=mode)
+        if pack:
+            assert len(b.classes()) > 1   # several LDS sizes: mode 0 runs the bins launch
         b.reset_envs(ids, to_dev(st))
         b.step(4)
         res.append(b.state_numpy())
-    for k in res[0]:
-        assert np.array_equal(res[0][k], res[1][k]), k
+    for r in res[1:]:
+        for k in res[0]:
+            assert np.array_equal(res[0][k], r[k]), k
     # a few envs stepped alone give the same bits as inside the mixed batch
     for e in (0, 17, 95):
         one = sc.subset([e])
