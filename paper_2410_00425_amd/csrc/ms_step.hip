@@ -2445,7 +2445,8 @@ ms_step_kernel_one_w2(const BatchDev* __restrict__ batches, const Tile* __restri
 }
 
 // One launch for every tile of a batch: workgroups of BIN_WAVES wavefronts, one bin each; wave w
-// runs tile w of its bin in the bin's LDS at that tile's offset.  Waves of a bin share nothing
+// runs tile w of its bin in the bin's LDS at that tile's offset (the scalar-env build for a tile
+// of one env on all 64 lanes, the general build otherwise).  Waves of a bin share nothing
 // but the allocation (every env lives in one wave), so they need no barrier.
 extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) __attribute__((amdgpu_waves_per_eu(2)))
 ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles,
@@ -2456,7 +2457,10 @@ ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict
     if (b >= n_bins) return;
     const Bin& bin = bins[b];
     if (wave >= bin.count) return;
-    step_tile<false>(lds + bin.off[wave], batches, tiles[bin.tile[wave]], tenv, n_steps, int(threadIdx.x) & (WAVE - 1));
+    const Tile tile = tiles[bin.tile[wave]];
+    const int lane = int(threadIdx.x) & (WAVE - 1);
+    if (tile.lanes == WAVE && tile.count == 1) step_tile<true>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
+    else step_tile<false>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
 }
 
 // ============================================================================= reset kernel
