@@ -203,26 +203,33 @@ constexpr int BIN_BUDGET = 40960;   // bin LDS budget in words: a CU's 160 KiB, 
 // Bins for the single-launch form: tiles (sorted by LDS need, largest first) placed first-fit
 // into bins of at most BIN_WAVES tiles and BIN_BUDGET words.  Only for batches with more than
 // one LDS class; otherwise the class launch is already a single launch.
-void make_bins(Plan& out) {
-    out.bins.clear();
-    out.bin_words = 0;
-    if (out.classes.size() < 2 || out.launch_mode == 1) return;
+template <class TileRef>
+int pack_bins(int n_tiles, TileRef tile_ref, std::vector<Bin>& bins) {
+    bins.clear();
+    int bin_words = 0;
     std::vector<int> used;
-    for (int t = 0; t < int(out.tiles.size()); ++t) {
-        const int w = out.tiles[t].lds_words;
+    for (int t = 0; t < n_tiles; ++t) {
+        const int w = tile_ref(t).lds_words;
         int k = 0;
-        while (k < int(out.bins.size()) && (out.bins[k].count == BIN_WAVES || used[k] + w > BIN_BUDGET)) ++k;
-        if (k == int(out.bins.size())) {
-            out.bins.push_back(Bin{});
+        while (k < int(bins.size()) && (bins[k].count == BIN_WAVES || used[k] + w > BIN_BUDGET)) ++k;
+        if (k == int(bins.size())) {
+            bins.push_back(Bin{});
             used.push_back(0);
         }
-        Bin& bn = out.bins[k];
+        Bin& bn = bins[k];
         bn.tile[bn.count] = t;
         bn.off[bn.count] = used[k];
         bn.count++;
         used[k] += w;
-        out.bin_words = std::max(out.bin_words, used[k]);
+        bin_words = std::max(bin_words, used[k]);
     }
+    return bin_words;
+}
+void make_bins(Plan& out) {
+    out.bins.clear();
+    out.bin_words = 0;
+    if (out.classes.size() < 2 || out.launch_mode == 1) return;
+    out.bin_words = pack_bins(int(out.tiles.size()), [&](int t) -> const Tile& { return out.tiles[t]; }, out.bins);
 }
 
 constexpr int TILE_BUDGET = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
@@ -983,7 +990,8 @@ ms_status ms_graph_destroy(ms_graph* g) {
 static size_t many_bytes(ms_batch* const* batches, int32_t n) {
     size_t tiles = 0, tenv = 0;
     for (int i = 0; i < n; ++i) { tiles += batches[i]->plan.tiles.size(); tenv += batches[i]->plan.tenv.size(); }
-    return align_up(size_t(n) * sizeof(BatchDev)) + align_up(tiles * sizeof(Tile)) + align_up(tenv * sizeof(TileEnv));
+    return align_up(size_t(n) * sizeof(BatchDev)) + align_up(tiles * sizeof(Tile)) + align_up(tenv * sizeof(TileEnv)) +
+           align_up(tiles * sizeof(Bin));
 }
 
 ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, size_t* bytes) {
@@ -1086,6 +1094,14 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
         tt[k] = u;
     }
     cut_classes(int(order.size()), [&](int k) -> Tile& { return tt[k]; }, true, cls);
+    // several LDS sizes: one launch of bins (as for a single batch)
+    Bin* hb = reinterpret_cast<Bin*>(reinterpret_cast<char*>(te) + align_up(size_t(tenv_base[n_batches]) * sizeof(TileEnv)));
+    std::vector<Bin> bins;
+    int bin_words = 0;
+    if (cls.size() > 1) {
+        bin_words = pack_bins(int(order.size()), [&](int k) -> const Tile& { return tt[k]; }, bins);
+        std::copy(bins.begin(), bins.end(), hb);
+    }
     HIP_OK(hipMemcpyAsync(dev_scratch, st.host, need, hipMemcpyHostToDevice, s));
     HIP_OK(hipEventRecord(st.ev, s));
     st.pending = true;
@@ -1093,6 +1109,14 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     const BatchDev* dtb = reinterpret_cast<const BatchDev*>(d);
     const Tile* dtt = reinterpret_cast<const Tile*>(d + (reinterpret_cast<char*>(tt) - h));
     const TileEnv* dte = reinterpret_cast<const TileEnv*>(d + (reinterpret_cast<char*>(te) - h));
+    if (!bins.empty()) {
+        const Bin* dbins = reinterpret_cast<const Bin*>(d + (reinterpret_cast<char*>(hb) - h));
+        const int nb = int(bins.size());
+        hipLaunchKernelGGL(ms_step_kernel_bins, dim3(nb), dim3(WAVE * BIN_WAVES), size_t(bin_words) * 4, s, dtb, dtt, dbins,
+                           nb, dte, int(n_steps));
+        HIP_OK(hipGetLastError());
+        return MS_OK;
+    }
     if (cls.size() > 1 && !st.ev_fork) {
         HIP_OK(hipEventCreateWithFlags(&st.ev_fork, hipEventDisableTiming));
         for (int k = 1; k < MAX_CLASSES; ++k) {
