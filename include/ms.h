@@ -245,7 +245,8 @@ ms_status ms_graph_launch(ms_graph* g, void* hip_stream);
 ms_status ms_graph_destroy(ms_graph* g);
 
 /* Fused step over several batches in one launch (the serving path): the env tiles of every
- * batch are concatenated into one work list.  dev_targets (may be NULL) holds per-batch target
+ * batch are merged into one work list, run as one launch of LDS-packed bins when they need
+ * several LDS sizes (as ms_step does for one batch).  dev_targets (may be NULL) holds per-batch target
  * pointers as in ms_step.  dev_scratch is caller device memory of at least
  * ms_query_step_many_bytes() bytes (256-byte aligned) that receives the combined work list; it
  * must not be reused until the stream has passed this launch.  The batches must live on the
