@@ -317,7 +317,7 @@ const char* ms_last_error(void);
 const char* ms_version(void);
 
 /* Host-only consistency check of the kernel's LDS layout and pair indexing for every supported
- * env size; returns 0 when consistent.  Touches no device. */
+ * env size and of the packing of tiles into bins; returns 0 when consistent.  Touches no device. */
 int ms_selfcheck(void);
 
 #ifdef __cplusplus

@@ -471,6 +471,33 @@ int ms_selfcheck(void) {
                     if (L.SCAL + 32 > L.total || (L.total & 3)) return 4;
                 }
     }
+    // bin packing: every tile in exactly one bin slot, at most BIN_WAVES per bin, tile regions
+    // disjoint and inside the launch's LDS, which stays within one CU's LDS
+    uint32_t seed = 12345u;
+    for (int trial = 0; trial < 64; ++trial) {
+        std::vector<Tile> tl(1 + trial * 37 % 1500);
+        for (Tile& t : tl) {
+            seed = seed * 1664525u + 1013904223u;
+            t.lds_words = 4 * int(64 + (seed >> 8) % 4000);   // 1 KiB .. 17 KiB, multiples of 4 words
+        }
+        std::stable_sort(tl.begin(), tl.end(), [](const Tile& a, const Tile& b) { return a.lds_words > b.lds_words; });
+        std::vector<Bin> bins;
+        const int words = pack_bins(int(tl.size()), [&](int t) -> const Tile& { return tl[t]; }, bins);
+        if (words > BIN_BUDGET) return 5;
+        std::vector<int> seen(tl.size(), 0);
+        for (const Bin& bn : bins) {
+            if (bn.count < 1 || bn.count > BIN_WAVES) return 6;
+            int end = 0;
+            for (int k = 0; k < bn.count; ++k) {
+                if (bn.tile[k] < 0 || bn.tile[k] >= int(tl.size()) || seen[bn.tile[k]]++) return 7;
+                if (bn.off[k] != end || (bn.off[k] & 3)) return 8;
+                end += tl[bn.tile[k]].lds_words;
+            }
+            if (end > words) return 9;
+        }
+        for (int v : seen)
+            if (v != 1) return 10;
+    }
     return 0;
 }
 
