@@ -164,9 +164,12 @@ def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1,
     sc = S.by_name(name, n_envs, seed=seed)
     b = ms.Batch(sc, lanes_per_env=lanes, pack=pack)
     if tune:
+        import torch
         for _ in range(60):   # tune on a settled state (contacts formed), trials of 10 steps
             b.step(1)
         b.tune(10)
+        # then time from the initial state, like the untuned runs (same phase of the scene)
+        b.reset_envs(torch.arange(n_envs, dtype=torch.int32, device="cuda"))
     r = time_graph(b, steps, warmup, spl=spl) if graph else time_batch(b, steps, warmup, spl)
     flop = algorithmic_flop(sc, r["stats"], sc.params)
     plan = b.plan()
