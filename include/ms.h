@@ -214,8 +214,9 @@ ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes)
 /* Autotuner.  First the env tiling: for every group of envs that the planner gave the same
  * lanes per env (so 64 / lanes envs per wavefront), the whole batch is timed over trial_steps
  * steps with half and with twice as many lanes for that group, and a change is kept if it is
- * at least 3 % faster.  Then, for every LDS class, each kernel variant is timed over
- * trial_steps launches of that class alone and the fastest kept.  The tiling never changes a
+ * at least 3 % faster.  Then, when the batch runs as one launch per LDS class, each kernel
+ * variant of every class is timed over trial_steps launches of that class alone and the
+ * fastest kept (the bins launch has fixed builds).  The tiling never changes a
  * result.  The batch's state, status and work counters are saved before and restored after
  * (the trial steps leave no trace).  Synchronises `hip_stream`. */
 ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream);

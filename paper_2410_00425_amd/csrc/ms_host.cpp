@@ -904,7 +904,9 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
     //    each part timed alone
     const Tile* tiles = at<Tile>(w, L.tiles);
     const TileEnv* tenv = at<TileEnv>(w, L.tenv);
+    // the variants of class launches (a batch run as one launch of bins has fixed builds)
     for (LdsClass& c : b->plan.classes) {
+        if (!b->plan.bins.empty()) break;
         for (int part = 0; part < 2 && st == MS_OK; ++part) {
             const int first = part == 0 ? c.first_tile : c.first_tile + c.n_one;
             const int count = part == 0 ? c.n_one : c.n_tiles - c.n_one;
