@@ -142,8 +142,8 @@ typedef struct {
 /* Execution plan knobs.  lanes_per_env = 0 lets the library pick (autotuned or heuristic);
  * otherwise 1, 2, 4, 8, 16, 32 or 64 lanes of a 64-wide wavefront serve one env.  pack != 0
  * sorts envs by size class before tiling (heterogeneous batches).  launch_mode 0: a batch whose
- * tiles need several LDS sizes runs in one launch of workgroups of up to 8 wavefronts, each
- * workgroup holding a bin of tiles packed into one CU's LDS; 1: one launch per LDS class
+ * tiles need several LDS sizes runs in one launch of workgroups of up to 4 wavefronts, each
+ * workgroup holding a bin of tiles packed into half a CU's LDS; 1: one launch per LDS class
  * (concurrent streams).  Both give the same bits. */
 typedef struct {
     int32_t lanes_per_env;

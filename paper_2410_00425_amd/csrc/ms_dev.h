@@ -77,7 +77,7 @@ struct Tile {
 
 // A bin: up to BIN_WAVES tiles run by the wavefronts of one workgroup, tile k at word offset
 // off[k] of the workgroup's LDS (the single-launch form of a batch with tiles of several sizes).
-constexpr int BIN_WAVES = 8;
+constexpr int BIN_WAVES = 4;
 struct Bin {
     int count;
     int tile[BIN_WAVES];

@@ -198,7 +198,7 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     return MS_OK;
 }
 
-constexpr int BIN_BUDGET = 40960;   // bin LDS budget in words: a CU's 160 KiB, one bin per CU
+constexpr int BIN_BUDGET = 20480;   // bin LDS budget in words: half a CU's 160 KiB, two bins per CU
 
 // Bins for the single-launch form: tiles (sorted by LDS need, largest first) placed first-fit
 // into bins of at most BIN_WAVES tiles and BIN_BUDGET words.  Only for batches with more than
@@ -472,7 +472,7 @@ int ms_selfcheck(void) {
                 }
     }
     // bin packing: every tile in exactly one bin slot, at most BIN_WAVES per bin, tile regions
-    // disjoint and inside the launch's LDS, which stays within one CU's LDS
+    // disjoint and inside the launch's LDS, which stays within the bin budget
     uint32_t seed = 12345u;
     for (int trial = 0; trial < 64; ++trial) {
         std::vector<Tile> tl(1 + trial * 37 % 1500);
