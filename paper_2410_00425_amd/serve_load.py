@@ -74,7 +74,8 @@ def run_clients(ms, server, pool, lam, n_clients=8, sessions_per_client=2, reqs_
                 for r in range(reqs_per_session):
                     if rate is not None:
                         t_next += rng.exponential(1.0 / rate)
-                    arrival = t_next if rate is not None else (done_prev if done_prev is not None else clock())
+                    # closed loop: the first request of a client arrives at the common start time
+                    arrival = t_next if rate is not None else (done_prev if done_prev is not None else t_begin)
                     if done_prev is not None:
                         arrival = max(arrival, done_prev)
                     wait = arrival - clock()
