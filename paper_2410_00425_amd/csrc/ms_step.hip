@@ -1515,9 +1515,20 @@ __device__ __forceinline__ void bias_pass(const EnvCtx& c, int nman, float h, bo
 // entries (manifold | side << 15).
 // nn: the env's body count, 0 for a frozen env or an empty slot of the tile (which must not
 // touch the LDS it aliases).
+__device__ __forceinline__ void block_bodies(const EnvCtx& c, int blk, int& a, int& b) {
+    if (blk < c.lay.nj) {
+        const int* J = reinterpret_cast<const int*>(jrec(c, blk));
+        a = J[J_PA];
+        b = J[J_CH];
+    } else {
+        int f, cnt;
+        man_header(c, blk - c.lay.nj, a, b, f, cnt);
+    }
+}
 __device__ __forceinline__ void build_body_lists(const EnvCtx& c, int nn, int nman, int li, int G) {
     const Lay& l = c.lay;
     const int n = nn;
+    const int nb = l.nj + nman;   // blocks: joints, then manifolds
     int* OFF = iptr(c.L + l.CAND);
     uint16_t* ENT = reinterpret_cast<uint16_t*>(OFF + l.n + 1);
     const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
@@ -1525,9 +1536,9 @@ __device__ __forceinline__ void build_body_lists(const EnvCtx& c, int nn, int nm
     for (int i = li; i < n; i += G) {
         int deg = 0;
         if (is_dyn(c, i)) {
-            for (int p = 0; p < nman; ++p) {
-                int a, b, f, cnt;
-                man_header(c, int(ORD[p]), a, b, f, cnt);
+            for (int p = 0; p < nb; ++p) {
+                int a, b;
+                block_bodies(c, int(ORD[p]), a, b);
                 deg += (a == i ? 1 : 0) + (b == i ? 1 : 0);
             }
         }
@@ -1542,12 +1553,12 @@ __device__ __forceinline__ void build_body_lists(const EnvCtx& c, int nn, int nm
     for (int i = li; i < n; i += G) {
         if (!is_dyn(c, i)) continue;
         int o = OFF[i];
-        for (int p = 0; p < nman; ++p) {
-            const int m = int(ORD[p]);
-            int a, b, f, cnt;
-            man_header(c, m, a, b, f, cnt);
-            if (a == i) ENT[o++] = uint16_t(m);
-            if (b == i) ENT[o++] = uint16_t(m | 0x8000);
+        for (int p = 0; p < nb; ++p) {
+            const int blk = int(ORD[p]);
+            int a, b;
+            block_bodies(c, blk, a, b);
+            if (a == i) ENT[o++] = uint16_t(blk);
+            if (b == i) ENT[o++] = uint16_t(blk | 0x8000);
         }
     }
 }
@@ -1558,26 +1569,29 @@ __device__ __forceinline__ void build_body_lists(const EnvCtx& c, int nn, int nm
 __device__ __forceinline__ void build_body_lists_wave(const EnvCtx& c, int nn, int nman_in, int li) {
     const Lay& l = c.lay;
     const int n = __builtin_amdgcn_readfirstlane(nn);
-    const int nman = __builtin_amdgcn_readfirstlane(nman_in);
+    const int nman = __builtin_amdgcn_readfirstlane(l.nj + nman_in);   // blocks: joints, then manifolds
     int* OFF = iptr(c.L + l.CAND);
     uint16_t* ENT = reinterpret_cast<uint16_t*>(OFF + l.n + 1);
     const uint16_t* ORD = reinterpret_cast<const uint16_t*>(c.L + l.ORDER);
-    // (manifold << 16) | a | b << 8 of colour position r * 64 + li; 0xFFFF never matches a body
-    int hd[3];
+    // (block << 16) | a | b << 8 of colour position r * 64 + li (a = 0xFF for the world or the
+    // ground); 0xFFFF never matches a body
+    int hd[4];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const int p = r * WAVE + li;
         int w = 0xFFFF;
         if (p < nman) {
-            const int m = int(ORD[p]);
-            w = (iptr(c.L + l.MAN + m * M_WORDS)[M_AB] & 0xFFFF) | (m << 16);
+            const int blk = int(ORD[p]);
+            int a, b;
+            block_bodies(c, blk, a, b);
+            w = (a < 0 ? 0xFF : a) | (b << 8) | (blk << 16);
         }
         hd[r] = w;
     }
     const bool mine = li < n && is_dyn(c, li);
     int deg = 0;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const int kend = min(WAVE, nman - r * WAVE);
         for (int k = 0; k < kend; ++k) {
             const int w = __builtin_amdgcn_readlane(hd[r], k);
@@ -1596,7 +1610,7 @@ __device__ __forceinline__ void build_body_lists_wave(const EnvCtx& c, int nn, i
     if (li == 0 && n > 0) OFF[0] = 0;
     int o = incl - deg;
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const int kend = min(WAVE, nman - r * WAVE);
         for (int k = 0; k < kend; ++k) {
             const int w = __builtin_amdgcn_readlane(hd[r], k);
@@ -1605,6 +1619,43 @@ __device__ __forceinline__ void build_body_lists_wave(const EnvCtx& c, int nn, i
             if (mine && ((w >> 8) & 0xFF) == li) ENT[o++] = uint16_t(m | 0x8000);
         }
     }
+}
+
+// Warm-start impulses of manifold m (points first .. first + cnt - 1) applied to one of its bodies
+// (side B adds, side A subtracts), as the coloured warm sweep applies them to that body.
+__device__ __forceinline__ void warm_manifold(const EnvCtx& c, int m, int first, int cnt, bool sideB, float im,
+                                              const S6& I, V3& v, V3& w) {
+    const int rrow = sideB ? R_RB : R_RA;
+    const int mrow = sideB ? M_RB : M_RA;
+    // every row of the block is read before any arithmetic (one LDS round trip); the
+    // rows past the block's count lie inside the env's region and are not used
+    float ln[4];
+    V3 nq[4], rq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = first + k;
+        ln[k] = pr(c, R_LN, q);
+        nq[k] = pr3(c, R_N, q);
+        rq[k] = pr3(c, rrow, q);
+    }
+    const V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m), mr = mf3(c, mrow, m);
+    const float lt1 = mf(c, M_LT1, m), lt2 = mf(c, M_LT2, m), ltw = mf(c, M_LTW, m);
+    // side A receives the negated impulses; negating the multiplier negates every product
+    // and sum below exactly, so adding them equals subtracting the unnegated ones
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < cnt) {
+            const V3 P = (sideB ? ln[k] : -ln[k]) * nq[k];
+            v = v + im * P;
+            w = w + muls(I, cross3(rq[k], P));
+        }
+    }
+    const V3 t2 = cross3(nb, t1);
+    const V3 P = (sideB ? lt1 : -lt1) * t1 + (sideB ? lt2 : -lt2) * t2;
+    const V3 L = (sideB ? ltw : -ltw) * nb;
+    v = v + im * P;
+    w = w + muls(I, cross3(mr, P));
+    w = w + muls(I, L);
 }
 
 // Gravity and damping of one dynamic body for a substep, then (after the first substep) its
@@ -1632,39 +1683,45 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
             const int first = fc & 0xFFFF, cnt = fc >> 16;
             const int ent_next = ENT[e + 1 < e1 ? e + 1 : e];
             const int fc_next = iptr(c.L + l.MAN + (ent_next & 0x7FFF) * M_WORDS)[M_FC];
-            const int rrow = sideB ? R_RB : R_RA;
-            const int mrow = sideB ? M_RB : M_RA;
-            // every row of the block is read before any arithmetic (one LDS round trip); the
-            // rows past the block's count lie inside the env's region and are not used
-            float ln[4];
-            V3 nq[4], rq[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int q = first + k;
-                ln[k] = pr(c, R_LN, q);
-                nq[k] = pr3(c, R_N, q);
-                rq[k] = pr3(c, rrow, q);
-            }
-            const V3 t1 = mf3(c, M_T1, m), nb = mf3(c, M_NB, m), mr = mf3(c, mrow, m);
-            const float lt1 = mf(c, M_LT1, m), lt2 = mf(c, M_LT2, m), ltw = mf(c, M_LTW, m);
-            // side A receives the negated impulses; negating the multiplier negates every product
-            // and sum below exactly, so adding them equals subtracting the unnegated ones
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (k < cnt) {
-                    const V3 P = (sideB ? ln[k] : -ln[k]) * nq[k];
-                    v = v + im * P;
-                    w = w + muls(I, cross3(rq[k], P));
-                }
-            }
-            const V3 t2 = cross3(nb, t1);
-            const V3 P = (sideB ? lt1 : -lt1) * t1 + (sideB ? lt2 : -lt2) * t2;
-            const V3 L = (sideB ? ltw : -ltw) * nb;
-            v = v + im * P;
-            w = w + muls(I, cross3(mr, P));
-            w = w + muls(I, L);
+            warm_manifold(c, m, first, cnt, sideB, im, I, v, w);
             ent = ent_next;
             fc = fc_next;
+        }
+    }
+    stv(c, i, v);
+    stw(c, i, w);
+}
+
+// Warm start of one dynamic body of a wavefront with joints, after the substep's joint pass: the
+// accumulated impulses of its blocks in colour order, joints as joint_warm and manifolds as the
+// manifold warm start apply them to this body (side A with negated multipliers, which is exact).
+__device__ __forceinline__ void body_warm_gather(const EnvCtx& c, int i) {
+    const Lay& l = c.lay;
+    V3 v = ldv(c, i), w = ldw(c, i);
+    const float im = body_rec(c, i)[B_IM];
+    const S6 I = load_iw(c, i);
+    const int* OFF = iptr(c.L + l.CAND);
+    const uint16_t* ENT = reinterpret_cast<const uint16_t*>(OFF + l.n + 1);
+    for (int e = OFF[i]; e < OFF[i + 1]; ++e) {
+        const int ent = ENT[e];
+        const int blk = ent & 0x7FFF;
+        const bool sideB = (ent >> 15) != 0;
+        if (blk < l.nj) {
+            const float* P = jinv(c, blk);
+            const float* J = jrec(c, blk);
+            const V3 r = jv3(P, sideB ? JI_RB : JI_RA), zA = jv3(P, JI_ZA), b1 = jv3(P, JI_B1), b2 = jv3(P, JI_B2);
+            const V3 lp = sideB ? v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]) : v3(-J[J_LP], -J[J_LP + 1], -J[J_LP + 2]);
+            const float la0 = sideB ? J[J_LA] : -J[J_LA], la1 = sideB ? J[J_LA + 1] : -J[J_LA + 1];
+            const float ld = sideB ? J[J_LD] : -J[J_LD];
+            v = v + im * lp;
+            w = w + muls(I, cross3(r, lp));
+            w = w + muls(I, la0 * b1 + la1 * b2);
+            w = w + muls(I, ld * zA);
+        } else {
+            const int m = blk - l.nj;
+            int a, b, first, cnt;
+            man_header(c, m, a, b, first, cnt);
+            warm_manifold(c, m, first, cnt, sideB, im, I, v, w);
         }
     }
     stv(c, i, v);
@@ -2312,8 +2369,9 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             // --------------------------------------------------------- S6 substeps
             const float ldmp = 1.0f / (1.0f + h * bd.lin_damp);
             const float admp = 1.0f / (1.0f + h * bd.ang_damp);
-            // joint-free waves warm-start body by body (fused with gravity); others sweep colours
-            if (pipe && S > 1) {
+            // warm start body by body: fused with gravity in joint-free waves, after the joint pass
+            // in the others
+            if (S > 1) {
                 if (G == WAVE) build_body_lists_wave(c, nn, nmanA, li);
                 else build_body_lists(c, nn, nmanA, li, G);
                 wave_sync();
@@ -2325,7 +2383,11 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 bias_pass(c, nmanA, h, false, li, G);
                 for (int j = li; j < (frozen ? 0 : nj); j += G) joint_prep(c, j, h);
                 wave_sync();
-                if (s > 0 && !pipe) run_schedule<OP_WARM, false>(c, l.SCHED, ns, ns_max, h, li);
+                if (s > 0 && !pipe) {   // waves with joints: gathered per body once the joint pass has run
+                    for (int i = li; i < nn; i += G)
+                        if (is_dyn(c, i)) body_warm_gather(c, i);
+                    wave_sync();
+                }
                 for (int it = 0; it < K; ++it) {
                     for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
                     (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
