@@ -960,7 +960,7 @@ __device__ __forceinline__ JFrame joint_frame(const EnvCtx& c, int j) {
 // record, so they stay fixed through the colour sweeps of a substep (poses change only when the
 // substep integrates): anchors and frame axes, the adjugate and determinant of the point block,
 // the position error, the angular block and its errors, the drive's softness terms.  joint_prep
-// stores them once per substep; joint_warm / joint_solve read them.  Same operations in the same
+// stores them once per substep; the warm start and joint_solve read them.  Same operations in the same
 // order as computing them inside every visit.
 enum { JI_RA = 0, JI_RB = 3, JI_ZA = 6, JI_B1 = 9, JI_B2 = 12, JI_ADJ = 15, JI_DET = 24, JI_CP = 25, JI_C1 = 28,
        JI_C2 = 29, JI_K11 = 30, JI_K12 = 31, JI_K22 = 32, JI_DET2 = 33, JI_GAM = 34, JI_KG = 35, JI_BCH = 36,
@@ -1046,19 +1046,6 @@ __device__ __forceinline__ void joint_prep(const EnvCtx& c, int j, float h) {
         P[JI_KG] = k + gamma;
         P[JI_BCH] = beta_d * C / h;
     }
-}
-
-__device__ __forceinline__ void joint_warm(const EnvCtx& c, int j) {
-    const float* P = jinv(c, j);
-    const float* J = jrec(c, j);
-    const int a = reinterpret_cast<const int*>(J)[J_PA], b = reinterpret_cast<const int*>(J)[J_CH];
-    const V3 rA = jv3(P, JI_RA), rB = jv3(P, JI_RB), zA = jv3(P, JI_ZA), b1 = jv3(P, JI_B1), b2 = jv3(P, JI_B2);
-    BodyR A = load_body(c, a), B = load_body(c, b);
-    imp_lin(A, B, rA, rB, v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]));
-    imp_ang(A, B, J[J_LA] * b1 + J[J_LA + 1] * b2);
-    imp_ang(A, B, J[J_LD] * zA);
-    store_body(c, a, A);
-    store_body(c, b, B);
 }
 
 __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, bool vpass) {
@@ -1302,21 +1289,6 @@ __device__ __forceinline__ void man_bodies(const EnvCtx& c, const ManPre& p, Bod
     B.im = p.imb; B.I = p.Ib; B.dyn = p.db;
 }
 
-// Warm start of a manifold block: re-apply its accumulated impulses (normal rows in point order,
-// then the two tangent rows and the twist row).
-__device__ __forceinline__ void man_warm_pre(const EnvCtx& c, const ManPre& p) {
-    BodyR A, B;
-    man_bodies(c, p, A, B);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (k < p.cnt) imp_lin(A, B, p.rA[k], p.rB[k], p.ln[k] * p.n[k]);
-    V3 t2 = cross3(p.nb, p.t1);
-    imp_lin(A, B, p.mrA, p.mrB, p.lt1 * p.t1 + p.lt2 * t2);
-    imp_ang(A, B, p.ltw * p.nb);
-    store_body(c, p.a, A);
-    store_body(c, p.b, B);
-}
-
 // One Gauss-Seidel visit of a manifold block: normal rows in point order (bias of the substep,
 // clamped accumulated impulse), then the friction
 // patch: two tangent rows and the twist row, clamped by mu and mu * r_t times the normal sum.
@@ -1507,12 +1479,13 @@ __device__ __forceinline__ void bias_pass(const EnvCtx& c, int nman, float h, bo
     }
 }
 
-// Per-body block lists for the warm start (envs without joints): for every dynamic body, the
-// manifolds touching it in colour order with the body's side.  A body sits in at most one block
-// per colour, and a warm-start impulse does not depend on any velocity, so applying a body's
-// blocks in this order reproduces, bit for bit, what the coloured warm sweep does to that body.
+// Per-body block lists for the warm start: for every dynamic body, the blocks (joints, then
+// manifolds, numbered as in the schedule) touching it in colour order with the body's side.  A
+// body sits in at most one block per colour, and a warm-start impulse does not depend on any
+// velocity, so applying a body's blocks in this order reproduces, bit for bit, what a coloured
+// warm sweep (every block of a colour applying its impulses to both bodies) does to that body.
 // Built once per step (after colouring) in the candidate area: offsets [n + 1] ints, then u16
-// entries (manifold | side << 15).
+// entries (block | side << 15).
 // nn: the env's body count, 0 for a frozen env or an empty slot of the tile (which must not
 // touch the LDS it aliases).
 __device__ __forceinline__ void block_bodies(const EnvCtx& c, int blk, int& a, int& b) {
@@ -1693,8 +1666,9 @@ __device__ __forceinline__ void body_substep_start(const EnvCtx& c, int i, float
 }
 
 // Warm start of one dynamic body of a wavefront with joints, after the substep's joint pass: the
-// accumulated impulses of its blocks in colour order, joints as joint_warm and manifolds as the
-// manifold warm start apply them to this body (side A with negated multipliers, which is exact).
+// accumulated impulses of its blocks in colour order: a joint's point impulse at its arm, its
+// two angular-block impulses about the frame axes and its drive impulse about the joint axis; a
+// manifold's as warm_manifold (side A with negated multipliers, which is exact).
 __device__ __forceinline__ void body_warm_gather(const EnvCtx& c, int i) {
     const Lay& l = c.lay;
     V3 v = ldv(c, i), w = ldw(c, i);
@@ -1728,7 +1702,7 @@ __device__ __forceinline__ void body_warm_gather(const EnvCtx& c, int i) {
     stw(c, i, w);
 }
 
-enum { OP_WARM = 0, OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
+enum { OP_SOLVE = 1, OP_VSOLVE = 2, OP_REST = 3, OP_JOINT = 4 };
 
 // Block of this lane at schedule entry e (-1: none).
 __device__ __forceinline__ int sched_block(const EnvCtx& c, int sched_off, int nsched, int e, int li) {
@@ -1740,8 +1714,8 @@ __device__ __forceinline__ int sched_block(const EnvCtx& c, int sched_off, int n
 }
 
 // One sweep over a schedule: entry by entry (colour order), each lane visiting its block of the
-// entry, a wavefront sync between entries.  A manifold block of a warm or solve sweep runs from
-// its rows loaded in one batch; when no env of the wave has joints (PIPE) the rows of a lane's
+// entry, a wavefront sync between entries.  A manifold block of a solve sweep runs from its rows
+// loaded in one batch; when no env of the wave has joints (PIPE) the rows of a lane's
 // next block are loaded at the end of the current entry, behind the compute of this one.
 template <int OP, bool PIPE>
 __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int nsched, int emax, float h, int li) {
@@ -1759,7 +1733,7 @@ __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int
         }
         return;
     }
-    constexpr bool PRE = OP == OP_WARM || OP == OP_SOLVE || OP == OP_VSOLVE;
+    constexpr bool PRE = OP == OP_SOLVE || OP == OP_VSOLVE;
     constexpr bool SOLVE = OP == OP_SOLVE || OP == OP_VSOLVE;
     int blk = sched_block(c, sched_off, nsched, 0, li);
     ManPre pre;
@@ -1767,14 +1741,12 @@ __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int
     for (int e = 0; e < emax; ++e) {
         if (blk >= 0) {
             if (!PIPE && blk < l.nj) {
-                if (OP == OP_WARM) joint_warm(c, blk);
-                else if (OP == OP_SOLVE || OP == OP_JOINT) joint_solve(c, blk, h, false);
+                if (OP == OP_SOLVE || OP == OP_JOINT) joint_solve(c, blk, h, false);
                 else if (OP == OP_VSOLVE) joint_solve(c, blk, h, true);
             } else {
                 const int m = blk - l.nj;
                 if (!PIPE && PRE) man_prefetch<SOLVE>(c, m, pre);
-                if (OP == OP_WARM) man_warm_pre(c, pre);
-                else if (OP == OP_SOLVE || OP == OP_VSOLVE) man_solve_pre(c, m, pre);
+                if (OP == OP_SOLVE || OP == OP_VSOLVE) man_solve_pre(c, m, pre);
                 else if (OP == OP_REST) manifold_restitution(c, m);
             }
         }
