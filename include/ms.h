@@ -208,7 +208,9 @@ ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds
  * workgroup, kernel variant (0 unconstrained, 1 two waves per SIMD, 2 and 3 the same two built
  * for tiles that hold one env on all 64 lanes; a class runs its one-env tiles with 2 or 3 and its
  * other tiles with 0 or 1, and the value reported is the first), lanes per env, first tile}
- * into host_classes (may be NULL). */
+ * into host_classes (may be NULL).  With launch_mode 0 a plan of several classes runs as one
+ * launch of bins; the classes still describe its tiles' LDS sizes, and ms_get_plan reports the
+ * bins (grid = number of bins, LDS bytes per bin). */
 ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes);
 
 /* Autotuner.  First the env tiling: for every group of envs that the planner gave the same
