@@ -603,7 +603,7 @@ template <class T> inline void narrow_plane(Out<T>& o, T pz, const Shape<T>& B, 
 // Manifold reduction to at most 4 points: deepest; farthest from it; largest triangle; the point
 // adding the most area outside the triangle.  Lowest index wins every tie.  Kept points stay in
 // their original order.
-template <class T> inline void reduce4(Out<T>& o) {
+template <class T> inline void reduce4(Out<T>& o, int* picked = nullptr) {
     if (o.n <= 4) return;
     int n = o.n;
     bool used[16] = {false};
@@ -645,6 +645,7 @@ template <class T> inline void reduce4(Out<T>& o) {
         if (k3 < 0 || best > b3) { b3 = best; k3 = k; }
     }
     used[k3] = true;
+    if (picked) { picked[0] = k0; picked[1] = k1; picked[2] = k2; picked[3] = k3; }
     int m = 0;
     for (int k = 0; k < n; ++k) if (used[k]) o.pt[m++] = o.pt[k];
     o.n = m;
@@ -1524,6 +1525,20 @@ int or_narrow(int shape_a, const double* dims_a, const double* pose_a, int shape
         r[6] = o.pt[k].s;
     }
     *decision = o.decision;
+    return o.n;
+}
+
+// Manifold reduction of n <= 16 points (double [n][4] = p, s; normal +z) for the pins: writes
+// the indices picked in selection order (deepest, farthest, largest triangle, largest added
+// area) to picked[4] and returns the number of points kept (picked is untouched when n <= 4).
+int or_reduce4(const double* pts, int n, int32_t* picked) {
+    Out<double> o;
+    o.n = n < 16 ? n : 16;
+    for (int k = 0; k < o.n; ++k) o.pt[k] = Pt<double>{mk(pts[4 * k], pts[4 * k + 1], pts[4 * k + 2]), mk(0.0, 0.0, 1.0),
+                                                       pts[4 * k + 3]};
+    int pk[4] = {-1, -1, -1, -1};
+    reduce4(o, pk);
+    for (int k = 0; k < 4; ++k) picked[k] = pk[k];
     return o.n;
 }
 

@@ -24,21 +24,22 @@ COUNTER_NAMES = ["pairs_tested", "candidates", "points", "manifolds", "colours",
                  "joints"] + [f"kind{k}" for k in range(12)]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with g++ (-O2, no FP contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def build(force: bool = False, out: str = _LIB, extra=()) -> str:
+    """Compile the oracle with g++ (-O2, no FP contraction); `extra` adds flags (sanitizers)."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-pthread", "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-pthread", *extra, "-o", tmp, _SRC])
+        os.replace(tmp, out)
+    return out
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        # MS_ORACLE_LIB names an alternative build of the same source (the sanitizer test)
+        path = os.environ.get("MS_ORACLE_LIB") or build()
+        L = C.CDLL(path)
         P = C.c_void_p
         L.or_create.restype = P
         L.or_create.argtypes = [P, C.c_int, P, P, P, P, C.c_int]
@@ -57,6 +58,8 @@ def lib():
         L.or_narrow.restype = C.c_int
         L.or_narrow.argtypes = [C.c_int, P, P, C.c_int, P, P, C.c_double, P, P]
         L.or_box_box_sat.argtypes = [P, P, P, P, P, P]
+        L.or_reduce4.restype = C.c_int
+        L.or_reduce4.argtypes = [P, C.c_int, P]
         assert L.or_n_counters() == N_COUNTERS
         _lib = L
     return _lib
@@ -171,3 +174,13 @@ def box_box_sat(dims_a, pose_a, dims_b, pose_b):
     valid = np.zeros(15, np.int32)
     lib().or_box_box_sat(*[_ptr(a) for a in arrs], _ptr(sep), _ptr(valid))
     return sep, valid.astype(bool)
+
+
+def reduce4(points, s):
+    """Manifold reduction of a point list (float64 [n, 3] positions, [n] separations, normal +z):
+    the indices picked in selection order (deepest, farthest from it, largest triangle, largest
+    added area; [-1] * 4 when n <= 4) and the number of points kept."""
+    p = np.ascontiguousarray(np.column_stack([np.asarray(points, np.float64), np.asarray(s, np.float64)]))
+    picked = np.zeros(4, np.int32)
+    n = lib().or_reduce4(_ptr(p), len(p), _ptr(picked))
+    return [int(x) for x in picked], n
