@@ -6,7 +6,11 @@ seeded.  A step is one ms_step call advancing all 4096 envs by one dt: load from
 boxes, candidate pairs, narrowphase, contact rows, colouring, 8 substeps of the coloured
 Gauss-Seidel solve with integration, store.  W untimed warm-up steps, then exactly K timed steps
 bracketed by device synchronisation; HIP events on the launch stream time every launch (p50 /
-p99) and the whole region.
+p99) and the whole region.  Before the warm-up every workload first runs --settle untimed steps
+(default 200 = 1 s of simulated time for the tray) from the generator state, so the timed window
+is the contact-rich, settled phase of the scene whatever --steps / --warmup are; the line names
+the window.  The warm-up and timed steps of the headline sit inside a profiler region
+(roctxProfilerResume / Pause), so `rocprofv3 --selected-regions` traces exactly them.
 
 The line also carries:
   * roofline: the step kernel against the chip's FP32 vector peak; achieved = algorithmic FLOP
@@ -66,6 +70,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--settle", type=int, default=200,
+                    help="untimed steps from the generator state before the warm-up (contact-rich window)")
     ap.add_argument("--workload", default="tray")
     ap.add_argument("--envs", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
@@ -80,9 +86,52 @@ def parse():
     return ap.parse_args()
 
 
-def time_batch(batch, steps, warmup, spl, targets=None):
+class _Region:
+    """roctxProfilerResume / roctxProfilerPause around the timed steps (a no-op without the
+    library): under `rocprofv3 --selected-regions` only the region is traced."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(os.path.join("/opt/rocm/lib", name))
+                break
+            except OSError:
+                continue
+        if self.lib is not None:
+            # roctx_thread_id_t is 64-bit; 0 = the calling thread
+            for f in ("roctxProfilerResume", "roctxProfilerPause"):
+                getattr(self.lib, f).argtypes = [ctypes.c_uint64]
+                getattr(self.lib, f).restype = None
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+
+REGION = _Region()
+
+
+def settle(batch, steps, spl=10, targets=None):
+    """Untimed steps from the generator state into the settled, contact-rich phase."""
+    done = 0
+    while done < steps:
+        k = min(spl, steps - done)
+        batch.step(k, targets)
+        done += k
+
+
+def time_batch(batch, steps, warmup, spl, targets=None, region=False):
     import numpy as np
     import torch
+    torch.cuda.synchronize()
+    if region:
+        REGION.resume()
     for _ in range(max(1, warmup // spl)):
         batch.step(spl, targets)
     torch.cuda.synchronize()
@@ -97,10 +146,13 @@ def time_batch(batch, steps, warmup, spl, targets=None):
         ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if region:
+        REGION.pause()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n_launch)])
     total_ms = ev[0].elapsed_time(ev[-1])
     st = batch.stats()
     return dict(total_ms=total_ms, wall_s=wall, n_steps=n_launch * spl, n_launch=n_launch,
+                n_warm=max(1, warmup // spl) * spl,
                 launch_ms=total_ms / n_launch, p50_ms=float(np.percentile(per, 50)) / spl,
                 p99_ms=float(np.percentile(per, 99)) / spl, stats=st)
 
@@ -139,6 +191,7 @@ def time_graph(batch, steps, warmup, per_graph=10, spl=1):
     import torch
     for _ in range(max(1, warmup)):
         batch.step(1)
+    n_warm = max(1, warmup)
     per_graph = max(1, per_graph // spl) * spl   # whole launches per replay
     g = batch.graph(spl, per_graph // spl)
     g.launch()
@@ -157,32 +210,38 @@ def time_graph(batch, steps, warmup, per_graph=10, spl=1):
     st = batch.stats()
     n_steps = n_rep * per_graph
     return dict(total_ms=total_ms, n_steps=n_steps, n_launch=n_steps // spl, launch_ms=total_ms / (n_steps // spl),
+                n_warm=n_warm + per_graph,
                 p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), stats=st)
 
 
-def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False):
+def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False, settle_steps=200,
+                 region=False):
+    """Settle, (tune,) warm up, then time; returns the scene, the raw timing and the summary."""
+    import torch
     sc = S.by_name(name, n_envs, seed=seed)
     b = ms.Batch(sc, lanes_per_env=lanes, pack=pack)
+    settle(b, settle_steps)
     if tune:
-        import torch
-        for _ in range(60):   # tune on a settled state (contacts formed), trials of 10 steps
-            b.step(1)
+        # tune on the settled state (trials of 10 steps), then time from that same state
+        saved = b.get_state()
         b.tune(10)
-        # then time from the initial state, like the untuned runs (same phase of the scene)
-        b.reset_envs(torch.arange(n_envs, dtype=torch.int32, device="cuda"))
-    r = time_graph(b, steps, warmup, spl=spl) if graph else time_batch(b, steps, warmup, spl)
+        b.reset_envs(torch.arange(n_envs, dtype=torch.int32, device="cuda"), saved)
+    r = time_graph(b, steps, warmup, spl=spl) if graph else time_batch(b, steps, warmup, spl, region=region)
     flop = algorithmic_flop(sc, r["stats"], sc.params)
     plan = b.plan()
     b.close()
     launches = r["n_launch"]
+    first = settle_steps + r["n_warm"] + 1
     return sc, r, dict(workload=name, envs=n_envs, bodies=sc.n_bodies, joints=sc.n_joints,
                        env_steps_per_s=n_envs * r["n_steps"] / (r["total_ms"] / 1e3), ms_per_step=r["total_ms"] / r["n_steps"],
                        p50_ms=r["p50_ms"], p99_ms=r["p99_ms"], flop_per_launch=flop / launches,
-                       tflops=flop / (r["total_ms"] / 1e3) / 1e12, tiles=plan["n_tiles"], lds_bytes=plan["lds_bytes"])
+                       tflops=flop / (r["total_ms"] / 1e3) / 1e12, tiles=plan["n_tiles"], lds_bytes=plan["lds_bytes"],
+                       timed_steps=f"{first}..{first + r['n_steps'] - 1}")
 
 
-def cpu_baseline(name, seed, budget_s=15.0):
-    """The float32 oracle on all host threads over a bounded sample of the same workload."""
+def cpu_baseline(name, seed, settle_steps=200, budget_s=15.0):
+    """The float32 oracle on all host threads over a bounded sample of the same workload, timed
+    in the same settled window as the GPU run (settle_steps untimed steps first)."""
     from oracle.oracle import Oracle
     from paper_2410_00425_amd import scenes as S
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -190,18 +249,18 @@ def cpu_baseline(name, seed, budget_s=15.0):
     n_env = 256
     sc = S.by_name(name, n_env, seed=seed)
     o = Oracle(sc, 32)
-    o.step(40, n_threads=threads)  # same warm-up as the GPU run
+    o.step(settle_steps, n_threads=threads)
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
         o.step(5, n_threads=threads)
         steps += 5
     dt = time.perf_counter() - t0
     return dict(value=n_env * steps / dt, unit="env-steps/s", cores=threads, kind="oracle",
-                sample=f"{n_env} {name} envs x {steps} steps after 40 warm-up steps (float32 oracle, "
-                       f"{threads} threads, {dt:.1f} s)")
+                sample=f"{n_env} {name} envs x {steps} steps ({settle_steps + 1}..{settle_steps + steps}) after "
+                       f"{settle_steps} untimed settling steps (float32 oracle, {threads} threads, {dt:.1f} s)")
 
 
-def cpu_variants(name, seed, budget_s=4.0):
+def cpu_variants(name, seed, settle_steps=200, budget_s=4.0):
     """The oracle at both precisions on one thread and on all host threads (short samples of the
     same workload), and the host CPU's model name."""
     from oracle.oracle import Oracle
@@ -220,7 +279,7 @@ def cpu_variants(name, seed, budget_s=4.0):
             n_env = 256 if th > 1 else 32
             sc = S.by_name(name, n_env, seed=seed)
             o = Oracle(sc, prec)
-            o.step(40, n_threads=th)
+            o.step(settle_steps, n_threads=th)
             steps, t0 = 0, time.perf_counter()
             while time.perf_counter() - t0 < budget_s:
                 o.step(2, n_threads=th)
@@ -228,7 +287,8 @@ def cpu_variants(name, seed, budget_s=4.0):
             dt = time.perf_counter() - t0
             o.close()
             out["runs"].append({"precision": f"f{prec}", "threads": th, "env_steps_per_s": n_env * steps / dt,
-                                "sample": f"{n_env} {name} envs x {steps} steps after 40 warm-up steps, {dt:.1f} s"})
+                                "sample": f"{n_env} {name} envs x {steps} steps after {settle_steps} settling steps, "
+                                          f"{dt:.1f} s"})
     return out
 
 
@@ -313,7 +373,7 @@ def main():
     from paper_2410_00425_amd import ms, scenes as S
     torch.cuda.init()
     sc, r, head = run_workload(ms, S, args.workload, args.envs, args.steps, args.warmup, args.steps_per_launch,
-                               args.seed, args.lanes)
+                               args.seed, args.lanes, settle_steps=args.settle, region=True)
     value = head["env_steps_per_s"]
     achieved = head["flop_per_launch"] / (r["launch_ms"] / 1e3)
     out = {
@@ -323,7 +383,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload} x {sc.n_envs} envs ({sc.n_bodies // sc.n_envs} bodies/env), "
                                f"dt {float(sc.params['dt'])}, {int(sc.params['pos_iters'])} TGS substeps, "
-                               f"{args.steps_per_launch} step(s) per launch",
+                               f"{args.steps_per_launch} step(s) per launch; timed steps {head['timed_steps']} "
+                               f"after {args.settle} untimed settling steps and {r['n_warm']} warm-up steps",
                    "envs": sc.n_envs, "bodies": sc.n_bodies, "tiles": head["tiles"], "lds_bytes": head["lds_bytes"]},
         "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
@@ -346,19 +407,22 @@ def main():
         # the padded baseline is the plain launch: one tile per env, one LDS size for all (pack=0)
         for name, n, pack in (("drop_boxes", 4096, 1), ("arm_cube", 1024, 1), ("hetero", 4096, 1),
                               ("hetero_padded", 4096, 0)):
-            _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed, pack=pack)
+            _, _, res = run_workload(ms, S, name, n, 100, 20, 1, args.seed, pack=pack, settle_steps=args.settle)
             extra[name] = res
         # the batched form with the autotuned tiling, its steps replayed from a captured graph
-        _, _, res = run_workload(ms, S, "hetero", 4096, 100, 20, 1, args.seed, tune=True, graph=True)
+        _, _, res = run_workload(ms, S, "hetero", 4096, 100, 20, 1, args.seed, tune=True, graph=True,
+                                 settle_steps=args.settle)
         extra["hetero_tuned_graph"] = res
         extra["hetero_speedup_vs_padded"] = extra["hetero"]["env_steps_per_s"] / extra["hetero_padded"]["env_steps_per_s"]
         extra["hetero_tuned_graph_speedup_vs_padded"] = (extra["hetero_tuned_graph"]["env_steps_per_s"] /
                                                          extra["hetero_padded"]["env_steps_per_s"])
         # persistent launches of one 60 Hz control step (2 steps of the 120 Hz simulation) each,
         # replayed from a graph: the batched form and, like for like, the padded form
-        _, _, res = run_workload(ms, S, "hetero", 4096, 100, 20, 2, args.seed, tune=True, graph=True)
+        _, _, res = run_workload(ms, S, "hetero", 4096, 100, 20, 2, args.seed, tune=True, graph=True,
+                                 settle_steps=args.settle)
         extra["hetero_tuned_graph_2spl"] = res
-        _, _, res = run_workload(ms, S, "hetero_padded", 4096, 100, 20, 2, args.seed, pack=0, graph=True)
+        _, _, res = run_workload(ms, S, "hetero_padded", 4096, 100, 20, 2, args.seed, pack=0, graph=True,
+                                 settle_steps=args.settle)
         extra["hetero_padded_graph_2spl"] = res
         extra["hetero_2spl_speedup_vs_padded_plain"] = (extra["hetero_tuned_graph_2spl"]["env_steps_per_s"] /
                                                                 extra["hetero_padded"]["env_steps_per_s"])
@@ -372,9 +436,10 @@ def main():
         out["roofline"]["frac_measured"] = out["roofline"]["achieved"] / pk["fp32_mul_add_tflops"]
         out["extra"] = extra
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, settle_steps=args.settle)
         if not args.quick:
-            out.setdefault("extra", {})["cpu_oracle_variants"] = cpu_variants(args.workload, args.seed)
+            out.setdefault("extra", {})["cpu_oracle_variants"] = cpu_variants(args.workload, args.seed,
+                                                                              settle_steps=args.settle)
     print(json.dumps(out), flush=True)
 
 

@@ -43,6 +43,7 @@ typedef enum {
 enum { MS_SPHERE = 0, MS_CAPSULE = 1, MS_BOX = 2 };
 enum { MS_BODY_STATIC = 1 };            /* zero inverse mass and inertia; never integrated */
 enum { MS_SOLVER_TGS = 0, MS_SOLVER_PGS = 1 };
+enum { MS_JOINT_REVOLUTE = 0, MS_JOINT_PRISMATIC = 1 };
 
 /* Per-env status bits written by the step (status[E], int32). */
 enum {
@@ -56,6 +57,7 @@ enum {
 /* Limits of the fused kernel. */
 #define MS_MAX_BODIES_PER_ENV 64
 #define MS_MAX_JOINTS_PER_ENV 64
+#define MS_MAX_BLOCKS_PER_ENV 256   /* joints + manifold capacity of one env */
 
 /* One rigid body.  Shape dims: sphere (r, -, -); capsule (r, half_len, -) with its axis along
  * body-local z and half_len = half the cylinder length; box (hx, hy, hz) half-extents.
@@ -78,7 +80,7 @@ typedef struct {
 /* One revolute joint about the z axis of its joint frame.  parent = -1 attaches the child to
  * the static world.  frame_* = (px, py, pz, qw, qx, qy, qz) in the body's local frame (the world
  * frame for parent = -1).  kp (N m / rad) and kd (N m s / rad) define the PD position drive
- * toward `target` (rad); kp = kd = 0 disables the drive.  76 bytes, no padding. */
+ * toward `target` (rad); kp = kd = 0 disables the drive.  92 bytes, no padding. */
 typedef struct {
     int32_t parent;
     int32_t child;
@@ -87,6 +89,10 @@ typedef struct {
     float kp;
     float kd;
     float target;
+    int32_t type;       /* MS_JOINT_REVOLUTE or MS_JOINT_PRISMATIC */
+    int32_t limited;    /* != 0: position limits [lower, upper] */
+    float lower;
+    float upper;
 } ms_joint_desc;
 
 /* A batch of envs in compressed form: env e owns bodies [env_body_off[e], env_body_off[e+1]) and
@@ -240,6 +246,8 @@ ms_status ms_destroy_batch(ms_batch* b);
  * synchronisation).  The graph reads dev_targets (J floats, may be NULL) at replay time, so the
  * caller may rewrite that buffer between replays; it must stay valid while the graph exists.
  * The graph holds no memset nodes.  A graph belongs to its batch: destroy it before the batch.
+ * ms_tune_batch re-plans the batch's tiles; a graph captured before it replays the old launch
+ * geometry, so ms_graph_launch then returns MS_E_STATE (destroy the graph and capture again).
  * Errors: invalid arguments or a failed capture return a status and leave nothing behind. */
 typedef struct ms_graph ms_graph;
 ms_status ms_graph_create(ms_batch* b, const float* dev_targets, int32_t steps_per_launch, int32_t n_launches,

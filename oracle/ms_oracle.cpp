@@ -45,6 +45,8 @@ struct JointDesc {
     int32_t parent, child;
     float frame_parent[7], frame_child[7];
     float kp, kd, target;
+    int32_t type, limited;
+    float lower, upper;
 };
 struct Params {
     float dt;
@@ -61,10 +63,11 @@ struct Params {
     int32_t max_manifolds_per_env;
 };
 static_assert(sizeof(BodyDesc) == 88, "body record layout");
-static_assert(sizeof(JointDesc) == 76, "joint record layout");
+static_assert(sizeof(JointDesc) == 92, "joint record layout");
 
 enum { SPHERE = 0, CAPSULE = 1, BOX = 2 };
 enum { STATIC = 1 };
+enum { REVOLUTE = 0, PRISMATIC = 1 };
 enum { ST_NONFINITE = 1, ST_CONTACT_OVERFLOW = 2, ST_COLOR_OVERFLOW = 4 };
 constexpr int PLANE_ID = 0xFFFF;
 constexpr int MAX_COLORS = 64;
@@ -179,9 +182,12 @@ template <class T> struct Body {
 };
 template <class T> struct Joint {
     int parent, child;
+    int type;      // REVOLUTE: rotation about the joint frame's z; PRISMATIC: translation along it
+    bool limited;  // position limits [lower, upper] (rad or m)
     V3<T> aA, aB;  // anchors in body frames
     Q<T> QA, QB;   // joint-frame rotations in body frames
     T kp, kd, target;
+    T lower, upper;
 };
 
 struct PairRec { int32_t env, a, b, npts, decision, kind; double margin, lt1, lt2, ltw, mu, rt; };
@@ -669,12 +675,16 @@ template <class T> struct Manifold {
     T mt1, mt2, mtw, mu, rt;
     T lt1, lt2, ltw;
 };
-template <class T> struct JState { T lp[3], la[2], ld; };
+// Accumulated joint impulses of a step: revolute lp = point block, la[0..1] = angular block;
+// prismatic lp[0..1] = the two rows across the slide axis, la[0..2] = the rotation lock; ld =
+// drive; ll = lower and upper limit rows.
+template <class T> struct JState { T lp[3], la[3], ld, ll[2]; };
 
 template <class T> struct Env {
     std::vector<Body<T>> bodies;
     std::vector<Joint<T>> joints;
     int status = 0;
+    std::vector<V3<T>> force;  // net contact force on each body, averaged over the last step
 };
 
 template <class T> struct StepCtx {
@@ -727,6 +737,71 @@ template <class T> inline V3<T> onb_t1(V3<T> n) {
     T a = T(-1) / (sg + n.z);
     T b = n.x * n.y * a;
     return mk<T>(T(1) + sg * n.x * n.x * a, sg * b, -sg * n.x);
+}
+
+// ----------------------------------------------------------------------------- random draws
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+// SC'11): ten rounds of the multiply-xor bijection on a 4 x 32-bit counter, the 2 x 32-bit key
+// bumped by the Weyl constants between rounds.
+inline void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = uint64_t(0xD2511F53u) * c0, p1 = uint64_t(0xCD9E8D57u) * c2;
+        const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0, n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = uint32_t(p1); c2 = n2; c3 = uint32_t(p0);
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+// A uniform in [0, 1) from the top 24 bits of a draw (exact in float and double).
+template <class T> inline T unit24(uint32_t x) { return T(x >> 8) * T(5.9604644775390625e-08); }
+
+// Reset draws of one env: stream (env, reset_count, purpose, index) under key = the seed.
+struct ResetStream {
+    uint32_t key[2], env, count;
+    void draw(uint32_t purpose, uint32_t index, uint32_t out[4]) const {
+        const uint32_t ctr[4] = {env, count, purpose, index};
+        philox4x32_10(ctr, key, out);
+    }
+};
+// A standard normal deviate approximated by the sum of 12 uniforms minus 6 (the Irwin-Hall
+// construction: mean 0, variance 1), from three consecutive blocks; summed in draw order.
+template <class T> inline T normal12(const ResetStream& rs, uint32_t purpose, uint32_t first_block) {
+    T sum = 0;
+    for (uint32_t b = 0; b < 3; ++b) {
+        uint32_t u[4];
+        rs.draw(purpose, first_block + b, u);
+        for (int k = 0; k < 4; ++k) sum = sum + unit24<T>(u[k]);
+    }
+    return sum - T(6);
+}
+// sin and cos of x in [-pi/2 - 0.2, pi/2 + 0.2] by their Taylor series to x^17 / x^18 (Horner in
+// x^2; truncation below 1e-11), from correctly rounded operations only.
+template <class T> inline T sin_series(T x) {
+    const T x2 = x * x;
+    T p = T(1) / T(355687428096000.0);                // 1 / 17!
+    p = T(-1) / T(1307674368000.0) + x2 * p;          // 1 / 15!
+    p = T(1) / T(6227020800.0) + x2 * p;              // 1 / 13!
+    p = T(-1) / T(39916800.0) + x2 * p;               // 1 / 11!
+    p = T(1) / T(362880.0) + x2 * p;                  // 1 / 9!
+    p = T(-1) / T(5040.0) + x2 * p;                   // 1 / 7!
+    p = T(1) / T(120.0) + x2 * p;                     // 1 / 5!
+    p = T(-1) / T(6.0) + x2 * p;                      // 1 / 3!
+    p = T(1) + x2 * p;
+    return x * p;
+}
+template <class T> inline T cos_series(T x) {
+    const T x2 = x * x;
+    T p = T(-1) / T(6402373705728000.0);              // 1 / 18!
+    p = T(1) / T(20922789888000.0) + x2 * p;          // 1 / 16!
+    p = T(-1) / T(87178291200.0) + x2 * p;            // 1 / 14!
+    p = T(1) / T(479001600.0) + x2 * p;               // 1 / 12!
+    p = T(-1) / T(3628800.0) + x2 * p;                // 1 / 10!
+    p = T(1) / T(40320.0) + x2 * p;                   // 1 / 8!
+    p = T(-1) / T(720.0) + x2 * p;                    // 1 / 6!
+    p = T(1) / T(24.0) + x2 * p;                      // 1 / 4!
+    p = T(-1) / T(2.0) + x2 * p;                      // 1 / 2!
+    return T(1) + x2 * p;
 }
 
 // Result of one env step for the test record.
@@ -975,11 +1050,15 @@ template <class T> struct Stepper {
         if (rec)
             for (int bidx = 0; bidx < int(colour.size()); ++bidx)
                 rec->blocks.push_back(BlockRec{env_id, bidx < nj ? 0 : 1, bidx < nj ? bidx : bidx - nj, colour[bidx]});
-        js.assign(nj, JState<T>{{0, 0, 0}, {0, 0}, 0});
+        js.assign(nj, JState<T>{{0, 0, 0}, {0, 0, 0}, 0, {0, 0}});
     }
 
     // ------------------------------------------------------------- joint block
-    struct JFrame { int a, b; V3<T> rA, rB, zA, b1, b2; };
+    // Frames of a joint from the current poses: arms rA = R(qA) aA, rB = R(qB) aB, the axes b1,
+    // b2, zA of the parent's joint frame (columns of R(qA QA)) and the anchors' separation
+    // d = (xB + rB) - (xA + rA).  A prismatic joint's parent arm reaches the child anchor,
+    // rA + d, so that its rows act at one point on both bodies.
+    struct JFrame { int a, b; V3<T> rA, rB, zA, b1, b2, d; };
     JFrame jframe(const Joint<T>& j) const {
         JFrame f;
         f.a = j.parent; f.b = j.child;
@@ -989,42 +1068,103 @@ template <class T> struct Stepper {
         f.rB = rotate(B.q, j.aB);
         M3<T> Ra = rotm(qmul(qa, j.QA));
         f.zA = col(Ra, 2); f.b1 = col(Ra, 0); f.b2 = col(Ra, 1);
+        f.d = (pos_of(f.b) + f.rB) - (pos_of(f.a) + f.rA);
+        if (j.type == PRISMATIC) f.rA = f.rA + f.d;
         return f;
     }
     V3<T> pos_of(int i) const { return i >= 0 ? E.bodies[i].x : mk<T>(0, 0, 0); }
     V3<T> lin_of(int i) const { return i >= 0 ? E.bodies[i].v : mk<T>(0, 0, 0); }
     V3<T> ang_of(int i) const { return i >= 0 ? E.bodies[i].w : mk<T>(0, 0, 0); }
 
-    // Drive error: twist of B's joint frame relative to A's about the joint axis, minus target.
-    T drive_error(const Joint<T>& j, T target) const {
+    // Joint position: the twist of the child's joint frame relative to the parent's about zA,
+    // 2 atan2(q_rel.z, q_rel.w) with q_rel.w >= 0 (revolute), or the anchors' separation along
+    // the slide axis, zA . d (prismatic).
+    T joint_pos(const Joint<T>& j, const JFrame& f) const {
+        if (j.type == PRISMATIC) return dot(f.zA, f.d);
         Q<T> qa = j.parent >= 0 ? E.bodies[j.parent].q : Q<T>{1, 0, 0, 0};
         Q<T> rel = qmul(qconj(qmul(qa, j.QA)), qmul(E.bodies[j.child].q, j.QB));
         if (rel.w < T(0)) rel = Q<T>{-rel.w, -rel.x, -rel.y, -rel.z};
-        T th = T(2) * atan2_pos(rel.z, rel.w);
-        T c = th - target;
+        return T(2) * atan2_pos(rel.z, rel.w);
+    }
+    // Drive error: joint position minus target; an angle is wrapped into (-pi, pi].
+    T drive_error(const Joint<T>& j, const JFrame& f, T target) const {
+        T c = joint_pos(j, f) - target;
+        if (j.type == PRISMATIC) return c;
         // wrap into (-pi, pi] with the exact IEEE remainder (non-finite stays non-finite)
         const T pi = T(3.14159265358979323846);
         c = std::remainder(c, T(2) * pi);
         if (c <= -pi) c = c + T(2) * pi;
         return c;
     }
+    // The joint's free axis zA as a row: inverse effective mass k of a unit impulse along it
+    // (angular for a revolute joint, linear at the arms for a prismatic one), the relative
+    // velocity along it, and the application of an impulse l along it (-l on A, +l on B).
+    T axis_k(const Joint<T>& j, const JFrame& f) const {
+        if (j.type == PRISMATIC) {
+            T k = invm(f.a) + invm(f.b);
+            if (f.a >= 0) { V3<T> c = cross(f.rA, f.zA); k = k + dot(c, mul(bv[f.a].Iw, c)); }
+            V3<T> c = cross(f.rB, f.zA);
+            return k + dot(c, mul(bv[f.b].Iw, c));
+        }
+        return dot(f.zA, mul(bv[f.b].Iw, f.zA)) + (f.a >= 0 ? dot(f.zA, mul(bv[f.a].Iw, f.zA)) : T(0));
+    }
+    T axis_vel(const Joint<T>& j, const JFrame& f) const {
+        if (j.type == PRISMATIC)
+            return dot(f.zA, (lin_of(f.b) + cross(ang_of(f.b), f.rB)) - (lin_of(f.a) + cross(ang_of(f.a), f.rA)));
+        return dot(f.zA, ang_of(f.b) - ang_of(f.a));
+    }
+    void axis_apply(const Joint<T>& j, const JFrame& f, T l) {
+        if (j.type == PRISMATIC) apply(f.a, f.b, f.rA, f.rB, l * f.zA);
+        else apply_ang(f.a, f.b, l * f.zA);
+    }
 
     void joint_warm(int ji) {
         const Joint<T>& j = E.joints[ji];
         JFrame f = jframe(j);
         JState<T>& s = js[ji];
-        apply(f.a, f.b, f.rA, f.rB, mk(s.lp[0], s.lp[1], s.lp[2]));
-        apply_ang(f.a, f.b, s.la[0] * f.b1 + s.la[1] * f.b2);
-        apply_ang(f.a, f.b, s.ld * f.zA);
+        if (j.type == PRISMATIC) {
+            apply(f.a, f.b, f.rA, f.rB, s.lp[0] * f.b1 + s.lp[1] * f.b2);
+            apply_ang(f.a, f.b, mk(s.la[0], s.la[1], s.la[2]));
+        } else {
+            apply(f.a, f.b, f.rA, f.rB, mk(s.lp[0], s.lp[1], s.lp[2]));
+            apply_ang(f.a, f.b, s.la[0] * f.b1 + s.la[1] * f.b2);
+        }
+        axis_apply(j, f, s.ld);
+        if (j.limited) axis_apply(j, f, s.ll[0] - s.ll[1]);
     }
 
-    void joint_solve(int ji, const T* targets, bool velocity_pass) {
-        const Joint<T>& j = E.joints[ji];
-        JFrame f = jframe(j);
-        JState<T>& st = js[ji];
-        const T beta = velocity_pass ? T(0) : T(P.joint_baumgarte);
+    // 3x3 solve lam = -K^-1 rhs by adjugate and determinant (no change when det = 0).
+    static bool solve3(const M3<T>& K, V3<T> rhs, V3<T>& lam) {
+        T c00 = K.m[1][1] * K.m[2][2] - K.m[1][2] * K.m[2][1];
+        T c01 = K.m[0][2] * K.m[2][1] - K.m[0][1] * K.m[2][2];
+        T c02 = K.m[0][1] * K.m[1][2] - K.m[0][2] * K.m[1][1];
+        T c10 = K.m[1][2] * K.m[2][0] - K.m[1][0] * K.m[2][2];
+        T c11 = K.m[0][0] * K.m[2][2] - K.m[0][2] * K.m[2][0];
+        T c12 = K.m[0][2] * K.m[1][0] - K.m[0][0] * K.m[1][2];
+        T c20 = K.m[1][0] * K.m[2][1] - K.m[1][1] * K.m[2][0];
+        T c21 = K.m[0][1] * K.m[2][0] - K.m[0][0] * K.m[2][1];
+        T c22 = K.m[0][0] * K.m[1][1] - K.m[0][1] * K.m[1][0];
+        T det = K.m[0][0] * c00 + K.m[0][1] * c10 + K.m[0][2] * c20;
+        if (det == T(0)) return false;
+        T id = T(1) / det;
+        lam = mk(-(c00 * rhs.x + c01 * rhs.y + c02 * rhs.z) * id, -(c10 * rhs.x + c11 * rhs.y + c12 * rhs.z) * id,
+                 -(c20 * rhs.x + c21 * rhs.y + c22 * rhs.z) * id);
+        return true;
+    }
+    // 2x2 symmetric solve (l1, l2) = -K^-1 (r1, r2) (no change when det = 0).
+    static bool solve2(T k11, T k12, T k22, T r1, T r2, T& l1, T& l2) {
+        T det = k11 * k22 - k12 * k12;
+        if (det == T(0)) return false;
+        T id = T(1) / det;
+        l1 = -(k22 * r1 - k12 * r2) * id;
+        l2 = -(-k12 * r1 + k11 * r2) * id;
+        return true;
+    }
+
+    // Revolute: the anchors coincide (3x3 point block) and the joint axes stay aligned (2 angular
+    // rows about b1, b2).
+    void revolute_lock(const Joint<T>& j, const JFrame& f, JState<T>& st, T beta) {
         const int a = f.a, b = f.b;
-        // point block (3 rows, solved together)
         {
             M3<T> K{};
             T im = invm(a) + invm(b);
@@ -1044,30 +1184,14 @@ template <class T> struct Stepper {
             };
             if (a >= 0) add_arm(f.rA, bv[a].Iw);
             add_arm(f.rB, bv[b].Iw);
-            V3<T> C = (pos_of(b) + f.rB) - (pos_of(a) + f.rA);
             V3<T> Cd = (lin_of(b) + cross(ang_of(b), f.rB)) - (lin_of(a) + cross(ang_of(a), f.rA));
-            V3<T> rhs = Cd + (beta / T(P.dt)) * C;
-            // K^-1 via adjugate / determinant
-            T c00 = K.m[1][1] * K.m[2][2] - K.m[1][2] * K.m[2][1];
-            T c01 = K.m[0][2] * K.m[2][1] - K.m[0][1] * K.m[2][2];
-            T c02 = K.m[0][1] * K.m[1][2] - K.m[0][2] * K.m[1][1];
-            T c10 = K.m[1][2] * K.m[2][0] - K.m[1][0] * K.m[2][2];
-            T c11 = K.m[0][0] * K.m[2][2] - K.m[0][2] * K.m[2][0];
-            T c12 = K.m[0][2] * K.m[1][0] - K.m[0][0] * K.m[1][2];
-            T c20 = K.m[1][0] * K.m[2][1] - K.m[1][1] * K.m[2][0];
-            T c21 = K.m[0][1] * K.m[2][0] - K.m[0][0] * K.m[2][1];
-            T c22 = K.m[0][0] * K.m[1][1] - K.m[0][1] * K.m[1][0];
-            T det = K.m[0][0] * c00 + K.m[0][1] * c10 + K.m[0][2] * c20;
-            if (det != T(0)) {
-                T id = T(1) / det;
-                V3<T> lam = mk(-(c00 * rhs.x + c01 * rhs.y + c02 * rhs.z) * id,
-                               -(c10 * rhs.x + c11 * rhs.y + c12 * rhs.z) * id,
-                               -(c20 * rhs.x + c21 * rhs.y + c22 * rhs.z) * id);
+            V3<T> rhs = Cd + (beta / T(P.dt)) * f.d;
+            V3<T> lam;
+            if (solve3(K, rhs, lam)) {
                 st.lp[0] = st.lp[0] + lam.x; st.lp[1] = st.lp[1] + lam.y; st.lp[2] = st.lp[2] + lam.z;
                 apply(a, b, f.rA, f.rB, lam);
             }
         }
-        // angular block (2 rows keeping the joint axes aligned)
         {
             Q<T> qb = qmul(E.bodies[b].q, j.QB);
             V3<T> zB = col(rotm(qb), 2);
@@ -1080,27 +1204,90 @@ template <class T> struct Stepper {
                 for (int q = 0; q < 3; ++q) Isum.m[p][q] = (a >= 0 ? bv[a].Iw.m[p][q] : T(0)) + bv[b].Iw.m[p][q];
             T k11 = dot(f.b1, mul(Isum, f.b1)), k12 = dot(f.b1, mul(Isum, f.b2)), k22 = dot(f.b2, mul(Isum, f.b2));
             T r1 = Cd1 + (beta / T(P.dt)) * C1, r2 = Cd2 + (beta / T(P.dt)) * C2;
-            T det = k11 * k22 - k12 * k12;
-            if (det != T(0)) {
-                T id = T(1) / det;
-                T l1 = -(k22 * r1 - k12 * r2) * id;
-                T l2 = -(-k12 * r1 + k11 * r2) * id;
+            T l1, l2;
+            if (solve2(k11, k12, k22, r1, r2, l1, l2)) {
                 st.la[0] = st.la[0] + l1; st.la[1] = st.la[1] + l2;
                 apply_ang(a, b, l1 * f.b1 + l2 * f.b2);
             }
         }
-        // PD drive as a soft row about the joint axis
+    }
+
+    // Prismatic: the rotation is locked (3 angular rows, error 2 vec(q_rel) in the parent's joint
+    // frame, q_rel.w >= 0) and the child anchor stays on the slide line (2 rows along b1, b2 at
+    // the arms rA + d and rB).
+    void prismatic_lock(const Joint<T>& j, const JFrame& f, JState<T>& st, T beta) {
+        const int a = f.a, b = f.b;
+        {
+            Q<T> qa = a >= 0 ? E.bodies[a].q : Q<T>{1, 0, 0, 0};
+            Q<T> rel = qmul(qconj(qmul(qa, j.QA)), qmul(E.bodies[b].q, j.QB));
+            if (rel.w < T(0)) rel = Q<T>{-rel.w, -rel.x, -rel.y, -rel.z};
+            V3<T> e = (T(2) * rel.x) * f.b1 + (T(2) * rel.y) * f.b2 + (T(2) * rel.z) * f.zA;
+            M3<T> K{};
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) K.m[p][q] = (a >= 0 ? bv[a].Iw.m[p][q] : T(0)) + bv[b].Iw.m[p][q];
+            V3<T> rhs = (ang_of(b) - ang_of(a)) + (beta / T(P.dt)) * e;
+            V3<T> lam;
+            if (solve3(K, rhs, lam)) {
+                st.la[0] = st.la[0] + lam.x; st.la[1] = st.la[1] + lam.y; st.la[2] = st.la[2] + lam.z;
+                apply_ang(a, b, lam);
+            }
+        }
+        {
+            const M3<T> Z{};
+            const M3<T>& IA = a >= 0 ? bv[a].Iw : Z;
+            const M3<T>& IB = bv[b].Iw;
+            V3<T> cA1 = cross(f.rA, f.b1), cA2 = cross(f.rA, f.b2), cB1 = cross(f.rB, f.b1), cB2 = cross(f.rB, f.b2);
+            T im = invm(a) + invm(b);
+            T k11 = (im + dot(cA1, mul(IA, cA1))) + dot(cB1, mul(IB, cB1));
+            T k12 = dot(cA1, mul(IA, cA2)) + dot(cB1, mul(IB, cB2));
+            T k22 = (im + dot(cA2, mul(IA, cA2))) + dot(cB2, mul(IB, cB2));
+            V3<T> vr = (lin_of(b) + cross(ang_of(b), f.rB)) - (lin_of(a) + cross(ang_of(a), f.rA));
+            T r1 = dot(f.b1, vr) + (beta / T(P.dt)) * dot(f.b1, f.d);
+            T r2 = dot(f.b2, vr) + (beta / T(P.dt)) * dot(f.b2, f.d);
+            T l1, l2;
+            if (solve2(k11, k12, k22, r1, r2, l1, l2)) {
+                st.lp[0] = st.lp[0] + l1; st.lp[1] = st.lp[1] + l2;
+                apply(a, b, f.rA, f.rB, l1 * f.b1 + l2 * f.b2);
+            }
+        }
+    }
+
+    void joint_solve(int ji, const T* targets, bool velocity_pass) {
+        const Joint<T>& j = E.joints[ji];
+        JFrame f = jframe(j);
+        JState<T>& st = js[ji];
+        const T beta = velocity_pass ? T(0) : T(P.joint_baumgarte);
+        if (j.type == PRISMATIC) prismatic_lock(j, f, st, beta);
+        else revolute_lock(j, f, st, beta);
+        // PD drive as a soft row along the free axis
         if (j.kp != T(0) || j.kd != T(0)) {
-            V3<T> ax = f.zA;
-            T k = dot(ax, mul(bv[b].Iw, ax)) + (a >= 0 ? dot(ax, mul(bv[a].Iw, ax)) : T(0));
+            T k = axis_k(j, f);
             T den = j.kd + h * j.kp;
             T gamma = T(1) / (h * den);
             T beta_d = h * j.kp / den;
-            T C = drive_error(j, targets[ji]);
-            T Cd = dot(ax, ang_of(b) - ang_of(a));
+            T C = drive_error(j, f, targets[ji]);
+            T Cd = axis_vel(j, f);
             T dl = -(Cd + beta_d * C / h + gamma * st.ld) / (k + gamma);
             st.ld = st.ld + dl;
-            apply_ang(a, b, dl * ax);
+            axis_apply(j, f, dl);
+        }
+        // Position limits: two one-sided rows along the free axis on the gaps s_lo = x - lower and
+        // s_hi = upper - x; speculative (bias s / h) while the gap is open, Baumgarte at the
+        // joint rate per step once it is closed, accumulated impulses >= 0.
+        if (j.limited) {
+            T k = axis_k(j, f);
+            T m = k > T(0) ? T(1) / k : T(0);
+            T x = joint_pos(j, f);
+            for (int side = 0; side < 2; ++side) {
+                T gap = side == 0 ? x - j.lower : j.upper - x;
+                T bias = gap > T(0) ? gap / h : (velocity_pass ? T(0) : (T(P.joint_baumgarte) / T(P.dt)) * gap);
+                T v = axis_vel(j, f);
+                if (side == 1) v = -v;
+                T nl = std::max(st.ll[side] - m * (v + bias), T(0));
+                T dl = nl - st.ll[side];
+                st.ll[side] = nl;
+                axis_apply(j, f, side == 0 ? dl : -dl);
+            }
         }
     }
 
@@ -1193,6 +1380,27 @@ template <class T> struct Stepper {
         }
     }
 
+    // Contact impulses of the step, per body (touch sensing): every substep's final multipliers
+    // are that substep's impulses (the warm start re-applies the previous substep's, the sweeps
+    // add to them), so the step's total is the sum over substeps 1 .. S-1 after their sweeps plus
+    // the final multipliers after the velocity and restitution passes.  Each addition takes the
+    // normal impulses of a body's points and the two tangent impulses of its friction patches
+    // (added on the B side, subtracted on the A side; manifolds in order, points before the
+    // patch).  The twist impulse is a torque and is left out.
+    void accumulate_forces() {
+        for (const Manifold<T>& m : mans) {
+            for (int k = 0; k < m.count; ++k) {
+                const CRow<T>& r = rows[m.first + k];
+                const V3<T> Pn = r.ln * r.n;
+                E.force[m.b] = E.force[m.b] + Pn;
+                if (m.a >= 0) E.force[m.a] = E.force[m.a] - Pn;
+            }
+            const V3<T> Pt = m.lt1 * m.t1 + m.lt2 * m.t2;
+            E.force[m.b] = E.force[m.b] + Pt;
+            if (m.a >= 0) E.force[m.a] = E.force[m.a] - Pt;
+        }
+    }
+
     void sweep(const T* targets, bool velocity_pass) {
         const int nj = int(E.joints.size());
         for (auto& ob : order) {
@@ -1215,6 +1423,7 @@ template <class T> struct Stepper {
         const T ld = T(1) / (T(1) + h * T(P.lin_damping));
         const T ad = T(1) / (T(1) + h * T(P.ang_damping));
         const int nj = int(E.joints.size());
+        E.force.assign(n, mk<T>(0, 0, 0));
         for (int s = 0; s < S; ++s) {
             for (int i = 0; i < n; ++i) {
                 Body<T>& b = E.bodies[i];
@@ -1234,6 +1443,7 @@ template <class T> struct Stepper {
                         if (ob.second < nj) joint_solve(ob.second, targets, false);
                 sweep(targets, false);
             }
+            if (s + 1 < S) accumulate_forces();
             for (int i = 0; i < n; ++i) {
                 Body<T>& b = E.bodies[i];
                 if (!b.dyn()) continue;
@@ -1259,6 +1469,14 @@ template <class T> struct Stepper {
             for (T v : vals) if (!std::isfinite(double(v))) bad = true;
         }
         if (bad) { E.bodies = saved; E.status |= ST_NONFINITE; }
+        // net contact force averaged over the step: the step's contact impulses / dt (zero when
+        // the step went non-finite)
+        if (bad) E.force.assign(n, mk<T>(0, 0, 0));
+        else {
+            accumulate_forces();
+            const T idt = T(1) / T(P.dt);
+            for (V3<T>& f : E.force) f = idt * f;
+        }
         if (rec) {
             for (const Manifold<T>& m : mans) {
                 PairRec& pr = rec->pairs[m.pair];
@@ -1286,7 +1504,71 @@ struct Handle {
     std::vector<Env<double>> ed;
     std::vector<float> targets;  // [total joints]
     std::vector<EnvRecord> recs;
+    std::vector<Env<float>> ef0;   // initial state (resets)
+    std::vector<Env<double>> ed0;
 };
+
+// Joint position (twist angle or slide) of joint j in env E's current state.
+template <class T> static T joint_position(const Params& P, Env<T>& E, int j) {
+    Stepper<T> st(P, E, nullptr, 0);
+    typename Stepper<T>::JFrame f = st.jframe(E.joints[j]);
+    return st.joint_pos(E.joints[j], f);
+}
+
+// Randomised reset of one env (the paper's reset randomisation: initial robot joint positions
+// drawn around a reference configuration, objects' planar position and yaw drawn uniformly).
+// From the initial state: every free dynamic body (the child of no joint) moves by
+// xy_half * (2u - 1) in x and in y and turns about the world z axis through its centre by
+// yaw_half * (2u - 1); every joint in index order takes the position q0 = q_init +
+// joint_sigma * N (N from normal12) and poses its child from its parent (forward kinematics);
+// all velocities are zero and the status is cleared; with targets_follow the joint's drive
+// target becomes q0.  Draws: body i uses block (env, count, 1, i); joint j blocks (env, count, 0,
+// 3j .. 3j + 2).  Returns -1 when a joint's parent is posed by a later joint.
+struct ResetNoise { float joint_sigma, xy_half, yaw_half; int32_t targets_follow; };
+template <class T> static int reset_env_random(const Params& P, Env<T>& E, Env<T>& init, int env_id,
+                                               const ResetNoise& nz, uint64_t seed, uint32_t count, float* targets) {
+    const int n = int(init.bodies.size()), nj = int(init.joints.size());
+    std::vector<int> is_child(n, 0), posed(n, 0);
+    for (const Joint<T>& j : init.joints) is_child[j.child] = 1;
+    for (int i = 0; i < n; ++i) posed[i] = !is_child[i];
+    for (const Joint<T>& j : init.joints) {
+        if (j.parent >= 0 && !posed[j.parent]) return -1;
+        posed[j.child] = 1;
+    }
+    std::vector<T> q_init(nj);
+    for (int j = 0; j < nj; ++j) q_init[j] = joint_position(P, init, j);
+    ResetStream rs{{uint32_t(seed & 0xFFFFFFFFu), uint32_t(seed >> 32)}, uint32_t(env_id), count};
+    E.bodies = init.bodies;
+    for (Body<T>& b : E.bodies) { b.v = mk<T>(0, 0, 0); b.w = mk<T>(0, 0, 0); }
+    for (int i = 0; i < n; ++i) {
+        Body<T>& b = E.bodies[i];
+        if (!b.dyn() || is_child[i]) continue;
+        uint32_t u[4];
+        rs.draw(1, uint32_t(i), u);
+        b.x.x = b.x.x + T(nz.xy_half) * (T(2) * unit24<T>(u[0]) - T(1));
+        b.x.y = b.x.y + T(nz.xy_half) * (T(2) * unit24<T>(u[1]) - T(1));
+        const T half = T(0.5) * (T(nz.yaw_half) * (T(2) * unit24<T>(u[2]) - T(1)));
+        b.q = qnormalize(qmul(Q<T>{cos_series(half), T(0), T(0), sin_series(half)}, b.q));
+    }
+    for (int j = 0; j < nj; ++j) {
+        const Joint<T>& J = E.joints[j];
+        const T q0 = q_init[j] + T(nz.joint_sigma) * normal12<T>(rs, 0, uint32_t(3 * j));
+        const Q<T> qp = J.parent >= 0 ? E.bodies[J.parent].q : Q<T>{1, 0, 0, 0};
+        const V3<T> xp = J.parent >= 0 ? E.bodies[J.parent].x : mk<T>(0, 0, 0);
+        const Q<T> qpf = qmul(qp, J.QA);
+        const Q<T> rot = J.type == PRISMATIC ? Q<T>{1, 0, 0, 0}
+                                             : Q<T>{cos_series(T(0.5) * q0), T(0), T(0), sin_series(T(0.5) * q0)};
+        Body<T>& c = E.bodies[J.child];
+        c.q = qnormalize(qmul(qmul(qpf, rot), qconj(J.QB)));
+        V3<T> anchor = xp + rotate(qp, J.aA);
+        if (J.type == PRISMATIC) anchor = anchor + q0 * col(rotm(qpf), 2);
+        c.x = anchor - rotate(c.q, J.aB);
+        if (nz.targets_follow && targets) targets[j] = float(q0);
+    }
+    E.status = 0;
+    E.force.assign(n, mk<T>(0, 0, 0));
+    return 0;
+}
 
 template <class T> static void load_env(Env<T>& E, const BodyDesc* bd, int nb, const JointDesc* jd, int nj) {
     E.bodies.resize(nb);
@@ -1315,8 +1597,12 @@ template <class T> static void load_env(Env<T>& E, const BodyDesc* bd, int nb, c
         j.aB = mk(T(d.frame_child[0]), T(d.frame_child[1]), T(d.frame_child[2]));
         j.QB = Q<T>{T(d.frame_child[3]), T(d.frame_child[4]), T(d.frame_child[5]), T(d.frame_child[6])};
         j.kp = T(d.kp); j.kd = T(d.kd); j.target = T(d.target);
+        j.type = d.type;
+        j.limited = d.limited != 0;
+        j.lower = T(d.lower); j.upper = T(d.upper);
     }
     E.status = 0;
+    E.force.assign(nb, mk<T>(0, 0, 0));
 }
 
 template <class T> static void run_env(Handle& H, std::vector<Env<T>>& envs, int e, int n_steps, bool record) {
@@ -1324,6 +1610,7 @@ template <class T> static void run_env(Handle& H, std::vector<Env<T>>& envs, int
     EnvRecord& R = H.recs[e];
     std::vector<T> tg(E.joints.size());
     for (size_t j = 0; j < tg.size(); ++j) tg[j] = T(H.targets[H.joint_off[e] + j]);
+    if (E.status & ST_NONFINITE) E.force.assign(E.bodies.size(), mk<T>(0, 0, 0));
     for (int s = 0; s < n_steps; ++s) {
         if (E.status & ST_NONFINITE) break;
         bool last = s == n_steps - 1;
@@ -1405,6 +1692,8 @@ void* or_create(const Params* p, int n_envs, const int32_t* body_off, const Body
     int nj = joint_off[n_envs];
     H->targets.resize(nj);
     for (int j = 0; j < nj; ++j) H->targets[j] = joints[j].target;
+    H->ef0 = H->ef;
+    H->ed0 = H->ed;
     return H;
 }
 
@@ -1486,6 +1775,71 @@ void or_env_counters(void* h, int64_t* out, double* min_margin) {
         for (int c = 0; c < N_CNT; ++c) out[int64_t(e) * N_CNT + c] = H->recs[e].cnt[c];
         min_margin[e] = H->recs[e].min_margin;
     }
+}
+
+// Randomised reset of the listed envs (noise = joint_sigma, xy_half, yaw_half); returns 0, or
+// -1 when an env's joints are not ordered parents first (nothing is changed then).
+int or_reset_random(void* h, const int32_t* env_ids, int n_ids, const float* noise, int targets_follow, uint64_t seed,
+                    uint32_t count) {
+    Handle* H = static_cast<Handle*>(h);
+    ResetNoise nz{noise[0], noise[1], noise[2], targets_follow};
+    for (int k = 0; k < n_ids; ++k) {
+        const int e = env_ids[k];
+        if (e < 0 || e >= H->n_envs) continue;
+        float* tg = H->targets.data() + H->joint_off[e];
+        int r = H->prec == 64 ? reset_env_random(H->P, H->ed[e], H->ed0[e], e, nz, seed, count, tg)
+                              : reset_env_random(H->P, H->ef[e], H->ef0[e], e, nz, seed, count, tg);
+        if (r != 0) return r;
+    }
+    return 0;
+}
+
+// Target delta joint position controller: target += clip(a, -1, 1) (high - low) / 2 per joint
+// (low / high per joint, or the scalars when the arrays are null), in float32 like the targets.
+void or_apply_actions(void* h, const float* actions, const float* low, const float* high, float lo, float hi) {
+    Handle* H = static_cast<Handle*>(h);
+    for (size_t j = 0; j < H->targets.size(); ++j) {
+        const float a = actions[j];
+        const float c = a < -1.0f ? -1.0f : (a > 1.0f ? 1.0f : a);
+        const float l = low ? low[j] : lo, u = high ? high[j] : hi;
+        H->targets[j] = H->targets[j] + c * (0.5f * (u - l));
+    }
+}
+void or_get_targets(void* h, float* out) {
+    Handle* H = static_cast<Handle*>(h);
+    std::copy(H->targets.begin(), H->targets.end(), out);
+}
+
+// Current joint positions [J] and net contact forces of the last step [3][B] (double).
+void or_joint_positions(void* h, double* out) {
+    Handle* H = static_cast<Handle*>(h);
+    for (int e = 0; e < H->n_envs; ++e)
+        for (int j = H->joint_off[e]; j < H->joint_off[e + 1]; ++j)
+            out[j] = H->prec == 64 ? joint_position(H->P, H->ed[e], j - H->joint_off[e])
+                                   : double(joint_position(H->P, H->ef[e], j - H->joint_off[e]));
+}
+void or_contact_forces(void* h, double* out) {
+    Handle* H = static_cast<Handle*>(h);
+    const int B = H->body_off[H->n_envs];
+    for (int e = 0; e < H->n_envs; ++e) {
+        const int nb = H->body_off[e + 1] - H->body_off[e];
+        for (int i = 0; i < nb; ++i) {
+            const int g = H->body_off[e] + i;
+            double f[3] = {0, 0, 0};
+            if (H->prec == 64) { const auto& v = H->ed[e].force[i]; f[0] = v.x; f[1] = v.y; f[2] = v.z; }
+            else { const auto& v = H->ef[e].force[i]; f[0] = v.x; f[1] = v.y; f[2] = v.z; }
+            out[g] = f[0]; out[B + g] = f[1]; out[2 * B + g] = f[2];
+        }
+    }
+}
+
+// The random-draw building blocks, exposed for the pins.
+void or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
+double or_sin_series(double x, int precision) { return precision == 64 ? sin_series<double>(x) : double(sin_series<float>(float(x))); }
+double or_cos_series(double x, int precision) { return precision == 64 ? cos_series<double>(x) : double(cos_series<float>(float(x))); }
+double or_normal12(uint64_t seed, uint32_t env, uint32_t count, uint32_t purpose, uint32_t first_block, int precision) {
+    ResetStream rs{{uint32_t(seed & 0xFFFFFFFFu), uint32_t(seed >> 32)}, env, count};
+    return precision == 64 ? normal12<double>(rs, purpose, first_block) : double(normal12<float>(rs, purpose, first_block));
 }
 
 // The drive's arctangent, exposed for the pins (float64 and float32).

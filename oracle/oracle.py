@@ -3,7 +3,7 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg use this module.  It
 loads ``liboracle.so`` built from ``ms_oracle.cpp`` with g++ (no GPU code, no shared source with
 the GPU library).  Descriptor arrays are the records produced by the input generators: the
-oracle reads them by byte layout (88-byte bodies, 76-byte joints, 88-byte parameters).
+oracle reads them by byte layout (88-byte bodies, 92-byte joints, 88-byte parameters).
 """
 from __future__ import annotations
 
@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "ms_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 76, 88
+BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 92, 88
 N_COUNTERS = 20
 COUNTER_NAMES = ["pairs_tested", "candidates", "points", "manifolds", "colours", "dynamic", "static",
                  "joints"] + [f"kind{k}" for k in range(12)]
@@ -60,6 +60,19 @@ def lib():
         L.or_box_box_sat.argtypes = [P, P, P, P, P, P]
         L.or_reduce4.restype = C.c_int
         L.or_reduce4.argtypes = [P, C.c_int, P]
+        L.or_reset_random.restype = C.c_int
+        L.or_reset_random.argtypes = [P, P, C.c_int, P, C.c_int, C.c_uint64, C.c_uint32]
+        L.or_apply_actions.argtypes = [P, P, P, P, C.c_float, C.c_float]
+        L.or_get_targets.argtypes = [P, P]
+        L.or_joint_positions.argtypes = [P, P]
+        L.or_contact_forces.argtypes = [P, P]
+        L.or_philox4x32_10.argtypes = [P, P, P]
+        L.or_sin_series.restype = C.c_double
+        L.or_sin_series.argtypes = [C.c_double, C.c_int]
+        L.or_cos_series.restype = C.c_double
+        L.or_cos_series.argtypes = [C.c_double, C.c_int]
+        L.or_normal12.restype = C.c_double
+        L.or_normal12.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
         assert L.or_n_counters() == N_COUNTERS
         _lib = L
     return _lib
@@ -138,6 +151,40 @@ class Oracle:
         return dict(pairs=pairs, margin=pm[:, 0].copy(), patch=pm[:, 1:].copy(), point_ids=ids, points=pts,
                     blocks=blocks)
 
+    def reset_random(self, env_ids, joint_sigma=0.0, xy_half=0.0, yaw_half=0.0, targets_follow=True, seed=0, count=0):
+        """Randomised reset of the listed envs (see reset_env_random in ms_oracle.cpp)."""
+        ids = np.ascontiguousarray(env_ids, dtype=np.int32)
+        nz = np.array([joint_sigma, xy_half, yaw_half], np.float32)
+        r = lib().or_reset_random(self._h, _ptr(ids), len(ids), _ptr(nz), 1 if targets_follow else 0, int(seed),
+                                  int(count))
+        if r != 0:
+            raise ValueError("joints are not ordered parents first")
+
+    def apply_actions(self, actions, low=None, high=None, lo=-1.0, hi=1.0):
+        """Target delta controller: targets += clip(a, -1, 1) (high - low) / 2."""
+        a = np.ascontiguousarray(actions, dtype=np.float32)
+        assert a.shape == (self.n_joints,)
+        lw = None if low is None else np.ascontiguousarray(low, dtype=np.float32)
+        hg = None if high is None else np.ascontiguousarray(high, dtype=np.float32)
+        lib().or_apply_actions(self._h, _ptr(a), _ptr(lw) if lw is not None else None,
+                               _ptr(hg) if hg is not None else None, float(lo), float(hi))
+
+    def targets(self):
+        out = np.zeros(self.n_joints, np.float32)
+        lib().or_get_targets(self._h, _ptr(out))
+        return out
+
+    def joint_positions(self):
+        out = np.zeros(self.n_joints)
+        lib().or_joint_positions(self._h, _ptr(out))
+        return out
+
+    def contact_forces(self):
+        """Net contact force on every body over the last step's last substep, [3, B]."""
+        out = np.zeros((3, self.n_bodies))
+        lib().or_contact_forces(self._h, _ptr(out))
+        return out
+
     def counters(self):
         """Per-env work counters of the last step (int64 [E, N_COUNTERS]) and minimum margins."""
         out = np.zeros((self.n_envs, N_COUNTERS), np.int64)
@@ -184,3 +231,23 @@ def reduce4(points, s):
     picked = np.zeros(4, np.int32)
     n = lib().or_reduce4(_ptr(p), len(p), _ptr(picked))
     return [int(x) for x in picked], n
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def sin_series(x, precision=64):
+    return lib().or_sin_series(float(x), precision)
+
+
+def cos_series(x, precision=64):
+    return lib().or_cos_series(float(x), precision)
+
+
+def normal12(seed, env, count, purpose, first_block, precision=64):
+    return lib().or_normal12(int(seed), int(env), int(count), int(purpose), int(first_block), precision)

@@ -16,8 +16,10 @@ constexpr int N_COLOURS = 64;  // colours 0..63 are parallel; colour 64 is the s
 //   p1 = {dim0, dim1, dim2, 0}
 //   p2 = {principal inverse inertia x, y, z, 0}
 // Joint record in HBM: JREC floats per joint: parent, child (int bits), anchor A (3), frame
-// rotation A (4), anchor B (3), frame rotation B (4), kp, kd.
-constexpr int JREC = 18;
+// rotation A (4), anchor B (3), frame rotation B (4), kp, kd, type | limited << 8 (int bits),
+// lower, upper, 0.
+constexpr int JREC = 22;
+enum { JOINT_REVOLUTE = 0, JOINT_PRISMATIC = 1 };
 
 // One batch as the kernels see it (device memory, read by every tile of the batch).
 struct BatchDev {
@@ -47,8 +49,8 @@ struct BatchDev {
     float* dbg_man;        // [sum mcap_e][8]: pair index, colour, lt1, lt2, ltw, mu, rt, count
     const int* dbg_man_off;
     int* dbg_counts;       // [E][4]: candidates, points, manifolds, colours
-    // work counters, accumulated over launches: [E][NSTAT] (see STAT_*)
-    int* stats;
+    // work counters, accumulated over launches in 64 bits: [E][NSTAT] (see STAT_*)
+    long long* stats;
 };
 
 // Work counters per env: steps, candidate pairs per shape kind (3 * min + max shape for body
@@ -116,8 +118,8 @@ __host__ __device__ inline Lay make_lay(int n, int nj, int cap, int mcap) {
     L.CM = o; o += 2 * n;  // colour masks (u64)
     L.JM = o; o += 2 * n;  // jointed-partner masks (u64)
     // 55 n words so far
-    L.JNT = o; o += 26 * nj;
-    L.JINV = o; o += 39 * nj;   // per-joint quantities fixed within a substep
+    L.JNT = o; o += 31 * nj;    // joint records (J_WORDS)
+    L.JINV = o; o += 40 * nj;   // per-joint quantities fixed within a substep (JI_WORDS)
 
     // candidate pairs (u16) during S2-S4; afterwards the per-body block lists (offsets [n + 1],
     // entries u16 [2 (nj + mcap)])

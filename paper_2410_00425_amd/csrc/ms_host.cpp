@@ -10,10 +10,14 @@
 #include <mutex>
 #include <string>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "ms.h"
 #include "ms_dev.h"
+
+static_assert(sizeof(ms_body_desc) == 88 && sizeof(ms_joint_desc) == 92 && sizeof(ms_sim_params) == 88,
+              "descriptor layouts are part of the ABI");
 
 using namespace msdev;
 
@@ -173,6 +177,16 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
         if (nj < 0 || nj > MS_MAX_JOINTS_PER_ENV)
             return fail(MS_E_CAPACITY, "env %d has %d joints (0..%d supported)", e, nj, MS_MAX_JOINTS_PER_ENV);
         if (nj > 0 && !s->joints) return fail(MS_E_INVALID_ARG, "null joints array");
+        {
+            // solver blocks (joints + manifolds) of one env: the one-env warm-start lists hold
+            // their headers in 4 registers of 64 lanes
+            int n_dyn = 0;
+            for (int i = 0; i < nb; ++i) n_dyn += (s->bodies[s->env_body_off[e] + i].flags & MS_BODY_STATIC) ? 0 : 1;
+            const int mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(3 * n_dyn + 4, 192);
+            if (nj + mcap > MS_MAX_BLOCKS_PER_ENV)
+                return fail(MS_E_CAPACITY, "env %d: %d joints + %d manifolds exceed %d solver blocks per env", e, nj, mcap,
+                            MS_MAX_BLOCKS_PER_ENV);
+        }
         for (int i = 0; i < nb; ++i) {
             const ms_body_desc& b = s->bodies[s->env_body_off[e] + i];
             if (b.shape < MS_SPHERE || b.shape > MS_BOX) return fail(MS_E_INVALID_ARG, "env %d body %d: bad shape", e, i);
@@ -193,6 +207,15 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
                 return fail(MS_E_INVALID_ARG, "env %d joint %d: child must be dynamic", e, j);
             if (!std::isfinite(d.target) || !std::isfinite(d.kp) || !std::isfinite(d.kd) || d.kp < 0 || d.kd < 0)
                 return fail(MS_E_INVALID_ARG, "env %d joint %d: kp, kd must be finite and >= 0, target finite", e, j);
+            if (d.type != MS_JOINT_REVOLUTE && d.type != MS_JOINT_PRISMATIC)
+                return fail(MS_E_INVALID_ARG, "env %d joint %d: unknown joint type %d", e, j, d.type);
+            if (d.limited) {
+                const float lim = d.type == MS_JOINT_REVOLUTE ? 3.14159265f : 1e30f;
+                if (!std::isfinite(d.lower) || !std::isfinite(d.upper) || !(d.lower <= d.upper) || d.lower < -lim ||
+                    d.upper > lim)
+                    return fail(MS_E_INVALID_ARG, "env %d joint %d: limits need finite lower <= upper (within "
+                                "[-pi, pi] for a revolute joint)", e, j);
+            }
         }
     }
     return MS_OK;
@@ -318,7 +341,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.bins = take(E * sizeof(Bin));     // and for its bins
     L.tenv = take(pl.tenv.size() * sizeof(TileEnv));
     L.bd = take(sizeof(BatchDev));
-    L.stats = take(E * NSTAT * 4);
+    L.stats = take(E * NSTAT * 8);
     if (p->debug_export) {
         L.dbg_pairs = take(size_t(pl.dbg_pair_off[E]) * 16);
         L.dbg_pair_off = take((E + 1) * 4);
@@ -383,6 +406,9 @@ struct ms_batch {
     size_t lds_bytes = 0;
     bool pack = true;
     int max_resident_groups = 0;
+    // bumped whenever the tiles, bins or their launch geometry are rewritten (retile); a graph
+    // captured under another generation would replay stale launch geometry
+    uint64_t plan_gen = 0;
     // fork / join streams for LDS classes after the first (default priority)
     hipStream_t side[MAX_CLASSES] = {};
     hipEvent_t ev_fork = nullptr;
@@ -421,7 +447,7 @@ void fill_batchdev(ms_batch* b) {
     d.plane = p.plane_enabled ? 1 : 0;
     d.beta = p.baumgarte; d.max_depen = p.max_depen_vel; d.beta_j = p.joint_baumgarte; d.bounce = p.bounce_threshold;
     d.lin_damp = p.lin_damping; d.ang_damp = p.ang_damping;
-    d.stats = at<int>(w, L.stats);
+    d.stats = at<long long>(w, L.stats);
     if (p.debug_export) {
         d.dbg_pairs = at<int>(w, L.dbg_pairs); d.dbg_pair_off = at<int>(w, L.dbg_pair_off);
         d.dbg_pts = at<float>(w, L.dbg_pts); d.dbg_pt_off = at<int>(w, L.dbg_pt_off);
@@ -461,7 +487,7 @@ int ms_selfcheck(void) {
                     // cursors when there are no joints)
                     const int start[] = {L.JM, L.JNT, L.JINV, L.CAND, L.PT, L.MAN, L.BCOL, L.ORDER, L.SCHED,
                                          L.JSCHED, L.CSTART, L.SCAL};
-                    const int size[] = {2 * n, 26 * nj, 39 * nj, std::max((P + 1) / 2, n + 1 + nj + mcap), 14 * cap, 23 * mcap, (nj + mcap + 1) / 2,
+                    const int size[] = {2 * n, 31 * nj, 40 * nj, std::max((P + 1) / 2, n + 1 + nj + mcap), 14 * cap, 23 * mcap, (nj + mcap + 1) / 2,
                                         (nj + mcap + 1) / 2, nj + mcap + 66, nj > 0 ? nj + mcap + 66 : N_COLOURS + 1,
                                         N_COLOURS + 2, 32};
                     for (int r = 0; r < 12; ++r) {
@@ -594,6 +620,11 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
         for (int k = 0; k < 4; ++k) r[12 + k] = d.frame_child[3 + k];
         r[16] = d.kp;
         r[17] = d.kd;
+        const int tl = d.type | (d.limited ? 1 << 8 : 0);
+        std::memcpy(&r[18], &tl, 4);
+        r[19] = d.limited ? d.lower : 0.0f;
+        r[20] = d.limited ? d.upper : 0.0f;
+        r[21] = 0.0f;
         tg[j] = d.target;
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -614,8 +645,8 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     if (e == hipSuccess) e = up(L.ivel, &hs[7 * B], p3);
     if (e == hipSuccess) e = up(L.iang, &hs[10 * B], p3);
     if (e == hipSuccess) e = up(L.status, zeros.data(), E * 4);
-    std::vector<int> zstats(E * NSTAT, 0);
-    if (e == hipSuccess) e = up(L.stats, zstats.data(), E * NSTAT * 4);
+    std::vector<long long> zstats(E * NSTAT, 0);
+    if (e == hipSuccess) e = up(L.stats, zstats.data(), E * NSTAT * 8);
     if (e == hipSuccess) e = up(L.bpar, bp.data(), 3 * B * 16);
     if (e == hipSuccess) e = up(L.body_off, b->body_off.data(), (E + 1) * 4);
     if (e == hipSuccess) e = up(L.joint_off, b->joint_off.data(), (E + 1) * 4);
@@ -666,6 +697,7 @@ static ms_status retile(ms_batch* b, const std::vector<int>& lanes, hipStream_t 
     if (size_t(np.max_tile_words) * 4 > size_t(max_lds))
         return fail(MS_E_CAPACITY, "a tile would need %d bytes of LDS", np.max_tile_words * 4);
     b->plan = std::move(np);
+    b->plan_gen++;
     b->lds_bytes = size_t(b->plan.max_tile_words) * 4;
     const int n_tiles = int(b->plan.tiles.size());
     b->grid = b->max_resident_groups > 0 ? std::min(n_tiles, b->max_resident_groups) : n_tiles;
@@ -851,8 +883,8 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
     size_t o = L.save;
     for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + o, w + st_off[k], st_bytes[k], hipMemcpyDeviceToDevice, s)); o += st_bytes[k]; }
     HIP_OK(hipMemcpyAsync(w + o, w + L.status, E * 4, hipMemcpyDeviceToDevice, s));
-    std::vector<int> stats_save(E * NSTAT);
-    HIP_OK(hipMemcpyAsync(stats_save.data(), w + L.stats, E * NSTAT * 4, hipMemcpyDeviceToHost, s));
+    std::vector<long long> stats_save(E * NSTAT);
+    HIP_OK(hipMemcpyAsync(stats_save.data(), w + L.stats, E * NSTAT * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     auto restore = [&]() -> ms_status {
         size_t oo = L.save;
@@ -935,7 +967,7 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ms_status rs = restore();
-    HIP_OK(hipMemcpyAsync(w + L.stats, stats_save.data(), E * NSTAT * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(w + L.stats, stats_save.data(), E * NSTAT * 8, hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
     return st != MS_OK ? st : rs;
 }
@@ -946,13 +978,13 @@ ms_status ms_get_stats(ms_batch* b, int64_t* host_stats, int32_t reset, void* hi
     HIP_OK(hipStreamSynchronize(s));
     const size_t n = size_t(b->E) * NSTAT;
     if (host_stats) {
-        std::vector<int> tmp(n);
-        HIP_OK(hipMemcpy(tmp.data(), b->hbd.stats, n * 4, hipMemcpyDeviceToHost));
-        for (size_t k = 0; k < n; ++k) host_stats[k] = tmp[k];
+        std::vector<long long> tmp(n);
+        HIP_OK(hipMemcpy(tmp.data(), b->hbd.stats, n * 8, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < n; ++k) host_stats[k] = int64_t(tmp[k]);
     }
     if (reset) {
-        std::vector<int> z(n, 0);
-        HIP_OK(hipMemcpy(b->hbd.stats, z.data(), n * 4, hipMemcpyHostToDevice));
+        std::vector<long long> z(n, 0);
+        HIP_OK(hipMemcpy(b->hbd.stats, z.data(), n * 8, hipMemcpyHostToDevice));
     }
     return MS_OK;
 }
@@ -965,6 +997,7 @@ ms_status ms_destroy_batch(ms_batch* b) {
 // ----------------------------------------------------------------------------- fused multi-batch step
 struct ms_graph {
     ms_batch* b = nullptr;
+    uint64_t plan_gen = 0;   // the batch's plan generation at capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~ms_graph() {
@@ -986,6 +1019,7 @@ ms_status ms_graph_create(ms_batch* b, const float* dev_targets, int32_t steps_p
     HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     std::unique_ptr<ms_graph> g(new ms_graph());
     g->b = b;
+    g->plan_gen = b->plan_gen;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     ms_status st = e == hipSuccess ? MS_OK : fail(MS_E_DEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     if (st == MS_OK) {
@@ -1007,6 +1041,9 @@ ms_status ms_graph_create(ms_batch* b, const float* dev_targets, int32_t steps_p
 
 ms_status ms_graph_launch(ms_graph* g, void* hip_stream) {
     if (!g || !g->exec) return fail(MS_E_INVALID_ARG, "null graph");
+    if (g->plan_gen != g->b->plan_gen)
+        return fail(MS_E_STATE, "the batch was re-planned (ms_tune_batch) after this graph was captured: "
+                                "destroy the graph and capture it again");
     HIP_OK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream)));
     return MS_OK;
 }
@@ -1034,6 +1071,9 @@ ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, 
 namespace {
 // Pinned host staging for the combined work list, reused once the previous upload completed,
 // and the side streams of the LDS-class fork / join (one set per host thread and device).
+// The thread that loaded the library (the process's main thread in practice): its staging is
+// left to process exit, when the runtime may already be going away.
+const std::thread::id g_load_thread = std::this_thread::get_id();
 struct Staging {
     void* host = nullptr;
     size_t cap = 0;
@@ -1043,6 +1083,23 @@ struct Staging {
     hipStream_t side[MAX_CLASSES] = {};
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[MAX_CLASSES] = {};
+    // Wait for this thread's last upload and launches, then free its pinned buffer, events and
+    // side streams (a server worker thread's staging, when the worker exits).
+    void release() {
+        if (ev) { (void)hipEventSynchronize(ev); (void)hipEventDestroy(ev); ev = nullptr; }
+        for (int k = 0; k < MAX_CLASSES; ++k) {
+            if (side[k]) { (void)hipStreamSynchronize(side[k]); (void)hipStreamDestroy(side[k]); side[k] = nullptr; }
+            if (ev_join[k]) { (void)hipEventDestroy(ev_join[k]); ev_join[k] = nullptr; }
+        }
+        if (ev_fork) { (void)hipEventDestroy(ev_fork); ev_fork = nullptr; }
+        if (host) { (void)hipHostFree(host); host = nullptr; }
+        cap = 0;
+        pending = false;
+        device = -1;
+    }
+    ~Staging() {
+        if (std::this_thread::get_id() != g_load_thread) release();
+    }
 };
 thread_local Staging g_stage;
 
@@ -1069,14 +1126,8 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Staging& st = g_stage;
     if (st.device != dev) {
-        if (st.ev) { (void)hipEventSynchronize(st.ev); (void)hipEventDestroy(st.ev); st.ev = nullptr; }
-        for (int k = 0; k < MAX_CLASSES; ++k) {
-            if (st.side[k]) { (void)hipStreamSynchronize(st.side[k]); (void)hipStreamDestroy(st.side[k]); st.side[k] = nullptr; }
-            if (st.ev_join[k]) { (void)hipEventDestroy(st.ev_join[k]); st.ev_join[k] = nullptr; }
-        }
-        if (st.ev_fork) { (void)hipEventDestroy(st.ev_fork); st.ev_fork = nullptr; }
+        st.release();
         st.device = dev;
-        st.pending = false;
         HIP_OK(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
     }
     if (st.pending) { HIP_OK(hipEventSynchronize(st.ev)); st.pending = false; }

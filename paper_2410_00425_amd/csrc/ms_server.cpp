@@ -278,6 +278,9 @@ void ms_server::run() {
         ms_status st = ok ? ms_step_many(bl.data(), tg.data(), int32_t(bl.size()), k, arena, scratch_bytes, stream)
                           : MS_E_DEVICE;
         std::string err = st != MS_OK ? std::string(ms_last_error()) : std::string();
+        // a failed launch may still have queued the target copies from the pinned buffer: let
+        // the stream drain before that buffer is written or freed again
+        if (st != MS_OK) (void)hipStreamSynchronize(stream);
         if (st == MS_OK && (hipEventRecord(ev, stream) != hipSuccess || hipEventSynchronize(ev) != hipSuccess)) {
             st = MS_E_DEVICE;
             err = "event wait after the fused launch failed";

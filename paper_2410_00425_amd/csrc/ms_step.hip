@@ -101,10 +101,13 @@ enum { R_RA = 0, R_RB = 3, R_N = 6, R_MN = 9, R_S0 = 10, R_VN = 11, R_LN = 12, R
 // restitution 22.
 enum { M_AB = 0, M_FC = 1, M_RA = 2, M_RB = 5, M_NB = 8, M_T1 = 11, M_MT1 = 14, M_MT2 = 15, M_MTW = 16,
        M_MU = 17, M_RT = 18, M_LT1 = 19, M_LT2 = 20, M_LTW = 21, M_REST = 22 };
-// Joint record in LDS (26 words): parent, child, aA 2..4, QA 5..8, aB 9..11, QB 12..15, kp 16,
-// kd 17, target 18, lp 19..21, la 22..23, ld 24.
+// Joint record in LDS (31 words): parent, child, aA 2..4, QA 5..8, aB 9..11, QB 12..15, kp 16,
+// kd 17, target 18, accumulated impulses of the step: lp 19..21 (revolute point block; prismatic
+// rows across the slide axis in 19..20), la 22..24 (revolute angular block in 22..23; prismatic
+// rotation lock), ld 25 (drive), ll 26..27 (lower / upper limit); type | limited << 8 28 (int),
+// lower 29, upper 30.
 enum { J_PA = 0, J_CH = 1, J_AA = 2, J_QA = 5, J_AB = 9, J_QB = 12, J_KP = 16, J_KD = 17, J_TG = 18,
-       J_LP = 19, J_LA = 22, J_LD = 24, J_WORDS = 26 };
+       J_LP = 19, J_LA = 22, J_LD = 25, J_LL = 26, J_TYP = 28, J_LO = 29, J_HI = 30, J_WORDS = 31 };
 // Scalars.
 enum { SC_NCAND = 0, SC_NPTS = 1, SC_NMAN = 2, SC_NCOL = 3, SC_STATUS = 4, SC_NSCHED = 5, SC_NJSCHED = 6,
        SC_NDYN = 7 };
@@ -933,8 +936,15 @@ __device__ __forceinline__ float atan2_w(float y, float w) {
     return y < 0.0f ? -a : a;
 }
 
-struct JFrame { int a, b; V3 rA, rB, zA, b1, b2; Qt qa, qb; };
+// Frames of a joint from the current poses: arms rA = R(qA) aA, rB = R(qB) aB, the axes of the
+// parent's joint frame and the anchors' separation d = (xB + rB) - (xA + rA); a prismatic
+// joint's parent arm reaches the child anchor (rA + d).
+struct JFrame { int a, b; V3 rA, rB, zA, b1, b2, d; Qt qa, qb; };
 __device__ __forceinline__ float* jrec(const EnvCtx& c, int j) { return c.L + c.lay.JNT + J_WORDS * j; }
+__device__ __forceinline__ bool jprism(const float* J) {
+    return (reinterpret_cast<const int*>(J)[J_TYP] & 0xFF) == JOINT_PRISMATIC;
+}
+__device__ __forceinline__ bool jlimited(const float* J) { return (reinterpret_cast<const int*>(J)[J_TYP] >> 8) & 1; }
 __device__ __forceinline__ V3 x_of(const EnvCtx& c, int i) {
     return i < 0 ? v3(0, 0, 0) : ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
 }
@@ -953,6 +963,8 @@ __device__ __forceinline__ JFrame joint_frame(const EnvCtx& c, int j) {
     f.rB = mulv(rotm(f.qb), v3(J[J_AB], J[J_AB + 1], J[J_AB + 2]));
     M3 Ra = rotm(qmul(f.qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]}));
     f.zA = colm(Ra, 2); f.b1 = colm(Ra, 0); f.b2 = colm(Ra, 1);
+    f.d = (x_of(c, f.b) + f.rB) - (x_of(c, f.a) + f.rA);
+    if (jprism(J)) f.rA = f.rA + f.d;
     return f;
 }
 
@@ -962,24 +974,46 @@ __device__ __forceinline__ JFrame joint_frame(const EnvCtx& c, int j) {
 // the position error, the angular block and its errors, the drive's softness terms.  joint_prep
 // stores them once per substep; the warm start and joint_solve read them.  Same operations in the same
 // order as computing them inside every visit.
+// A revolute joint's 3x3 block is its point block (ADJ, DET, position error CP = d) and its 2x2
+// block the axis alignment (K11..DET2, errors C1, C2); a prismatic joint's 3x3 block is its
+// rotation lock (K = IA + IB, error CP = 2 vec(q_rel) in the world) and its 2x2 block the rows
+// across the slide axis (errors b1 . d, b2 . d).  Limits: MLIM = 1 / k of the free axis and the
+// gaps SLO = x - lower, SHI = upper - x.
 enum { JI_RA = 0, JI_RB = 3, JI_ZA = 6, JI_B1 = 9, JI_B2 = 12, JI_ADJ = 15, JI_DET = 24, JI_CP = 25, JI_C1 = 28,
        JI_C2 = 29, JI_K11 = 30, JI_K12 = 31, JI_K22 = 32, JI_DET2 = 33, JI_GAM = 34, JI_KG = 35, JI_BCH = 36,
-       JI_WORDS = 39 };
+       JI_MLIM = 37, JI_SLO = 38, JI_SHI = 39, JI_WORDS = 40 };
 __device__ __forceinline__ float* jinv(const EnvCtx& c, int j) { return c.L + c.lay.JINV + JI_WORDS * j; }
 __device__ __forceinline__ V3 jv3(const float* P, int o) { return v3(P[o], P[o + 1], P[o + 2]); }
 __device__ __forceinline__ void jst3(float* P, int o, V3 v) { P[o] = v.x; P[o + 1] = v.y; P[o + 2] = v.z; }
+
+// Adjugate (row-major) and determinant of a 3x3 matrix.
+__device__ __forceinline__ void adj3(const float K[3][3], float* A9, float& det) {
+    A9[0] = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+    A9[1] = K[0][2] * K[2][1] - K[0][1] * K[2][2];
+    A9[2] = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+    A9[3] = K[1][2] * K[2][0] - K[1][0] * K[2][2];
+    A9[4] = K[0][0] * K[2][2] - K[0][2] * K[2][0];
+    A9[5] = K[0][2] * K[1][0] - K[0][0] * K[1][2];
+    A9[6] = K[1][0] * K[2][1] - K[1][1] * K[2][0];
+    A9[7] = K[0][1] * K[2][0] - K[0][0] * K[2][1];
+    A9[8] = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+    det = K[0][0] * A9[0] + K[0][1] * A9[3] + K[0][2] * A9[6];
+}
 
 __device__ __forceinline__ void joint_prep(const EnvCtx& c, int j, float h) {
     JFrame f = joint_frame(c, j);
     const float* J = jrec(c, j);
     float* P = jinv(c, j);
     const int a = f.a, b = f.b;
+    const bool prism = jprism(J);
     const S6 Ia = a >= 0 ? load_iw(c, a) : S6{0, 0, 0, 0, 0, 0};
     const S6 Ib = load_iw(c, b);
     const float ima = invm_of(c, a), imb = invm_of(c, b);
     jst3(P, JI_RA, f.rA); jst3(P, JI_RB, f.rB); jst3(P, JI_ZA, f.zA); jst3(P, JI_B1, f.b1); jst3(P, JI_B2, f.b2);
-    // point block: K = (mA^-1 + mB^-1) I - [rA]x IA [rA]x - [rB]x IB [rB]x, its adjugate and determinant
-    {
+    const Qt qaf = qmul(f.qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]});
+    const Qt qbf = qmul(f.qb, Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
+    if (!prism) {
+        // point block: K = (mA^-1 + mB^-1) I - [rA]x IA [rA]x - [rB]x IB [rB]x, its adjugate and determinant
         float im = ima + imb;
         float K[3][3] = {{im, 0, 0}, {0, im, 0}, {0, 0, im}};
 #pragma unroll
@@ -999,22 +1033,9 @@ __device__ __forceinline__ void joint_prep(const EnvCtx& c, int j, float h) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) K[p][q] -= SI[p][0] * Sx[0][q] + SI[p][1] * Sx[1][q] + SI[p][2] * Sx[2][q];
         }
-        float* A9 = P + JI_ADJ;
-        A9[0] = K[1][1] * K[2][2] - K[1][2] * K[2][1];
-        A9[1] = K[0][2] * K[2][1] - K[0][1] * K[2][2];
-        A9[2] = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-        A9[3] = K[1][2] * K[2][0] - K[1][0] * K[2][2];
-        A9[4] = K[0][0] * K[2][2] - K[0][2] * K[2][0];
-        A9[5] = K[0][2] * K[1][0] - K[0][0] * K[1][2];
-        A9[6] = K[1][0] * K[2][1] - K[1][1] * K[2][0];
-        A9[7] = K[0][1] * K[2][0] - K[0][0] * K[2][1];
-        A9[8] = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-        P[JI_DET] = K[0][0] * A9[0] + K[0][1] * A9[3] + K[0][2] * A9[6];
-        jst3(P, JI_CP, (x_of(c, b) + f.rB) - (x_of(c, a) + f.rA));
-    }
-    // angular block: axis misalignment and the 2x2 block
-    {
-        Qt qbf = qmul(f.qb, Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
+        adj3(K, P + JI_ADJ, P[JI_DET]);
+        jst3(P, JI_CP, f.d);
+        // angular block: axis misalignment and the 2x2 block
         V3 zB = colm(rotm(qbf), 2);
         V3 zc = cross3(f.zA, zB);
         P[JI_C1] = dot3(f.b1, zc);
@@ -1023,28 +1044,89 @@ __device__ __forceinline__ void joint_prep(const EnvCtx& c, int j, float h) {
         float k11 = dot3(f.b1, muls(Is, f.b1)), k12 = dot3(f.b1, muls(Is, f.b2)), k22 = dot3(f.b2, muls(Is, f.b2));
         P[JI_K11] = k11; P[JI_K12] = k12; P[JI_K22] = k22;
         P[JI_DET2] = k11 * k22 - k12 * k12;
-    }
-    // drive: soft-row terms and the twist error wrapped into (-pi, pi]
-    float kp = J[J_KP], kd = J[J_KD];
-    if (kp != 0.0f || kd != 0.0f) {
-        V3 ax = f.zA;
-        float k = dot3(ax, muls(Ib, ax)) + (a >= 0 ? dot3(ax, muls(Ia, ax)) : 0.0f);
-        float den = kd + h * kp;
-        float gamma = 1.0f / (h * den);
-        float beta_d = h * kp / den;
-        Qt qa = qmul(f.qa, Qt{J[J_QA], J[J_QA + 1], J[J_QA + 2], J[J_QA + 3]});
-        Qt qbf = qmul(f.qb, Qt{J[J_QB], J[J_QB + 1], J[J_QB + 2], J[J_QB + 3]});
-        Qt rel = qmul(Qt{qa.w, -qa.x, -qa.y, -qa.z}, qbf);
+    } else {
+        // rotation lock: error 2 vec(q_rel) (q_rel.w >= 0) in the parent's joint frame, K = IA + IB
+        Qt rel = qmul(Qt{qaf.w, -qaf.x, -qaf.y, -qaf.z}, qbf);
         if (rel.w < 0.0f) rel = Qt{-rel.w, -rel.x, -rel.y, -rel.z};
-        float th = 2.0f * atan2_w(rel.z, rel.w);
-        float C = th - J[J_TG];
-        // wrap into (-pi, pi] with the exact IEEE remainder (non-finite stays non-finite)
-        const float pi = 3.14159265358979323846f;
-        C = remainderf(C, 2.0f * pi);
-        if (C <= -pi) C += 2.0f * pi;
-        P[JI_GAM] = gamma;
-        P[JI_KG] = k + gamma;
-        P[JI_BCH] = beta_d * C / h;
+        V3 e = (2.0f * rel.x) * f.b1 + (2.0f * rel.y) * f.b2 + (2.0f * rel.z) * f.zA;
+        float K[3][3] = {{Ia.xx + Ib.xx, Ia.xy + Ib.xy, Ia.xz + Ib.xz},
+                         {Ia.xy + Ib.xy, Ia.yy + Ib.yy, Ia.yz + Ib.yz},
+                         {Ia.xz + Ib.xz, Ia.yz + Ib.yz, Ia.zz + Ib.zz}};
+        adj3(K, P + JI_ADJ, P[JI_DET]);
+        jst3(P, JI_CP, e);
+        // the child anchor on the slide line: rows along b1, b2 at the arms rA + d and rB
+        const V3 cA1 = cross3(f.rA, f.b1), cA2 = cross3(f.rA, f.b2), cB1 = cross3(f.rB, f.b1), cB2 = cross3(f.rB, f.b2);
+        const float im = ima + imb;
+        const float k11 = (im + dot3(cA1, muls(Ia, cA1))) + dot3(cB1, muls(Ib, cB1));
+        const float k12 = dot3(cA1, muls(Ia, cA2)) + dot3(cB1, muls(Ib, cB2));
+        const float k22 = (im + dot3(cA2, muls(Ia, cA2))) + dot3(cB2, muls(Ib, cB2));
+        P[JI_K11] = k11; P[JI_K12] = k12; P[JI_K22] = k22;
+        P[JI_DET2] = k11 * k22 - k12 * k12;
+        P[JI_C1] = dot3(f.b1, f.d);
+        P[JI_C2] = dot3(f.b2, f.d);
+    }
+    // the free axis: drive (soft-row terms) and limits (effective mass, gaps)
+    const float kp = J[J_KP], kd = J[J_KD];
+    const bool drive = kp != 0.0f || kd != 0.0f, lim = jlimited(J);
+    if (drive || lim) {
+        const V3 ax = f.zA;
+        float k, x;
+        if (prism) {
+            k = ima + imb;
+            if (a >= 0) { V3 cc = cross3(f.rA, ax); k = k + dot3(cc, muls(Ia, cc)); }
+            V3 cc = cross3(f.rB, ax);
+            k = k + dot3(cc, muls(Ib, cc));
+            x = dot3(ax, f.d);
+        } else {
+            k = dot3(ax, muls(Ib, ax)) + (a >= 0 ? dot3(ax, muls(Ia, ax)) : 0.0f);
+            Qt rel = qmul(Qt{qaf.w, -qaf.x, -qaf.y, -qaf.z}, qbf);
+            if (rel.w < 0.0f) rel = Qt{-rel.w, -rel.x, -rel.y, -rel.z};
+            x = 2.0f * atan2_w(rel.z, rel.w);
+        }
+        if (drive) {
+            float den = kd + h * kp;
+            float gamma = 1.0f / (h * den);
+            float beta_d = h * kp / den;
+            float C = x - J[J_TG];
+            if (!prism) {
+                // wrap into (-pi, pi] with the exact IEEE remainder (non-finite stays non-finite)
+                const float pi = 3.14159265358979323846f;
+                C = remainderf(C, 2.0f * pi);
+                if (C <= -pi) C += 2.0f * pi;
+            }
+            P[JI_GAM] = gamma;
+            P[JI_KG] = k + gamma;
+            P[JI_BCH] = beta_d * C / h;
+        }
+        if (lim) {
+            P[JI_MLIM] = k > 0.0f ? 1.0f / k : 0.0f;
+            P[JI_SLO] = x - J[J_LO];
+            P[JI_SHI] = J[J_HI] - x;
+        }
+    }
+}
+
+// The two one-sided limit rows of a joint along its free axis (lower, then upper): speculative
+// while the gap is open (bias gap / h), Baumgarte at the joint rate per step once closed (none in
+// a velocity pass); accumulated impulses >= 0.
+__device__ __forceinline__ void joint_limits(const EnvCtx& c, int j, bool prism, BodyR& A, BodyR& B, bool has_a, V3 rA,
+                                             V3 rB, V3 ax, float h, float brate, bool vpass) {
+    const float* P = jinv(c, j);
+    float* J = jrec(c, j);
+    const float m = P[JI_MLIM];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const float gap = side == 0 ? P[JI_SLO] : P[JI_SHI];
+        const float bias = gap > 0.0f ? gap / h : (vpass ? 0.0f : brate * gap);
+        float v = prism ? dot3(ax, relv(A, B, has_a, rA, rB)) : dot3(ax, B.w - A.w);
+        if (side == 1) v = -v;
+        const float old = J[J_LL + side];
+        const float nl = fmaxf(old - m * (v + bias), 0.0f);
+        const float dl = nl - old;
+        J[J_LL + side] = nl;
+        const float l = side == 0 ? dl : -dl;
+        if (prism) imp_lin(A, B, rA, rB, l * ax);
+        else imp_ang(A, B, l * ax);
     }
 }
 
@@ -1053,13 +1135,15 @@ __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, boo
     const float* P = jinv(c, j);
     float* J = jrec(c, j);
     const int a = reinterpret_cast<const int*>(J)[J_PA], b = reinterpret_cast<const int*>(J)[J_CH];
+    const bool prism = jprism(J);
     const V3 rA = jv3(P, JI_RA), rB = jv3(P, JI_RB);
     const float brate = vpass ? 0.0f : bd.beta_j / bd.dt;
     BodyR A = load_body(c, a), B = load_body(c, b);
-    // point block
+    const bool has_a = a >= 0;
+    // 3x3 block: revolute point block (linear at the arms), prismatic rotation lock (angular)
     {
         V3 C = jv3(P, JI_CP);
-        V3 Cd = (B.v + cross3(B.w, rB)) - (A.v + cross3(A.w, rA));
+        V3 Cd = prism ? B.w - A.w : (B.v + cross3(B.w, rB)) - (A.v + cross3(A.w, rA));
         V3 rhs = Cd + brate * C;
         const float det = P[JI_DET];
         if (det != 0.0f) {
@@ -1067,15 +1151,27 @@ __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, boo
             float id = 1.0f / det;
             V3 lam = v3(-(A9[0] * rhs.x + A9[1] * rhs.y + A9[2] * rhs.z) * id, -(A9[3] * rhs.x + A9[4] * rhs.y + A9[5] * rhs.z) * id,
                         -(A9[6] * rhs.x + A9[7] * rhs.y + A9[8] * rhs.z) * id);
-            J[J_LP] += lam.x; J[J_LP + 1] += lam.y; J[J_LP + 2] += lam.z;
-            imp_lin(A, B, rA, rB, lam);
+            if (prism) {
+                J[J_LA] += lam.x; J[J_LA + 1] += lam.y; J[J_LA + 2] += lam.z;
+                imp_ang(A, B, lam);
+            } else {
+                J[J_LP] += lam.x; J[J_LP + 1] += lam.y; J[J_LP + 2] += lam.z;
+                imp_lin(A, B, rA, rB, lam);
+            }
         }
     }
-    // angular block: keep the joint axes aligned (2 rows)
+    // 2x2 block: revolute axis alignment (angular about b1, b2), prismatic rows across the slide
+    // axis (linear along b1, b2 at the arms)
     {
         const V3 b1 = jv3(P, JI_B1), b2 = jv3(P, JI_B2);
-        V3 dw = B.w - A.w;
-        float Cd1 = dot3(b1, dw), Cd2 = dot3(b2, dw);
+        float Cd1, Cd2;
+        if (prism) {
+            V3 vr = relv(A, B, has_a, rA, rB);
+            Cd1 = dot3(b1, vr); Cd2 = dot3(b2, vr);
+        } else {
+            V3 dw = B.w - A.w;
+            Cd1 = dot3(b1, dw); Cd2 = dot3(b2, dw);
+        }
         const float k11 = P[JI_K11], k12 = P[JI_K12], k22 = P[JI_K22];
         float r1 = Cd1 + brate * P[JI_C1], r2 = Cd2 + brate * P[JI_C2];
         float det = P[JI_DET2];
@@ -1083,19 +1179,26 @@ __device__ __forceinline__ void joint_solve(const EnvCtx& c, int j, float h, boo
             float id = 1.0f / det;
             float l1 = -(k22 * r1 - k12 * r2) * id;
             float l2 = -(-k12 * r1 + k11 * r2) * id;
-            J[J_LA] += l1; J[J_LA + 1] += l2;
-            imp_ang(A, B, l1 * b1 + l2 * b2);
+            if (prism) {
+                J[J_LP] += l1; J[J_LP + 1] += l2;
+                imp_lin(A, B, rA, rB, l1 * b1 + l2 * b2);
+            } else {
+                J[J_LA] += l1; J[J_LA + 1] += l2;
+                imp_ang(A, B, l1 * b1 + l2 * b2);
+            }
         }
     }
-    // PD drive: soft row about the joint axis
+    // PD drive: soft row along the free axis
+    const V3 ax = jv3(P, JI_ZA);
     float kp = J[J_KP], kd = J[J_KD];
     if (kp != 0.0f || kd != 0.0f) {
-        V3 ax = jv3(P, JI_ZA);
-        float Cd = dot3(ax, B.w - A.w);
+        float Cd = prism ? dot3(ax, relv(A, B, has_a, rA, rB)) : dot3(ax, B.w - A.w);
         float dl = -(Cd + P[JI_BCH] + P[JI_GAM] * J[J_LD]) / P[JI_KG];
         J[J_LD] += dl;
-        imp_ang(A, B, dl * ax);
+        if (prism) imp_lin(A, B, rA, rB, dl * ax);
+        else imp_ang(A, B, dl * ax);
     }
+    if (jlimited(J)) joint_limits(c, j, prism, A, B, has_a, rA, rB, ax, h, brate, vpass);
     store_body(c, a, A);
     store_body(c, b, B);
 }
@@ -1108,16 +1211,18 @@ struct JointPre {
     int a, b;
     V3 rA, rB, zA, b1, b2, CP, lp;
     float adj[9];
-    float det, C1, C2, k11, k12, k22, det2, gam, kg, bch, kp, kd, la0, la1, ld;
+    float det, C1, C2, k11, k12, k22, det2, gam, kg, bch, kp, kd, la0, la1, la2, ld;
     float ima, imb;
     S6 Ia, Ib;
-    bool da, db;
+    bool da, db, prism, lim;
 };
 __device__ __forceinline__ void joint_prefetch(const EnvCtx& c, int j, JointPre& q) {
     const float* P = jinv(c, j);
     const float* J = jrec(c, j);
     q.a = reinterpret_cast<const int*>(J)[J_PA];
     q.b = reinterpret_cast<const int*>(J)[J_CH];
+    q.prism = jprism(J);
+    q.lim = jlimited(J);
     q.rA = jv3(P, JI_RA); q.rB = jv3(P, JI_RB); q.zA = jv3(P, JI_ZA); q.b1 = jv3(P, JI_B1); q.b2 = jv3(P, JI_B2);
     q.CP = jv3(P, JI_CP);
 #pragma unroll
@@ -1126,15 +1231,16 @@ __device__ __forceinline__ void joint_prefetch(const EnvCtx& c, int j, JointPre&
     q.k11 = P[JI_K11]; q.k12 = P[JI_K12]; q.k22 = P[JI_K22]; q.det2 = P[JI_DET2];
     q.gam = P[JI_GAM]; q.kg = P[JI_KG]; q.bch = P[JI_BCH];
     q.kp = J[J_KP]; q.kd = J[J_KD];
-    q.lp = v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]); q.la0 = J[J_LA]; q.la1 = J[J_LA + 1]; q.ld = J[J_LD];
+    q.lp = v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]); q.la0 = J[J_LA]; q.la1 = J[J_LA + 1]; q.la2 = J[J_LA + 2]; q.ld = J[J_LD];
     q.da = is_dyn(c, q.a); q.db = is_dyn(c, q.b);
     q.ima = invm_of(c, q.a); q.imb = invm_of(c, q.b);
     q.Ia = q.a >= 0 ? load_iw(c, q.a) : S6{0, 0, 0, 0, 0, 0};
     q.Ib = load_iw(c, q.b);
 }
-__device__ __forceinline__ void joint_solve_pre(const EnvCtx& c, int j, const JointPre& q, float brate) {
+__device__ __forceinline__ void joint_solve_pre(const EnvCtx& c, int j, const JointPre& q, float brate, float h) {
     float* J = jrec(c, j);
     const int n = c.lay.n;
+    const bool has_a = q.a >= 0;
     BodyR A, B;
     if (q.a >= 0) { A.v = ldv(c, q.a); A.w = ldw(c, q.a); }
     else { A.v = v3(0, 0, 0); A.w = v3(0, 0, 0); }
@@ -1143,36 +1249,54 @@ __device__ __forceinline__ void joint_solve_pre(const EnvCtx& c, int j, const Jo
     A.im = q.ima; A.I = q.Ia; A.dyn = q.da;
     B.im = q.imb; B.I = q.Ib; B.dyn = q.db;
     {
-        V3 Cd = (B.v + cross3(B.w, q.rB)) - (A.v + cross3(A.w, q.rA));
+        V3 Cd = q.prism ? B.w - A.w : (B.v + cross3(B.w, q.rB)) - (A.v + cross3(A.w, q.rA));
         V3 rhs = Cd + brate * q.CP;
         if (q.det != 0.0f) {
             float id = 1.0f / q.det;
             V3 lam = v3(-(q.adj[0] * rhs.x + q.adj[1] * rhs.y + q.adj[2] * rhs.z) * id,
                         -(q.adj[3] * rhs.x + q.adj[4] * rhs.y + q.adj[5] * rhs.z) * id,
                         -(q.adj[6] * rhs.x + q.adj[7] * rhs.y + q.adj[8] * rhs.z) * id);
-            J[J_LP] = q.lp.x + lam.x; J[J_LP + 1] = q.lp.y + lam.y; J[J_LP + 2] = q.lp.z + lam.z;
-            imp_lin(A, B, q.rA, q.rB, lam);
+            if (q.prism) {
+                J[J_LA] = q.la0 + lam.x; J[J_LA + 1] = q.la1 + lam.y; J[J_LA + 2] = q.la2 + lam.z;
+                imp_ang(A, B, lam);
+            } else {
+                J[J_LP] = q.lp.x + lam.x; J[J_LP + 1] = q.lp.y + lam.y; J[J_LP + 2] = q.lp.z + lam.z;
+                imp_lin(A, B, q.rA, q.rB, lam);
+            }
         }
     }
     {
-        V3 dw = B.w - A.w;
-        float Cd1 = dot3(q.b1, dw), Cd2 = dot3(q.b2, dw);
+        float Cd1, Cd2;
+        if (q.prism) {
+            V3 vr = relv(A, B, has_a, q.rA, q.rB);
+            Cd1 = dot3(q.b1, vr); Cd2 = dot3(q.b2, vr);
+        } else {
+            V3 dw = B.w - A.w;
+            Cd1 = dot3(q.b1, dw); Cd2 = dot3(q.b2, dw);
+        }
         float r1 = Cd1 + brate * q.C1, r2 = Cd2 + brate * q.C2;
         if (q.det2 != 0.0f) {
             float id = 1.0f / q.det2;
             float l1 = -(q.k22 * r1 - q.k12 * r2) * id;
             float l2 = -(-q.k12 * r1 + q.k11 * r2) * id;
-            J[J_LA] = q.la0 + l1; J[J_LA + 1] = q.la1 + l2;
-            imp_ang(A, B, l1 * q.b1 + l2 * q.b2);
+            if (q.prism) {
+                J[J_LP] = q.lp.x + l1; J[J_LP + 1] = q.lp.y + l2;
+                imp_lin(A, B, q.rA, q.rB, l1 * q.b1 + l2 * q.b2);
+            } else {
+                J[J_LA] = q.la0 + l1; J[J_LA + 1] = q.la1 + l2;
+                imp_ang(A, B, l1 * q.b1 + l2 * q.b2);
+            }
         }
     }
     if (q.kp != 0.0f || q.kd != 0.0f) {
         V3 ax = q.zA;
-        float Cd = dot3(ax, B.w - A.w);
+        float Cd = q.prism ? dot3(ax, relv(A, B, has_a, q.rA, q.rB)) : dot3(ax, B.w - A.w);
         float dl = -(Cd + q.bch + q.gam * q.ld) / q.kg;
         J[J_LD] = q.ld + dl;
-        imp_ang(A, B, dl * ax);
+        if (q.prism) imp_lin(A, B, q.rA, q.rB, dl * ax);
+        else imp_ang(A, B, dl * ax);
     }
+    if (q.lim) joint_limits(c, j, q.prism, A, B, has_a, q.rA, q.rB, q.zA, h, brate, false);
     store_body(c, q.a, A);
     store_body(c, q.b, B);
 }
@@ -1684,13 +1808,34 @@ __device__ __forceinline__ void body_warm_gather(const EnvCtx& c, int i) {
             const float* P = jinv(c, blk);
             const float* J = jrec(c, blk);
             const V3 r = jv3(P, sideB ? JI_RB : JI_RA), zA = jv3(P, JI_ZA), b1 = jv3(P, JI_B1), b2 = jv3(P, JI_B2);
-            const V3 lp = sideB ? v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]) : v3(-J[J_LP], -J[J_LP + 1], -J[J_LP + 2]);
-            const float la0 = sideB ? J[J_LA] : -J[J_LA], la1 = sideB ? J[J_LA + 1] : -J[J_LA + 1];
             const float ld = sideB ? J[J_LD] : -J[J_LD];
-            v = v + im * lp;
-            w = w + muls(I, cross3(r, lp));
-            w = w + muls(I, la0 * b1 + la1 * b2);
-            w = w + muls(I, ld * zA);
+            const float lim = sideB ? J[J_LL] - J[J_LL + 1] : -(J[J_LL] - J[J_LL + 1]);
+            if (!jprism(J)) {
+                // point impulse at the arm, the angular block about b1, b2, drive and limits about zA
+                const V3 lp = sideB ? v3(J[J_LP], J[J_LP + 1], J[J_LP + 2]) : v3(-J[J_LP], -J[J_LP + 1], -J[J_LP + 2]);
+                const float la0 = sideB ? J[J_LA] : -J[J_LA], la1 = sideB ? J[J_LA + 1] : -J[J_LA + 1];
+                v = v + im * lp;
+                w = w + muls(I, cross3(r, lp));
+                w = w + muls(I, la0 * b1 + la1 * b2);
+                w = w + muls(I, ld * zA);
+                if (jlimited(J)) w = w + muls(I, lim * zA);
+            } else {
+                // rows across the slide axis at the arm, the rotation lock, drive and limits along zA
+                const float p0 = sideB ? J[J_LP] : -J[J_LP], p1 = sideB ? J[J_LP + 1] : -J[J_LP + 1];
+                const V3 la = sideB ? v3(J[J_LA], J[J_LA + 1], J[J_LA + 2]) : v3(-J[J_LA], -J[J_LA + 1], -J[J_LA + 2]);
+                const V3 P1 = p0 * b1 + p1 * b2;
+                v = v + im * P1;
+                w = w + muls(I, cross3(r, P1));
+                w = w + muls(I, la);
+                const V3 P2 = ld * zA;
+                v = v + im * P2;
+                w = w + muls(I, cross3(r, P2));
+                if (jlimited(J)) {
+                    const V3 P3 = lim * zA;
+                    v = v + im * P3;
+                    w = w + muls(I, cross3(r, P3));
+                }
+            }
         } else {
             const int m = blk - l.nj;
             int a, b, first, cnt;
@@ -1726,7 +1871,7 @@ __device__ __forceinline__ void run_schedule(const EnvCtx& c, int sched_off, int
         JointPre jp;
         if (blk >= 0) joint_prefetch(c, blk, jp);
         for (int e = 0; e < emax; ++e) {
-            if (blk >= 0) joint_solve_pre(c, blk, jp, brate);
+            if (blk >= 0) joint_solve_pre(c, blk, jp, brate, h);
             blk = sched_block(c, sched_off, nsched, e + 1, li);
             if (blk >= 0) joint_prefetch(c, blk, jp);
             wave_sync();
@@ -2141,8 +2286,11 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
         for (int j = li; j < njA; j += G) {
             const float* src = bd.jrec + size_t(c.j0 + j) * JREC;
             float* J = jrec(c, j);
-            for (int w = 0; w < JREC; ++w) J[w] = src[w];
+            for (int w = 0; w < 18; ++w) J[w] = src[w];
             J[J_TG] = bd.targets[c.j0 + j];
+            J[J_TYP] = src[18];
+            J[J_LO] = src[19];
+            J[J_HI] = src[20];
         }
         if (c.active && li == 0) SC[SC_STATUS] = bd.status[c.env];
         for (int k = li; k < (c.active ? NSTAT : 0); k += G) SC[16 + k] = 0;
@@ -2200,7 +2348,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             // joint impulses start every step from zero (no cross-step warm start)
             for (int j = li; j < (frozen ? 0 : nj); j += G) {
                 float* J = jrec(c, j);
-                for (int w = J_LP; w <= J_LD; ++w) J[w] = 0.0f;
+                for (int w = J_LP; w < J_LL + 2; ++w) J[w] = 0.0f;
             }
             wave_sync();
 
@@ -2435,7 +2583,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = body_rec(c, i)[B_W + r];
         }
         if (c.active && li == 0) bd.status[c.env] = SC[SC_STATUS];
-        for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += SC[16 + k];
+        for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += (long long)SC[16 + k];
         wave_sync();
     }
 }

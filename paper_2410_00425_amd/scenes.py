@@ -30,7 +30,8 @@ BODY_DTYPE = np.dtype([
 ])
 JOINT_DTYPE = np.dtype([
     ("parent", "<i4"), ("child", "<i4"), ("frame_parent", "<f4", 7), ("frame_child", "<f4", 7),
-    ("kp", "<f4"), ("kd", "<f4"), ("target", "<f4"),
+    ("kp", "<f4"), ("kd", "<f4"), ("target", "<f4"), ("type", "<i4"), ("limited", "<i4"),
+    ("lower", "<f4"), ("upper", "<f4"),
 ])
 PARAMS_DTYPE = np.dtype([
     ("dt", "<f4"), ("pos_iters", "<i4"), ("vel_iters", "<i4"), ("solver", "<i4"),
@@ -40,9 +41,10 @@ PARAMS_DTYPE = np.dtype([
     ("lin_damping", "<f4"), ("ang_damping", "<f4"), ("max_contacts_per_env", "<i4"),
     ("debug_export", "<i4"), ("joint_iters", "<i4"), ("max_manifolds_per_env", "<i4"),
 ])
-assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 76 and PARAMS_DTYPE.itemsize == 88
+assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 92 and PARAMS_DTYPE.itemsize == 88
 
 SPHERE, CAPSULE, BOX = 0, 1, 2
+REVOLUTE, PRISMATIC = 0, 1
 STATIC = 1
 TGS, PGS = 0, 1
 
@@ -160,7 +162,7 @@ def uniforms(seed: int, env_ids, purpose: int, n: int, sub: int = 0) -> np.ndarr
 
 
 # purposes (stream ids)
-P_HEIGHT, P_QUAT, P_SIZE, P_SHAPE, P_MU, P_POS, P_LINK, P_CUBE, P_TARGET, P_COUNT, P_ARM = range(11)
+P_HEIGHT, P_QUAT, P_SIZE, P_SHAPE, P_MU, P_POS, P_LINK, P_CUBE, P_TARGET, P_COUNT, P_ARM, P_POLE, P_CART = range(13)
 
 
 def shoemake_quat(u):
@@ -188,10 +190,14 @@ def _body(shape, dims, pos, quat=(1, 0, 0, 0), mass=0.0, density=1000.0, mu=0.5,
     return b
 
 
-def _joint(parent, child, fp, fc, kp=0.0, kd=0.0, target=0.0):
+def _joint(parent, child, fp, fc, kp=0.0, kd=0.0, target=0.0, type=REVOLUTE, limits=None):
+    """A joint record; limits = (lower, upper) in rad (revolute) or m (prismatic), None = free."""
     j = np.zeros(1, dtype=JOINT_DTYPE)
     j["parent"], j["child"], j["frame_parent"], j["frame_child"] = parent, child, fp, fc
     j["kp"], j["kd"], j["target"] = kp, kd, target
+    j["type"] = type
+    if limits is not None:
+        j["limited"], j["lower"], j["upper"] = 1, limits[0], limits[1]
     return j
 
 
@@ -271,6 +277,54 @@ def arm_cube(n_envs: int = 1024, seed: int = 0, first_env: int = 0) -> Scene:
         env_j.append(jj)
     return concat_envs("arm_cube", make_params(dt=0.01, pos_iters=8), env_b, env_j,
                        dict(seed=seed, steps=1000, redraw_every=50))
+
+
+# ----------------------------------------------------------------------------- cartpole
+# A cart on a horizontal rail (prismatic joint to the world along x, 1 m above the ground, limits
+# +-CART_LIMIT, PD position drive) and a pole hinged on the cart's top (revolute about y, free).
+# Geometry and masses are this project's choice (the paper's benchmark uses a cart-pole robot
+# description that is not available here).
+CART_HALF = (0.1, 0.075, 0.05)
+CART_MASS, CART_KP, CART_KD, CART_LIMIT, RAIL_Z = 1.0, 200.0, 20.0, 1.5, 1.0
+POLE_R, POLE_HL, POLE_MASS = 0.03, 0.25, 0.1
+_Q_X = (math.sqrt(0.5), 0.0, math.sqrt(0.5), 0.0)   # joint frame whose z is the world x
+
+
+def cartpole_bodies_joints(theta0: float, x0: float = 0.0, cart_target: float = 0.0):
+    """One cart-pole: the pole tilted by theta0 (rad, about y) from upright, the cart at x0."""
+    hx, hy, hz = CART_HALF
+    cart = _body(BOX, CART_HALF, (x0, 0.0, RAIL_Z), mass=CART_MASS, mu=0.5)
+    d = POLE_HL + POLE_R                                  # hinge to pole centre
+    c, s_ = math.cos(theta0), math.sin(theta0)
+    pq = (math.cos(0.5 * theta0), 0.0, math.sin(0.5 * theta0), 0.0)   # rotation about y by theta0
+    pole = _body(CAPSULE, (POLE_R, POLE_HL, 0.0), (x0 + d * s_, 0.0, RAIL_Z + hz + d * c), pq,
+                 mass=POLE_MASS, mu=0.5)
+    rail = _joint(-1, 0, (0.0, 0.0, RAIL_Z) + _Q_X, (0.0, 0.0, 0.0) + _Q_X, CART_KP, CART_KD, cart_target,
+                  type=PRISMATIC, limits=(-CART_LIMIT, CART_LIMIT))
+    hinge = _joint(0, 1, (0.0, 0.0, hz) + _Q_Y, (0.0, 0.0, -d) + _Q_Y, type=REVOLUTE)
+    return [cart, pole], [rail, hinge]
+
+
+def cartpole(n_envs: int = 4096, seed: int = 0, first_env: int = 0) -> Scene:
+    """The paper's simulation-only benchmark workload: a cart-pole per env at 120 Hz simulation
+    with 4 position and 0 velocity solver iterations (control at 60 Hz: 2 steps per control
+    step).  Pole angle U[-0.1, 0.1] rad from upright, cart at U[-0.5, 0.5] m; no ground contact."""
+    ids = np.arange(first_env, first_env + n_envs)
+    u = uniforms(seed, ids, P_POLE, 2)
+    env_b, env_j = [], []
+    for k in range(n_envs):
+        b, j = cartpole_bodies_joints(-0.1 + 0.2 * u[k, 0], -0.5 + u[k, 1])
+        env_b.append(np.concatenate(b))
+        env_j.append(np.concatenate(j))
+    return concat_envs("cartpole", make_params(dt=1.0 / 120.0, pos_iters=4, vel_iters=0, plane_enabled=0), env_b, env_j,
+                       dict(seed=seed, steps=500, control_every=2))
+
+
+def cartpole_targets(seed: int, env_ids, draw: int) -> np.ndarray:
+    """Cart drive targets (m) of control step `draw`: U[-1, 1]; the pole joint's target is 0."""
+    t = np.zeros((len(env_ids), 2), np.float32)
+    t[:, 0] = 2.0 * uniforms(seed, env_ids, P_CART, 1, sub=draw)[:, 0] - 1.0
+    return t.reshape(-1)
 
 
 # ----------------------------------------------------------------------------- random primitives
@@ -442,6 +496,8 @@ def by_name(name: str, n_envs: int, seed: int = 0, first_env: int = 0) -> Scene:
         return hetero(n_envs, seed, first_env=first_env)
     if name == "hetero_padded":
         return hetero(n_envs, seed, pad_to=64, first_env=first_env)
+    if name == "cartpole":
+        return cartpole(n_envs, seed, first_env=first_env)
     raise ValueError(name)
 
 

@@ -75,25 +75,28 @@ def one_step_parity(scene, st, targets=None, max_excused=None):
     limit = max(1, int(0.001 * scene.n_envs)) if max_excused is None else max_excused
     assert len(excused) <= limit, f"{len(excused)} excused envs"
     assert np.array_equal(g["status"], os_["status"])
-    # contact points of envs without ties
+    # contact points and manifold colours of every env without a tie, env by env (an excused
+    # env elsewhere in the batch does not hide the others)
     ok_env = np.array([e not in excused for e in range(scene.n_envs)])
     gp, op = gc["points"], rec["points"]
-    pe = rec["point_ids"][:, 0]
-    if len(op):
-        m = ok_env[pe]
-        assert len(gp) == len(op) or not np.all(ok_env)
-        if len(gp) == len(op):
-            assert np.allclose(gp[m, :3], op[m, :3], atol=2e-5)
-            assert np.allclose(gp[m, 3:6], op[m, 3:6], atol=2e-4)
-            assert np.allclose(gp[m, 6], op[m, 6], atol=2e-5)
-            assert np.all(gp[:, 7] >= 0)
-    # colours of the manifolds match (they fix the Gauss-Seidel order)
+    g_env = np.repeat(gc["pairs"][:, 0], np.maximum(gc["pairs"][:, 3], 0))
+    o_env = rec["point_ids"][:, 0]
+    assert len(g_env) == len(gp)
+    assert np.all(gp[:, 7] >= 0)
     ob = rec["blocks"]
     om = ob[ob[:, 1] == 1]
     gm = gc["manifolds"]
-    if len(om) == len(gm):
-        keep = ok_env[om[:, 0]]
-        assert np.array_equal(gm[keep, 2].astype(int), om[keep, 3])
+    gm_env = gm[:, 0].astype(int)
+    for e in np.nonzero(ok_env)[0]:
+        ge, oe = gp[g_env == e], op[o_env == e]
+        assert len(ge) == len(oe), f"env {e}: {len(ge)} GPU points, {len(oe)} oracle points"
+        if len(oe):
+            assert np.allclose(ge[:, :3], oe[:, :3], atol=2e-5)
+            assert np.allclose(ge[:, 3:6], oe[:, 3:6], atol=2e-4)
+            assert np.allclose(ge[:, 6], oe[:, 6], atol=2e-5)
+        gme, ome = gm[gm_env == e], om[om[:, 0] == e]
+        assert len(gme) == len(ome), f"env {e}: manifold counts differ"
+        assert np.array_equal(gme[:, 2].astype(int), ome[:, 3])
     b.close()
     return g, os_, len(excused)
 
