@@ -266,6 +266,21 @@ ms_status ms_query_step_many_bytes(ms_batch* const* batches, int32_t n_batches, 
 ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches,
                        int32_t n_steps, void* dev_scratch, size_t scratch_bytes, void* hip_stream);
 
+/* ms_step_many for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): the same fused launch, with the
+ * combined work list in a static device array of MS_STEP_MANY_NOALLOC_BYTES that the library
+ * holds on each GPU it runs on until the process ends, instead of caller scratch.  The call
+ * allocates nothing (no device, pinned or heap memory); the work list is uploaded from a static
+ * host image.  Results are bit-identical to ms_step_many.  Limits: the work list (the size
+ * ms_query_step_many_bytes reports) must fit MS_STEP_MANY_NOALLOC_BYTES and n_batches <= 4096,
+ * else MS_E_CAPACITY and nothing is enqueued.  Every call on one GPU shares that GPU's array and
+ * overwrites it completely: calls on one stream are ordered, but calls on different streams of
+ * one GPU whose launches may overlap race on it (serialise them on one stream or use
+ * ms_step_many).  The host part of concurrent calls is serialised by a lock. */
+#define MS_STEP_MANY_NOALLOC_BYTES (4u << 20)
+ms_status ms_step_many_noalloc(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches,
+                               int32_t n_steps, void* hip_stream);
+
 /* Serving (Sec. "GPU Parallelized Simulation and Rendering": all state stays on one GPU; Sec.
  * "Heterogeneous GPU Simulation": envs of different sizes share the GPU).  A server owns a
  * worker thread and a stream on the current device, and a caller-owned device arena of

@@ -102,8 +102,27 @@ inline bool one_env_tile(const Tile& t) { return t.lanes == WAVE && t.count == 1
 // needs less than 2/3 of the class maximum, at most MAX_CLASSES.  Default kernels: two waves per SIMD for the one-env part; for
 // the rest, two waves per SIMD in a class that starts with 64-lane tiles (large envs), else the
 // unconstrained build.
-template <class TileRef>
-void cut_classes(int n, TileRef tile_ref, bool split_ok, std::vector<LdsClass>& cls) {
+// A vector over caller storage of fixed capacity (the planner's containers in the entry point
+// that allocates nothing); push_back past the capacity is a programming error, checked by the
+// callers' size bounds.
+template <class T>
+struct FixedVec {
+    T* d;
+    size_t cap, n = 0;
+    FixedVec(T* data, size_t capacity) : d(data), cap(capacity) {}
+    void clear() { n = 0; }
+    bool empty() const { return n == 0; }
+    size_t size() const { return n; }
+    void push_back(const T& v) { d[n++] = v; }
+    T& back() { return d[n - 1]; }
+    T& operator[](size_t i) { return d[i]; }
+    const T& operator[](size_t i) const { return d[i]; }
+    T* begin() { return d; }
+    T* end() { return d + n; }
+};
+
+template <class TileRef, class ClassVec>
+void cut_classes(int n, TileRef tile_ref, bool split_ok, ClassVec& cls) {
     cls.clear();
     for (int t = 0; t < n; ++t) {
         const Tile& tl = tile_ref(t);
@@ -226,11 +245,11 @@ constexpr int BIN_BUDGET = 20480;   // bin LDS budget in words: half a CU's 160 
 // Bins for the single-launch form: tiles (sorted by LDS need, largest first) placed first-fit
 // into bins of at most BIN_WAVES tiles and BIN_BUDGET words.  Only for batches with more than
 // one LDS class; otherwise the class launch is already a single launch.
-template <class TileRef>
-int pack_bins(int n_tiles, TileRef tile_ref, std::vector<Bin>& bins) {
+template <class TileRef, class BinVec, class IntVec>
+int pack_bins(int n_tiles, TileRef tile_ref, BinVec& bins, IntVec& used) {
     bins.clear();
+    used.clear();
     int bin_words = 0;
-    std::vector<int> used;
     for (int t = 0; t < n_tiles; ++t) {
         const int w = tile_ref(t).lds_words;
         int k = 0;
@@ -252,7 +271,8 @@ void make_bins(Plan& out) {
     out.bins.clear();
     out.bin_words = 0;
     if (out.classes.size() < 2 || out.launch_mode == 1) return;
-    out.bin_words = pack_bins(int(out.tiles.size()), [&](int t) -> const Tile& { return out.tiles[t]; }, out.bins);
+    std::vector<int> used;
+    out.bin_words = pack_bins(int(out.tiles.size()), [&](int t) -> const Tile& { return out.tiles[t]; }, out.bins, used);
 }
 
 constexpr int TILE_BUDGET = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
@@ -508,7 +528,8 @@ int ms_selfcheck(void) {
         }
         std::stable_sort(tl.begin(), tl.end(), [](const Tile& a, const Tile& b) { return a.lds_words > b.lds_words; });
         std::vector<Bin> bins;
-        const int words = pack_bins(int(tl.size()), [&](int t) -> const Tile& { return tl[t]; }, bins);
+        std::vector<int> used;
+        const int words = pack_bins(int(tl.size()), [&](int t) -> const Tile& { return tl[t]; }, bins, used);
         if (words > BIN_BUDGET) return 5;
         std::vector<int> seen(tl.size(), 0);
         for (const Bin& bn : bins) {
@@ -1177,9 +1198,10 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     // several LDS sizes: one launch of bins (as for a single batch)
     Bin* hb = reinterpret_cast<Bin*>(reinterpret_cast<char*>(te) + align_up(size_t(tenv_base[n_batches]) * sizeof(TileEnv)));
     std::vector<Bin> bins;
+    std::vector<int> used;
     int bin_words = 0;
     if (cls.size() > 1) {
-        bin_words = pack_bins(int(order.size()), [&](int k) -> const Tile& { return tt[k]; }, bins);
+        bin_words = pack_bins(int(order.size()), [&](int k) -> const Tile& { return tt[k]; }, bins, used);
         std::copy(bins.begin(), bins.end(), hb);
     }
     HIP_OK(hipMemcpyAsync(dev_scratch, st.host, need, hipMemcpyHostToDevice, s));
@@ -1215,6 +1237,124 @@ if (ms_status r = launch_class(cls[k], dtb, dtt, dte, int(n_steps), 0, sk); r !=
         }
     }
     return MS_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------- fused step, no allocation
+// Work-list scratch of ms_step_many_noalloc: a file-scope device array, one copy per GPU that the
+// library runs on, held until the process ends.  Host code never uses its name as an address:
+// each device's copy is found once with hipGetSymbolAddress and that pointer is what the
+// upload and the kernels receive.
+static __device__ __align__(256) unsigned char scratch[MS_STEP_MANY_NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr int NOALLOC_MAX_BATCHES = 4096;
+constexpr size_t NOALLOC_MAX_TILES = MS_STEP_MANY_NOALLOC_BYTES / sizeof(Tile);
+// Host side of the entry point, all static: the per-device scratch addresses, the host image of
+// the work list (uploaded from pageable memory: the copy call returns once the runtime has
+// taken the bytes, so the image may be rebuilt by the next call) and the planner's working
+// arrays.  One mutex serialises the host part of concurrent calls.
+std::mutex g_noalloc_mu;
+void* g_noalloc_dev[NOALLOC_MAX_DEVICES] = {};
+alignas(256) unsigned char g_noalloc_host[MS_STEP_MANY_NOALLOC_BYTES];
+int g_noalloc_used[NOALLOC_MAX_TILES];
+int g_noalloc_head[NOALLOC_MAX_BATCHES];
+int g_noalloc_tenv_base[NOALLOC_MAX_BATCHES + 1];
+LdsClass g_noalloc_cls[MAX_CLASSES];
+}  // namespace
+
+extern "C" {
+
+ms_status ms_step_many_noalloc(ms_batch* const* batches, const float* const* dev_targets, int32_t n_batches,
+                               int32_t n_steps, void* hip_stream) {
+    if (!batches || n_batches <= 0) return fail(MS_E_INVALID_ARG, "bad batch list");
+    if (n_steps < 1) return fail(MS_E_INVALID_ARG, "n_steps must be >= 1");
+    if (n_batches > NOALLOC_MAX_BATCHES)
+        return fail(MS_E_CAPACITY, "%d batches, at most %d in one call", n_batches, NOALLOC_MAX_BATCHES);
+    for (int i = 0; i < n_batches; ++i)
+        if (!batches[i]) return fail(MS_E_INVALID_ARG, "null batch %d", i);
+    const size_t need = many_bytes(batches, n_batches);
+    if (need > size_t(MS_STEP_MANY_NOALLOC_BYTES))
+        return fail(MS_E_CAPACITY, "the fused work list needs %zu bytes, more than the %u-byte static scratch "
+                    "(use ms_step_many with caller scratch)", need, unsigned(MS_STEP_MANY_NOALLOC_BYTES));
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(MS_E_DEVICE, "device %d beyond the library's table", dev);
+    for (int i = 0; i < n_batches; ++i)
+        if (batches[i]->device != dev) return fail(MS_E_INVALID_ARG, "batch %d lives on device %d, not %d", i, batches[i]->device, dev);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_dev[dev]) {
+        // first call on this device (current): its own copy of the array
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MS_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        g_noalloc_dev[dev] = p;
+    }
+    char* d = static_cast<char*>(g_noalloc_dev[dev]);
+    char* h = reinterpret_cast<char*>(g_noalloc_host);
+
+    // host image: batch table, merged tiles, env slots, bins (the layout of ms_step_many)
+    size_t n_tiles = 0;
+    for (int i = 0; i < n_batches; ++i) n_tiles += batches[i]->plan.tiles.size();
+    BatchDev* tb = reinterpret_cast<BatchDev*>(h);
+    Tile* tt = reinterpret_cast<Tile*>(h + align_up(size_t(n_batches) * sizeof(BatchDev)));
+    TileEnv* te = reinterpret_cast<TileEnv*>(reinterpret_cast<char*>(tt) + align_up(n_tiles * sizeof(Tile)));
+    int* tenv_base = g_noalloc_tenv_base;
+    tenv_base[0] = 0;
+    for (int i = 0; i < n_batches; ++i) {
+        ms_batch* b = batches[i];
+        tb[i] = b->hbd;
+        tenv_base[i + 1] = tenv_base[i] + int(b->plan.tenv.size());
+        for (size_t k = 0; k < b->plan.tenv.size(); ++k) {
+            TileEnv f = b->plan.tenv[k];
+            f.batch = i;
+            te[tenv_base[i] + k] = f;
+        }
+        g_noalloc_head[i] = 0;
+        if (dev_targets && dev_targets[i] && b->J > 0)
+            HIP_OK(hipMemcpyAsync(const_cast<float*>(b->hbd.targets), dev_targets[i], size_t(b->J) * 4,
+                                  hipMemcpyDeviceToDevice, s));
+    }
+    // merge the batches' tile lists (each ordered by LDS need, largest first) into one list of
+    // the same order, earlier batches first among equals
+    for (size_t k = 0; k < n_tiles; ++k) {
+        int best = -1, best_words = -1;
+        for (int i = 0; i < n_batches; ++i) {
+            const std::vector<Tile>& T = batches[i]->plan.tiles;
+            if (g_noalloc_head[i] < int(T.size()) && T[g_noalloc_head[i]].lds_words > best_words) {
+                best = i;
+                best_words = T[g_noalloc_head[i]].lds_words;
+            }
+        }
+        Tile u = batches[best]->plan.tiles[g_noalloc_head[best]++];
+        u.first += tenv_base[best];
+        tt[k] = u;
+    }
+    FixedVec<LdsClass> cls(g_noalloc_cls, MAX_CLASSES);
+    cut_classes(int(n_tiles), [&](int k) -> Tile& { return tt[k]; }, true, cls);
+    Bin* hb = reinterpret_cast<Bin*>(reinterpret_cast<char*>(te) + align_up(size_t(tenv_base[n_batches]) * sizeof(TileEnv)));
+    FixedVec<Bin> bins(hb, n_tiles);
+    FixedVec<int> used(g_noalloc_used, n_tiles);
+    int bin_words = 0;
+    if (cls.size() > 1) bin_words = pack_bins(int(n_tiles), [&](int k) -> const Tile& { return tt[k]; }, bins, used);
+    HIP_OK(hipMemcpyAsync(d, h, need, hipMemcpyHostToDevice, s));
+    const BatchDev* dtb = reinterpret_cast<const BatchDev*>(d);
+    const Tile* dtt = reinterpret_cast<const Tile*>(d + (reinterpret_cast<char*>(tt) - h));
+    const TileEnv* dte = reinterpret_cast<const TileEnv*>(d + (reinterpret_cast<char*>(te) - h));
+    if (cls.size() > 1) {
+        const Bin* dbins = reinterpret_cast<const Bin*>(d + (reinterpret_cast<char*>(hb) - h));
+        const int nb = int(bins.size());
+        hipLaunchKernelGGL(ms_step_kernel_bins, dim3(nb), dim3(WAVE * BIN_WAVES), size_t(bin_words) * 4, s, dtb, dtt, dbins,
+                           nb, dte, int(n_steps));
+        HIP_OK(hipGetLastError());
+        return MS_OK;
+    }
+    return launch_class(cls[0], dtb, dtt, dte, int(n_steps), 0, s);
 }
 
 }  // extern "C"

@@ -26,6 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 MS_OK, MS_E_INVALID_ARG, MS_E_NO_WORKSPACE, MS_E_BUDGET, MS_E_DEVICE, MS_E_CAPACITY, MS_E_STATE = range(7)
 STATUS_NONFINITE, STATUS_CONTACT_OVERFLOW, STATUS_COLOR_OVERFLOW = 1, 2, 4
 PLANE = 0xFFFF
+STEP_MANY_NOALLOC_BYTES = 4 << 20   # MS_STEP_MANY_NOALLOC_BYTES
 
 
 class MsError(RuntimeError):
@@ -78,6 +79,9 @@ _sig = {
     "ms_server_stats": [_P, _P],
     "ms_server_destroy": [_P],
     "ms_peak_fp32": [_P, _I, _I, _P],
+    "ms_query_step_many_bytes": [_P, _I, C.POINTER(C.c_size_t)],
+    "ms_step_many": [_P, _P, _I, _I, _P, C.c_size_t, _P],
+    "ms_step_many_noalloc": [_P, _P, _I, _I, _P],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -291,6 +295,45 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def _batch_lists(batches, targets):
+    hs = (C.c_void_p * len(batches))(*[b._h for b in batches])
+    tp = None
+    if targets is not None:
+        assert len(targets) == len(batches)
+        for b, t in zip(batches, targets):
+            assert t is None or (t.is_cuda and t.is_contiguous() and t.numel() == b.n_joints)
+        tp = (C.c_void_p * len(batches))(*[None if t is None else t.data_ptr() for t in targets])
+    return hs, tp
+
+
+def query_step_many_bytes(batches) -> int:
+    hs, _ = _batch_lists(batches, None)
+    out = C.c_size_t()
+    _check(_lib.ms_query_step_many_bytes(hs, len(batches), C.byref(out)))
+    return out.value
+
+
+def step_many(batches, n_steps: int = 1, targets=None, scratch=None, stream=None):
+    """ms_step_many: one fused launch over several batches; scratch is a uint8 device tensor of
+    at least query_step_many_bytes() bytes (allocated here when None)."""
+    import torch
+    need = query_step_many_bytes(batches)
+    if scratch is None:
+        scratch = torch.empty(need + 256, dtype=torch.uint8, device=batches[0].device)
+    ptr = (scratch.data_ptr() + 255) & ~255
+    avail = scratch.numel() - (ptr - scratch.data_ptr())
+    hs, tp = _batch_lists(batches, targets)
+    _check(_lib.ms_step_many(hs, tp, len(batches), int(n_steps), C.c_void_p(ptr), avail, _stream(stream)))
+    return scratch
+
+
+def step_many_noalloc(batches, n_steps: int = 1, targets=None, stream=None):
+    """ms_step_many_noalloc: the same fused launch with the library's static work-list scratch
+    (nothing is allocated)."""
+    hs, tp = _batch_lists(batches, targets)
+    _check(_lib.ms_step_many_noalloc(hs, tp, len(batches), int(n_steps), _stream(stream)))
 
 
 class ms_request_info(C.Structure):
