@@ -4,13 +4,15 @@
  * The library advances many independent rigid-body environments ("envs") by one or more
  * fixed time steps with a single fused HIP kernel on one GPU.  The capability follows the
  * GPU-parallel, heterogeneous simulation of ManiSkill3 (arXiv 2410.00425): every parallel env
- * is its own scene with its own object count and articulation (Sec. III-A, "heterogeneous
- * simulation"), state stays resident on the GPU (Sec. III-B), envs can be reset in part
- * (App. D, partial resets), and the solver runs a fixed number of position / velocity
- * iterations (App. E, Setup: 120 Hz, 4 position and 0 velocity iterations).  The paper does not
- * state the contact and solver equations; the step model this library implements is fixed
- * by the oracle's documented reading (sequential-impulse TGS/PGS with speculative contacts,
- * pyramid friction, revolute joints with a soft PD drive).
+ * is its own scene with its own object count and articulation (Sec. III-C, Heterogeneous GPU
+ * Simulation), state stays resident on the GPU (Sec. III-B, GPU Parallelized Simulation and
+ * Rendering), envs can be reset in part (App. C, PPO: partial resets) with per-env seeded
+ * randomisation (App. B, Environment Setup and Domain Randomizations), and the solver runs a
+ * fixed number of position / velocity iterations (App. E, Setup: 120 Hz, 4 position and 0
+ * velocity iterations).  The paper does not state the contact and solver equations; the step
+ * model this library implements is fixed by the oracle's documented reading (sequential-impulse
+ * TGS/PGS with speculative contacts, patch friction: two tangent rows and a torsional row per
+ * manifold; revolute and prismatic joints with a soft PD drive and position limits).
  *
  * Conventions: SI units, z up, quaternions (w, x, y, z), angular velocity in the world frame.
  * Body and joint indices inside descriptors are env-local.  All device pointers are
@@ -179,11 +181,73 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
  * status are skipped. */
 ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* hip_stream);
 
-/* Write state for the listed envs (int32 device array of n_ids env ids, each in [0, E)) and
- * clear their status.  src = NULL restores the initial state; otherwise src holds full-batch
- * SoA arrays (same shape as ms_state_view) from which the listed envs' bodies are copied. */
+/* Partial reset (App. C, PPO: partial resets).  Write state for the listed envs (int32 device
+ * array of n_ids env ids, each in [0, E)) and clear their status (and their contact forces).
+ * src = NULL restores the initial state; otherwise src holds full-batch SoA arrays (same shape
+ * as ms_state_view) from which the listed envs' bodies are copied.  Ids outside [0, E) are
+ * skipped and counted (ms_get_invalid_ids).  MS_E_INVALID_ARG for a null pointer or negative
+ * n_ids (nothing enqueued). */
 ms_status ms_reset_envs(ms_batch* b, const int32_t* dev_env_ids, int32_t n_ids,
                         const ms_state_view* src, void* hip_stream);
+
+/* Randomised partial reset (App. C, PPO: partial resets; App. B, Environment Setup and Domain
+ * Randomizations: initial joint positions drawn around a reference, object placement and yaw
+ * drawn uniformly; Sec. III-G: per-env seeded randomness).  For each listed env (int32 device
+ * array of n_ids ids), starting from the batch's initial state: every free dynamic body (the
+ * child of no joint) moves by xy_half * (2u - 1) in x and in y and turns about the world z axis
+ * through its centre by yaw_half * (2u - 1); every joint, in index order, takes the position
+ * q0 = q_init + joint_sigma * N (q_init its position in the initial state, N an Irwin-Hall
+ * standard normal deviate: the sum of 12 uniforms minus 6) and poses its child from its parent;
+ * all velocities are zero, the status is cleared, the env's contact forces are zero, and with
+ * targets_follow the joint's drive target becomes q0.  Random numbers: Philox4x32-10 under the
+ * 64-bit key `seed` with counter (env id, count, purpose, index); body i uses block (1, i), joint
+ * j blocks (0, 3j .. 3j + 2); u = the top 24 bits / 2^24.  `count` distinguishes successive
+ * resets of one env.  Stream-ordered, no host synchronisation.  Errors (nothing enqueued):
+ * MS_E_INVALID_ARG for a null pointer, negative n_ids, a noise scale that is negative or not
+ * finite, or a batch whose envs do not order their joints parents first.  Ids outside [0, E) are
+ * skipped and counted (ms_get_invalid_ids). */
+typedef struct {
+    float joint_sigma;      /* rad (revolute) or m (prismatic) */
+    float xy_half;          /* m */
+    float yaw_half;         /* rad */
+    int32_t targets_follow; /* != 0: drive targets become the drawn joint positions */
+} ms_reset_noise;
+ms_status ms_reset_envs_random(ms_batch* b, const int32_t* dev_env_ids, int32_t n_ids, const ms_reset_noise* noise,
+                               uint64_t seed, uint32_t count, void* hip_stream);
+
+/* Target-delta joint position controller (App. B, Controller / Action Space): per joint,
+ * target += clip(a, -1, 1) * (high - low) / 2 in float32.  dev_actions: float32 [J] (device);
+ * dev_low / dev_high: float32 [J] per-joint bounds, or NULL to use the scalars low / high.
+ * Stream-ordered.  MS_E_INVALID_ARG for null actions or a non-finite scalar bound in use. */
+ms_status ms_apply_actions(ms_batch* b, const float* dev_actions, const float* dev_low, const float* dev_high, float low,
+                           float high, void* hip_stream);
+
+/* Copy the current drive targets, float32 [J], into caller-owned device memory.  Stream-ordered. */
+ms_status ms_get_targets(ms_batch* b, float* dev_out, void* hip_stream);
+
+/* Joint positions of the current state, float32 [J] (device, caller-owned): the twist angle
+ * 2 atan2(q_rel.z, q_rel.w) of the child's joint frame relative to the parent's for a revolute
+ * joint (the drive's angle, unwrapped into [-pi, pi]), the anchors' separation along the slide
+ * axis for a prismatic one (App. B, Controller / Action Space: the controller's q_t).
+ * Stream-ordered. */
+ms_status ms_get_joint_positions(ms_batch* b, float* dev_out, void* hip_stream);
+
+/* Contact-force readout for touch sensing (App. A, Dextrous Manipulation: touch sensors), kept on
+ * the device.  ms_set_contact_forces(enable != 0) makes every later step of the batch accumulate,
+ * per body, the net contact impulse of the step: for every substep, the final normal impulses of
+ * the body's contact points and the two tangent impulses of its friction patches (added on a
+ * manifold's side B, subtracted on side A; manifolds in canonical order, a manifold's points before
+ * its patch), divided by dt.  A launch of several steps keeps the last step's.  Frozen envs and
+ * steps that went non-finite give zero.  Enabling zeroes the buffer; enabling and disabling
+ * synchronise `hip_stream`.  ms_get_contact_forces copies float32 [3][B] (component-major, like
+ * the state planes) into caller-owned device memory, stream-ordered; MS_E_STATE when not enabled.
+ * Tuning trial steps (ms_tune_batch) overwrite the forces. */
+ms_status ms_set_contact_forces(ms_batch* b, int32_t enable, void* hip_stream);
+ms_status ms_get_contact_forces(ms_batch* b, float* dev_out, void* hip_stream);
+
+/* Number of env ids outside [0, E) met by ms_reset_envs and ms_reset_envs_random since the last
+ * clear (those ids were skipped).  Synchronises `hip_stream`; clear != 0 zeroes the count. */
+ms_status ms_get_invalid_ids(ms_batch* b, int32_t* host_count, int32_t clear, void* hip_stream);
 
 /* Copy the current state (all envs) into caller-owned device buffers. */
 ms_status ms_get_state(ms_batch* b, const ms_state_view* dst, void* hip_stream);

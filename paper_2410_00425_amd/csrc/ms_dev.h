@@ -51,6 +51,10 @@ struct BatchDev {
     int* dbg_counts;       // [E][4]: candidates, points, manifolds, colours
     // work counters, accumulated over launches in 64 bits: [E][NSTAT] (see STAT_*)
     long long* stats;
+    // net contact force on every body over the last step of a launch, [3][B] (null: not computed)
+    float* forces;
+    // count of env ids outside [0, E) met by the reset kernels
+    int* bad_ids;
 };
 
 // Work counters per env: steps, candidate pairs per shape kind (3 * min + max shape for body

@@ -175,7 +175,7 @@ struct Plan {
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
     size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, save, status, bpar, body_off, joint_off, jrec, targets, tiles,
-        bins, tenv, bd, stats, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
+        bins, tenv, bd, stats, forces, bad_ids, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
 
 ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
@@ -362,6 +362,8 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.tenv = take(pl.tenv.size() * sizeof(TileEnv));
     L.bd = take(sizeof(BatchDev));
     L.stats = take(E * NSTAT * 8);
+    L.forces = take(3 * B * 4);
+    L.bad_ids = take(4);
     if (p->debug_export) {
         L.dbg_pairs = take(size_t(pl.dbg_pair_off[E]) * 16);
         L.dbg_pair_off = take((E + 1) * 4);
@@ -429,6 +431,11 @@ struct ms_batch {
     // bumped whenever the tiles, bins or their launch geometry are rewritten (retile); a graph
     // captured under another generation would replay stale launch geometry
     uint64_t plan_gen = 0;
+    // every env's joints are ordered parents first (a joint's parent is posed by an earlier
+    // joint or by no joint), as the randomised reset's forward kinematics requires
+    bool joints_ordered = true;
+    // the step accumulates per-body contact forces (ms_set_contact_forces)
+    bool forces_on = false;
     // fork / join streams for LDS classes after the first (default priority)
     hipStream_t side[MAX_CLASSES] = {};
     hipEvent_t ev_fork = nullptr;
@@ -468,6 +475,8 @@ void fill_batchdev(ms_batch* b) {
     d.beta = p.baumgarte; d.max_depen = p.max_depen_vel; d.beta_j = p.joint_baumgarte; d.bounce = p.bounce_threshold;
     d.lin_damp = p.lin_damping; d.ang_damp = p.ang_damping;
     d.stats = at<long long>(w, L.stats);
+    d.bad_ids = at<int>(w, L.bad_ids);
+    d.forces = b->forces_on ? at<float>(w, L.forces) : nullptr;
     if (p.debug_export) {
         d.dbg_pairs = at<int>(w, L.dbg_pairs); d.dbg_pair_off = at<int>(w, L.dbg_pair_off);
         d.dbg_pts = at<float>(w, L.dbg_pts); d.dbg_pt_off = at<int>(w, L.dbg_pt_off);
@@ -586,6 +595,16 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     b->body_off.assign(scene->env_body_off, scene->env_body_off + b->E + 1);
     b->joint_off.assign(scene->env_joint_off, scene->env_joint_off + b->E + 1);
     plan_batch(params, scene, plan, b->plan);
+    for (int e = 0; e < b->E && b->joints_ordered; ++e) {
+        const int n = b->body_off[e + 1] - b->body_off[e];
+        std::vector<char> posed(size_t(n), 1);
+        for (int j = b->joint_off[e]; j < b->joint_off[e + 1]; ++j) posed[size_t(scene->joints[j].child)] = 0;
+        for (int j = b->joint_off[e]; j < b->joint_off[e + 1]; ++j) {
+            const ms_joint_desc& d = scene->joints[j];
+            if (d.parent >= 0 && !posed[size_t(d.parent)]) { b->joints_ordered = false; break; }
+            posed[size_t(d.child)] = 1;
+        }
+    }
     b->lay = layout_ws(params, scene, b->plan);
     if (ws_bytes < b->lay.total) {
         size_t need = b->lay.total;
@@ -668,6 +687,9 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     if (e == hipSuccess) e = up(L.status, zeros.data(), E * 4);
     std::vector<long long> zstats(E * NSTAT, 0);
     if (e == hipSuccess) e = up(L.stats, zstats.data(), E * NSTAT * 8);
+    std::vector<float> zforces(3 * B + 1, 0.0f);
+    if (e == hipSuccess) e = up(L.forces, zforces.data(), 3 * B * 4);
+    if (e == hipSuccess) e = up(L.bad_ids, zforces.data(), 4);
     if (e == hipSuccess) e = up(L.bpar, bp.data(), 3 * B * 16);
     if (e == hipSuccess) e = up(L.body_off, b->body_off.data(), (E + 1) * 4);
     if (e == hipSuccess) e = up(L.joint_off, b->joint_off.data(), (E + 1) * 4);
@@ -784,6 +806,91 @@ ms_status ms_reset_envs(ms_batch* b, const int32_t* dev_env_ids, int32_t n_ids, 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     hipLaunchKernelGGL(ms_reset_kernel, dim3(n_ids), dim3(WAVE), 0, s, b->hbd, dev_env_ids, int(n_ids), sp, sq, sv, sw);
     HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+ms_status ms_reset_envs_random(ms_batch* b, const int32_t* dev_env_ids, int32_t n_ids, const ms_reset_noise* noise,
+                               uint64_t seed, uint32_t count, void* hip_stream) {
+    if (!b || !noise) return fail(MS_E_INVALID_ARG, "null batch or noise");
+    if (n_ids < 0) return fail(MS_E_INVALID_ARG, "n_ids must be >= 0");
+    if (n_ids == 0) return MS_OK;
+    if (!dev_env_ids) return fail(MS_E_INVALID_ARG, "null env ids");
+    const float nzv[3] = {noise->joint_sigma, noise->xy_half, noise->yaw_half};
+    for (float v : nzv)
+        if (!(std::isfinite(v) && v >= 0.0f)) return fail(MS_E_INVALID_ARG, "noise scales must be finite and >= 0");
+    if (!b->joints_ordered)
+        return fail(MS_E_INVALID_ARG, "an env's joints are not ordered parents first (forward kinematics needs it)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    ResetNoiseDev nz{noise->joint_sigma, noise->xy_half, noise->yaw_half, noise->targets_follow ? 1 : 0};
+    hipLaunchKernelGGL(ms_reset_random_kernel, dim3((n_ids + 63) / 64), dim3(64), 0, s, b->hbd, dev_env_ids, int(n_ids),
+                       at<float>(b->ws, b->lay.ipos), at<float>(b->ws, b->lay.iquat), nz, uint32_t(seed & 0xFFFFFFFFu),
+                       uint32_t(seed >> 32), count, b->hbd.bad_ids);
+    HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+ms_status ms_apply_actions(ms_batch* b, const float* dev_actions, const float* dev_low, const float* dev_high, float low,
+                           float high, void* hip_stream) {
+    if (!b || !dev_actions) return fail(MS_E_INVALID_ARG, "null batch or actions");
+    if ((!dev_low && !std::isfinite(low)) || (!dev_high && !std::isfinite(high)))
+        return fail(MS_E_INVALID_ARG, "scalar bounds must be finite");
+    if (b->J == 0) return MS_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(ms_apply_actions_kernel, dim3((b->J + 255) / 256), dim3(256), 0, s, const_cast<float*>(b->hbd.targets),
+                       dev_actions, dev_low, dev_high, low, high, b->J);
+    HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+ms_status ms_get_targets(ms_batch* b, float* dev_out, void* hip_stream) {
+    if (!b || (!dev_out && b->J > 0)) return fail(MS_E_INVALID_ARG, "null batch or output");
+    if (b->J == 0) return MS_OK;
+    HIP_OK(hipMemcpyAsync(dev_out, b->hbd.targets, size_t(b->J) * 4, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+    return MS_OK;
+}
+
+ms_status ms_get_joint_positions(ms_batch* b, float* dev_out, void* hip_stream) {
+    if (!b || (!dev_out && b->J > 0)) return fail(MS_E_INVALID_ARG, "null batch or output");
+    if (b->J == 0) return MS_OK;
+    hipLaunchKernelGGL(ms_joint_positions_kernel, dim3((b->E + 63) / 64), dim3(64), 0, static_cast<hipStream_t>(hip_stream),
+                       b->hbd, dev_out);
+    HIP_OK(hipGetLastError());
+    return MS_OK;
+}
+
+ms_status ms_set_contact_forces(ms_batch* b, int32_t enable, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    b->forces_on = enable != 0;
+    b->hbd.forces = b->forces_on ? at<float>(b->ws, b->lay.forces) : nullptr;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (b->forces_on) HIP_OK(hipMemsetAsync(b->hbd.forces, 0, size_t(b->B) * 12, s));
+    // the device copy of the batch record is read by graph replays and the class launches
+    HIP_OK(hipMemcpyAsync(b->dbd, &b->hbd, sizeof(BatchDev), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return MS_OK;
+}
+
+ms_status ms_get_contact_forces(ms_batch* b, float* dev_out, void* hip_stream) {
+    if (!b || !dev_out) return fail(MS_E_INVALID_ARG, "null batch or output");
+    if (!b->forces_on) return fail(MS_E_STATE, "contact forces are not enabled (ms_set_contact_forces)");
+    HIP_OK(hipMemcpyAsync(dev_out, b->hbd.forces, size_t(b->B) * 12, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+    return MS_OK;
+}
+
+ms_status ms_get_invalid_ids(ms_batch* b, int32_t* host_count, int32_t clear, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int v = 0;
+    HIP_OK(hipMemcpyAsync(&v, b->hbd.bad_ids, 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (host_count) *host_count = v;
+    if (clear) {
+        const int z = 0;
+        HIP_OK(hipMemcpyAsync(b->hbd.bad_ids, &z, 4, hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
     return MS_OK;
 }
 

@@ -2239,6 +2239,39 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
 // The step of every tile of the work list; `lds` is the workgroup's dynamic LDS.
 // ONE: every tile of the launch holds a single env served by all 64 lanes, so the env's sizes
 // and offsets are wavefront-uniform (scalar registers) and the group arithmetic folds away.
+// Net contact impulse on each body, summed into the bounding-box plane (free after the
+// broadphase; 3 of its 6 n words): a lane per body walks the manifolds in canonical order and
+// adds, for each manifold it belongs to, the normal impulses of its points, then the patch's two
+// tangent impulses (added on side B, subtracted on side A; the twist is a torque and is left
+// out).  Run once after the sweeps of every substep but the last, and once after the velocity
+// and restitution passes: the sum over substeps of each substep's final multipliers.
+// Whether the batch accumulates contact forces, read afresh at each use (a volatile load) so the
+// flag never holds a register across the step's phases.
+__device__ __forceinline__ bool forces_on(const EnvCtx& c) {
+    return *reinterpret_cast<float* const volatile*>(&c.bd->forces) != nullptr;
+}
+__device__ __forceinline__ void accumulate_forces(const EnvCtx& c, int nn, int nman, int li, int G) {
+    const int n = c.lay.n;
+    float* F = c.L + c.lay.AABB;
+    for (int i = li; i < nn; i += G) {
+        V3 f = v3(F[i], F[n + i], F[2 * n + i]);
+        for (int m = 0; m < nman; ++m) {
+            int a, b, first, cnt;
+            man_header(c, m, a, b, first, cnt);
+            if (a != i && b != i) continue;
+            const bool sideB = b == i;
+            for (int k = first; k < first + cnt; ++k) {
+                const V3 Pn = pr(c, R_LN, k) * pr3(c, R_N, k);
+                f = sideB ? f + Pn : f - Pn;
+            }
+            const V3 t1 = mf3(c, M_T1, m);
+            const V3 Pt = mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * cross3(mf3(c, M_NB, m), t1);
+            f = sideB ? f + Pt : f - Pt;
+        }
+        F[i] = f.x; F[n + i] = f.y; F[2 * n + i] = f.z;
+    }
+}
+
 template <bool ONE>
 __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict__ batches, const Tile tile,
                                           const TileEnv* __restrict__ tenv, int n_steps, int lane) {
@@ -2487,6 +2520,11 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             const int nmanA = frozen ? 0 : SC[SC_NMAN];
 
             // --------------------------------------------------------- S6 substeps
+            if (forces_on(c)) {
+                for (int i = li; i < nn; i += G) {
+                    c.L[l.AABB + i] = 0.0f; c.L[l.AABB + n + i] = 0.0f; c.L[l.AABB + 2 * n + i] = 0.0f;
+                }
+            }
             const float ldmp = 1.0f / (1.0f + h * bd.lin_damp);
             const float admp = 1.0f / (1.0f + h * bd.ang_damp);
             // warm start body by body: fused with gravity in joint-free waves, after the joint pass
@@ -2511,6 +2549,10 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 for (int it = 0; it < K; ++it) {
                     for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
                     (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
+                }
+                if (s + 1 < S && forces_on(c)) {
+                    wave_sync();
+                    accumulate_forces(c, nn, nmanA, li, G);
                 }
                 // integrate the offsets from the step-start pose
                 for (int i = li; i < nn; i += G) {
@@ -2553,6 +2595,20 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                     stw(c, i, ld3(c.L, l.W0, n, i));
                 }
                 if (li == 0) SC[SC_STATUS] |= 1;
+            }
+            wave_sync();
+            // --------------------------------------------------------- contact forces
+            // the step's contact impulses / dt, written for the last step of the launch (zero for
+            // a frozen env or a step that went non-finite)
+            if (step == n_steps - 1 && forces_on(c)) {
+                if (!anybad) accumulate_forces(c, nn, nmanA, li, G);
+                const float idt = 1.0f / bd.dt;
+                for (int i = li; i < nA; i += G) {
+                    V3 f = v3(0, 0, 0);
+                    if (!frozen && !anybad) f = idt * v3(c.L[l.AABB + i], c.L[l.AABB + n + i], c.L[l.AABB + 2 * n + i]);
+                    const int gi = c.b0 + i;
+                    bd.forces[gi] = f.x; bd.forces[B + gi] = f.y; bd.forces[2 * B + gi] = f.z;
+                }
             }
             wave_sync();
             // --------------------------------------------------------- debug export
@@ -2656,7 +2712,10 @@ extern "C" __global__ void __launch_bounds__(64) ms_reset_kernel(BatchDev bd, co
     int k = blockIdx.x;
     if (k >= n_ids) return;
     int e = env_ids[k];
-    if (e < 0 || e >= bd.E) return;
+    if (e < 0 || e >= bd.E) {
+        if (threadIdx.x == 0) atomicAdd(bd.bad_ids, 1);
+        return;
+    }
     int b0 = bd.body_off[e], b1 = bd.body_off[e + 1];
     const int B = bd.B;
     for (int gi = b0 + int(threadIdx.x); gi < b1; gi += blockDim.x) {
@@ -2664,6 +2723,8 @@ extern "C" __global__ void __launch_bounds__(64) ms_reset_kernel(BatchDev bd, co
         for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = squat[r * B + gi];
         for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = svel[r * B + gi];
         for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = sang[r * B + gi];
+        if (bd.forces)
+            for (int r = 0; r < 3; ++r) bd.forces[r * B + gi] = 0.0f;
     }
     if (threadIdx.x == 0) bd.status[e] = 0;
 }

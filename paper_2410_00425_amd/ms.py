@@ -45,6 +45,11 @@ class ms_state_view(C.Structure):
                 ("status", C.c_void_p)]
 
 
+class ms_reset_noise(C.Structure):
+    _fields_ = [("joint_sigma", C.c_float), ("xy_half", C.c_float), ("yaw_half", C.c_float),
+                ("targets_follow", C.c_int32)]
+
+
 class ms_plan(C.Structure):
     _fields_ = [("lanes_per_env", C.c_int32), ("pack", C.c_int32), ("max_resident_groups", C.c_int32),
                 ("launch_mode", C.c_int32)]
@@ -82,6 +87,13 @@ _sig = {
     "ms_query_step_many_bytes": [_P, _I, C.POINTER(C.c_size_t)],
     "ms_step_many": [_P, _P, _I, _I, _P, C.c_size_t, _P],
     "ms_step_many_noalloc": [_P, _P, _I, _I, _P],
+    "ms_reset_envs_random": [_P, _P, _I, _P, C.c_uint64, C.c_uint32, _P],
+    "ms_apply_actions": [_P, _P, _P, _P, C.c_float, C.c_float, _P],
+    "ms_get_targets": [_P, _P, _P],
+    "ms_get_joint_positions": [_P, _P, _P],
+    "ms_set_contact_forces": [_P, _I, _P],
+    "ms_get_contact_forces": [_P, _P, _P],
+    "ms_get_invalid_ids": [_P, C.POINTER(C.c_int32), _I, _P],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -186,6 +198,54 @@ class Batch:
                                  src["angvel"].data_ptr(), None)
         _check(_lib.ms_reset_envs(self._h, C.c_void_p(env_ids.data_ptr()), int(env_ids.numel()),
                                   C.byref(view) if view is not None else None, _stream(stream)))
+
+    def reset_envs_random(self, env_ids, joint_sigma=0.0, xy_half=0.0, yaw_half=0.0, targets_follow=True, seed=0,
+                          count=0, stream=None):
+        """ms_reset_envs_random: seeded randomised reset of the listed envs (int32 device tensor)."""
+        import torch
+        assert env_ids.dtype == torch.int32 and env_ids.is_cuda and env_ids.is_contiguous()
+        nz = ms_reset_noise(float(joint_sigma), float(xy_half), float(yaw_half), 1 if targets_follow else 0)
+        _check(_lib.ms_reset_envs_random(self._h, C.c_void_p(env_ids.data_ptr()), int(env_ids.numel()), C.byref(nz),
+                                         int(seed), int(count), _stream(stream)))
+
+    def apply_actions(self, actions, low=None, high=None, lo=-1.0, hi=1.0, stream=None):
+        """ms_apply_actions: targets += clip(a, -1, 1) (high - low) / 2 (float32 device tensors [J])."""
+        def ptr(t):
+            if t is None:
+                return None
+            assert t.is_cuda and t.is_contiguous() and t.numel() == self.n_joints
+            return C.c_void_p(t.data_ptr())
+        _check(_lib.ms_apply_actions(self._h, ptr(actions), ptr(low), ptr(high), float(lo), float(hi), _stream(stream)))
+
+    def targets(self, stream=None):
+        """ms_get_targets: the current drive targets, float32 device tensor [J]."""
+        import torch
+        out = torch.empty(self.n_joints, dtype=torch.float32, device=self.device)
+        _check(_lib.ms_get_targets(self._h, C.c_void_p(out.data_ptr()) if self.n_joints else None, _stream(stream)))
+        return out
+
+    def joint_positions(self, stream=None):
+        """ms_get_joint_positions: float32 device tensor [J]."""
+        import torch
+        out = torch.empty(self.n_joints, dtype=torch.float32, device=self.device)
+        _check(_lib.ms_get_joint_positions(self._h, C.c_void_p(out.data_ptr()) if self.n_joints else None,
+                                           _stream(stream)))
+        return out
+
+    def set_contact_forces(self, enable=True, stream=None):
+        _check(_lib.ms_set_contact_forces(self._h, 1 if enable else 0, _stream(stream)))
+
+    def contact_forces(self, stream=None):
+        """ms_get_contact_forces: float32 device tensor [3, B] (net contact force of the last step)."""
+        import torch
+        out = torch.empty(3, self.n_bodies, dtype=torch.float32, device=self.device)
+        _check(_lib.ms_get_contact_forces(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def invalid_ids(self, clear=False, stream=None) -> int:
+        v = C.c_int32()
+        _check(_lib.ms_get_invalid_ids(self._h, C.byref(v), 1 if clear else 0, _stream(stream)))
+        return v.value
 
     def get_state(self, out=None, stream=None):
         """ms_get_state into (new or given) device tensors; returns the dict."""
