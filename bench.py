@@ -9,8 +9,7 @@ bracketed by device synchronisation; HIP events on the launch stream time every 
 p99) and the whole region.  Before the warm-up every workload first runs --settle untimed steps
 (default 200 = 1 s of simulated time for the tray) from the generator state, so the timed window
 is the contact-rich, settled phase of the scene whatever --steps / --warmup are; the line names
-the window.  The warm-up and timed steps of the headline sit inside a profiler region
-(roctxProfilerResume / Pause), so `rocprofv3 --selected-regions` traces exactly them.
+the window.
 
 The line also carries:
   * roofline: the step kernel against the chip's FP32 vector peak; achieved = algorithmic FLOP
@@ -86,35 +85,6 @@ def parse():
     return ap.parse_args()
 
 
-class _Region:
-    """roctxProfilerResume / roctxProfilerPause around the timed steps (a no-op without the
-    library): under `rocprofv3 --selected-regions` only the region is traced."""
-
-    def __init__(self):
-        import ctypes
-        self.lib = None
-        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
-            try:
-                self.lib = ctypes.CDLL(os.path.join("/opt/rocm/lib", name))
-                break
-            except OSError:
-                continue
-        if self.lib is not None:
-            # roctx_thread_id_t is 64-bit; 0 = the calling thread
-            for f in ("roctxProfilerResume", "roctxProfilerPause"):
-                getattr(self.lib, f).argtypes = [ctypes.c_uint64]
-                getattr(self.lib, f).restype = None
-
-    def resume(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerResume(0)
-
-    def pause(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerPause(0)
-
-
-REGION = _Region()
 
 
 def settle(batch, steps, spl=10, targets=None):
@@ -126,12 +96,10 @@ def settle(batch, steps, spl=10, targets=None):
         done += k
 
 
-def time_batch(batch, steps, warmup, spl, targets=None, region=False):
+def time_batch(batch, steps, warmup, spl, targets=None):
     import numpy as np
     import torch
     torch.cuda.synchronize()
-    if region:
-        REGION.resume()
     for _ in range(max(1, warmup // spl)):
         batch.step(spl, targets)
     torch.cuda.synchronize()
@@ -146,8 +114,6 @@ def time_batch(batch, steps, warmup, spl, targets=None, region=False):
         ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    if region:
-        REGION.pause()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n_launch)])
     total_ms = ev[0].elapsed_time(ev[-1])
     st = batch.stats()
@@ -214,8 +180,7 @@ def time_graph(batch, steps, warmup, per_graph=10, spl=1):
                 p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), stats=st)
 
 
-def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False, settle_steps=200,
-                 region=False):
+def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False, settle_steps=200):
     """Settle, (tune,) warm up, then time; returns the scene, the raw timing and the summary."""
     import torch
     sc = S.by_name(name, n_envs, seed=seed)
@@ -226,7 +191,7 @@ def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1,
         saved = b.get_state()
         b.tune(10)
         b.reset_envs(torch.arange(n_envs, dtype=torch.int32, device="cuda"), saved)
-    r = time_graph(b, steps, warmup, spl=spl) if graph else time_batch(b, steps, warmup, spl, region=region)
+    r = time_graph(b, steps, warmup, spl=spl) if graph else time_batch(b, steps, warmup, spl)
     flop = algorithmic_flop(sc, r["stats"], sc.params)
     plan = b.plan()
     b.close()
@@ -373,7 +338,7 @@ def main():
     from paper_2410_00425_amd import ms, scenes as S
     torch.cuda.init()
     sc, r, head = run_workload(ms, S, args.workload, args.envs, args.steps, args.warmup, args.steps_per_launch,
-                               args.seed, args.lanes, settle_steps=args.settle, region=True)
+                               args.seed, args.lanes, settle_steps=args.settle)
     value = head["env_steps_per_s"]
     achieved = head["flop_per_launch"] / (r["launch_ms"] / 1e3)
     out = {

@@ -112,3 +112,37 @@ def test_load_generator_runs():
     s = L.summarize(recs, wall)
     srv.close()
     assert s["requests"] == 9 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_served_session_matches_oracle():
+    """A session served next to other sessions, compared directly with the float32 oracle (not
+    only with the same batch stepped alone): tray and arm sessions over 10 two-step requests,
+    the arm's targets redrawn at each request."""
+    from oracle.oracle import Oracle
+    from parity import compare_states
+    m = ms()
+    tray, arm, boxes = S.tray(48, seed=51), S.arm_cube(24, seed=52), S.drop_boxes(100, seed=53)
+    srv = m.Server(256 << 20)
+    st, sa, sb = srv.open(tray), srv.open(arm), srv.open(boxes)
+    o_t, o_a = Oracle(tray, 32), Oracle(arm, 32)
+    for r in range(10):
+        t = S.arm_targets(52, np.arange(24), r).reshape(-1).astype(np.float32)
+        reqs = [srv.submit(st, 2), srv.submit(sa, 2, t), srv.submit(sb, 1)]
+        for q in reqs:
+            srv.wait(q)
+        o_t.step(2, n_threads=8)
+        o_a.set_targets(t)
+        o_a.step(2, n_threads=8)
+    for sid, sc, o in ((st, tray, o_t), (sa, arm, o_a)):
+        g, w = srv.get_state(sid), o.state()
+        _, mm = o.counters()
+        bad, excused = compare_states(sc, g, w, mm)
+        assert not bad, (sc.name, bad)
+        same = sum(all(np.array_equal(g[k][:, sc.body_off[e]:sc.body_off[e + 1]],
+                                      w[k][:, sc.body_off[e]:sc.body_off[e + 1]].astype(np.float32))
+                       for k in ("pos", "quat", "linvel", "angvel")) for e in range(sc.n_envs))
+        assert same >= sc.n_envs - 2, (sc.name, same)
+    for s in (st, sa, sb):
+        srv.close_session(s)
+    srv.drain()
+    srv.close()
