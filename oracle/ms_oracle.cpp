@@ -5,7 +5,7 @@
 // exists to decide what the GPU step must compute.
 //
 // What it computes.  ManiSkill3 (arXiv 2410.00425) advances thousands of independent,
-// heterogeneous scenes with GPU rigid-body simulation (Sec. III-A), tuned by solver position /
+// heterogeneous scenes with GPU rigid-body simulation (Sec. III-C), tuned by solver position /
 // velocity iteration counts (App. E, Setup) and PD joint drives (App. B, Controller).  The paper
 // states no contact or solver equations, so this file implements one documented step model,
 // each phase named after the published method it restates:
@@ -14,12 +14,14 @@
 //      "Real-Time Collision Detection" 5.1.9; separating axes after Gottschalk's OBB test;
 //      Sutherland-Hodgman clipping) with a <= 4 point manifold reduction;
 //   S4 contact rows (tangent basis after Duff et al. 2017, "Building an Orthonormal Basis,
-//      Revisited"); S5 greedy colouring that fixes the Gauss-Seidel order;
+//      Revisited"); S4b (optional) cross-step warm start from a contact cache matched by pair
+//      and body-frame position; S5 greedy colouring that fixes the Gauss-Seidel order;
 //   S6 TGS substeps (sequential impulses with clamped accumulated impulses, warm start across
 //      substeps, speculative contacts, Baumgarte bias; patch friction at the manifold centroid
-//      with a torsional row; revolute point + 2 angular rows with a per-step Baumgarte rate and
-//      extra joint-only passes; PD drive as a soft row after Catto, "Soft Constraints", GDC
-//      2011); symplectic Euler on offsets from the step-start pose;
+//      with a torsional row; revolute point + 2 angular rows, prismatic rotation lock + 2 rows
+//      across the slide axis, each with a per-step Baumgarte rate and extra joint-only passes;
+//      one-sided limit rows; PD drive as a soft row after Catto, "Soft Constraints", GDC 2011);
+//      symplectic Euler on offsets from the step-start pose;
 //   S7 velocity iterations and a restitution pass; S8 write-back with a non-finite guard.
 // Templated on float and double.  Built with -ffp-contract=off: no fused multiply-add anywhere.
 // Parity pins live in the CPU test suite (closed forms, invariants, brute force).
@@ -61,7 +63,10 @@ struct Params {
     int32_t debug_export;
     int32_t joint_iters;
     int32_t max_manifolds_per_env;
+    int32_t warm_start;   // != 0: cross-step warm start from the contact cache (S4b)
+    float warm_radius;    // matching radius of the cache, m
 };
+static_assert(sizeof(Params) == 96, "parameter record layout");
 static_assert(sizeof(BodyDesc) == 88, "body record layout");
 static_assert(sizeof(JointDesc) == 92, "joint record layout");
 
@@ -191,7 +196,7 @@ template <class T> struct Joint {
 };
 
 struct PairRec { int32_t env, a, b, npts, decision, kind; double margin, lt1, lt2, ltw, mu, rt; };
-struct PointRec { int32_t env, pair; double p[3], n[3], s, ln; };
+struct PointRec { int32_t env, pair; double p[3], n[3], s, ln, ln0; };
 struct BlockRec { int32_t env, kind, index, colour; };
 // Per-env counters for the work model: candidate pairs per shape pair, points, manifolds, joints,
 // colours, dynamic bodies, static bodies.
@@ -664,6 +669,7 @@ template <class T> struct CRow {
     V3<T> rA, rB, n;
     T mn, s0, e, vnpre;
     T ln;
+    T ln0;     // the impulse the step started from (cross-step warm start; 0 otherwise), for the record
 };
 // One manifold: its points' normal rows plus the friction patch at the points' centroid (two
 // tangent rows bounded by mu times the summed normal impulse, and a torsional row about the
@@ -680,11 +686,20 @@ template <class T> struct Manifold {
 // drive; ll = lower and upper limit rows.
 template <class T> struct JState { T lp[3], la[3], ld, ll[2]; };
 
+// Contact cache of the cross-step warm start (S4b): the last step's manifolds in canonical order,
+// each with its pair key, the tangential impulse of its friction patch as a world vector, its
+// twist impulse and its points, and per point the contact position in body B's frame at that
+// step's start and the final normal impulse.
+template <class T> struct CacheMan { int key, first, count; V3<T> pt; T ltw; };
+template <class T> struct CachePt { V3<T> rl; T ln; };
+
 template <class T> struct Env {
     std::vector<Body<T>> bodies;
     std::vector<Joint<T>> joints;
     int status = 0;
     std::vector<V3<T>> force;  // net contact force on each body, averaged over the last step
+    std::vector<CacheMan<T>> cman;
+    std::vector<CachePt<T>> cpt;
 };
 
 template <class T> struct StepCtx {
@@ -870,6 +885,66 @@ template <class T> struct Stepper {
     }
 
     // ------------------------------------------------------------- S0..S5: detection and rows
+    // ------------------------------------------------------------- S4b cross-step warm start
+    // Pair key of a manifold, increasing in canonical order: (lower body, partner), the ground
+    // plane after every partner of its body.
+    static int man_key(const Manifold<T>& m) { return m.a >= 0 ? (m.a << 8) | m.b : (m.b << 8) | 0xFF; }
+    // Initial impulses from the last step's cache: a manifold whose pair is cached takes, for each
+    // of its points, the normal impulse of the nearest cached point of that pair (positions in
+    // body B's frame at the step start, squared distance below warm_radius^2, the first cached
+    // point on ties, none beyond the radius), and the cached tangential impulse vector projected
+    // on its new tangents t1, t2, and the cached twist impulse.
+    void warm_from_cache() {
+        const T r2 = T(P.warm_radius) * T(P.warm_radius);
+        const int nc = int(E.cman.size());
+        for (Manifold<T>& M : mans) {
+            const int key = man_key(M);
+            int lo = 0, hi = nc;
+            while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                if (E.cman[mid].key < key) lo = mid + 1; else hi = mid;
+            }
+            if (lo == nc || E.cman[lo].key != key) continue;
+            const CacheMan<T>& C = E.cman[lo];
+            const M3<T> RB = rotm(q0[M.b]);
+            for (int k = 0; k < M.count; ++k) {
+                CRow<T>& r = rows[M.first + k];
+                const V3<T> rl = mulT(RB, r.rB);
+                T best = r2;
+                int bj = -1;
+                for (int j = 0; j < C.count; ++j) {
+                    const V3<T> d = rl - E.cpt[C.first + j].rl;
+                    const T d2 = dot(d, d);
+                    if (d2 < best) { best = d2; bj = j; }
+                }
+                if (bj >= 0) r.ln = E.cpt[C.first + bj].ln;
+                r.ln0 = r.ln;
+            }
+            M.lt1 = dot(C.pt, M.t1);
+            M.lt2 = dot(C.pt, M.t2);
+            M.ltw = C.ltw;
+        }
+    }
+    // The cache for the next step: every manifold and point of this step with its final impulses.
+    void write_cache() {
+        E.cman.clear();
+        E.cpt.clear();
+        for (const Manifold<T>& M : mans) {
+            CacheMan<T> C;
+            C.key = man_key(M);
+            C.first = int(E.cpt.size());
+            C.count = M.count;
+            C.pt = M.lt1 * M.t1 + M.lt2 * M.t2;
+            C.ltw = M.ltw;
+            E.cman.push_back(C);
+            const M3<T> RB = rotm(q0[M.b]);
+            for (int k = 0; k < M.count; ++k) {
+                const CRow<T>& r = rows[M.first + k];
+                E.cpt.push_back(CachePt<T>{mulT(RB, r.rB), r.ln});
+            }
+        }
+    }
+
     void prepare(double& min_margin, int64_t* cnt) {
         const int n = int(E.bodies.size());
         const T delta = T(P.contact_offset);
@@ -983,6 +1058,7 @@ template <class T> struct Stepper {
                     r.s0 = o.pt[k].s;
                     r.e = e;
                     r.ln = 0;
+                    r.ln0 = 0;
                     rows.push_back(r);
                     csum = csum + p;
                     nsum = nsum + r.n;
@@ -1014,6 +1090,7 @@ template <class T> struct Stepper {
                 mans.push_back(M);
             }
         }
+        if (P.warm_start) warm_from_cache();
         cnt[CNT_POINTS] += int64_t(rows.size());
         cnt[CNT_MANIFOLDS] += int64_t(mans.size());
         cnt[CNT_JOINTS] += int64_t(E.joints.size());
@@ -1431,7 +1508,9 @@ template <class T> struct Stepper {
                 b.v = ld * (b.v + h * g);
                 b.w = ad * b.w;
             }
-            if (s > 0)
+            // warm start: the previous substep's impulses; in the first substep, those taken from
+            // the contact cache (joint impulses start from zero every step)
+            if (s > 0 || P.warm_start)
                 for (auto& ob : order) {
                     if (ob.second < nj) joint_warm(ob.second);
                     else manifold_warm(mans[ob.second - nj]);
@@ -1469,6 +1548,10 @@ template <class T> struct Stepper {
             for (T v : vals) if (!std::isfinite(double(v))) bad = true;
         }
         if (bad) { E.bodies = saved; E.status |= ST_NONFINITE; }
+        if (P.warm_start) {
+            if (bad) { E.cman.clear(); E.cpt.clear(); }
+            else write_cache();
+        }
         // net contact force averaged over the step: the step's contact impulses / dt (zero when
         // the step went non-finite)
         if (bad) E.force.assign(n, mk<T>(0, 0, 0));
@@ -1487,7 +1570,7 @@ template <class T> struct Stepper {
                     V3<T> p = m.base + (r.a >= 0 ? r.rA : r.rB + m.offB);
                     rec->points.push_back(PointRec{env_id, m.pair, {double(p.x), double(p.y), double(p.z)},
                                                    {double(r.n.x), double(r.n.y), double(r.n.z)}, double(r.s0),
-                                                   double(r.ln)});
+                                                   double(r.ln), double(r.ln0)});
                 }
             }
         }
@@ -1567,6 +1650,8 @@ template <class T> static int reset_env_random(const Params& P, Env<T>& E, Env<T
     }
     E.status = 0;
     E.force.assign(n, mk<T>(0, 0, 0));
+    E.cman.clear();
+    E.cpt.clear();
     return 0;
 }
 
@@ -1657,6 +1742,8 @@ template <class T> static void set_state_t(Handle* H, std::vector<Env<T>>& envs,
     const int B = H->body_off[H->n_envs];
     for (int e = 0; e < H->n_envs; ++e) {
         envs[e].status = 0;
+        envs[e].cman.clear();
+        envs[e].cpt.clear();
         for (size_t i = 0; i < envs[e].bodies.size(); ++i) {
             Body<T>& b = envs[e].bodies[i];
             int g = H->body_off[e] + int(i);
@@ -1750,9 +1837,9 @@ void or_record_points(void* h, int32_t* ids, double* out) {
     for (auto& r : H->recs)
         for (auto& p : r.points) {
             ids[2 * k] = p.env; ids[2 * k + 1] = p.pair;
-            double* o = out + 8 * k;
+            double* o = out + 9 * k;
             for (int i = 0; i < 3; ++i) { o[i] = p.p[i]; o[3 + i] = p.n[i]; }
-            o[6] = p.s; o[7] = p.ln;
+            o[6] = p.s; o[7] = p.ln; o[8] = p.ln0;
             ++k;
         }
 }

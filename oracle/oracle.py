@@ -3,7 +3,7 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg use this module.  It
 loads ``liboracle.so`` built from ``ms_oracle.cpp`` with g++ (no GPU code, no shared source with
 the GPU library).  Descriptor arrays are the records produced by the input generators: the
-oracle reads them by byte layout (88-byte bodies, 92-byte joints, 88-byte parameters).
+oracle reads them by byte layout (88-byte bodies, 92-byte joints, 96-byte parameters).
 """
 from __future__ import annotations
 
@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "ms_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 92, 88
+BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 92, 96
 N_COUNTERS = 20
 COUNTER_NAMES = ["pairs_tested", "candidates", "points", "manifolds", "colours", "dynamic", "static",
                  "joints"] + [f"kind{k}" for k in range(12)]
@@ -134,8 +134,8 @@ class Oracle:
     def record(self):
         """The last recorded step: candidate pairs (env, a, b, n_points, decision, kind) with their
         decision margin and friction patch (lambda_t1, lambda_t2, lambda_twist, mu, torsional
-        radius) in ``patch``; contact points (env, pair) + (p, n, s0, lambda_n); solver blocks
-        (env, kind, index, colour)."""
+        radius) in ``patch``; contact points (env, pair) + (p, n, s0, lambda_n, lambda_n at the
+        step start: the cross-step warm start's, else 0); solver blocks (env, kind, index, colour)."""
         L = lib()
         n = [C.c_int64(), C.c_int64(), C.c_int64()]
         L.or_record_sizes(self._h, *[C.byref(x) for x in n])
@@ -143,7 +143,7 @@ class Oracle:
         pairs = np.zeros((npair, 6), np.int32)
         pm = np.zeros((npair, 6))
         ids = np.zeros((npt, 2), np.int32)
-        pts = np.zeros((npt, 8))
+        pts = np.zeros((npt, 9))
         blocks = np.zeros((nblk, 4), np.int32)
         L.or_record_pairs(self._h, _ptr(pairs), _ptr(pm))
         L.or_record_points(self._h, _ptr(ids), _ptr(pts))

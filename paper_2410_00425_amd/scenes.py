@@ -40,8 +40,9 @@ PARAMS_DTYPE = np.dtype([
     ("max_depen_vel", "<f4"), ("joint_baumgarte", "<f4"), ("bounce_threshold", "<f4"),
     ("lin_damping", "<f4"), ("ang_damping", "<f4"), ("max_contacts_per_env", "<i4"),
     ("debug_export", "<i4"), ("joint_iters", "<i4"), ("max_manifolds_per_env", "<i4"),
+    ("warm_start", "<i4"), ("warm_radius", "<f4"),
 ])
-assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 92 and PARAMS_DTYPE.itemsize == 88
+assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 92 and PARAMS_DTYPE.itemsize == 96
 
 SPHERE, CAPSULE, BOX = 0, 1, 2
 REVOLUTE, PRISMATIC = 0, 1
@@ -57,7 +58,7 @@ def make_params(**kw) -> np.ndarray:
                     contact_offset=0.01, baumgarte=0.2, max_depen_vel=1.0, joint_baumgarte=0.2,
                     bounce_threshold=1.0, lin_damping=0.0, ang_damping=0.0,
                     max_contacts_per_env=0, debug_export=0, joint_iters=4,
-                    max_manifolds_per_env=0)
+                    max_manifolds_per_env=0, warm_start=0, warm_radius=0.01)
     defaults.update(kw)
     for k, v in defaults.items():
         p[k] = v
