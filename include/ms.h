@@ -113,7 +113,16 @@ typedef struct {
  * selects the default min(6 * n_dyn + 8, 384) contact points per env, max_manifolds_per_env <= 0
  * min(3 * n_dyn + 4, 192) manifolds (n_dyn: dynamic bodies of the env); pairs beyond them lose
  * their points and the env's status gets bit 2.  debug_export != 0 makes the step also write the last
- * step's pair list, contact points and colours (read with ms_get_contacts). */
+ * step's pair list, contact points and colours (read with ms_get_contacts).
+ * Cross-step warm start (warm_start != 0; the solver's iteration counts of App. E, Setup, assume
+ * contacts that persist across steps): each step ends by caching, per env in the workspace, every
+ * manifold's body pair, its friction patch's tangential impulse as a world vector and its twist
+ * impulse, and every contact point's final normal impulse with its position in body B's frame at
+ * the step start.  The next step starts each new point from the nearest cached point of the same
+ * body pair closer than warm_radius (none beyond it), projects the cached tangential impulse on
+ * the patch's new tangents, and applies these impulses in its first substep as well.  The cache
+ * is part of the batch, not of ms_state_view: a step is then a function of the state and the
+ * cache; ms_reset_envs and ms_reset_envs_random clear the listed envs' caches.  96 bytes. */
 typedef struct {
     float dt;
     int32_t pos_iters;
@@ -135,6 +144,8 @@ typedef struct {
     int32_t debug_export;
     int32_t joint_iters;
     int32_t max_manifolds_per_env;
+    int32_t warm_start;   /* != 0: cross-step warm start from the contact cache (see below) */
+    float warm_radius;    /* m: matching radius of the contact cache */
 } ms_sim_params;
 
 /* Caller-owned device buffers in structure-of-arrays form over all B bodies of the batch:

@@ -55,7 +55,19 @@ struct BatchDev {
     float* forces;
     // count of env ids outside [0, E) met by the reset kernels
     int* bad_ids;
+    // cross-step warm start: the contact cache of the last step (null when off).  Per env: header
+    // {manifolds, points}; manifold records {pair key, first | count << 16 (int bits), tangential
+    // impulse vector (3), twist impulse} at cache_man_off[e]; point records {position in body B's
+    // frame at the step start (3), normal impulse} at cache_pt_off[e]
+    int* cache_hdr;
+    float* cache_man;
+    const int* cache_man_off;
+    float* cache_pt;
+    const int* cache_pt_off;
+    float warm_radius;
+    int pad6;
 };
+constexpr int CM_WORDS = 6, CP_WORDS = 4;
 
 // Work counters per env: steps, candidate pairs per shape kind (3 * min + max shape for body
 // pairs, 9 + shape for plane pairs), contact points, manifolds, colours.

@@ -16,7 +16,7 @@
 #include "ms.h"
 #include "ms_dev.h"
 
-static_assert(sizeof(ms_body_desc) == 88 && sizeof(ms_joint_desc) == 92 && sizeof(ms_sim_params) == 88,
+static_assert(sizeof(ms_body_desc) == 88 && sizeof(ms_joint_desc) == 92 && sizeof(ms_sim_params) == 96,
               "descriptor layouts are part of the ABI");
 
 using namespace msdev;
@@ -88,14 +88,18 @@ struct LdsClass {
 };
 
 typedef void (*StepKernel)(const BatchDev*, const Tile*, int, const TileEnv*, int);
-inline StepKernel kernel_of(int variant) {
+// Kernel of a variant; opt selects the twin that carries the optional phases (contact forces,
+// contact cache).
+inline StepKernel kernel_of(int variant, bool opt) {
     switch (variant) {
-        case 1: return ms_step_kernel_w2;
-        case 2: return ms_step_kernel_one;
-        case 3: return ms_step_kernel_one_w2;
-        default: return ms_step_kernel;
+        case 1: return opt ? ms_step_kernel_w2_opt : ms_step_kernel_w2;
+        case 2: return opt ? ms_step_kernel_one_opt : ms_step_kernel_one;
+        case 3: return opt ? ms_step_kernel_one_w2_opt : ms_step_kernel_one_w2;
+        default: return opt ? ms_step_kernel_opt : ms_step_kernel;
     }
 }
+typedef void (*BinsKernel)(const BatchDev*, const Tile*, const Bin*, int, const TileEnv*, int);
+inline BinsKernel bins_kernel(bool opt) { return opt ? ms_step_kernel_bins_opt : ms_step_kernel_bins; }
 inline bool one_env_tile(const Tile& t) { return t.lanes == WAVE && t.count == 1; }
 
 // Cut tiles sorted by LDS need (largest first) into launch classes — a new class when a tile
@@ -144,14 +148,14 @@ void cut_classes(int n, TileRef tile_ref, bool split_ok, ClassVec& cls) {
 
 // Launch one class on stream s: the one-env part, then the general part.
 ms_status launch_class(const LdsClass& c, const BatchDev* dbd, const Tile* tiles, const TileEnv* tenv, int n_steps,
-                       int grid_cap, hipStream_t s) {
+                       int grid_cap, hipStream_t s, bool opt) {
     const size_t lds = size_t(c.lds_words) * 4;
     const int parts[2][3] = {{c.first_tile, c.n_one, c.variant},
                              {c.first_tile + c.n_one, c.n_tiles - c.n_one, c.variant_gen}};
     for (const auto& pt : parts) {
         if (pt[1] <= 0) continue;
         const int grid = grid_cap > 0 ? std::max(1, std::min(pt[1], grid_cap)) : pt[1];
-        hipLaunchKernelGGL(kernel_of(pt[2]), dim3(grid), dim3(WAVE), lds, s, dbd, tiles + pt[0], pt[1], tenv, n_steps);
+        hipLaunchKernelGGL(kernel_of(pt[2], opt), dim3(grid), dim3(WAVE), lds, s, dbd, tiles + pt[0], pt[1], tenv, n_steps);
         HIP_OK(hipGetLastError());
     }
     return MS_OK;
@@ -175,7 +179,8 @@ struct Plan {
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
     size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, save, status, bpar, body_off, joint_off, jrec, targets, tiles,
-        bins, tenv, bd, stats, forces, bad_ids, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
+        bins, tenv, bd, stats, forces, bad_ids, cache_hdr, cache_man, cache_man_off, cache_pt, cache_pt_off, cache_save,
+        cache_bytes, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
 
 ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
@@ -187,6 +192,8 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     if (p->vel_iters < 0 || p->vel_iters > 256) return fail(MS_E_INVALID_ARG, "vel_iters out of range [0, 256]");
     if (p->solver != MS_SOLVER_TGS && p->solver != MS_SOLVER_PGS) return fail(MS_E_INVALID_ARG, "unknown solver");
     if (p->joint_iters < 0 || p->joint_iters > 64) return fail(MS_E_INVALID_ARG, "joint_iters out of range [0, 64]");
+    if (p->warm_start && !(std::isfinite(p->warm_radius) && p->warm_radius >= 0.0f))
+        return fail(MS_E_INVALID_ARG, "warm_radius must be finite and >= 0");
     if (s->env_body_off[0] != 0 || s->env_joint_off[0] != 0) return fail(MS_E_INVALID_ARG, "offsets must start at 0");
     for (int e = 0; e < s->n_envs; ++e) {
         int nb = s->env_body_off[e + 1] - s->env_body_off[e];
@@ -364,6 +371,18 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.stats = take(E * NSTAT * 8);
     L.forces = take(3 * B * 4);
     L.bad_ids = take(4);
+    if (p->warm_start) {
+        // contact cache: header [E][2], manifold records [sum mcap][6], point records [sum cap][4],
+        // and a copy of all three for the tuner's save / restore
+        const size_t hdr = E * 8, man = size_t(pl.dbg_man_off[E]) * CM_WORDS * 4, pt = size_t(pl.dbg_pt_off[E]) * CP_WORDS * 4;
+        L.cache_hdr = take(hdr);
+        L.cache_man = take(man);
+        L.cache_pt = take(pt);
+        L.cache_man_off = take((E + 1) * 4);
+        L.cache_pt_off = take((E + 1) * 4);
+        L.cache_bytes = L.cache_man_off - L.cache_hdr;   // hdr + man + pt sections, contiguous
+        L.cache_save = take(L.cache_bytes);
+    }
     if (p->debug_export) {
         L.dbg_pairs = take(size_t(pl.dbg_pair_off[E]) * 16);
         L.dbg_pair_off = take((E + 1) * 4);
@@ -449,6 +468,9 @@ struct ms_batch {
     }
 };
 
+// The batch runs the kernel twins with the optional phases (contact forces or contact cache on).
+static bool batch_opt(const ms_batch* b) { return b->forces_on || b->P.warm_start != 0; }
+
 namespace {
 template <class T> T* at(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
 
@@ -476,6 +498,14 @@ void fill_batchdev(ms_batch* b) {
     d.lin_damp = p.lin_damping; d.ang_damp = p.ang_damping;
     d.stats = at<long long>(w, L.stats);
     d.bad_ids = at<int>(w, L.bad_ids);
+    if (p.warm_start) {
+        d.cache_hdr = at<int>(w, L.cache_hdr);
+        d.cache_man = at<float>(w, L.cache_man);
+        d.cache_man_off = at<int>(w, L.cache_man_off);
+        d.cache_pt = at<float>(w, L.cache_pt);
+        d.cache_pt_off = at<int>(w, L.cache_pt_off);
+        d.warm_radius = p.warm_radius;
+    }
     d.forces = b->forces_on ? at<float>(w, L.forces) : nullptr;
     if (p.debug_export) {
         d.dbg_pairs = at<int>(w, L.dbg_pairs); d.dbg_pair_off = at<int>(w, L.dbg_pair_off);
@@ -690,6 +720,13 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     std::vector<float> zforces(3 * B + 1, 0.0f);
     if (e == hipSuccess) e = up(L.forces, zforces.data(), 3 * B * 4);
     if (e == hipSuccess) e = up(L.bad_ids, zforces.data(), 4);
+    if (params->warm_start) {
+        std::vector<int> zh(2 * E, 0);
+        if (e == hipSuccess) e = up(L.cache_hdr, zh.data(), 2 * E * 4);
+        if (e == hipSuccess) e = up(L.cache_man_off, b->plan.dbg_man_off.data(), (E + 1) * 4);
+        if (e == hipSuccess) e = up(L.cache_pt_off, b->plan.dbg_pt_off.data(), (E + 1) * 4);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
     if (e == hipSuccess) e = up(L.bpar, bp.data(), 3 * B * 16);
     if (e == hipSuccess) e = up(L.body_off, b->body_off.data(), (E + 1) * 4);
     if (e == hipSuccess) e = up(L.joint_off, b->joint_off.data(), (E + 1) * 4);
@@ -765,10 +802,11 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     const Tile* tiles = at<Tile>(b->ws, b->lay.tiles);
     const TileEnv* tenv = at<TileEnv>(b->ws, b->lay.tenv);
     const int grid_cap = b->max_resident_groups;
-    if (cls.size() == 1) return launch_class(cls[0], b->dbd, tiles, tenv, int(n_steps), grid_cap, s);
+    const bool opt = batch_opt(b);
+    if (cls.size() == 1) return launch_class(cls[0], b->dbd, tiles, tenv, int(n_steps), grid_cap, s, opt);
     if (!b->plan.bins.empty()) {   // every tile in one launch, a bin per workgroup
         const int nb = int(b->plan.bins.size());
-        hipLaunchKernelGGL(ms_step_kernel_bins, dim3(nb), dim3(WAVE * BIN_WAVES), size_t(b->plan.bin_words) * 4, s, b->dbd,
+        hipLaunchKernelGGL(bins_kernel(opt), dim3(nb), dim3(WAVE * BIN_WAVES), size_t(b->plan.bin_words) * 4, s, b->dbd,
                            tiles, at<Bin>(b->ws, b->lay.bins), nb, tenv, int(n_steps));
         HIP_OK(hipGetLastError());
         return MS_OK;
@@ -780,7 +818,7 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     for (size_t k = 0; k < cls.size(); ++k) {
         hipStream_t sk = k == 0 ? s : b->side[k];
         if (k > 0) HIP_OK(hipStreamWaitEvent(sk, b->ev_fork, 0));
-        if (ms_status st = launch_class(cls[k], b->dbd, tiles, tenv, int(n_steps), grid_cap, sk); st != MS_OK) return st;
+        if (ms_status st = launch_class(cls[k], b->dbd, tiles, tenv, int(n_steps), grid_cap, sk, opt); st != MS_OK) return st;
         if (k > 0) {
             HIP_OK(hipEventRecord(b->ev_join[k], sk));
             HIP_OK(hipStreamWaitEvent(s, b->ev_join[k], 0));
@@ -861,6 +899,7 @@ ms_status ms_get_joint_positions(ms_batch* b, float* dev_out, void* hip_stream) 
 
 ms_status ms_set_contact_forces(ms_batch* b, int32_t enable, void* hip_stream) {
     if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+    if (b->forces_on != (enable != 0)) b->plan_gen++;   // the kernel twin changes: captured graphs are stale
     b->forces_on = enable != 0;
     b->hbd.forces = b->forces_on ? at<float>(b->ws, b->lay.forces) : nullptr;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1011,6 +1050,7 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
     size_t o = L.save;
     for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + o, w + st_off[k], st_bytes[k], hipMemcpyDeviceToDevice, s)); o += st_bytes[k]; }
     HIP_OK(hipMemcpyAsync(w + o, w + L.status, E * 4, hipMemcpyDeviceToDevice, s));
+    if (b->P.warm_start) HIP_OK(hipMemcpyAsync(w + L.cache_save, w + L.cache_hdr, L.cache_bytes, hipMemcpyDeviceToDevice, s));
     std::vector<long long> stats_save(E * NSTAT);
     HIP_OK(hipMemcpyAsync(stats_save.data(), w + L.stats, E * NSTAT * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -1018,6 +1058,7 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
         size_t oo = L.save;
         for (int k = 0; k < 4; ++k) { HIP_OK(hipMemcpyAsync(w + st_off[k], w + oo, st_bytes[k], hipMemcpyDeviceToDevice, s)); oo += st_bytes[k]; }
         HIP_OK(hipMemcpyAsync(w + L.status, w + oo, E * 4, hipMemcpyDeviceToDevice, s));
+        if (b->P.warm_start) HIP_OK(hipMemcpyAsync(w + L.cache_hdr, w + L.cache_save, L.cache_bytes, hipMemcpyDeviceToDevice, s));
         return MS_OK;
     };
     hipEvent_t e0, e1;
@@ -1076,12 +1117,12 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
             for (int v = part == 0 ? 2 : 0; v < (part == 0 ? 4 : 2) && st == MS_OK; ++v) {
                 st = restore();
                 if (st != MS_OK) break;
-                hipLaunchKernelGGL(kernel_of(v), dim3(count), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
+                hipLaunchKernelGGL(kernel_of(v, batch_opt(b)), dim3(count), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
                                    tiles + first, count, tenv, 1);
                 HIP_OK(hipEventRecord(e0, s));
                 for (int t = 0; t < trial_steps; ++t)
-                    hipLaunchKernelGGL(kernel_of(v), dim3(count), dim3(WAVE), size_t(c.lds_words) * 4, s, b->dbd,
-                                       tiles + first, count, tenv, 1);
+                    hipLaunchKernelGGL(kernel_of(v, batch_opt(b)), dim3(count), dim3(WAVE), size_t(c.lds_words) * 4,
+                                       s, b->dbd, tiles + first, count, tenv, 1);
                 HIP_OK(hipGetLastError());
                 HIP_OK(hipEventRecord(e1, s));
                 HIP_OK(hipEventSynchronize(e1));
@@ -1252,6 +1293,8 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     for (int i = 0; i < n_batches; ++i)
         if (batches[i]->device != dev) return fail(MS_E_INVALID_ARG, "batch %d lives on device %d, not %d", i, batches[i]->device, dev);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    bool opt = false;
+    for (int i = 0; i < n_batches; ++i) opt = opt || batch_opt(batches[i]);
     Staging& st = g_stage;
     if (st.device != dev) {
         st.release();
@@ -1321,7 +1364,7 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     if (!bins.empty()) {
         const Bin* dbins = reinterpret_cast<const Bin*>(d + (reinterpret_cast<char*>(hb) - h));
         const int nb = int(bins.size());
-        hipLaunchKernelGGL(ms_step_kernel_bins, dim3(nb), dim3(WAVE * BIN_WAVES), size_t(bin_words) * 4, s, dtb, dtt, dbins,
+        hipLaunchKernelGGL(bins_kernel(opt), dim3(nb), dim3(WAVE * BIN_WAVES), size_t(bin_words) * 4, s, dtb, dtt, dbins,
                            nb, dte, int(n_steps));
         HIP_OK(hipGetLastError());
         return MS_OK;
@@ -1337,7 +1380,7 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     for (size_t k = 0; k < cls.size(); ++k) {
         hipStream_t sk = k == 0 ? s : st.side[k];
         if (k > 0) HIP_OK(hipStreamWaitEvent(sk, st.ev_fork, 0));
-if (ms_status r = launch_class(cls[k], dtb, dtt, dte, int(n_steps), 0, sk); r != MS_OK) return r;
+        if (ms_status r = launch_class(cls[k], dtb, dtt, dte, int(n_steps), 0, sk, opt); r != MS_OK) return r;
         if (k > 0) {
             HIP_OK(hipEventRecord(st.ev_join[k], sk));
             HIP_OK(hipStreamWaitEvent(s, st.ev_join[k], 0));
@@ -1392,6 +1435,8 @@ ms_status ms_step_many_noalloc(ms_batch* const* batches, const float* const* dev
     for (int i = 0; i < n_batches; ++i)
         if (batches[i]->device != dev) return fail(MS_E_INVALID_ARG, "batch %d lives on device %d, not %d", i, batches[i]->device, dev);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    bool opt = false;
+    for (int i = 0; i < n_batches; ++i) opt = opt || batch_opt(batches[i]);
 
     std::lock_guard<std::mutex> lock(g_noalloc_mu);
     if (!g_noalloc_dev[dev]) {
@@ -1456,12 +1501,12 @@ ms_status ms_step_many_noalloc(ms_batch* const* batches, const float* const* dev
     if (cls.size() > 1) {
         const Bin* dbins = reinterpret_cast<const Bin*>(d + (reinterpret_cast<char*>(hb) - h));
         const int nb = int(bins.size());
-        hipLaunchKernelGGL(ms_step_kernel_bins, dim3(nb), dim3(WAVE * BIN_WAVES), size_t(bin_words) * 4, s, dtb, dtt, dbins,
+        hipLaunchKernelGGL(bins_kernel(opt), dim3(nb), dim3(WAVE * BIN_WAVES), size_t(bin_words) * 4, s, dtb, dtt, dbins,
                            nb, dte, int(n_steps));
         HIP_OK(hipGetLastError());
         return MS_OK;
     }
-    return launch_class(cls[0], dtb, dtt, dte, int(n_steps), 0, s);
+    return launch_class(cls[0], dtb, dtt, dte, int(n_steps), 0, s, opt);
 }
 
 }  // extern "C"

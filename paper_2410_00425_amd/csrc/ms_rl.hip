@@ -158,6 +158,7 @@ extern "C" __global__ void __launch_bounds__(64) ms_reset_random_kernel(BatchDev
         if (nz.targets_follow) const_cast<float*>(bd.targets)[j0 + j] = q0;
     }
     bd.status[e] = 0;
+    if (bd.cache_hdr) { bd.cache_hdr[2 * e] = 0; bd.cache_hdr[2 * e + 1] = 0; }
 }
 
 // Target-delta joint position controller: target += clip(a, -1, 1) (high - low) / 2 per joint,

@@ -2272,7 +2272,101 @@ __device__ __forceinline__ void accumulate_forces(const EnvCtx& c, int nn, int n
     }
 }
 
-template <bool ONE>
+// ----------------------------------------------------------------------------- S4b contact cache
+// Pair key of manifold m, increasing in canonical order: (lower body, partner), the ground plane
+// after every partner of its body.
+__device__ __forceinline__ int man_key(const EnvCtx& c, int m) {
+    int a, b, first, cnt;
+    man_header(c, m, a, b, first, cnt);
+    return a >= 0 ? (a << 8) | b : (b << 8) | 0xFF;
+}
+// Initial impulses from the last step's cache (lane per manifold): a manifold whose pair is
+// cached takes, for each point, the normal impulse of the nearest cached point of that pair
+// (positions in body B's frame at the step start, squared distance below warm_radius^2, the
+// first cached point on ties), and the cached tangential impulse vector projected on its new
+// tangents, and the cached twist impulse.  The cached keys are staged in the candidate area
+// (free between the row setup and the block lists) for a binary search per lane.
+__device__ __forceinline__ void warm_from_cache(const EnvCtx& c, int nman, int li, int G) {
+    const BatchDev& bd = *c.bd;
+    __threadfence();   // this env's cache may have been written by this wave's previous step
+    const int nc = bd.cache_hdr[2 * c.env];
+    const int* CM = reinterpret_cast<const int*>(bd.cache_man) + size_t(bd.cache_man_off[c.env]) * CM_WORDS;
+    const float* CP = bd.cache_pt + size_t(bd.cache_pt_off[c.env]) * CP_WORDS;
+    int* KEYS = iptr(c.L + c.lay.CAND);
+    for (int k = li; k < nc; k += G) KEYS[k] = CM[k * CM_WORDS];
+    wave_sync();
+    const float r2 = bd.warm_radius * bd.warm_radius;
+    for (int m = li; m < nman; m += G) {
+        const int key = man_key(c, m);
+        int lo = 0, hi = nc;
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (KEYS[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        if (lo == nc || KEYS[lo] != key) continue;
+        const int* rec = CM + lo * CM_WORDS;
+        const int cfc = rec[1];
+        const int cfirst = cfc & 0xFFFF, ccount = cfc >> 16;
+        const V3 pt = v3(__int_as_float(rec[2]), __int_as_float(rec[3]), __int_as_float(rec[4]));
+        int a, b, first, cnt;
+        man_header(c, m, a, b, first, cnt);
+        const M3 RB = rotm(ldp4(c, b, P_Q0));
+        for (int k = first; k < first + cnt; ++k) {
+            const V3 rl = mulTv(RB, pr3(c, R_RB, k));
+            float best = r2;
+            int bj = -1;
+            for (int j = 0; j < ccount; ++j) {
+                const float* q = CP + (cfirst + j) * CP_WORDS;
+                const V3 d = rl - v3(q[0], q[1], q[2]);
+                const float d2 = dot3(d, d);
+                if (d2 < best) { best = d2; bj = j; }
+            }
+            if (bj >= 0) pr(c, R_LN, k) = CP[(cfirst + bj) * CP_WORDS + 3];
+        }
+        const V3 t1 = mf3(c, M_T1, m);
+        mfr(c, M_LT1, m) = dot3(pt, t1);
+        mfr(c, M_LT2, m) = dot3(pt, cross3(mf3(c, M_NB, m), t1));
+        mfr(c, M_LTW, m) = __int_as_float(rec[5]);
+    }
+    wave_sync();
+}
+// The cache for the next step (lane per manifold): every manifold of this step with its final
+// impulses and its points' positions in body B's frame; a step that went non-finite leaves an
+// empty cache.
+__device__ __forceinline__ void write_cache(const EnvCtx& c, int nman, int npts, bool bad, int li, int G) {
+    const BatchDev& bd = *c.bd;
+    int* CM = reinterpret_cast<int*>(bd.cache_man) + size_t(bd.cache_man_off[c.env]) * CM_WORDS;
+    float* CP = bd.cache_pt + size_t(bd.cache_pt_off[c.env]) * CP_WORDS;
+    if (li == 0) {
+        bd.cache_hdr[2 * c.env] = bad ? 0 : nman;
+        bd.cache_hdr[2 * c.env + 1] = bad ? 0 : npts;
+    }
+    if (bad) return;
+    for (int m = li; m < nman; m += G) {
+        int a, b, first, cnt;
+        man_header(c, m, a, b, first, cnt);
+        const V3 t1 = mf3(c, M_T1, m);
+        const V3 pt = mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * cross3(mf3(c, M_NB, m), t1);
+        int* rec = CM + m * CM_WORDS;
+        rec[0] = a >= 0 ? (a << 8) | b : (b << 8) | 0xFF;
+        rec[1] = first | (cnt << 16);
+        rec[2] = __float_as_int(pt.x); rec[3] = __float_as_int(pt.y); rec[4] = __float_as_int(pt.z);
+        rec[5] = __float_as_int(mf(c, M_LTW, m));
+        const M3 RB = rotm(ldp4(c, b, P_Q0));
+        for (int k = first; k < first + cnt; ++k) {
+            const V3 rl = mulTv(RB, pr3(c, R_RB, k));
+            float* q = CP + k * CP_WORDS;
+            q[0] = rl.x; q[1] = rl.y; q[2] = rl.z; q[3] = pr(c, R_LN, k);
+        }
+    }
+}
+__device__ __forceinline__ bool warm_on(const EnvCtx& c) {
+    return *reinterpret_cast<int* const volatile*>(&c.bd->cache_hdr) != nullptr;
+}
+
+// OPT: the build with the optional phases (contact-force readout, contact cache); the default
+// builds leave them out entirely, so that they cost the plain step no registers.
+template <bool ONE, bool OPT>
 __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict__ batches, const Tile tile,
                                           const TileEnv* __restrict__ tenv, int n_steps, int lane) {
     {
@@ -2502,6 +2596,10 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 SC[16 + STAT_MANIFOLDS] += nman;
             }
             wave_sync();
+            // --------------------------------------------------------- S4b cross-step warm start
+            // (the batch's flag is re-read at each use, a volatile scalar load, so that it holds
+            // no register through the substeps)
+            if (OPT && !frozen && warm_on(c)) warm_from_cache(c, nman, li, G);
 
             // --------------------------------------------------------- S5 colouring
             if (G == WAVE) {
@@ -2520,7 +2618,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             const int nmanA = frozen ? 0 : SC[SC_NMAN];
 
             // --------------------------------------------------------- S6 substeps
-            if (forces_on(c)) {
+            if (OPT && forces_on(c)) {
                 for (int i = li; i < nn; i += G) {
                     c.L[l.AABB + i] = 0.0f; c.L[l.AABB + n + i] = 0.0f; c.L[l.AABB + 2 * n + i] = 0.0f;
                 }
@@ -2529,19 +2627,20 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             const float admp = 1.0f / (1.0f + h * bd.ang_damp);
             // warm start body by body: fused with gravity in joint-free waves, after the joint pass
             // in the others
-            if (S > 1) {
+            if (S > 1 || (OPT && warm_on(c))) {
                 if (G == WAVE) build_body_lists_wave(c, nn, nmanA, li);
                 else build_body_lists(c, nn, nmanA, li, G);
                 wave_sync();
             }
             for (int s = 0; s < S; ++s) {
-                const bool gather = pipe && s > 0;
+                // warm start: the previous substep's impulses, or the cached ones in the first
+                const bool gather = pipe && (s > 0 || (OPT && !frozen && warm_on(c)));
                 for (int i = li; i < nn; i += G)
                     if (is_dyn(c, i)) body_substep_start(c, i, h, ldmp, admp, gather);
                 bias_pass(c, nmanA, h, false, li, G);
                 for (int j = li; j < (frozen ? 0 : nj); j += G) joint_prep(c, j, h);
                 wave_sync();
-                if (s > 0 && !pipe) {   // waves with joints: gathered per body once the joint pass has run
+                if ((s > 0 || (OPT && !frozen && warm_on(c))) && !pipe) {   // waves with joints: gathered per body once the joint pass has run
                     for (int i = li; i < nn; i += G)
                         if (is_dyn(c, i)) body_warm_gather(c, i);
                     wave_sync();
@@ -2550,7 +2649,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                     for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
                     (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
                 }
-                if (s + 1 < S && forces_on(c)) {
+                if (OPT && s + 1 < S && forces_on(c)) {
                     wave_sync();
                     accumulate_forces(c, nn, nmanA, li, G);
                 }
@@ -2597,10 +2696,11 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 if (li == 0) SC[SC_STATUS] |= 1;
             }
             wave_sync();
+            if (OPT && !frozen && warm_on(c)) write_cache(c, nmanA, SC[SC_NPTS], anybad, li, G);
             // --------------------------------------------------------- contact forces
             // the step's contact impulses / dt, written for the last step of the launch (zero for
             // a frozen env or a step that went non-finite)
-            if (step == n_steps - 1 && forces_on(c)) {
+            if (OPT && step == n_steps - 1 && forces_on(c)) {
                 if (!anybad) accumulate_forces(c, nn, nmanA, li, G);
                 const float idt = 1.0f / bd.dt;
                 for (int i = li; i < nA; i += G) {
@@ -2645,50 +2745,22 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
 }
 
 // Workgroups of one wavefront walking the tile list.
-template <bool ONE>
+template <bool ONE, bool OPT>
 __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restrict__ batches,
                                            const Tile* __restrict__ tiles, int n_tiles,
                                            const TileEnv* __restrict__ tenv, int n_steps) {
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x)
-        step_tile<ONE>(lds, batches, tiles[t], tenv, n_steps, int(threadIdx.x));
-}
-
-// Builds of the same step: any tiling with unconstrained register allocation (small envs, where
-// the wave count is bounded by LDS anyway) or capped at 256 registers per lane (two waves per
-// SIMD); and the same two for launches whose tiles all hold one env served by the whole
-// wavefront.  The planner / tuner picks one per LDS class.
-extern "C" __global__ void __launch_bounds__(64) ms_step_kernel(const BatchDev* __restrict__ batches,
-                                                              const Tile* __restrict__ tiles, int n_tiles,
-                                                              const TileEnv* __restrict__ tenv, int n_steps) {
-    extern __shared__ float lds[];
-    step_tiles<false>(lds, batches, tiles, n_tiles, tenv, n_steps);
-}
-extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-ms_step_kernel_w2(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, int n_tiles,
-                  const TileEnv* __restrict__ tenv, int n_steps) {
-    extern __shared__ float lds[];
-    step_tiles<false>(lds, batches, tiles, n_tiles, tenv, n_steps);
-}
-extern "C" __global__ void __launch_bounds__(64) ms_step_kernel_one(const BatchDev* __restrict__ batches,
-                                                                  const Tile* __restrict__ tiles, int n_tiles,
-                                                                  const TileEnv* __restrict__ tenv, int n_steps) {
-    extern __shared__ float lds[];
-    step_tiles<true>(lds, batches, tiles, n_tiles, tenv, n_steps);
-}
-extern "C" __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-ms_step_kernel_one_w2(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, int n_tiles,
-                      const TileEnv* __restrict__ tenv, int n_steps) {
-    extern __shared__ float lds[];
-    step_tiles<true>(lds, batches, tiles, n_tiles, tenv, n_steps);
+        step_tile<ONE, OPT>(lds, batches, tiles[t], tenv, n_steps, int(threadIdx.x));
 }
 
 // One launch for every tile of a batch: workgroups of BIN_WAVES wavefronts, one bin each; wave w
 // runs tile w of its bin in the bin's LDS at that tile's offset (the scalar-env build for a tile
 // of one env on all 64 lanes, the general build otherwise).  Waves of a bin share nothing
 // but the allocation (every env lives in one wave), so they need no barrier.
-extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) __attribute__((amdgpu_waves_per_eu(2)))
-ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles,
-                    const Bin* __restrict__ bins, int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
+template <bool OPT>
+__device__ __forceinline__ void step_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles,
+                                          const Bin* __restrict__ bins, int n_bins, const TileEnv* __restrict__ tenv,
+                                          int n_steps) {
     extern __shared__ float lds[];
     const int wave = int(threadIdx.x) / WAVE;
     const int b = int(blockIdx.x);
@@ -2697,8 +2769,41 @@ ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict
     if (wave >= bin.count) return;
     const Tile tile = tiles[bin.tile[wave]];
     const int lane = int(threadIdx.x) & (WAVE - 1);
-    if (tile.lanes == WAVE && tile.count == 1) step_tile<true>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
-    else step_tile<false>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
+    if (tile.lanes == WAVE && tile.count == 1) step_tile<true, OPT>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
+    else step_tile<false, OPT>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
+}
+
+// Builds of the same step: any tiling with unconstrained register allocation (small envs, where
+// the wave count is bounded by LDS anyway) or capped at 256 registers per lane (two waves per
+// SIMD); the same two for launches whose tiles all hold one env served by the whole wavefront;
+// and the bins launch.  The planner / tuner picks one per LDS class.  The *_opt twins carry the
+// optional phases (batches with contact forces or the contact cache on).
+#define MS_TILE_KERNEL(NAME, ONE, OPT, ATTR)                                                                   \
+    extern "C" __global__ void __launch_bounds__(64) ATTR NAME(const BatchDev* __restrict__ batches,            \
+                                                               const Tile* __restrict__ tiles, int n_tiles,    \
+                                                               const TileEnv* __restrict__ tenv, int n_steps) { \
+        extern __shared__ float lds[];                                                                         \
+        step_tiles<ONE, OPT>(lds, batches, tiles, n_tiles, tenv, n_steps);                                      \
+    }
+#define MS_W2 __attribute__((amdgpu_waves_per_eu(2)))
+MS_TILE_KERNEL(ms_step_kernel, false, false, )
+MS_TILE_KERNEL(ms_step_kernel_w2, false, false, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_one, true, false, )
+MS_TILE_KERNEL(ms_step_kernel_one_w2, true, false, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_opt, false, true, )
+MS_TILE_KERNEL(ms_step_kernel_w2_opt, false, true, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_one_opt, true, true, )
+MS_TILE_KERNEL(ms_step_kernel_one_w2_opt, true, true, MS_W2)
+
+extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) MS_W2
+ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, const Bin* __restrict__ bins,
+                    int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
+    step_bins<false>(batches, tiles, bins, n_bins, tenv, n_steps);
+}
+extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) MS_W2
+ms_step_kernel_bins_opt(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, const Bin* __restrict__ bins,
+                        int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
+    step_bins<true>(batches, tiles, bins, n_bins, tenv, n_steps);
 }
 
 // ============================================================================= reset kernel
@@ -2726,5 +2831,8 @@ extern "C" __global__ void __launch_bounds__(64) ms_reset_kernel(BatchDev bd, co
         if (bd.forces)
             for (int r = 0; r < 3; ++r) bd.forces[r * B + gi] = 0.0f;
     }
-    if (threadIdx.x == 0) bd.status[e] = 0;
+    if (threadIdx.x == 0) {
+        bd.status[e] = 0;
+        if (bd.cache_hdr) { bd.cache_hdr[2 * e] = 0; bd.cache_hdr[2 * e + 1] = 0; }
+    }
 }
