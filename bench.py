@@ -180,11 +180,21 @@ def time_graph(batch, steps, warmup, per_graph=10, spl=1):
                 p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)), stats=st)
 
 
-def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False, settle_steps=200):
-    """Settle, (tune,) warm up, then time; returns the scene, the raw timing and the summary."""
+def run_workload(ms, S, name, n_envs, steps, warmup, spl, seed, lanes=0, pack=1, tune=False, graph=False, settle_steps=200,
+                 warm_start=False, forces=False, targets=None):
+    """Settle, (tune,) warm up, then time; returns the scene, the raw timing and the summary.
+    warm_start: the cross-step contact cache on; forces: the contact-force readout on; targets:
+    drive targets (numpy, [J]) set for every step."""
     import torch
     sc = S.by_name(name, n_envs, seed=seed)
+    if warm_start:
+        sc.params["warm_start"] = 1
     b = ms.Batch(sc, lanes_per_env=lanes, pack=pack)
+    if forces:
+        b.set_contact_forces(True)
+    tg = None if targets is None else torch.from_numpy(targets).cuda()
+    if tg is not None:
+        b.step(1, tg)
     settle(b, settle_steps)
     if tune:
         # tune on the settled state (trials of 10 steps), then time from that same state
@@ -393,6 +403,19 @@ def main():
                                                                 extra["hetero_padded"]["env_steps_per_s"])
         extra["hetero_2spl_speedup_vs_padded_2spl"] = (extra["hetero_tuned_graph_2spl"]["env_steps_per_s"] /
                                                        extra["hetero_padded_graph_2spl"]["env_steps_per_s"])
+        # the paper's simulation-only workload: cart-poles at 120 Hz, 4 position / 0 velocity
+        # iterations, one 60 Hz control step (2 simulation steps) per launch, cart targets set
+        ids = list(range(4096))
+        _, _, res = run_workload(ms, S, "cartpole", 4096, 200, 20, 2, args.seed, settle_steps=args.settle,
+                                 targets=S.cartpole_targets(args.seed, ids, 0))
+        extra["cartpole"] = res
+        # the headline workload with the cross-step contact cache, and with the contact-force readout
+        _, _, res = run_workload(ms, S, args.workload, args.envs, 100, 20, 1, args.seed, settle_steps=args.settle,
+                                 warm_start=True)
+        extra[f"{args.workload}_warm_start"] = res
+        _, _, res = run_workload(ms, S, args.workload, args.envs, 100, 20, 1, args.seed, settle_steps=args.settle,
+                                 forces=True)
+        extra[f"{args.workload}_contact_forces"] = res
         extra["serving"] = serving(ms, full=args.serve_full, seed=args.seed)
         pk = measured_peaks(ms)
         extra["measured_peaks"] = pk

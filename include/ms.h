@@ -79,10 +79,14 @@ typedef struct {
     float angvel[3];
 } ms_body_desc;
 
-/* One revolute joint about the z axis of its joint frame.  parent = -1 attaches the child to
+/* One joint (the paper's articulations, Sec. III-F1, driven by PD joint-position controllers,
+ * App. B, Controller / Action Space): revolute about the z axis of its joint frame, or prismatic
+ * along it (App. A, Classic Control: the cart-pole's slider).  parent = -1 attaches the child to
  * the static world.  frame_* = (px, py, pz, qw, qx, qy, qz) in the body's local frame (the world
- * frame for parent = -1).  kp (N m / rad) and kd (N m s / rad) define the PD position drive
- * toward `target` (rad); kp = kd = 0 disables the drive.  92 bytes, no padding. */
+ * frame for parent = -1).  kp (N m / rad or N / m) and kd (N m s / rad or N s / m) define the PD
+ * position drive toward `target` (rad or m); kp = kd = 0 disables the drive.  limited != 0 adds
+ * one-sided limit rows at lower / upper (App. A, Locomotion: constrained joint limits).  Parent
+ * and child never collide with each other.  92 bytes, no padding. */
 typedef struct {
     int32_t parent;
     int32_t child;
@@ -173,12 +177,16 @@ typedef struct {
 
 typedef struct ms_batch ms_batch;
 
-/* Device workspace bytes needed by a batch (state, parameters, joints, targets, tiles, debug).
- * Host-only, never touches the device. */
+/* Device workspace bytes needed by a batch (state, parameters, joints, targets, tiles, contact
+ * cache, debug).  The workspace is all the device memory a batch uses, so an HBM budget can be
+ * checked before anything is allocated (Sec. III-B: GPU memory efficiency).  Host-only, never
+ * touches the device.  Errors: MS_E_INVALID_ARG / MS_E_CAPACITY for invalid descriptors. */
 ms_status ms_query_batch_bytes(const ms_sim_params* params, const ms_scene_desc* scene,
                                const ms_plan* plan, size_t* bytes);
 
-/* Validate the scene, lay out the workspace (caller-owned device memory of at least
+/* Create a batch of independent, possibly heterogeneous envs (Sec. III-C, Heterogeneous GPU
+ * Simulation: per-env object counts and articulations).
+ * Validate the scene, lay out the workspace (caller-owned device memory of at least
  * ms_query_batch_bytes() bytes, 256-byte aligned) and upload the initial state on `hip_stream`
  * (NULL = the default stream).  The initial state is kept for ms_reset_envs(src = NULL).
  * Reconfiguration is a destroy + create. */
@@ -186,7 +194,9 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
                           const ms_plan* plan, void* dev_workspace, size_t ws_bytes,
                           void* hip_stream, ms_batch** out);
 
-/* Advance every env by n_steps steps (n_steps >= 1) in one fused launch.  dev_targets holds one
+/* The batched physics step (Sec. III-B: all envs advanced in parallel on the GPU; App. E, Setup:
+ * position iterations = TGS substeps).
+ * Advance every env by n_steps steps (n_steps >= 1) in one fused launch.  dev_targets holds one
  * drive target per joint of the batch (float32 [total joints], device) and replaces the
  * descriptor targets for this and later calls; NULL keeps the current ones.  Envs with a frozen
  * status are skipped. */
@@ -245,11 +255,12 @@ ms_status ms_get_joint_positions(ms_batch* b, float* dev_out, void* hip_stream);
 
 /* Contact-force readout for touch sensing (App. A, Dextrous Manipulation: touch sensors), kept on
  * the device.  ms_set_contact_forces(enable != 0) makes every later step of the batch accumulate,
- * per body, the net contact impulse of the step: for every substep, the final normal impulses of
- * the body's contact points and the two tangent impulses of its friction patches (added on a
- * manifold's side B, subtracted on side A; manifolds in canonical order, a manifold's points before
- * its patch), divided by dt.  A launch of several steps keeps the last step's.  Frozen envs and
- * steps that went non-finite give zero.  Enabling zeroes the buffer; enabling and disabling
+ * per dynamic body, the net contact impulse of the step: for every substep, the final normal
+ * impulses of the body's contact points and the two tangent impulses of its friction patches
+ * (added on a manifold's side B, subtracted on side A; the body's manifolds in the solver's colour
+ * order, a manifold's points before its patch), divided by dt.  Static bodies report zero.  A
+ * launch of several steps keeps the last step's.  Frozen envs and steps that went non-finite give
+ * zero.  Enabling zeroes the buffer; enabling and disabling
  * synchronise `hip_stream`.  ms_get_contact_forces copies float32 [3][B] (component-major, like
  * the state planes) into caller-owned device memory, stream-ordered; MS_E_STATE when not enabled.
  * Tuning trial steps (ms_tune_batch) overwrite the forces. */
@@ -260,7 +271,8 @@ ms_status ms_get_contact_forces(ms_batch* b, float* dev_out, void* hip_stream);
  * clear (those ids were skipped).  Synchronises `hip_stream`; clear != 0 zeroes the count. */
 ms_status ms_get_invalid_ids(ms_batch* b, int32_t* host_count, int32_t clear, void* hip_stream);
 
-/* Copy the current state (all envs) into caller-owned device buffers. */
+/* Copy the current state (all envs) into caller-owned device buffers (Sec. III-B: observations
+ * stay on the GPU).  Stream-ordered device-to-device copies. */
 ms_status ms_get_state(ms_batch* b, const ms_state_view* dst, void* hip_stream);
 
 /* Body and joint offsets of the batch (host arrays of n_envs + 1 entries each), and totals. */
@@ -294,14 +306,18 @@ ms_status ms_get_plan(ms_batch* b, int32_t* n_tiles, int32_t* grid, int32_t* lds
  * bins (grid = number of bins, LDS bytes per bin). */
 ms_status ms_get_classes(ms_batch* b, int32_t* n_classes, int32_t* host_classes);
 
-/* Autotuner.  First the env tiling: for every group of envs that the planner gave the same
- * lanes per env (so 64 / lanes envs per wavefront), the whole batch is timed over trial_steps
- * steps with half and with twice as many lanes for that group, and a change is kept if it is
- * at least 3 % faster.  Then, when the batch runs as one launch per LDS class, each kernel
+/* Autotuner (the batching pattern's project-written tuner of envs per workgroup and solver
+ * tiling).  First the env tiling: for every group of envs that the planner gave the same lanes per
+ * env (so 64 / lanes envs per wavefront), the whole batch is timed over trial_steps steps with
+ * half and with twice as many lanes for that group, and a change is kept if it is at least 3 %
+ * faster.  Then, for a batch that runs as one launch of bins, the bins' shape: at most 2, 3 or 4
+ * tiles per bin packed into a quarter, a third or half of a CU's LDS (default: 4 in half), kept
+ * if at least 3 % faster.  Then, when the batch runs as one launch per LDS class, each kernel
  * variant of every class is timed over trial_steps launches of that class alone and the
- * fastest kept (the bins launch has fixed builds).  The tiling never changes a
- * result.  The batch's state, status and work counters are saved before and restored after
- * (the trial steps leave no trace).  Synchronises `hip_stream`. */
+ * fastest kept (the bins launch has fixed builds).  The tiling never changes a result.  The
+ * batch's state, status, contact cache and work counters are saved before and restored after (the
+ * trial steps leave no trace; contact forces, if enabled, are overwritten).  Synchronises
+ * `hip_stream`. */
 ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream);
 
 /* Work counters accumulated by every step since the last reset, int64 [n_envs][16]: steps,
@@ -311,6 +327,8 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream);
  * `hip_stream`. */
 ms_status ms_get_stats(ms_batch* b, int64_t* host_stats, int32_t reset, void* hip_stream);
 
+/* Free the batch's host-side record (the workspace stays the caller's).  Destroy its graphs first;
+ * the caller must let the stream pass the batch's last launch before reusing the workspace. */
 ms_status ms_destroy_batch(ms_batch* b);
 
 /* Captured step sequences (Sec. "GPU Parallelized Simulation and Rendering": the step stays on
@@ -321,8 +339,9 @@ ms_status ms_destroy_batch(ms_batch* b);
  * synchronisation).  The graph reads dev_targets (J floats, may be NULL) at replay time, so the
  * caller may rewrite that buffer between replays; it must stay valid while the graph exists.
  * The graph holds no memset nodes.  A graph belongs to its batch: destroy it before the batch.
- * ms_tune_batch re-plans the batch's tiles; a graph captured before it replays the old launch
- * geometry, so ms_graph_launch then returns MS_E_STATE (destroy the graph and capture again).
+ * ms_tune_batch re-plans the batch's tiles and ms_set_contact_forces switches its kernel build; a
+ * graph captured before either replays the old launch, so ms_graph_launch then returns MS_E_STATE
+ * (destroy the graph and capture again).
  * Errors: invalid arguments or a failed capture return a status and leave nothing behind. */
 typedef struct ms_graph ms_graph;
 ms_status ms_graph_create(ms_batch* b, const float* dev_targets, int32_t steps_per_launch, int32_t n_launches,

@@ -1457,24 +1457,29 @@ template <class T> struct Stepper {
         }
     }
 
-    // Contact impulses of the step, per body (touch sensing): every substep's final multipliers
-    // are that substep's impulses (the warm start re-applies the previous substep's, the sweeps
-    // add to them), so the step's total is the sum over substeps 1 .. S-1 after their sweeps plus
-    // the final multipliers after the velocity and restitution passes.  Each addition takes the
-    // normal impulses of a body's points and the two tangent impulses of its friction patches
-    // (added on the B side, subtracted on the A side; manifolds in order, points before the
-    // patch).  The twist impulse is a torque and is left out.
+    // Contact impulses of the step, per dynamic body (touch sensing): every substep's final
+    // multipliers are that substep's impulses (the warm start re-applies the previous substep's,
+    // the sweeps add to them), so the step's total is the sum over substeps 1 .. S-1 after their
+    // sweeps plus the final multipliers after the velocity and restitution passes.  Each addition
+    // takes the normal impulses of a body's points and the two tangent impulses of its friction
+    // patches (added on the B side, subtracted on the A side; a body's manifolds in colour order,
+    // the solver's order, points before the patch).  The twist impulse is a torque and is left
+    // out; static bodies report no force.
     void accumulate_forces() {
-        for (const Manifold<T>& m : mans) {
+        const int nj = int(E.joints.size());
+        for (const auto& ob : order) {
+            if (ob.second < nj) continue;
+            const Manifold<T>& m = mans[ob.second - nj];
+            const bool db = dyn(m.b), da = dyn(m.a);
             for (int k = 0; k < m.count; ++k) {
                 const CRow<T>& r = rows[m.first + k];
                 const V3<T> Pn = r.ln * r.n;
-                E.force[m.b] = E.force[m.b] + Pn;
-                if (m.a >= 0) E.force[m.a] = E.force[m.a] - Pn;
+                if (db) E.force[m.b] = E.force[m.b] + Pn;
+                if (da) E.force[m.a] = E.force[m.a] - Pn;
             }
             const V3<T> Pt = m.lt1 * m.t1 + m.lt2 * m.t2;
-            E.force[m.b] = E.force[m.b] + Pt;
-            if (m.a >= 0) E.force[m.a] = E.force[m.a] - Pt;
+            if (db) E.force[m.b] = E.force[m.b] + Pt;
+            if (da) E.force[m.a] = E.force[m.a] - Pt;
         }
     }
 

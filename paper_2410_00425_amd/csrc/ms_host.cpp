@@ -57,6 +57,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 constexpr int MAX_CLASSES = 4;  // one stream per class; the default four hardware queues
+constexpr int BIN_BUDGET = 20480;   // default bin LDS budget in words: half a CU's 160 KiB, two bins per CU
 
 // Per-env sizes used by the planner.
 struct EnvInfo {
@@ -171,6 +172,8 @@ struct Plan {
     // BIN_WAVES tiles packed first-fit by decreasing size into one workgroup's LDS
     std::vector<Bin> bins;
     int bin_words = 0;
+    int bin_tiles = BIN_WAVES;     // bin shape: at most this many tiles (wavefronts) per bin
+    int bin_budget = BIN_BUDGET;   // and this many LDS words, unless one tile needs more
     int launch_mode = 0;   // 0: bins when several LDS classes, 1: always class launches
     // debug offsets
     std::vector<int> dbg_pair_off, dbg_pt_off, dbg_man_off;
@@ -247,20 +250,20 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     return MS_OK;
 }
 
-constexpr int BIN_BUDGET = 20480;   // bin LDS budget in words: half a CU's 160 KiB, two bins per CU
 
 // Bins for the single-launch form: tiles (sorted by LDS need, largest first) placed first-fit
 // into bins of at most BIN_WAVES tiles and BIN_BUDGET words.  Only for batches with more than
 // one LDS class; otherwise the class launch is already a single launch.
 template <class TileRef, class BinVec, class IntVec>
-int pack_bins(int n_tiles, TileRef tile_ref, BinVec& bins, IntVec& used) {
+int pack_bins(int n_tiles, TileRef tile_ref, BinVec& bins, IntVec& used, int max_tiles = BIN_WAVES,
+              int budget = BIN_BUDGET) {
     bins.clear();
     used.clear();
     int bin_words = 0;
     for (int t = 0; t < n_tiles; ++t) {
         const int w = tile_ref(t).lds_words;
         int k = 0;
-        while (k < int(bins.size()) && (bins[k].count == BIN_WAVES || used[k] + w > BIN_BUDGET)) ++k;
+        while (k < int(bins.size()) && (bins[k].count == max_tiles || used[k] + w > budget)) ++k;
         if (k == int(bins.size())) {
             bins.push_back(Bin{});
             used.push_back(0);
@@ -279,7 +282,8 @@ void make_bins(Plan& out) {
     out.bin_words = 0;
     if (out.classes.size() < 2 || out.launch_mode == 1) return;
     std::vector<int> used;
-    out.bin_words = pack_bins(int(out.tiles.size()), [&](int t) -> const Tile& { return out.tiles[t]; }, out.bins, used);
+    out.bin_words = pack_bins(int(out.tiles.size()), [&](int t) -> const Tile& { return out.tiles[t]; }, out.bins, used,
+                              out.bin_tiles, out.bin_budget);
 }
 
 constexpr int TILE_BUDGET = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
@@ -1099,6 +1103,25 @@ ms_status ms_tune_batch(ms_batch* b, int32_t trial_steps, void* hip_stream) {
             st = time_batch(t);
             if (st == MS_OK && t < 0.97f * best) { best = t; lanes = trial; }
         }
+        if (st == MS_OK) st = retile(b, lanes, s);
+    }
+    // 1b. the shape of the bins launch (batches whose tiles need several LDS sizes): at most 2,
+    //     3 or 4 tiles per bin in a quarter, a third or half of a CU's LDS (the default is 4 in
+    //     half); keep a shape only if the batch steps at least 3 % faster
+    if (st == MS_OK && !b->plan.bins.empty()) {
+        const int shapes[][2] = {{2, 10240}, {3, 13652}, {4, 13652}, {2, 20480}};
+        int best_t = b->plan.bin_tiles, best_b = b->plan.bin_budget;
+        for (const auto& sh : shapes) {
+            if (st != MS_OK) break;
+            b->plan.bin_tiles = sh[0];
+            b->plan.bin_budget = sh[1];
+            if (retile(b, lanes, s) != MS_OK) continue;
+            float t = 0.0f;
+            st = time_batch(t);
+            if (st == MS_OK && t < 0.97f * best) { best = t; best_t = sh[0]; best_b = sh[1]; }
+        }
+        b->plan.bin_tiles = best_t;
+        b->plan.bin_budget = best_b;
         if (st == MS_OK) st = retile(b, lanes, s);
     }
     // 2. kernel variant per part of each LDS class (one-env part: 2 / 3, general part: 0 / 1),

@@ -2239,27 +2239,35 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
 // The step of every tile of the work list; `lds` is the workgroup's dynamic LDS.
 // ONE: every tile of the launch holds a single env served by all 64 lanes, so the env's sizes
 // and offsets are wavefront-uniform (scalar registers) and the group arithmetic folds away.
-// Net contact impulse on each body, summed into the bounding-box plane (free after the
-// broadphase; 3 of its 6 n words): a lane per body walks the manifolds in canonical order and
-// adds, for each manifold it belongs to, the normal impulses of its points, then the patch's two
-// tangent impulses (added on side B, subtracted on side A; the twist is a torque and is left
-// out).  Run once after the sweeps of every substep but the last, and once after the velocity
-// and restitution passes: the sum over substeps of each substep's final multipliers.
+// Net contact impulse on each dynamic body, summed into the bounding-box plane (free after the
+// broadphase; 3 of its 6 n words): a lane per body walks its block list (colour order, built for
+// the warm start) and adds, for each manifold it belongs to, the normal impulses of its points,
+// then the patch's two tangent impulses (added on side B, subtracted on side A; the twist is a
+// torque and is left out; static bodies keep zero).  Run once after the sweeps of every substep
+// but the last, and once after the velocity and restitution passes: the sum over substeps of
+// each substep's final multipliers.
 // Whether the batch accumulates contact forces, read afresh at each use (a volatile load) so the
 // flag never holds a register across the step's phases.
 __device__ __forceinline__ bool forces_on(const EnvCtx& c) {
     return *reinterpret_cast<float* const volatile*>(&c.bd->forces) != nullptr;
 }
-__device__ __forceinline__ void accumulate_forces(const EnvCtx& c, int nn, int nman, int li, int G) {
-    const int n = c.lay.n;
-    float* F = c.L + c.lay.AABB;
+__device__ __forceinline__ void accumulate_forces(const EnvCtx& c, int nn, int li, int G) {
+    const Lay& l = c.lay;
+    const int n = l.n;
+    float* F = c.L + l.AABB;
+    const int* OFF = iptr(c.L + l.CAND);
+    const uint16_t* ENT = reinterpret_cast<const uint16_t*>(OFF + l.n + 1);
     for (int i = li; i < nn; i += G) {
+        if (!is_dyn(c, i)) continue;
         V3 f = v3(F[i], F[n + i], F[2 * n + i]);
-        for (int m = 0; m < nman; ++m) {
+        for (int e = OFF[i]; e < OFF[i + 1]; ++e) {
+            const int ent = ENT[e];
+            const int blk = ent & 0x7FFF;
+            if (blk < l.nj) continue;
+            const bool sideB = (ent >> 15) != 0;
+            const int m = blk - l.nj;
             int a, b, first, cnt;
             man_header(c, m, a, b, first, cnt);
-            if (a != i && b != i) continue;
-            const bool sideB = b == i;
             for (int k = first; k < first + cnt; ++k) {
                 const V3 Pn = pr(c, R_LN, k) * pr3(c, R_N, k);
                 f = sideB ? f + Pn : f - Pn;
@@ -2627,7 +2635,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             const float admp = 1.0f / (1.0f + h * bd.ang_damp);
             // warm start body by body: fused with gravity in joint-free waves, after the joint pass
             // in the others
-            if (S > 1 || (OPT && warm_on(c))) {
+            if (S > 1 || (OPT && (warm_on(c) || forces_on(c)))) {   // warm start, force sums
                 if (G == WAVE) build_body_lists_wave(c, nn, nmanA, li);
                 else build_body_lists(c, nn, nmanA, li, G);
                 wave_sync();
@@ -2651,7 +2659,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 }
                 if (OPT && s + 1 < S && forces_on(c)) {
                     wave_sync();
-                    accumulate_forces(c, nn, nmanA, li, G);
+                    accumulate_forces(c, nn, li, G);
                 }
                 // integrate the offsets from the step-start pose
                 for (int i = li; i < nn; i += G) {
@@ -2701,7 +2709,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             // the step's contact impulses / dt, written for the last step of the launch (zero for
             // a frozen env or a step that went non-finite)
             if (OPT && step == n_steps - 1 && forces_on(c)) {
-                if (!anybad) accumulate_forces(c, nn, nmanA, li, G);
+                if (!anybad) accumulate_forces(c, nn, li, G);
                 const float idt = 1.0f / bd.dt;
                 for (int i = li; i < nA; i += G) {
                     V3 f = v3(0, 0, 0);

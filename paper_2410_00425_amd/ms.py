@@ -17,6 +17,10 @@ from . import scenes
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libms.so")
 
+# torch first: its HIP runtime is then the one libms binds to (loading libms first would bring in
+# a second copy of the runtime, and torch's device calls and the library's would not share a device)
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_00425_amd.build` "
                       "(hipcc, gfx950) before using the GPU step")
