@@ -1,14 +1,19 @@
 // ms_server.cpp — the serving runtime of libms: sessions (batches of envs) admitted against an
 // HBM budget, and continuous batching of their step requests into fused ms_step_many launches.
 //
-// One worker thread per server owns a HIP stream on the server's device.  Each iteration it
-//   1. admits waiting sessions in arrival order while their workspace fits in the arena (a
-//      session that does not fit blocks the ones behind it, so none starves);
-//   2. takes the head request of every admitted session (a session's requests run in order),
-//      as many as the fused work list fits in the scratch reserve;
-//   3. advances all of them by the smallest remaining step count in one ms_step_many call,
-//      waits for it, and completes the requests that have no steps left.
-// Requests that arrive while a launch runs join the next iteration.
+// Two threads per server, each with its own HIP stream on the server's device:
+//   * the admitter admits waiting sessions in arrival order while their workspace fits in the
+//     arena (a session that does not fit blocks the ones behind it, so none starves): it carves
+//     the block, then builds the batch (host planning and uploads, which synchronise the
+//     admission stream) outside the server lock, so admission never stalls the launches;
+//   * the worker keeps up to two fused launches in flight.  Each launch takes, for every admitted
+//     session, its first request that still has steps to enqueue (a session's requests run in
+//     order), as many sessions as the fused work list fits in the scratch reserve, and advances
+//     them by the smallest such step count in one ms_step_many call.  While the GPU runs one
+//     launch the worker plans and enqueues the next; it then waits on the older launch's event
+//     and completes the requests that have no steps left.
+// Launches on one stream run in order, so a session's steps and its work list uploads need no
+// other synchronisation.  Requests that arrive while launches run join the next launch.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -76,14 +81,15 @@ struct Session {
     int32_t n_envs = 0, n_joints = 0;
     ms_batch* b = nullptr;
     float* dev_targets = nullptr;
-    bool admitted = false, closing = false, busy = false;
+    bool admitted = false, closing = false;
+    int inflight = 0;   // launches in flight that step this session
     ms_status admit_status = MS_OK;
     std::deque<int64_t> queue;
 };
 
 struct Request {
     int64_t id = 0, session = 0;
-    int32_t n_steps = 0, remaining = 0;
+    int32_t n_steps = 0, remaining = 0, enqueued = 0;   // steps not yet completed / already launched
     std::vector<float> targets;
     bool has_targets = false, done = false;
     ms_status status = MS_OK;
@@ -93,64 +99,68 @@ struct Request {
 
 }  // namespace
 
+namespace {
+// One fused launch in flight: its completion event and the steps it advances each request by.
+struct Flight {
+    int slot = 0;
+    double t0 = 0;
+    ms_status st = MS_OK;
+    std::string err;
+    std::vector<std::pair<int64_t, int32_t>> items;   // (request, steps)
+    std::vector<int64_t> sessions;
+};
+}  // namespace
+
 struct ms_server {
     int device = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
+    hipStream_t stream = nullptr, admit_stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the launch in each of the two slots
     char* arena = nullptr;
     size_t arena_bytes = 0, scratch_bytes = 0;
     Arena alloc;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_admit;
     bool stop = false;
-    bool in_flight = false;
-    uint64_t gen = 0;   // bumped by every client action (open, submit, close, stop)
-    std::thread worker;
+    uint64_t gen = 0;        // bumped by every client action (open, submit, close, stop) and admission
+    uint64_t admit_gen = 0;  // bumped when a session queues for admission or arena space is freed
+    std::deque<Flight> flights;
+    int next_slot = 0;
+    double last_done = 0;    // end of the busy interval so far (for the busy-time counter)
+    std::thread worker, admitter;
     int64_t next_id = 1;
     std::map<int64_t, Session> sessions;   // ordered by id = arrival order
     std::deque<int64_t> admit_queue;
     std::unordered_map<int64_t, Request> reqs;
-    void* pinned = nullptr;
-    size_t pinned_cap = 0;
+    void* pinned[2] = {nullptr, nullptr};   // host staging of drive targets, one per launch slot
+    size_t pinned_cap[2] = {0, 0};
     std::string last_error;
     // counters: launches, fused batches, env-steps, requests done, sessions admitted,
-    // busy microseconds, peak arena bytes, sessions rejected
+    // busy microseconds (GPU time with a launch in flight), peak arena bytes, sessions rejected
     int64_t stats[8] = {};
     void run();
+    void admit_loop();
 };
 
 namespace {
 
-bool has_work(ms_server* s) {
-    if (s->stop) return true;
-    if (!s->admit_queue.empty()) return true;
-    for (auto& kv : s->sessions) {
-        const Session& ss = kv.second;
-        if (ss.admitted && (!ss.queue.empty() || ss.closing)) return true;
+// The first request of a session that still has steps to launch (-1: none).
+int64_t next_request(ms_server* s, const Session& ss) {
+    for (int64_t r : ss.queue) {
+        const Request& rq = s->reqs.at(r);
+        if (rq.enqueued < rq.n_steps) return r;
     }
-    return false;
+    return -1;
 }
 
-// Admission of one session (worker thread, lock held): carve its block, create its batch.
-ms_status admit(ms_server* s, Session& ss, bool& fits) {
-    fits = s->alloc.alloc(ss.bytes, ss.off);
-    if (!fits) return MS_OK;
-    ms_scene_desc sd{ss.n_envs, ss.body_off.data(), ss.bodies.data(), ss.joint_off.data(),
-                     ss.joints.empty() ? nullptr : ss.joints.data()};
-    char* base = s->arena + ss.off;
-    ms_status st = ms_create_batch(&ss.params, &sd, ss.has_plan ? &ss.plan : nullptr, base, ss.ws_bytes, s->stream, &ss.b);
-    if (st != MS_OK) {
-        s->alloc.release(ss.off, ss.bytes);
-        return st;
+bool worker_has_work(ms_server* s) {
+    if (!s->flights.empty()) return true;
+    if (s->stop) return true;
+    for (auto& kv : s->sessions) {
+        const Session& ss = kv.second;
+        if (ss.closing && ss.queue.empty() && ss.inflight == 0 && (ss.admitted || ss.admit_status != MS_OK)) return true;
+        if (ss.admitted && next_request(s, ss) >= 0) return true;
     }
-    ss.dev_targets = reinterpret_cast<float*>(base + align_up(ss.ws_bytes));
-    ss.admitted = true;
-    s->stats[4] += 1;
-    s->stats[6] = int64_t(s->alloc.peak);
-    // the descriptors are no longer needed on the host
-    std::vector<ms_body_desc>().swap(ss.bodies);
-    std::vector<ms_joint_desc>().swap(ss.joints);
-    return MS_OK;
+    return false;
 }
 
 void retire(ms_server* s, Session& ss) {
@@ -159,158 +169,226 @@ void retire(ms_server* s, Session& ss) {
     s->alloc.release(ss.off, ss.bytes);
 }
 
+void fail_queue(ms_server* s, Session& ss, ms_status st) {
+    for (int64_t r : ss.queue) {
+        Request& rq = s->reqs.at(r);
+        rq.done = true;
+        rq.status = st;
+        rq.t_done = now_s();
+    }
+    ss.queue.clear();
+}
+
 }  // namespace
+
+// Admission thread: sessions in arrival order, each as soon as its block fits.
+void ms_server::admit_loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    uint64_t seen = ~uint64_t(0);
+    for (;;) {
+        cv_admit.wait(lk, [&] { return (stop && admit_queue.empty()) || (!admit_queue.empty() && admit_gen != seen); });
+        if (admit_queue.empty()) break;   // stopping, nothing left to admit
+        seen = admit_gen;
+        Session& ss = sessions.at(admit_queue.front());
+        size_t off = 0;
+        if (!alloc.alloc(ss.bytes, off)) continue;   // wait until a retirement frees space
+        ss.off = off;
+        stats[6] = int64_t(alloc.peak);
+        // build the batch outside the lock (its descriptors are not touched by other threads)
+        ms_scene_desc sd{ss.n_envs, ss.body_off.data(), ss.bodies.data(), ss.joint_off.data(),
+                         ss.joints.empty() ? nullptr : ss.joints.data()};
+        char* base = arena + off;
+        ms_batch* b = nullptr;
+        lk.unlock();
+        ms_status st = ms_create_batch(&ss.params, &sd, ss.has_plan ? &ss.plan : nullptr, base, ss.ws_bytes, admit_stream, &b);
+        std::string err = st != MS_OK ? std::string(ms_last_error()) : std::string();
+        lk.lock();
+        admit_queue.pop_front();
+        if (st != MS_OK) {
+            alloc.release(off, ss.bytes);
+            ss.admit_status = st;
+            last_error = err;
+            fail_queue(this, ss, st);
+            stats[7] += 1;
+        } else {
+            ss.b = b;
+            ss.dev_targets = reinterpret_cast<float*>(base + align_up(ss.ws_bytes));
+            ss.admitted = true;
+            stats[4] += 1;
+            // the descriptors are no longer needed on the host
+            std::vector<ms_body_desc>().swap(ss.bodies);
+            std::vector<ms_joint_desc>().swap(ss.joints);
+        }
+        seen = ~uint64_t(0);
+        gen += 1;
+        cv_work.notify_all();
+        cv_done.notify_all();
+    }
+}
 
 void ms_server::run() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     uint64_t idle_gen = ~uint64_t(0);   // generation at which the last iteration made no progress
     for (;;) {
-        cv_work.wait(lk, [&] { return has_work(this) && gen != idle_gen; });
+        cv_work.wait(lk, [&] { return !flights.empty() || (worker_has_work(this) && gen != idle_gen); });
         idle_gen = ~uint64_t(0);
-        bool progressed = false;
-        // 1. admission in arrival order
-        while (!admit_queue.empty()) {
-            Session& ss = sessions.at(admit_queue.front());
-            bool fits = false;
-            ms_status st = admit(this, ss, fits);
-            if (st != MS_OK) {
-                ss.admit_status = st;
-                last_error = ms_last_error();
-                for (int64_t r : ss.queue) {
-                    Request& rq = reqs.at(r);
-                    rq.done = true;
-                    rq.status = st;
-                    rq.t_done = now_s();
-                }
-                ss.queue.clear();
-                admit_queue.pop_front();
-                stats[7] += 1;
-                progressed = true;
-                continue;
-            }
-            if (!fits) break;
-            admit_queue.pop_front();
-            progressed = true;
-        }
-        // retire closed sessions with nothing left to run
+        // retire closed sessions with nothing queued and nothing in flight
+        bool freed = false;
         for (auto it = sessions.begin(); it != sessions.end();) {
             Session& ss = it->second;
-            bool gone = ss.closing && ss.queue.empty() && (ss.admitted || ss.admit_status != MS_OK);
-            if (gone) {
-                if (ss.admitted) retire(this, ss);
+            if (ss.closing && ss.queue.empty() && ss.inflight == 0 && (ss.admitted || ss.admit_status != MS_OK)) {
+                if (ss.admitted) { retire(this, ss); freed = true; }
                 it = sessions.erase(it);
-                progressed = true;
             } else {
                 ++it;
             }
         }
+        if (freed) { admit_gen += 1; cv_admit.notify_all(); }
         cv_done.notify_all();
-        if (stop && admit_queue.empty()) {
+        if (stop && admit_queue.empty() && flights.empty()) {
             bool idle = true;
             for (auto& kv : sessions) idle = idle && kv.second.queue.empty();
             if (idle) break;
         }
-        // 2. one head request per admitted session, while the fused work list fits
-        std::vector<Session*> run;
-        std::vector<ms_batch*> bl;
-        int32_t k = INT32_MAX;
-        for (auto& kv : sessions) {
-            Session& ss = kv.second;
-            if (!ss.admitted || ss.queue.empty()) continue;
-            bl.push_back(ss.b);
-            size_t need = 0;
-            if (ms_query_step_many_bytes(bl.data(), int32_t(bl.size()), &need) != MS_OK || need > scratch_bytes) {
-                bl.pop_back();
-                if (bl.empty()) {   // a single session whose work list exceeds the reserve
-                    Request& rq = reqs.at(ss.queue.front());
-                    rq.done = true;
-                    rq.status = MS_E_BUDGET;
-                    rq.t_done = now_s();
-                    ss.queue.pop_front();
-                    last_error = "fused work list exceeds the scratch reserve";
-                    continue;
+        // 1. plan and enqueue a launch while fewer than two are in flight
+        if (flights.size() < 2) {
+            std::vector<Session*> run;
+            std::vector<int64_t> rids;
+            std::vector<ms_batch*> bl;
+            int32_t k = INT32_MAX;
+            for (auto& kv : sessions) {
+                Session& ss = kv.second;
+                if (!ss.admitted) continue;
+                const int64_t r = next_request(this, ss);
+                if (r < 0) continue;
+                bl.push_back(ss.b);
+                size_t need = 0;
+                if (ms_query_step_many_bytes(bl.data(), int32_t(bl.size()), &need) != MS_OK || need > scratch_bytes) {
+                    bl.pop_back();
+                    if (bl.empty() && ss.inflight == 0 && r == ss.queue.front()) {
+                        // a single session whose work list exceeds the reserve
+                        Request& rq = reqs.at(r);
+                        rq.done = true;
+                        rq.status = MS_E_BUDGET;
+                        rq.t_done = now_s();
+                        ss.queue.pop_front();
+                        last_error = "fused work list exceeds the scratch reserve";
+                        continue;
+                    }
+                    break;
                 }
-                break;
+                run.push_back(&ss);
+                rids.push_back(r);
+                const Request& rq = reqs.at(r);
+                k = std::min(k, rq.n_steps - rq.enqueued);
             }
-            run.push_back(&ss);
-            Request& rq = reqs.at(ss.queue.front());
-            if (rq.t_start == 0) rq.t_start = now_s();
-            k = std::min(k, rq.remaining);
+            if (!run.empty()) {
+                Flight f;
+                f.slot = next_slot;
+                next_slot ^= 1;
+                // targets of requests starting now go through this slot's pinned buffer into the
+                // session's device buffer (the slot's previous launch has completed: at most two
+                // are in flight and the other one holds the other slot)
+                size_t tbytes = 0;
+                for (int64_t r : rids) {
+                    const Request& rq = reqs.at(r);
+                    if (rq.has_targets && rq.enqueued == 0) tbytes += rq.targets.size() * 4;
+                }
+                std::vector<const float*> tg(run.size(), nullptr);
+                bool ok = true;
+                if (tbytes) {
+                    void*& pin = pinned[f.slot];
+                    if (pinned_cap[f.slot] < tbytes) {
+                        if (pin) (void)hipHostFree(pin);
+                        pin = nullptr;
+                        pinned_cap[f.slot] = 0;
+                        ok = hipHostMalloc(&pin, tbytes, hipHostMallocDefault) == hipSuccess;
+                        if (ok) pinned_cap[f.slot] = tbytes;
+                    }
+                    size_t o = 0;
+                    for (size_t i = 0; ok && i < run.size(); ++i) {
+                        const Request& rq = reqs.at(rids[i]);
+                        if (!(rq.has_targets && rq.enqueued == 0)) continue;
+                        const size_t nb = rq.targets.size() * 4;
+                        std::memcpy(static_cast<char*>(pin) + o, rq.targets.data(), nb);
+                        ok = hipMemcpyAsync(run[i]->dev_targets, static_cast<char*>(pin) + o, nb, hipMemcpyHostToDevice,
+                                            stream) == hipSuccess;
+                        tg[i] = run[i]->dev_targets;
+                        o += nb;
+                    }
+                }
+                const double t0 = now_s();
+                for (size_t i = 0; i < run.size(); ++i) {
+                    Request& rq = reqs.at(rids[i]);
+                    if (rq.t_start == 0) rq.t_start = t0;
+                    rq.enqueued += k;
+                    run[i]->inflight += 1;
+                    f.items.emplace_back(rids[i], k);
+                    f.sessions.push_back(run[i]->id);
+                }
+                f.t0 = t0;
+                lk.unlock();
+                // the fused launch (outside the lock: clients keep submitting)
+                ms_status st = ok ? ms_step_many(bl.data(), tg.data(), int32_t(bl.size()), k, arena, scratch_bytes, stream)
+                                  : MS_E_DEVICE;
+                std::string err = st != MS_OK ? std::string(ms_last_error()) : std::string();
+                if (st == MS_OK && hipEventRecord(ev[f.slot], stream) != hipSuccess) {
+                    st = MS_E_DEVICE;
+                    err = "event record after the fused launch failed";
+                }
+                // a failed launch may still have queued copies from the pinned buffer: let the
+                // stream drain before that buffer is written or freed again
+                if (st != MS_OK) (void)hipStreamSynchronize(stream);
+                lk.lock();
+                f.st = st;
+                f.err = err.empty() && st != MS_OK ? "target upload failed" : err;
+                stats[0] += 1;
+                stats[1] += int64_t(run.size());
+                flights.push_back(std::move(f));
+                continue;   // plan the next launch while this one runs
+            }
         }
-        if (run.empty()) {   // nothing runnable: sleep until a client changes something
-            if (!progressed) idle_gen = gen;
+        // 2. wait for the older launch and complete its requests
+        if (!flights.empty()) {
+            Flight f = std::move(flights.front());
+            flights.pop_front();
+            lk.unlock();
+            if (f.st == MS_OK && hipEventSynchronize(ev[f.slot]) != hipSuccess) {
+                f.st = MS_E_DEVICE;
+                f.err = "event wait after the fused launch failed";
+            }
+            const double t1 = now_s();
+            lk.lock();
+            stats[5] += int64_t((t1 - std::max(f.t0, last_done)) * 1e6);
+            last_done = t1;
+            if (f.st != MS_OK) last_error = f.err;
+            for (size_t i = 0; i < f.items.size(); ++i) {
+                Session& ss = sessions.at(f.sessions[i]);
+                Request& rq = reqs.at(f.items[i].first);
+                ss.inflight -= 1;
+                rq.fused = int32_t(f.items.size());
+                if (f.st != MS_OK) {
+                    rq.status = f.st;
+                    rq.remaining = 0;
+                } else {
+                    rq.remaining -= f.items[i].second;
+                    stats[2] += int64_t(f.items[i].second) * ss.n_envs;
+                }
+                if (rq.remaining == 0 && !rq.done) {
+                    rq.done = true;
+                    rq.t_done = t1;
+                    // requests complete in their session's order: this one is at the front
+                    auto qi = std::find(ss.queue.begin(), ss.queue.end(), rq.id);
+                    if (qi != ss.queue.end()) ss.queue.erase(qi);
+                    stats[3] += 1;
+                }
+            }
+            cv_done.notify_all();
             continue;
         }
-        // targets of requests starting now go through pinned memory into the session's buffer
-        size_t tbytes = 0;
-        for (Session* ss : run) {
-            Request& rq = reqs.at(ss->queue.front());
-            if (rq.has_targets && rq.remaining == rq.n_steps) tbytes += rq.targets.size() * 4;
-        }
-        std::vector<const float*> tg(run.size(), nullptr);
-        bool ok = true;
-        if (tbytes) {
-            if (pinned_cap < tbytes) {
-                if (pinned) (void)hipHostFree(pinned);
-                pinned = nullptr;
-                pinned_cap = 0;
-                ok = hipHostMalloc(&pinned, tbytes, hipHostMallocDefault) == hipSuccess;
-                if (ok) pinned_cap = tbytes;
-            }
-            size_t o = 0;
-            for (size_t i = 0; ok && i < run.size(); ++i) {
-                Request& rq = reqs.at(run[i]->queue.front());
-                if (!(rq.has_targets && rq.remaining == rq.n_steps)) continue;
-                const size_t nb = rq.targets.size() * 4;
-                std::memcpy(static_cast<char*>(pinned) + o, rq.targets.data(), nb);
-                ok = hipMemcpyAsync(run[i]->dev_targets, static_cast<char*>(pinned) + o, nb, hipMemcpyHostToDevice,
-                                    stream) == hipSuccess;
-                tg[i] = run[i]->dev_targets;
-                o += nb;
-            }
-        }
-        for (Session* ss : run) ss->busy = true;
-        in_flight = true;
-        lk.unlock();
-        // 3. the fused launch (outside the lock: clients keep submitting)
-        const double t0 = now_s();
-        ms_status st = ok ? ms_step_many(bl.data(), tg.data(), int32_t(bl.size()), k, arena, scratch_bytes, stream)
-                          : MS_E_DEVICE;
-        std::string err = st != MS_OK ? std::string(ms_last_error()) : std::string();
-        // a failed launch may still have queued the target copies from the pinned buffer: let
-        // the stream drain before that buffer is written or freed again
-        if (st != MS_OK) (void)hipStreamSynchronize(stream);
-        if (st == MS_OK && (hipEventRecord(ev, stream) != hipSuccess || hipEventSynchronize(ev) != hipSuccess)) {
-            st = MS_E_DEVICE;
-            err = "event wait after the fused launch failed";
-        }
-        const double t1 = now_s();
-        lk.lock();
-        in_flight = false;
-        if (st != MS_OK) last_error = err.empty() ? "target upload failed" : err;
-        stats[0] += 1;
-        stats[1] += int64_t(run.size());
-        stats[5] += int64_t((t1 - t0) * 1e6);
-        for (Session* ss : run) {
-            ss->busy = false;
-            Request& rq = reqs.at(ss->queue.front());
-            rq.fused = int32_t(run.size());
-            if (st != MS_OK) {
-                rq.status = st;
-                rq.remaining = 0;
-            } else {
-                rq.remaining -= k;
-                stats[2] += int64_t(k) * ss->n_envs;
-            }
-            if (rq.remaining == 0) {
-                rq.done = true;
-                rq.t_done = t1;
-                ss->queue.pop_front();
-                stats[3] += 1;
-            }
-        }
-        cv_done.notify_all();
+        idle_gen = gen;   // nothing runnable: sleep until a client changes something
     }
 }
 
@@ -333,9 +411,12 @@ ms_status ms_server_create(void* dev_arena, size_t arena_bytes, size_t scratch_b
     s->scratch_bytes = scratch_bytes;
     s->alloc.init(scratch_bytes, (arena_bytes - scratch_bytes) & ~(ALIGN - 1));
     HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
-    HIP_OK(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming));
     ms_server* raw = s.get();
     raw->worker = std::thread([raw] { raw->run(); });
+    raw->admitter = std::thread([raw] { raw->admit_loop(); });
     *out = s.release();
     return MS_OK;
 }
@@ -364,8 +445,10 @@ ms_status ms_server_open(ms_server* s, const ms_sim_params* params, const ms_sce
     *session = ss.id;
     s->admit_queue.push_back(ss.id);
     s->gen += 1;
+    s->admit_gen += 1;
     s->sessions.emplace(ss.id, std::move(ss));
     s->cv_work.notify_all();
+    s->cv_admit.notify_all();
     return MS_OK;
 }
 
@@ -435,7 +518,7 @@ ms_status ms_server_get_state(ms_server* s, int64_t session, const ms_state_view
         auto it = s->sessions.find(session);
         if (it == s->sessions.end()) return true;
         const Session& ss = it->second;
-        return ss.admit_status != MS_OK || (ss.admitted && ss.queue.empty() && !ss.busy);
+        return ss.admit_status != MS_OK || (ss.admitted && ss.queue.empty() && ss.inflight == 0);
     };
     s->cv_done.wait(lk, ready);
     auto it = s->sessions.find(session);
@@ -449,7 +532,7 @@ ms_status ms_server_drain(ms_server* s) {
     if (!s) return fail(MS_E_INVALID_ARG, "null server");
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv_done.wait(lk, [&] {
-        if (!s->admit_queue.empty() || s->in_flight) return false;
+        if (!s->admit_queue.empty() || !s->flights.empty()) return false;
         for (auto& kv : s->sessions)
             if (!kv.second.queue.empty() || kv.second.closing) return false;
         return true;
@@ -473,14 +556,19 @@ ms_status ms_server_destroy(ms_server* s) {
         s->gen += 1;
         for (auto& kv : s->sessions) kv.second.closing = true;
         s->cv_work.notify_all();
+        s->cv_admit.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
+    if (s->admitter.joinable()) s->admitter.join();
     for (auto& kv : s->sessions)
         if (kv.second.admitted) retire(s, kv.second);
     s->sessions.clear();
-    if (s->pinned) (void)hipHostFree(s->pinned);
-    if (s->ev) (void)hipEventDestroy(s->ev);
+    for (int k = 0; k < 2; ++k) {
+        if (s->pinned[k]) (void)hipHostFree(s->pinned[k]);
+        if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+    }
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
     delete s;
     return MS_OK;
 }
