@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving sweep: arrival rates 0.1 .. 1.25 x saturation, budgets 48 MB / 128 MB / 256 MB / 1 GB")
+    ap.add_argument("--phase-clock", action="store_true",
+                    help="run the per-phase clock build (libms_clock.so) and report the step's phase split "
+                         "(the headline then carries the clock reads' overhead)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     return ap.parse_args()
@@ -328,6 +331,31 @@ def serving(ms, full=False, seed=0):
     return out
 
 
+PHASES = ["load", "pose_aabb", "broadphase", "narrowphase_rows", "contact_cache", "colouring", "block_lists",
+          "gravity_warm_start", "bias_joint_prep", "joint_wave_warm_start", "sweeps", "force_sums", "integration",
+          "velocity_restitution", "guard_exports", "store"]
+
+
+def phase_split(ms, S, name, n_envs, seed, settle_steps, steps=100):
+    """Wave-cycles per phase of the step over `steps` one-step launches after settling (per-phase
+    clock build only), as fractions of the total."""
+    import torch
+    sc = S.by_name(name, n_envs, seed=seed)
+    b = ms.Batch(sc)
+    settle(b, settle_steps)
+    torch.cuda.synchronize()
+    b.phase_clocks(reset=True)
+    for _ in range(steps):
+        b.step(1)
+    torch.cuda.synchronize()
+    cyc = b.phase_clocks()
+    b.close()
+    tot = float(cyc.sum())
+    return {"steps": steps, "window": f"{settle_steps + 1}..{settle_steps + steps}",
+            "fractions": {p: float(c) / tot for p, c in zip(PHASES, cyc) if c > 0},
+            "wave_cycles_per_env_step": tot / (steps * n_envs)}
+
+
 def traffic_from_profile(name):
     """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
     p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
@@ -346,6 +374,13 @@ def main():
                                    f"--gpus {args.gpus} is not supported"}), flush=True)
         sys.exit(2)
     import torch
+    if args.phase_clock:
+        from paper_2410_00425_amd import build as B
+        os.environ["MS_LIBRARY"] = B.CLOCK_LIB
+        if not os.path.exists(B.CLOCK_LIB):
+            print(json.dumps({"error": f"{B.CLOCK_LIB} is missing: build it with "
+                                       "`python -m paper_2410_00425_amd.build clock`"}), flush=True)
+            sys.exit(2)
     from paper_2410_00425_amd import ms, scenes as S
     torch.cuda.init()
     sc, r, head = run_workload(ms, S, args.workload, args.envs, args.steps, args.warmup, args.steps_per_launch,
@@ -370,6 +405,8 @@ def main():
                      "hbm_frac": algorithmic_bytes(sc) / (r["launch_ms"] / 1e3) / PEAK_HBM,
                      "kernel_source": kernel_source_hash()},
     }
+    if args.phase_clock:
+        out["phase_split"] = phase_split(ms, S, args.workload, args.envs, args.seed, args.settle)
     if args.copy_calibration:
         n = 64 << 20
         x = torch.empty(n, dtype=torch.float32, device="cuda")

@@ -430,6 +430,14 @@ double ms_server_clock(void);
  * of this kind can reach.  MS_E_INVALID_ARG for a null pointer or a non-positive size. */
 ms_status ms_peak_fp32(float* dev_out, int n_waves, int iters, void* hip_stream);
 
+/* Measurement helper of the per-phase clock build (libms built with -DMS_PHASE_CLOCK; the default
+ * build returns MS_E_STATE): wave-cycles spent by the batch's wavefronts in each phase of the step
+ * since the last reset, int64 [16]: load, pose + bounding boxes, broadphase, narrowphase + rows,
+ * contact cache, colouring, block lists, gravity + warm start, bias + joint prep, joint-wave warm
+ * start, sweeps, force sums, integration, velocity + restitution passes, guard + exports, store.
+ * Synchronises `hip_stream`; reset != 0 zeroes the counters. */
+ms_status ms_get_phase_clocks(ms_batch* b, int64_t* host_cycles, int32_t reset, void* hip_stream);
+
 /* Thread-local message of the last non-OK status returned on this thread. */
 const char* ms_last_error(void);
 

@@ -35,5 +35,16 @@ def build_library(verbose: bool = False, out: str = LIB, extra=()) -> str:
     return out
 
 
+CLOCK_LIB = os.path.join(HERE, "libms_clock.so")
+
+
+def build_clock_library(verbose: bool = False) -> str:
+    """The per-phase clock build (libms_clock.so: the same library with -DMS_PHASE_CLOCK), a
+    measurement tool; the binding loads it when MS_LIBRARY names it."""
+    return build_library(verbose, out=CLOCK_LIB, extra=["-DMS_PHASE_CLOCK"])
+
+
 if __name__ == "__main__":
     print(build_library(verbose=True))
+    if len(sys.argv) > 1 and sys.argv[1] == "clock":
+        print(build_clock_library(verbose=True))

@@ -66,6 +66,8 @@ struct BatchDev {
     const int* cache_pt_off;
     float warm_radius;
     int pad6;
+    // per-phase wave-cycles, [16], summed over the launches (only in the per-phase clock build)
+    unsigned long long* phase_clock;
 };
 constexpr int CM_WORDS = 6, CP_WORDS = 4;
 

@@ -182,7 +182,7 @@ struct Plan {
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
     size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, save, status, bpar, body_off, joint_off, jrec, targets, tiles,
-        bins, tenv, bd, stats, forces, bad_ids, cache_hdr, cache_man, cache_man_off, cache_pt, cache_pt_off, cache_save,
+        bins, tenv, bd, stats, forces, bad_ids, phase_clock, cache_hdr, cache_man, cache_man_off, cache_pt, cache_pt_off, cache_save,
         cache_bytes, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
 
@@ -375,6 +375,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.stats = take(E * NSTAT * 8);
     L.forces = take(3 * B * 4);
     L.bad_ids = take(4);
+    L.phase_clock = take(16 * 8);
     if (p->warm_start) {
         // contact cache: header [E][2], manifold records [sum mcap][6], point records [sum cap][4],
         // and a copy of all three for the tuner's save / restore
@@ -502,6 +503,7 @@ void fill_batchdev(ms_batch* b) {
     d.lin_damp = p.lin_damping; d.ang_damp = p.ang_damping;
     d.stats = at<long long>(w, L.stats);
     d.bad_ids = at<int>(w, L.bad_ids);
+    d.phase_clock = at<unsigned long long>(w, L.phase_clock);
     if (p.warm_start) {
         d.cache_hdr = at<int>(w, L.cache_hdr);
         d.cache_man = at<float>(w, L.cache_man);
@@ -724,6 +726,7 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     std::vector<float> zforces(3 * B + 1, 0.0f);
     if (e == hipSuccess) e = up(L.forces, zforces.data(), 3 * B * 4);
     if (e == hipSuccess) e = up(L.bad_ids, zforces.data(), 4);
+    if (e == hipSuccess) e = up(L.phase_clock, zforces.data(), 16 * 8);
     if (params->warm_start) {
         std::vector<int> zh(2 * E, 0);
         if (e == hipSuccess) e = up(L.cache_hdr, zh.data(), 2 * E * 4);
@@ -920,6 +923,26 @@ ms_status ms_get_contact_forces(ms_batch* b, float* dev_out, void* hip_stream) {
     HIP_OK(hipMemcpyAsync(dev_out, b->hbd.forces, size_t(b->B) * 12, hipMemcpyDeviceToDevice,
                           static_cast<hipStream_t>(hip_stream)));
     return MS_OK;
+}
+
+ms_status ms_get_phase_clocks(ms_batch* b, int64_t* host_cycles, int32_t reset, void* hip_stream) {
+    if (!b) return fail(MS_E_INVALID_ARG, "null batch");
+#ifndef MS_PHASE_CLOCK
+    (void)host_cycles; (void)reset; (void)hip_stream;
+    return fail(MS_E_STATE, "this build has no per-phase clock (build with -DMS_PHASE_CLOCK)");
+#else
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<int64_t> v(16, 0);
+    HIP_OK(hipMemcpyAsync(v.data(), b->hbd.phase_clock, 16 * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (host_cycles) std::copy(v.begin(), v.end(), host_cycles);
+    if (reset) {
+        std::fill(v.begin(), v.end(), 0);
+        HIP_OK(hipMemcpyAsync(b->hbd.phase_clock, v.data(), 16 * 8, hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    return MS_OK;
+#endif
 }
 
 ms_status ms_get_invalid_ids(ms_batch* b, int32_t* host_count, int32_t clear, void* hip_stream) {

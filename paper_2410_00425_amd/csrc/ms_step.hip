@@ -121,6 +121,25 @@ struct EnvCtx {
 };
 
 __device__ __forceinline__ int* iptr(float* p) { return reinterpret_cast<int*>(p); }
+
+// HBM accesses through address-space-1 (global) pointers: global loads and stores, which the
+// compiler may reorder freely against LDS accesses.  Through generic pointers it must emit flat
+// accesses and order every one of them against the LDS writes around it (a flat address could be
+// LDS), which serialises the loads of a phase into one HBM round trip each.
+#define MS_GPTR(T, p) ((__attribute__((address_space(1))) T*)(p))
+__device__ __forceinline__ float gld(const float* p) { return *MS_GPTR(const float, p); }
+__device__ __forceinline__ int gldi(const int* p) { return *MS_GPTR(const int, p); }
+__device__ __forceinline__ float4 gld4(const float4* p) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 v = *MS_GPTR(const f4, p);
+    return float4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void gst(float* p, float v) { *MS_GPTR(float, p) = v; }
+__device__ __forceinline__ void gsti(int* p, int v) { *MS_GPTR(int, p) = v; }
+// 64-bit add to HBM without a return value (no wait for the old value)
+__device__ __forceinline__ void gadd64(long long* p, long long v) {
+    __hip_atomic_fetch_add(MS_GPTR(long long, p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ uint16_t* hptr(float* p) { return reinterpret_cast<uint16_t*>(p); }
 
 __device__ __forceinline__ V3 ld3(const float* L, int off, int n, int i) {
@@ -2297,11 +2316,11 @@ __device__ __forceinline__ int man_key(const EnvCtx& c, int m) {
 __device__ __forceinline__ void warm_from_cache(const EnvCtx& c, int nman, int li, int G) {
     const BatchDev& bd = *c.bd;
     __threadfence();   // this env's cache may have been written by this wave's previous step
-    const int nc = bd.cache_hdr[2 * c.env];
+    const int nc = gldi(bd.cache_hdr + 2 * c.env);
     const int* CM = reinterpret_cast<const int*>(bd.cache_man) + size_t(bd.cache_man_off[c.env]) * CM_WORDS;
     const float* CP = bd.cache_pt + size_t(bd.cache_pt_off[c.env]) * CP_WORDS;
     int* KEYS = iptr(c.L + c.lay.CAND);
-    for (int k = li; k < nc; k += G) KEYS[k] = CM[k * CM_WORDS];
+    for (int k = li; k < nc; k += G) KEYS[k] = gldi(CM + k * CM_WORDS);
     wave_sync();
     const float r2 = bd.warm_radius * bd.warm_radius;
     for (int m = li; m < nman; m += G) {
@@ -2313,9 +2332,11 @@ __device__ __forceinline__ void warm_from_cache(const EnvCtx& c, int nman, int l
         }
         if (lo == nc || KEYS[lo] != key) continue;
         const int* rec = CM + lo * CM_WORDS;
-        const int cfc = rec[1];
+        int rw[6];
+        for (int w = 1; w < 6; ++w) rw[w] = gldi(rec + w);
+        const int cfc = rw[1];
         const int cfirst = cfc & 0xFFFF, ccount = cfc >> 16;
-        const V3 pt = v3(__int_as_float(rec[2]), __int_as_float(rec[3]), __int_as_float(rec[4]));
+        const V3 pt = v3(__int_as_float(rw[2]), __int_as_float(rw[3]), __int_as_float(rw[4]));
         int a, b, first, cnt;
         man_header(c, m, a, b, first, cnt);
         const M3 RB = rotm(ldp4(c, b, P_Q0));
@@ -2325,16 +2346,16 @@ __device__ __forceinline__ void warm_from_cache(const EnvCtx& c, int nman, int l
             int bj = -1;
             for (int j = 0; j < ccount; ++j) {
                 const float* q = CP + (cfirst + j) * CP_WORDS;
-                const V3 d = rl - v3(q[0], q[1], q[2]);
+                const V3 d = rl - v3(gld(q), gld(q + 1), gld(q + 2));
                 const float d2 = dot3(d, d);
                 if (d2 < best) { best = d2; bj = j; }
             }
-            if (bj >= 0) pr(c, R_LN, k) = CP[(cfirst + bj) * CP_WORDS + 3];
+            if (bj >= 0) pr(c, R_LN, k) = gld(CP + (cfirst + bj) * CP_WORDS + 3);
         }
         const V3 t1 = mf3(c, M_T1, m);
         mfr(c, M_LT1, m) = dot3(pt, t1);
         mfr(c, M_LT2, m) = dot3(pt, cross3(mf3(c, M_NB, m), t1));
-        mfr(c, M_LTW, m) = __int_as_float(rec[5]);
+        mfr(c, M_LTW, m) = __int_as_float(rw[5]);
     }
     wave_sync();
 }
@@ -2346,8 +2367,8 @@ __device__ __forceinline__ void write_cache(const EnvCtx& c, int nman, int npts,
     int* CM = reinterpret_cast<int*>(bd.cache_man) + size_t(bd.cache_man_off[c.env]) * CM_WORDS;
     float* CP = bd.cache_pt + size_t(bd.cache_pt_off[c.env]) * CP_WORDS;
     if (li == 0) {
-        bd.cache_hdr[2 * c.env] = bad ? 0 : nman;
-        bd.cache_hdr[2 * c.env + 1] = bad ? 0 : npts;
+        gsti(bd.cache_hdr + 2 * c.env, bad ? 0 : nman);
+        gsti(bd.cache_hdr + 2 * c.env + 1, bad ? 0 : npts);
     }
     if (bad) return;
     for (int m = li; m < nman; m += G) {
@@ -2356,15 +2377,16 @@ __device__ __forceinline__ void write_cache(const EnvCtx& c, int nman, int npts,
         const V3 t1 = mf3(c, M_T1, m);
         const V3 pt = mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * cross3(mf3(c, M_NB, m), t1);
         int* rec = CM + m * CM_WORDS;
-        rec[0] = a >= 0 ? (a << 8) | b : (b << 8) | 0xFF;
-        rec[1] = first | (cnt << 16);
-        rec[2] = __float_as_int(pt.x); rec[3] = __float_as_int(pt.y); rec[4] = __float_as_int(pt.z);
-        rec[5] = __float_as_int(mf(c, M_LTW, m));
+        gsti(rec, a >= 0 ? (a << 8) | b : (b << 8) | 0xFF);
+        gsti(rec + 1, first | (cnt << 16));
+        gsti(rec + 2, __float_as_int(pt.x)); gsti(rec + 3, __float_as_int(pt.y)); gsti(rec + 4, __float_as_int(pt.z));
+        gsti(rec + 5, __float_as_int(mf(c, M_LTW, m)));
         const M3 RB = rotm(ldp4(c, b, P_Q0));
         for (int k = first; k < first + cnt; ++k) {
             const V3 rl = mulTv(RB, pr3(c, R_RB, k));
             float* q = CP + k * CP_WORDS;
-            q[0] = rl.x; q[1] = rl.y; q[2] = rl.z; q[3] = pr(c, R_LN, k);
+            const float ln = pr(c, R_LN, k);
+            gst(q, rl.x); gst(q + 1, rl.y); gst(q + 2, rl.z); gst(q + 3, ln);
         }
     }
 }
@@ -2372,12 +2394,34 @@ __device__ __forceinline__ bool warm_on(const EnvCtx& c) {
     return *reinterpret_cast<int* const volatile*>(&c.bd->cache_hdr) != nullptr;
 }
 
+// Per-phase clock (a build flag, MS_PHASE_CLOCK, off in the library's default build): each
+// wavefront reads the shader clock at the phase boundaries of the step and adds the cycles spent
+// in each phase to bd.phase_clock[phase] at the end of its launch (wave-cycles, stalls included).
+enum { PH_LOAD, PH_POSE, PH_BROAD, PH_NARROW, PH_CACHE, PH_COLOUR, PH_LISTS, PH_SUBSTART, PH_BIAS, PH_WARMJ,
+       PH_SWEEP, PH_FORCES, PH_INTEG, PH_VEL, PH_GUARD, PH_STORE, N_PHASES };
+#ifdef MS_PHASE_CLOCK
+#define PHASE(k)                                              \
+    do {                                                      \
+        const uint64_t t_ = __builtin_amdgcn_s_memtime();     \
+        ph_acc[k] += t_ - ph_t;                               \
+        ph_t = t_;                                            \
+    } while (0)
+#else
+#define PHASE(k) \
+    do {         \
+    } while (0)
+#endif
+
 // OPT: the build with the optional phases (contact-force readout, contact cache); the default
 // builds leave them out entirely, so that they cost the plain step no registers.
 template <bool ONE, bool OPT>
 __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict__ batches, const Tile tile,
                                           const TileEnv* __restrict__ tenv, int n_steps, int lane) {
     {
+#ifdef MS_PHASE_CLOCK
+        uint64_t ph_acc[N_PHASES] = {};
+        uint64_t ph_t = __builtin_amdgcn_s_memtime();
+#endif
         const int G = ONE ? WAVE : tile.lanes;
         const int g = ONE ? 0 : lane / G, li = ONE ? lane : lane % G;
         EnvCtx c;
@@ -2399,13 +2443,19 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
         const int B = bd.B;
 
         // ------------------------------------------------------------- load (once per launch)
+        // every HBM value of a body first (16 loads in flight at once), then its LDS records
         for (int i = li; i < nA; i += G) {
-            int gi = c.b0 + i;
-            for (int r = 0; r < 3; ++r) pose_rec(c, i)[P_X0 + r] = bd.pos[r * B + gi];
-            for (int r = 0; r < 4; ++r) pose_rec(c, i)[P_QC + r] = bd.quat[r * B + gi];
-            for (int r = 0; r < 3; ++r) body_rec(c, i)[B_V + r] = bd.vel[r * B + gi];
-            for (int r = 0; r < 3; ++r) body_rec(c, i)[B_W + r] = bd.angvel[r * B + gi];
-            float4 p0 = bd.bpar[gi], p1 = bd.bpar[B + gi], p2 = bd.bpar[2 * B + gi];
+            const int gi = c.b0 + i;
+            float st[13];
+            for (int r = 0; r < 3; ++r) st[r] = gld(bd.pos + r * B + gi);
+            for (int r = 0; r < 4; ++r) st[3 + r] = gld(bd.quat + r * B + gi);
+            for (int r = 0; r < 3; ++r) st[7 + r] = gld(bd.vel + r * B + gi);
+            for (int r = 0; r < 3; ++r) st[10 + r] = gld(bd.angvel + r * B + gi);
+            const float4 p0 = gld4(bd.bpar + gi), p1 = gld4(bd.bpar + B + gi), p2 = gld4(bd.bpar + 2 * B + gi);
+            for (int r = 0; r < 3; ++r) pose_rec(c, i)[P_X0 + r] = st[r];
+            for (int r = 0; r < 4; ++r) pose_rec(c, i)[P_QC + r] = st[3 + r];
+            for (int r = 0; r < 3; ++r) body_rec(c, i)[B_V + r] = st[7 + r];
+            for (int r = 0; r < 3; ++r) body_rec(c, i)[B_W + r] = st[10 + r];
             int sh = __float_as_int(p0.x);
             iptr(c.L + l.SH)[i] = sh;
             bool dyn = !((sh >> 8) & 1);
@@ -2420,14 +2470,17 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
         }
         for (int j = li; j < njA; j += G) {
             const float* src = bd.jrec + size_t(c.j0 + j) * JREC;
+            float jr[21];
+            for (int w = 0; w < 21; ++w) jr[w] = gld(src + w);
+            const float tg = gld(bd.targets + c.j0 + j);
             float* J = jrec(c, j);
-            for (int w = 0; w < 18; ++w) J[w] = src[w];
-            J[J_TG] = bd.targets[c.j0 + j];
-            J[J_TYP] = src[18];
-            J[J_LO] = src[19];
-            J[J_HI] = src[20];
+            for (int w = 0; w < 18; ++w) J[w] = jr[w];
+            J[J_TG] = tg;
+            J[J_TYP] = jr[18];
+            J[J_LO] = jr[19];
+            J[J_HI] = jr[20];
         }
-        if (c.active && li == 0) SC[SC_STATUS] = bd.status[c.env];
+        if (c.active && li == 0) SC[SC_STATUS] = gldi(bd.status + c.env);
         for (int k = li; k < (c.active ? NSTAT : 0); k += G) SC[16 + k] = 0;
         wave_sync();
         // jointed-partner masks (parent-child pairs never collide)
@@ -2444,6 +2497,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             iptr(c.L + l.JM)[2 * i + 1] = int(uint32_t(m >> 32));
         }
         wave_sync();
+        PHASE(PH_LOAD);
 
         for (int step = 0; step < n_steps; ++step) {
             const bool frozen = !c.active || (SC[SC_STATUS] & 1);
@@ -2487,6 +2541,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             }
             wave_sync();
 
+            PHASE(PH_POSE);
             // --------------------------------------------------------- S2 candidate pairs
             const int P = frozen ? 0 : l.P;
             int ncand = 0;
@@ -2554,6 +2609,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             }
             wave_sync();
 
+            PHASE(PH_BROAD);
             // --------------------------------------------------------- S3 + S4 narrowphase, rows
             int npts = 0, nman = 0;
             bool overflow = false;
@@ -2604,11 +2660,13 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 SC[16 + STAT_MANIFOLDS] += nman;
             }
             wave_sync();
+            PHASE(PH_NARROW);
             // --------------------------------------------------------- S4b cross-step warm start
             // (the batch's flag is re-read at each use, a volatile scalar load, so that it holds
             // no register through the substeps)
             if (OPT && !frozen && warm_on(c)) warm_from_cache(c, nman, li, G);
 
+            PHASE(PH_CACHE);
             // --------------------------------------------------------- S5 colouring
             if (G == WAVE) {
                 if (!frozen) colour_env_wave(c);
@@ -2625,6 +2683,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             const bool pipe = __ballot(c.active && nj > 0) == 0;   // no joints anywhere in the wave
             const int nmanA = frozen ? 0 : SC[SC_NMAN];
 
+            PHASE(PH_COLOUR);
             // --------------------------------------------------------- S6 substeps
             if (OPT && forces_on(c)) {
                 for (int i = li; i < nn; i += G) {
@@ -2640,27 +2699,33 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 else build_body_lists(c, nn, nmanA, li, G);
                 wave_sync();
             }
+            PHASE(PH_LISTS);
             for (int s = 0; s < S; ++s) {
                 // warm start: the previous substep's impulses, or the cached ones in the first
                 const bool gather = pipe && (s > 0 || (OPT && !frozen && warm_on(c)));
                 for (int i = li; i < nn; i += G)
                     if (is_dyn(c, i)) body_substep_start(c, i, h, ldmp, admp, gather);
+                PHASE(PH_SUBSTART);
                 bias_pass(c, nmanA, h, false, li, G);
                 for (int j = li; j < (frozen ? 0 : nj); j += G) joint_prep(c, j, h);
                 wave_sync();
+                PHASE(PH_BIAS);
                 if ((s > 0 || (OPT && !frozen && warm_on(c))) && !pipe) {   // waves with joints: gathered per body once the joint pass has run
                     for (int i = li; i < nn; i += G)
                         if (is_dyn(c, i)) body_warm_gather(c, i);
                     wave_sync();
                 }
+                PHASE(PH_WARMJ);
                 for (int it = 0; it < K; ++it) {
                     for (int jx = 1; jx < JI; ++jx) run_schedule<OP_JOINT, false>(c, l.JSCHED, njs, njs_max, h, li);
                     (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_SOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_SOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
                 }
+                PHASE(PH_SWEEP);
                 if (OPT && s + 1 < S && forces_on(c)) {
                     wave_sync();
                     accumulate_forces(c, nn, li, G);
                 }
+                PHASE(PH_FORCES);
                 // integrate the offsets from the step-start pose
                 for (int i = li; i < nn; i += G) {
                     if (!is_dyn(c, i)) continue;
@@ -2674,6 +2739,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                     stp4(c, i, P_QC, qnorm(qmul(d, ldp4(c, i, P_Q0))));
                 }
                 wave_sync();
+                PHASE(PH_INTEG);
             }
             // --------------------------------------------------------- S7
             if (bd.V > 0) {
@@ -2683,6 +2749,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
             }
             for (int it = 0; it < bd.V; ++it) (pipe && G >= 2 ? run_schedule_pairs(c, l.SCHED, ns, ns_max, li, G) : pipe ? run_schedule<OP_VSOLVE, true>(c, l.SCHED, ns, ns_max, h, li) : run_schedule<OP_VSOLVE, false>(c, l.SCHED, ns, ns_max, h, li));
             run_schedule<OP_REST, false>(c, l.SCHED, ns, ns_max, h, li);
+            PHASE(PH_VEL);
 
             // --------------------------------------------------------- S8 non-finite guard
             bool bad = false;
@@ -2715,7 +2782,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                     V3 f = v3(0, 0, 0);
                     if (!frozen && !anybad) f = idt * v3(c.L[l.AABB + i], c.L[l.AABB + n + i], c.L[l.AABB + 2 * n + i]);
                     const int gi = c.b0 + i;
-                    bd.forces[gi] = f.x; bd.forces[B + gi] = f.y; bd.forces[2 * B + gi] = f.z;
+                    gst(bd.forces + gi, f.x); gst(bd.forces + B + gi, f.y); gst(bd.forces + 2 * B + gi, f.z);
                 }
             }
             wave_sync();
@@ -2735,20 +2802,30 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                     dc[0] = ncand; dc[1] = npts; dc[2] = nman; dc[3] = SC[SC_NCOL];
                 }
             }
+            PHASE(PH_GUARD);
         }
         wave_sync();
         // ------------------------------------------------------------- store
+        // a body's LDS words first, then its HBM stores; counters by 64-bit atomic adds (no read
+        // of the old value)
         for (int i = li; i < nA; i += G) {
-            int gi = c.b0 + i;
-            V3 x = ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
-            bd.pos[gi] = x.x; bd.pos[B + gi] = x.y; bd.pos[2 * B + gi] = x.z;
-            for (int r = 0; r < 4; ++r) bd.quat[r * B + gi] = pose_rec(c, i)[P_QC + r];
-            for (int r = 0; r < 3; ++r) bd.vel[r * B + gi] = body_rec(c, i)[B_V + r];
-            for (int r = 0; r < 3; ++r) bd.angvel[r * B + gi] = body_rec(c, i)[B_W + r];
+            const int gi = c.b0 + i;
+            const V3 x = ldp3(c, i, P_X0) + ldp3(c, i, P_DX);
+            const Qt q = ldp4(c, i, P_QC);
+            const V3 v = ldv(c, i), w = ldw(c, i);
+            gst(bd.pos + gi, x.x); gst(bd.pos + B + gi, x.y); gst(bd.pos + 2 * B + gi, x.z);
+            gst(bd.quat + gi, q.w); gst(bd.quat + B + gi, q.x); gst(bd.quat + 2 * B + gi, q.y); gst(bd.quat + 3 * B + gi, q.z);
+            gst(bd.vel + gi, v.x); gst(bd.vel + B + gi, v.y); gst(bd.vel + 2 * B + gi, v.z);
+            gst(bd.angvel + gi, w.x); gst(bd.angvel + B + gi, w.y); gst(bd.angvel + 2 * B + gi, w.z);
         }
-        if (c.active && li == 0) bd.status[c.env] = SC[SC_STATUS];
-        for (int k = li; k < (c.active ? NSTAT : 0); k += G) bd.stats[NSTAT * c.env + k] += (long long)SC[16 + k];
+        if (c.active && li == 0) gsti(bd.status + c.env, SC[SC_STATUS]);
+        for (int k = li; k < (c.active ? NSTAT : 0); k += G) gadd64(bd.stats + NSTAT * c.env + k, (long long)SC[16 + k]);
         wave_sync();
+        PHASE(PH_STORE);
+#ifdef MS_PHASE_CLOCK
+        if (lane == 0 && bd.phase_clock)
+            for (int k = 0; k < N_PHASES; ++k) atomicAdd(&bd.phase_clock[k], (unsigned long long)ph_acc[k]);
+#endif
     }
 }
 

@@ -15,7 +15,8 @@ import numpy as np
 from . import scenes
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libms.so")
+# MS_LIBRARY may name another build of the same library (the per-phase clock build)
+LIB_PATH = os.environ.get("MS_LIBRARY") or os.path.join(_HERE, "libms.so")
 
 # torch first: its HIP runtime is then the one libms binds to (loading libms first would bring in
 # a second copy of the runtime, and torch's device calls and the library's would not share a device)
@@ -98,6 +99,7 @@ _sig = {
     "ms_set_contact_forces": [_P, _I, _P],
     "ms_get_contact_forces": [_P, _P, _P],
     "ms_get_invalid_ids": [_P, C.POINTER(C.c_int32), _I, _P],
+    "ms_get_phase_clocks": [_P, _P, _I, _P],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -244,6 +246,12 @@ class Batch:
         import torch
         out = torch.empty(3, self.n_bodies, dtype=torch.float32, device=self.device)
         _check(_lib.ms_get_contact_forces(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def phase_clocks(self, reset=False, stream=None):
+        """ms_get_phase_clocks (per-phase clock build only): int64 [16] wave-cycles per phase."""
+        out = np.zeros(16, np.int64)
+        _check(_lib.ms_get_phase_clocks(self._h, out.ctypes.data, 1 if reset else 0, _stream(stream)))
         return out
 
     def invalid_ids(self, clear=False, stream=None) -> int:
