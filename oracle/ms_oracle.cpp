@@ -12,7 +12,9 @@
 //   S0 frozen step-start quantities; S1 exact AABBs; S2 all-pairs broadphase with filters;
 //   S3 narrowphase for sphere / capsule / box / plane pairs (closest points after Ericson,
 //      "Real-Time Collision Detection" 5.1.9; separating axes after Gottschalk's OBB test;
-//      Sutherland-Hodgman clipping) with a <= 4 point manifold reduction;
+//      Sutherland-Hodgman clipping) with a <= 4 point manifold reduction; compound bodies
+//      (up to 4 primitive parts, the convex pieces of a decomposed object) by every pair of
+//      parts, one manifold per pair of parts with points;
 //   S4 contact rows (tangent basis after Duff et al. 2017, "Building an Orthonormal Basis,
 //      Revisited"); S4b (optional) cross-step warm start from a contact cache matched by pair
 //      and body-frame position; S5 greedy colouring that fixes the Gauss-Seidel order;
@@ -36,7 +38,7 @@
 namespace orc {
 
 // ----------------------------------------------------------------------------- interface types
-// Byte layout of the descriptor records handed over by the input generators (88 / 76 bytes).
+// Byte layout of the descriptor records handed over by the input generators (88 / 92 bytes).
 struct BodyDesc {
     int32_t shape, flags;
     float dims[3];
@@ -70,7 +72,17 @@ static_assert(sizeof(Params) == 96, "parameter record layout");
 static_assert(sizeof(BodyDesc) == 88, "body record layout");
 static_assert(sizeof(JointDesc) == 92, "joint record layout");
 
-enum { SPHERE = 0, CAPSULE = 1, BOX = 2 };
+enum { SPHERE = 0, CAPSULE = 1, BOX = 2, COMPOUND = 3 };
+constexpr int MAX_CHILDREN = 4;
+// A compound body's parts: up to 4 primitives (sphere / capsule / box) with their poses in the
+// body frame (position, then quaternion w, x, y, z).  180 bytes.
+struct CompoundDesc {
+    int32_t n_children;
+    int32_t shape[MAX_CHILDREN];
+    float dims[MAX_CHILDREN][3];
+    float pose[MAX_CHILDREN][7];
+};
+static_assert(sizeof(CompoundDesc) == 180, "compound record layout");
 enum { STATIC = 1 };
 enum { REVOLUTE = 0, PRISMATIC = 1 };
 enum { ST_NONFINITE = 1, ST_CONTACT_OVERFLOW = 2, ST_COLOR_OVERFLOW = 4 };
@@ -173,9 +185,48 @@ template <class T> inline V3<T> shape_inertia(int shape, const T* d, T mass) {
     return {ixx, ixx, izz};
 }
 
+// Compound mass properties (uniform density over the parts; overlapping parts count twice): the
+// parts share the mass in proportion to their volumes; each part's inertia about its centre is
+// rotated into the body frame, R diag(I) R^T, and moved to the body origin by the parallel-axis
+// term m_k (|c|^2 delta_ij - c_i c_j); the parts are summed in order.  The body frame must be
+// the principal frame with the centre of mass at its origin (the scene generator builds
+// compounds so): only the diagonal is used.
+template <class T> struct Compound {
+    int n = 0;
+    int shape[MAX_CHILDREN] = {0, 0, 0, 0};
+    T dims[MAX_CHILDREN][3] = {};
+    V3<T> c[MAX_CHILDREN];
+    Q<T> q[MAX_CHILDREN];
+};
+template <class T> inline T compound_volume(const Compound<T>& C) {
+    T v = 0;
+    for (int k = 0; k < C.n; ++k) v = v + shape_volume<T>(C.shape[k], C.dims[k]);
+    return v;
+}
+template <class T> inline V3<T> compound_inertia(const Compound<T>& C, T mass) {
+    const T vt = compound_volume(C);
+    T I[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < C.n; ++k) {
+        const T mk_ = mass * (shape_volume<T>(C.shape[k], C.dims[k]) / vt);
+        const V3<T> Ik = shape_inertia<T>(C.shape[k], C.dims[k], mk_);
+        const M3<T> R = rotm(C.q[k]);
+        const T d[3] = {Ik.x, Ik.y, Ik.z};
+        const T cc[3] = {C.c[k].x, C.c[k].y, C.c[k].z};
+        const T c2 = dot(C.c[k], C.c[k]);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const T rot = R.m[i][0] * d[0] * R.m[j][0] + R.m[i][1] * d[1] * R.m[j][1] + R.m[i][2] * d[2] * R.m[j][2];
+                const T par = mk_ * ((i == j ? c2 : T(0)) - cc[i] * cc[j]);
+                I[i][j] = I[i][j] + (rot + par);
+            }
+    }
+    return {I[0][0], I[1][1], I[2][2]};
+}
+
 // ----------------------------------------------------------------------------- scene storage
 template <class T> struct Body {
     int shape = 0, flags = 0;
+    int comp = -1;   // compound index (shape COMPOUND)
     T dims[3] = {0, 0, 0};
     T invm = 0;
     V3<T> invI{0, 0, 0};  // body-frame principal inverse inertia
@@ -676,6 +727,7 @@ template <class T> struct CRow {
 // mean normal bounded by mu times the mean point radius times the summed normal impulse).
 template <class T> struct Manifold {
     int a, b, first, count, colour, pair;
+    int part;   // pair of parts of a compound body pair (0 for primitive pairs)
     V3<T> base, offB;  // frame of the contact geometry (for the record)
     V3<T> rA, rB, nb, t1, t2;
     T mt1, mt2, mtw, mu, rt;
@@ -694,6 +746,7 @@ template <class T> struct CacheMan { int key, first, count; V3<T> pt; T ltw; };
 template <class T> struct CachePt { V3<T> rl; T ln; };
 
 template <class T> struct Env {
+    const std::vector<Compound<T>>* comps = nullptr;   // the batch's compound table
     std::vector<Body<T>> bodies;
     std::vector<Joint<T>> joints;
     int status = 0;
@@ -713,6 +766,13 @@ template <class T> struct BodyView {
     T invm;
     M3<T> Iw;  // world inverse inertia, frozen for the step
 };
+
+// Half size along world axis r of a primitive with rotation R: add, multiply and abs only.
+template <class T> inline T part_half(int shape, const T* d, const M3<T>& R, int r) {
+    if (shape == BOX) return (std::fabs(R.m[r][0]) * d[0] + std::fabs(R.m[r][1]) * d[1]) + std::fabs(R.m[r][2]) * d[2];
+    if (shape == SPHERE) return d[0];
+    return std::fabs(R.m[r][2]) * d[1] + d[0];
+}
 
 template <class T> inline V3<T> vel_at(const Body<T>* b, V3<T> r) {
     if (!b) return mk<T>(0, 0, 0);
@@ -886,9 +946,11 @@ template <class T> struct Stepper {
 
     // ------------------------------------------------------------- S0..S5: detection and rows
     // ------------------------------------------------------------- S4b cross-step warm start
-    // Pair key of a manifold, increasing in canonical order: (lower body, partner), the ground
-    // plane after every partner of its body.
-    static int man_key(const Manifold<T>& m) { return m.a >= 0 ? (m.a << 8) | m.b : (m.b << 8) | 0xFF; }
+    // Key of a manifold, increasing in canonical order: (lower body, partner, pair of parts), the
+    // ground plane after every partner of its body.
+    static int man_key(const Manifold<T>& m) {
+        return ((m.a >= 0 ? (m.a << 8) | m.b : (m.b << 8) | 0xFF) << 4) | m.part;
+    }
     // Initial impulses from the last step's cache: a manifold whose pair is cached takes, for each
     // of its points, the normal impulse of the nearest cached point of that pair (positions in
     // body B's frame at the step start, squared distance below warm_radius^2, the first cached
@@ -945,6 +1007,112 @@ template <class T> struct Stepper {
         }
     }
 
+    // ------------------------------------------------------------- compound pairs
+    // The primitive parts of body i with its centre at `cen` (pair frame): the body itself, or
+    // each part of a compound at cen + R c_k with rotation R(q q_k).
+    int parts(int i, V3<T> cen, Shape<T>* out) const {
+        const Body<T>& b = E.bodies[i];
+        if (b.shape != COMPOUND) {
+            out[0] = shape_of(i);
+            out[0].c = cen;
+            return 1;
+        }
+        const Compound<T>& C = (*E.comps)[b.comp];
+        const M3<T> R = rotm(b.q);
+        for (int k = 0; k < C.n; ++k) {
+            out[k].type = C.shape[k];
+            out[k].c = cen + mul(R, C.c[k]);
+            out[k].R = rotm(qmul(b.q, C.q[k]));
+            out[k].d[0] = C.dims[k][0]; out[k].d[1] = C.dims[k][1]; out[k].d[2] = C.dims[k][2];
+        }
+        return C.n;
+    }
+    // Contact points of a pair with a compound body (a = -1: the ground plane; B's centre at cB):
+    // every pair of parts, A's parts outer, through the primitive narrowphase, each reduced to at
+    // most 4 points: one point set per pair of parts, each becoming its own manifold (its own
+    // friction patch: parts of one compound may touch a body from opposite sides).  Returns the
+    // number of part pairs; the decision code (in o[0]) is 64 + the index of the first part pair
+    // that produced points (63: none) and the margin the smallest over all; every part pair
+    // counts as a candidate of its primitive kind.
+    int compound_narrow(Out<T>* o, int a, int b, V3<T> cB, T delta, int64_t* cnt) const {
+        Shape<T> pa[MAX_CHILDREN], pb[MAX_CHILDREN];
+        const int na = a >= 0 ? parts(a, mk<T>(0, 0, 0), pa) : 1;
+        const int nb = parts(b, cB, pb);
+        int first_hit = -1, idx = 0;
+        double margin = 1e30;
+        for (int i = 0; i < na; ++i)
+            for (int j = 0; j < nb; ++j, ++idx) {
+                Out<T>& o2 = o[idx];
+                if (a < 0) {
+                    narrow_plane(o2, T(0), pb[j], delta);
+                    cnt[CNT_KIND0 + 9 + pb[j].type]++;
+                } else {
+                    narrow(o2, pa[i], pb[j], delta);
+                    cnt[CNT_KIND0 + 3 * std::min(pa[i].type, pb[j].type) + std::max(pa[i].type, pb[j].type)]++;
+                }
+                reduce4(o2);
+                if (o2.margin < margin) margin = o2.margin;
+                if (o2.n > 0 && first_hit < 0) first_hit = idx;
+            }
+        o[0].decision = first_hit < 0 ? 63 : 64 + first_hit;
+        o[0].margin = margin;
+        return idx;
+    }
+
+    // S4 for one point set: a normal row per kept point (arms from the step-start centres) and the
+    // manifold's friction patch at the points' centroid (tangent t1 along the pre-step sliding
+    // velocity there, else the Duff et al. basis of the mean normal).
+    void add_manifold(const Out<T>& o, int keep, int first, bool isplane, int a, int bb, V3<T> base, V3<T> offB,
+                      int pair_index, int part, double& min_margin) {
+        const Body<T>& A = E.bodies[a];
+        int ia = isplane ? -1 : a, ib = isplane ? a : bb;
+        T mu, e;
+        if (isplane) { mu = (T(P.plane_friction) + A.mu) / T(2); e = std::max(T(P.plane_restitution), A.e); }
+        else { mu = (A.mu + E.bodies[bb].mu) / T(2); e = std::max(A.e, E.bodies[bb].e); }
+        V3<T> csum = mk<T>(0, 0, 0), nsum = mk<T>(0, 0, 0);
+        for (int k = 0; k < keep; ++k) {
+            CRow<T> r;
+            r.a = ia; r.b = ib;
+            V3<T> p = o.pt[k].p;  // relative to `base`
+            r.n = o.pt[k].n;
+            r.rA = ia >= 0 ? p : mk<T>(0, 0, 0);
+            r.rB = p - offB;
+            V3<T> vrel = vel_at(&E.bodies[ib], r.rB) - (ia >= 0 ? vel_at(&E.bodies[ia], r.rA) : mk<T>(0, 0, 0));
+            r.vnpre = dot(vrel, r.n);
+            r.mn = eff(ia, ib, r.rA, r.rB, r.n);
+            r.s0 = o.pt[k].s;
+            r.e = e;
+            r.ln = 0;
+            r.ln0 = 0;
+            rows.push_back(r);
+            csum = csum + p;
+            nsum = nsum + r.n;
+        }
+        Manifold<T> M;
+        M.a = ia; M.b = ib; M.first = first; M.count = keep; M.colour = 0; M.pair = pair_index; M.part = part;
+        M.base = base; M.offB = offB;
+        V3<T> c = (T(1) / T(keep)) * csum;
+        M.nb = (T(1) / len(nsum)) * nsum;
+        M.rA = ia >= 0 ? c : mk<T>(0, 0, 0);
+        M.rB = c - offB;
+        V3<T> vrel = vel_at(&E.bodies[ib], M.rB) - (ia >= 0 ? vel_at(&E.bodies[ia], M.rA) : mk<T>(0, 0, 0));
+        V3<T> vt = vrel - dot(vrel, M.nb) * M.nb;
+        T vtl = len(vt);
+        if (std::fabs(double(vtl) - 1e-3) < min_margin) min_margin = std::fabs(double(vtl) - 1e-3);
+        M.t1 = vtl >= T(1e-3) ? (T(1) / vtl) * vt : onb_t1(M.nb);
+        M.t2 = cross(M.nb, M.t1);
+        M.mt1 = eff(ia, ib, M.rA, M.rB, M.t1);
+        M.mt2 = eff(ia, ib, M.rA, M.rB, M.t2);
+        T kw = (ia >= 0 ? dot(M.nb, mul(bv[ia].Iw, M.nb)) : T(0)) + dot(M.nb, mul(bv[ib].Iw, M.nb));
+        M.mtw = kw > T(0) ? T(1) / kw : T(0);
+        T rsum = 0;
+        for (int k = 0; k < keep; ++k) rsum = rsum + len(o.pt[k].p - c);
+        M.rt = rsum / T(keep);
+        M.mu = mu;
+        M.lt1 = M.lt2 = M.ltw = 0;
+        mans.push_back(M);
+    }
+
     void prepare(double& min_margin, int64_t* cnt) {
         const int n = int(E.bodies.size());
         const T delta = T(P.contact_offset);
@@ -962,14 +1130,21 @@ template <class T> struct Stepper {
             const Body<T>& b = E.bodies[i];
             M3<T> R = rotm(b.q);
             V3<T> half;
-            for (int r = 0; r < 3; ++r) {
-                T hv;
-                if (b.shape == BOX)
-                    hv = (std::fabs(R.m[r][0]) * b.dims[0] + std::fabs(R.m[r][1]) * b.dims[1]) + std::fabs(R.m[r][2]) * b.dims[2];
-                else if (b.shape == SPHERE) hv = b.dims[0];
-                else hv = std::fabs(R.m[r][2]) * b.dims[1] + b.dims[0];
-                set(half, r, hv + delta);
-            }
+            if (b.shape == COMPOUND) {
+                // the largest extent over the parts: |R c_k| + the part's own half size
+                const Compound<T>& C = (*E.comps)[b.comp];
+                T hm[3] = {0, 0, 0};
+                for (int k = 0; k < C.n; ++k) {
+                    const V3<T> o = mul(R, C.c[k]);
+                    const M3<T> Rk = rotm(qmul(b.q, C.q[k]));
+                    for (int r = 0; r < 3; ++r) {
+                        const T hv = std::fabs(get(o, r)) + part_half(C.shape[k], C.dims[k], Rk, r);
+                        if (hv > hm[r]) hm[r] = hv;
+                    }
+                }
+                for (int r = 0; r < 3; ++r) set(half, r, hm[r] + delta);
+            } else
+            for (int r = 0; r < 3; ++r) set(half, r, part_half(b.shape, b.dims, R, r) + delta);
             lo[i] = b.x - half;
             hi[i] = b.x + half;
         }
@@ -1004,90 +1179,64 @@ template <class T> struct Stepper {
                         continue;
                 }
                 cnt[CNT_CAND]++;
-                Out<T> o;
+                Out<T> outs[MAX_CHILDREN * MAX_CHILDREN];
+                Out<T>& o = outs[0];
+                int nout = 1;
                 int kind;
                 V3<T> base, offB;  // contact points come relative to `base`; B's centre is at offB
                 if (isplane) {
                     kind = 9 + A.shape;  // 9 plane-sphere, 10 plane-capsule, 11 plane-box
                     // frame: origin at (x, y) of the body on the ground plane
-                    Shape<T> sb = shape_of(a);
                     base = mk(A.x.x, A.x.y, T(P.plane_z));
-                    sb.c = mk(T(0), T(0), A.x.z - T(P.plane_z));
-                    narrow_plane(o, T(0), sb, delta);
-                    offB = sb.c;
+                    offB = mk(T(0), T(0), A.x.z - T(P.plane_z));
+                    if (A.shape == COMPOUND) {
+                        kind = 12;
+                        nout = compound_narrow(outs, -1, a, offB, delta, cnt);
+                    } else {
+                        Shape<T> sb = shape_of(a);
+                        sb.c = offB;
+                        narrow_plane(o, T(0), sb, delta);
+                    }
                 } else {
-                    int sa = A.shape, sb = E.bodies[bb].shape;
-                    int lo_s = std::min(sa, sb), hi_s = std::max(sa, sb);
-                    kind = lo_s * 3 + hi_s;  // 0 ss,1 sc,2 sb,4 cc,5 cb,8 bb
                     // frame: origin at A's centre (translation-invariant contact geometry)
-                    Shape<T> sa2 = shape_of(a), sb2 = shape_of(bb);
                     base = A.x;
-                    sa2.c = mk<T>(0, 0, 0);
-                    sb2.c = E.bodies[bb].x - A.x;
-                    narrow(o, sa2, sb2, delta);
-                    offB = sb2.c;
+                    offB = E.bodies[bb].x - A.x;
+                    int sa = A.shape, sb = E.bodies[bb].shape;
+                    if (sa == COMPOUND || sb == COMPOUND) {
+                        kind = 12;
+                        nout = compound_narrow(outs, a, bb, offB, delta, cnt);
+                    } else {
+                        int lo_s = std::min(sa, sb), hi_s = std::max(sa, sb);
+                        kind = lo_s * 3 + hi_s;  // 0 ss,1 sc,2 sb,4 cc,5 cb,8 bb
+                        Shape<T> sa2 = shape_of(a), sb2 = shape_of(bb);
+                        sa2.c = mk<T>(0, 0, 0);
+                        sb2.c = offB;
+                        narrow(o, sa2, sb2, delta);
+                    }
                 }
-                cnt[CNT_KIND0 + kind]++;
-                reduce4(o);
+                if (kind < 12) {
+                    cnt[CNT_KIND0 + kind]++;
+                    reduce4(o);
+                }
                 if (o.margin < min_margin) min_margin = o.margin;
                 int pair_index = rec ? int(rec->pairs.size()) : 0;
-                int first = int(rows.size());
-                int keep = o.n;
-                // overflow keeps the first points / manifolds in canonical pair order
-                if (first + keep > cap) { keep = cap - first; E.status |= ST_CONTACT_OVERFLOW; }
-                if (keep > 0 && int(mans.size()) >= mcap) { keep = 0; E.status |= ST_CONTACT_OVERFLOW; }
-                if (rec) rec->pairs.push_back(PairRec{env_id, a, isplane ? PLANE_ID : bb, keep, o.decision, kind, o.margin,
-                                                      0, 0, 0, 0, 0});
-                if (keep <= 0) continue;
-                int ia = isplane ? -1 : a, ib = isplane ? a : bb;
-                T mu, e;
-                if (isplane) { mu = (T(P.plane_friction) + A.mu) / T(2); e = std::max(T(P.plane_restitution), A.e); }
-                else { mu = (A.mu + E.bodies[bb].mu) / T(2); e = std::max(A.e, E.bodies[bb].e); }
-                // S4: one normal row per point (arms from the step-start centres).
-                V3<T> csum = mk<T>(0, 0, 0), nsum = mk<T>(0, 0, 0);
-                for (int k = 0; k < keep; ++k) {
-                    CRow<T> r;
-                    r.a = ia; r.b = ib;
-                    V3<T> p = o.pt[k].p;  // relative to `base`
-                    r.n = o.pt[k].n;
-                    r.rA = ia >= 0 ? p : mk<T>(0, 0, 0);
-                    r.rB = p - offB;
-                    V3<T> vrel = vel_at(&E.bodies[ib], r.rB) - (ia >= 0 ? vel_at(&E.bodies[ia], r.rA) : mk<T>(0, 0, 0));
-                    r.vnpre = dot(vrel, r.n);
-                    r.mn = eff(ia, ib, r.rA, r.rB, r.n);
-                    r.s0 = o.pt[k].s;
-                    r.e = e;
-                    r.ln = 0;
-                    r.ln0 = 0;
-                    rows.push_back(r);
-                    csum = csum + p;
-                    nsum = nsum + r.n;
+                const int decision = o.decision;
+                const double pmargin = o.margin;
+                int kept = 0;
+                for (int t = 0; t < nout; ++t) {
+                    Out<T>& ot = outs[t];
+                    if (ot.n == 0) continue;
+                    int first = int(rows.size());
+                    int keep = ot.n;
+                    // overflow keeps the first points / manifolds in canonical order
+                    if (first + keep > cap) { keep = cap - first; E.status |= ST_CONTACT_OVERFLOW; }
+                    if (keep > 0 && int(mans.size()) >= mcap) { keep = 0; E.status |= ST_CONTACT_OVERFLOW; }
+                    if (keep <= 0) continue;
+                    kept += keep;
+                    add_manifold(ot, keep, first, isplane, a, bb, base, offB, pair_index, t, min_margin);
                 }
-                // Friction patch at the centroid; tangent t1 along the pre-step sliding velocity
-                // there, else the Duff et al. basis of the mean normal.
-                Manifold<T> M;
-                M.a = ia; M.b = ib; M.first = first; M.count = keep; M.colour = 0; M.pair = pair_index;
-                M.base = base; M.offB = offB;
-                V3<T> c = (T(1) / T(keep)) * csum;
-                M.nb = (T(1) / len(nsum)) * nsum;
-                M.rA = ia >= 0 ? c : mk<T>(0, 0, 0);
-                M.rB = c - offB;
-                V3<T> vrel = vel_at(&E.bodies[ib], M.rB) - (ia >= 0 ? vel_at(&E.bodies[ia], M.rA) : mk<T>(0, 0, 0));
-                V3<T> vt = vrel - dot(vrel, M.nb) * M.nb;
-                T vtl = len(vt);
-                if (std::fabs(double(vtl) - 1e-3) < min_margin) min_margin = std::fabs(double(vtl) - 1e-3);
-                M.t1 = vtl >= T(1e-3) ? (T(1) / vtl) * vt : onb_t1(M.nb);
-                M.t2 = cross(M.nb, M.t1);
-                M.mt1 = eff(ia, ib, M.rA, M.rB, M.t1);
-                M.mt2 = eff(ia, ib, M.rA, M.rB, M.t2);
-                T kw = (ia >= 0 ? dot(M.nb, mul(bv[ia].Iw, M.nb)) : T(0)) + dot(M.nb, mul(bv[ib].Iw, M.nb));
-                M.mtw = kw > T(0) ? T(1) / kw : T(0);
-                T rsum = 0;
-                for (int k = 0; k < keep; ++k) rsum = rsum + len(o.pt[k].p - c);
-                M.rt = rsum / T(keep);
-                M.mu = mu;
-                M.lt1 = M.lt2 = M.ltw = 0;
-                mans.push_back(M);
+                if (rec) rec->pairs.push_back(PairRec{env_id, a, isplane ? PLANE_ID : bb, kept, decision, kind, pmargin,
+                                                      0, 0, 0, 0, 0});
             }
         }
         if (P.warm_start) warm_from_cache();
@@ -1594,6 +1743,8 @@ struct Handle {
     std::vector<EnvRecord> recs;
     std::vector<Env<float>> ef0;   // initial state (resets)
     std::vector<Env<double>> ed0;
+    std::vector<Compound<float>> cf;  // the compound table in each precision
+    std::vector<Compound<double>> cd;
 };
 
 // Joint position (twist angle or slide) of joint j in env E's current state.
@@ -1667,8 +1818,17 @@ template <class T> static void load_env(Env<T>& E, const BodyDesc* bd, int nb, c
         Body<T>& b = E.bodies[i];
         b.shape = d.shape; b.flags = d.flags;
         for (int k = 0; k < 3; ++k) b.dims[k] = T(d.dims[k]);
-        T m = d.mass > 0 ? T(d.mass) : T(d.density) * shape_volume<T>(d.shape, b.dims);
-        V3<T> I = shape_inertia<T>(d.shape, b.dims, m);
+        T m;
+        V3<T> I;
+        if (d.shape == COMPOUND) {
+            b.comp = int(d.dims[0]);
+            const Compound<T>& C = (*E.comps)[b.comp];
+            m = d.mass > 0 ? T(d.mass) : T(d.density) * compound_volume(C);
+            I = compound_inertia(C, m);
+        } else {
+            m = d.mass > 0 ? T(d.mass) : T(d.density) * shape_volume<T>(d.shape, b.dims);
+            I = shape_inertia<T>(d.shape, b.dims, m);
+        }
         if (b.flags & STATIC) { b.invm = 0; b.invI = mk<T>(0, 0, 0); }
         else { b.invm = T(1) / m; b.invI = mk(T(1) / I.x, T(1) / I.y, T(1) / I.z); }
         b.mu = T(d.friction); b.e = T(d.restitution);
@@ -1760,6 +1920,21 @@ template <class T> static void set_state_t(Handle* H, std::vector<Env<T>>& envs,
     }
 }
 
+template <class T> static void load_compounds(std::vector<Compound<T>>& out, const CompoundDesc* cd, int n) {
+    out.resize(n);
+    for (int i = 0; i < n; ++i) {
+        Compound<T>& C = out[i];
+        C.n = cd[i].n_children;
+        for (int k = 0; k < C.n; ++k) {
+            C.shape[k] = cd[i].shape[k];
+            for (int r = 0; r < 3; ++r) C.dims[k][r] = T(cd[i].dims[k][r]);
+            const float* ps = cd[i].pose[k];
+            C.c[k] = mk(T(ps[0]), T(ps[1]), T(ps[2]));
+            C.q[k] = Q<T>{T(ps[3]), T(ps[4]), T(ps[5]), T(ps[6])};
+        }
+    }
+}
+
 }  // namespace orc
 
 using namespace orc;
@@ -1767,19 +1942,22 @@ using namespace orc;
 extern "C" {
 
 void* or_create(const Params* p, int n_envs, const int32_t* body_off, const BodyDesc* bodies,
-                const int32_t* joint_off, const JointDesc* joints, int precision) {
+                const int32_t* joint_off, const JointDesc* joints, int precision, int n_compounds,
+                const CompoundDesc* compounds) {
     Handle* H = new Handle();
     H->P = *p;
     H->prec = precision;
     H->n_envs = n_envs;
+    load_compounds(H->cf, compounds, n_compounds);
+    load_compounds(H->cd, compounds, n_compounds);
     H->body_off.assign(body_off, body_off + n_envs + 1);
     H->joint_off.assign(joint_off, joint_off + n_envs + 1);
     if (precision == 64) H->ed.resize(n_envs); else H->ef.resize(n_envs);
     H->recs.resize(n_envs);
     for (int e = 0; e < n_envs; ++e) {
         int b0 = body_off[e], nb = body_off[e + 1] - b0, j0 = joint_off[e], nj = joint_off[e + 1] - j0;
-        if (precision == 64) load_env(H->ed[e], bodies + b0, nb, joints + j0, nj);
-        else load_env(H->ef[e], bodies + b0, nb, joints + j0, nj);
+        if (precision == 64) { H->ed[e].comps = &H->cd; load_env(H->ed[e], bodies + b0, nb, joints + j0, nj); }
+        else { H->ef[e].comps = &H->cf; load_env(H->ef[e], bodies + b0, nb, joints + j0, nj); }
     }
     int nj = joint_off[n_envs];
     H->targets.resize(nj);
@@ -1942,6 +2120,15 @@ float or_atan2_pos32(float y, float x) { return atan2_pos<float>(y, x); }
 void or_mass_props(int shape, const double* dims, double mass, double* volume, double* inertia) {
     *volume = shape_volume<double>(shape, dims);
     V3<double> I = shape_inertia<double>(shape, dims, mass);
+    inertia[0] = I.x; inertia[1] = I.y; inertia[2] = I.z;
+}
+
+// Volume and principal moments of a compound (mass `mass`) in float64, as the step uses them.
+void or_compound_props(const CompoundDesc* cd, double mass, double* volume, double* inertia) {
+    std::vector<Compound<double>> c;
+    load_compounds(c, cd, 1);
+    *volume = compound_volume(c[0]);
+    V3<double> I = compound_inertia(c[0], mass);
     inertia[0] = I.x; inertia[1] = I.y; inertia[2] = I.z;
 }
 

@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "ms_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-BODY_BYTES, JOINT_BYTES, PARAMS_BYTES = 88, 92, 96
+BODY_BYTES, JOINT_BYTES, PARAMS_BYTES, COMPOUND_BYTES = 88, 92, 96, 180
 N_COUNTERS = 20
 COUNTER_NAMES = ["pairs_tested", "candidates", "points", "manifolds", "colours", "dynamic", "static",
                  "joints"] + [f"kind{k}" for k in range(12)]
@@ -42,7 +42,7 @@ def lib():
         L = C.CDLL(path)
         P = C.c_void_p
         L.or_create.restype = P
-        L.or_create.argtypes = [P, C.c_int, P, P, P, P, C.c_int]
+        L.or_create.argtypes = [P, C.c_int, P, P, P, P, C.c_int, C.c_int, P]
         L.or_destroy.argtypes = [P]
         L.or_set_targets.argtypes = [P, P]
         L.or_step.argtypes = [P, C.c_int, C.c_int, C.c_int]
@@ -55,6 +55,7 @@ def lib():
         L.or_n_counters.restype = C.c_int
         L.or_env_counters.argtypes = [P, P, P]
         L.or_mass_props.argtypes = [C.c_int, P, C.c_double, P, P]
+        L.or_compound_props.argtypes = [P, C.c_double, P, P]
         L.or_narrow.restype = C.c_int
         L.or_narrow.argtypes = [C.c_int, P, P, C.c_int, P, P, C.c_double, P, P]
         L.or_box_box_sat.argtypes = [P, P, P, P, P, P]
@@ -92,12 +93,16 @@ class Oracle:
         self._keep = [p, np.ascontiguousarray(scene.body_off, np.int32), np.ascontiguousarray(scene.bodies),
                       np.ascontiguousarray(scene.joint_off, np.int32), np.ascontiguousarray(scene.joints)]
         assert self._keep[2].dtype.itemsize == BODY_BYTES and self._keep[4].dtype.itemsize == JOINT_BYTES
+        comps = np.ascontiguousarray(getattr(scene, "compounds", np.zeros(0, np.uint8)))
+        assert len(comps) == 0 or comps.dtype.itemsize == COMPOUND_BYTES
+        self._keep.append(comps)
         self.n_envs = scene.n_envs
         self.n_bodies = scene.n_bodies
         self.n_joints = scene.n_joints
         self.precision = precision
         self._h = L.or_create(_ptr(p), self.n_envs, _ptr(self._keep[1]), _ptr(self._keep[2]),
-                              _ptr(self._keep[3]), _ptr(self._keep[4]), precision)
+                              _ptr(self._keep[3]), _ptr(self._keep[4]), precision, len(comps),
+                              _ptr(comps) if len(comps) else None)
 
     def close(self):
         if self._h:
@@ -198,6 +203,16 @@ def mass_props(shape: int, dims, mass: float):
     vol = C.c_double()
     inertia = np.zeros(3)
     lib().or_mass_props(shape, _ptr(d), mass, C.byref(vol), _ptr(inertia))
+    return vol.value, inertia
+
+
+def compound_mass_props(record, mass: float):
+    """Volume and principal moments (float64) of a compound record (the scenes' COMPOUND_DTYPE)."""
+    rec = np.ascontiguousarray(np.asarray(record).reshape(1))
+    assert rec.dtype.itemsize == COMPOUND_BYTES
+    vol = C.c_double()
+    inertia = np.zeros(3)
+    lib().or_compound_props(_ptr(rec), mass, C.byref(vol), _ptr(inertia))
     return vol.value, inertia
 
 

@@ -4,7 +4,7 @@ Every random number is drawn from a counter-based Philox4x32-10 stream (Salmon e
 "Parallel random numbers: as easy as 1, 2, 3") keyed by the base seed and addressed by
 (env id, purpose, draw block), so a scene never depends on batch size, packing or env order.
 The paper motivates this with explicit per-parallel-env seeding so that runs can be replayed
-with a different number of envs (Sec. III-C, demonstrations).
+with a different number of envs (Sec. III-G, demonstration datasets).
 
 Workloads (all synthetic; the paper's assets are YCB / PartNet-Mobility meshes, which stand in
 here as primitive shapes of the same scale):
@@ -13,6 +13,10 @@ here as primitive shapes of the same scale):
   * tray         -- a static tray and 20 random boxes / spheres / capsules dropped into it.
   * hetero       -- per-env body counts from a truncated geometric law on 1..64, with or
                     without the 7-link arm; optionally padded to 64 bodies with far static pads.
+  * cartpole     -- the paper's simulation-only benchmark workload (prismatic cart, revolute pole).
+  * compound_tray -- the tray with 12 bodies, half of them compound bodies (dumbbells, benches,
+                    jacks: rigid unions of up to 4 primitives, the stand-in for the paper's
+                    convex-decomposed meshes, App. A, Room Scale Environments).
 The descriptor records match ``ms_body_desc`` / ``ms_joint_desc`` / ``ms_sim_params``.
 """
 from __future__ import annotations
@@ -33,6 +37,11 @@ JOINT_DTYPE = np.dtype([
     ("kp", "<f4"), ("kd", "<f4"), ("target", "<f4"), ("type", "<i4"), ("limited", "<i4"),
     ("lower", "<f4"), ("upper", "<f4"),
 ])
+# A compound body's parts (ms_compound_desc): up to 4 primitives with poses in the body frame.
+COMPOUND_DTYPE = np.dtype([
+    ("n_children", "<i4"), ("shape", "<i4", 4), ("dims", "<f4", (4, 3)), ("pose", "<f4", (4, 7)),
+])
+assert COMPOUND_DTYPE.itemsize == 180
 PARAMS_DTYPE = np.dtype([
     ("dt", "<f4"), ("pos_iters", "<i4"), ("vel_iters", "<i4"), ("solver", "<i4"),
     ("gravity", "<f4", 3), ("plane_z", "<f4"), ("plane_enabled", "<i4"), ("plane_friction", "<f4"),
@@ -44,7 +53,7 @@ PARAMS_DTYPE = np.dtype([
 ])
 assert BODY_DTYPE.itemsize == 88 and JOINT_DTYPE.itemsize == 92 and PARAMS_DTYPE.itemsize == 96
 
-SPHERE, CAPSULE, BOX = 0, 1, 2
+SPHERE, CAPSULE, BOX, COMPOUND = 0, 1, 2, 3
 REVOLUTE, PRISMATIC = 0, 1
 STATIC = 1
 TGS, PGS = 0, 1
@@ -75,6 +84,7 @@ class Scene:
     joint_off: np.ndarray
     joints: np.ndarray
     meta: dict = field(default_factory=dict)
+    compounds: np.ndarray = field(default_factory=lambda: np.zeros(0, COMPOUND_DTYPE))
 
     @property
     def n_envs(self) -> int:
@@ -108,7 +118,7 @@ class Scene:
         return Scene(self.name, self.params.copy(),
                      np.concatenate([[0], np.cumsum(nb)]).astype(np.int32), self.bodies[bsel].copy(),
                      np.concatenate([[0], np.cumsum(nj)]).astype(np.int32), self.joints[jsel].copy(),
-                     dict(self.meta))
+                     dict(self.meta), self.compounds.copy())
 
 
 def concat_envs(name, params, env_bodies, env_joints, meta=None) -> Scene:
@@ -163,7 +173,7 @@ def uniforms(seed: int, env_ids, purpose: int, n: int, sub: int = 0) -> np.ndarr
 
 
 # purposes (stream ids)
-P_HEIGHT, P_QUAT, P_SIZE, P_SHAPE, P_MU, P_POS, P_LINK, P_CUBE, P_TARGET, P_COUNT, P_ARM, P_POLE, P_CART = range(13)
+P_HEIGHT, P_QUAT, P_SIZE, P_SHAPE, P_MU, P_POS, P_LINK, P_CUBE, P_TARGET, P_COUNT, P_ARM, P_POLE, P_CART, P_COMP = range(14)
 
 
 def shoemake_quat(u):
@@ -485,6 +495,104 @@ def _place_slot(seed, ids, bound, prev, centre_half, wall_half, lo_z, hi_z, avoi
     raise RuntimeError(f"placement failed for slot {k} in {int(todo.sum())} envs")
 
 
+# ----------------------------------------------------------------------------- compound bodies
+_QID = (1.0, 0.0, 0.0, 0.0)
+
+
+def compound_record(parts):
+    """A compound record from [(shape, dims, pos, quat)] (at most 4 parts, body-frame poses)."""
+    c = np.zeros((), dtype=COMPOUND_DTYPE)
+    c["n_children"] = len(parts)
+    for k, (sh, d, pos, q) in enumerate(parts):
+        c["shape"][k] = sh
+        c["dims"][k] = list(d) + [0.0] * (3 - len(d))
+        c["pose"][k] = list(pos) + list(q)
+    return c
+
+
+def dumbbell(r_end, half_bar, r_bar):
+    """Two spheres joined by a capsule bar along z (symmetric: centre of mass at the origin,
+    principal axes along x, y, z)."""
+    return compound_record([(CAPSULE, (r_bar, half_bar), (0.0, 0.0, 0.0), _QID),
+                            (SPHERE, (r_end,), (0.0, 0.0, half_bar), _QID),
+                            (SPHERE, (r_end,), (0.0, 0.0, -half_bar), _QID)])
+
+
+def bench(ha, hb, ht, leg, hl):
+    """A box top (half sizes ha, hb, ht) on two slab legs (half sizes leg, hb, hl) under its
+    ends, shifted so that the centre of mass is the origin (mirror symmetry in x and y makes x,
+    y, z principal)."""
+    zt, zl = hl + ht, 0.0          # top above the legs' centres
+    vt, vl = 8 * ha * hb * ht, 8 * leg * hb * hl
+    zc = (vt * zt + 2 * vl * zl) / (vt + 2 * vl)
+    return compound_record([(BOX, (ha, hb, ht), (0.0, 0.0, zt - zc), _QID),
+                            (BOX, (leg, hb, hl), (ha - leg, 0.0, zl - zc), _QID),
+                            (BOX, (leg, hb, hl), (-(ha - leg), 0.0, zl - zc), _QID)])
+
+
+def jack(h, t):
+    """Three crossed boxes along x, y and z (half length h, half thickness t)."""
+    return compound_record([(BOX, (h, t, t), (0.0, 0.0, 0.0), _QID), (BOX, (t, h, t), (0.0, 0.0, 0.0), _QID),
+                            (BOX, (t, t, h), (0.0, 0.0, 0.0), _QID)])
+
+
+def compound_bound(rec):
+    """Bounding-sphere radius of a compound about its origin."""
+    r = 0.0
+    for k in range(int(rec["n_children"])):
+        d, c = rec["dims"][k], rec["pose"][k][:3]
+        sh = int(rec["shape"][k])
+        pr = np.linalg.norm(d) if sh == BOX else (d[0] if sh == SPHERE else d[0] + d[1])
+        r = max(r, float(np.linalg.norm(c)) + float(pr))
+    return r
+
+
+def compound_library(seed: int, n: int = 32) -> np.ndarray:
+    """n compound templates: dumbbells, benches and jacks with extents of 0.04-0.1 m (the tray
+    objects' scale), drawn from the seed's own stream (purpose P_COMP)."""
+    u = uniforms(seed, np.arange(n), P_COMP, 5)
+    recs = []
+    for k in range(n):
+        kind = min(int(u[k, 0] * 3), 2)
+        if kind == 0:
+            recs.append(dumbbell(0.01 + 0.01 * u[k, 1], 0.015 + 0.02 * u[k, 2], 0.004 + 0.004 * u[k, 3]))
+        elif kind == 1:
+            ha, hb = 0.02 + 0.02 * u[k, 1], 0.02 + 0.02 * u[k, 2]
+            recs.append(bench(ha, hb, 0.004 + 0.003 * u[k, 3], 0.004, 0.01 + 0.01 * u[k, 4]))
+        else:
+            recs.append(jack(0.02 + 0.02 * u[k, 1], 0.004 + 0.004 * u[k, 2]))
+    return np.array(recs, dtype=COMPOUND_DTYPE)
+
+
+def compound_tray(n_envs: int = 4096, seed: int = 0, n_objects: int = 12, first_env: int = 0) -> Scene:
+    """The tray holding 12 objects dropped from random poses: each a compound body (a template
+    of `compound_library`, U{0..31}) with probability 1/2, else a primitive with the tray laws;
+    density 1000 kg/m^3, mu U[0.3, 1.0]; dt = 0.005 s, 8 iterations.  Bodies 0..11 are the
+    objects, 12..15 the walls."""
+    ids = np.arange(first_env, first_env + n_envs)
+    lib = compound_library(seed)
+    shape, dims, bound, mu = _random_shapes(seed, ids, n_objects)
+    uc = uniforms(seed, ids, P_COMP, 2 * n_objects, sub=1).reshape(n_envs, n_objects, 2)
+    is_c = uc[..., 0] < 0.5
+    tmpl = np.minimum((uc[..., 1] * len(lib)).astype(np.int32), len(lib) - 1)
+    lib_bound = np.array([compound_bound(r) for r in lib])
+    shape = np.where(is_c, COMPOUND, shape)
+    dims = np.where(is_c[..., None], np.stack([tmpl, np.zeros_like(tmpl), np.zeros_like(tmpl)], -1), dims)
+    bound = np.where(is_c, lib_bound[tmpl], bound)
+    pos = _place_subset(seed, ids, bound, np.full(n_envs, n_objects), 0.15, TRAY_INNER / 2, 0.05, 0.6,
+                        np.zeros(n_envs))
+    q = shoemake_quat(uniforms(seed, ids, P_QUAT, 3 * n_objects).reshape(n_envs, n_objects, 3))
+    objs = _prims_to_bodies(shape, dims, pos, q, mu)
+    bodies = np.concatenate([objs, np.broadcast_to(tray_walls(), (n_envs, 4))], axis=1).reshape(-1)
+    nb = n_objects + 4
+    # a pair of compounds yields up to 9 manifolds (one per pair of parts): capacities above the
+    # defaults for 12 dynamic bodies (80 points, 40 manifolds)
+    params = make_params(dt=0.005, pos_iters=8, max_contacts_per_env=192, max_manifolds_per_env=64)
+    return Scene("compound_tray", params, np.arange(n_envs + 1, dtype=np.int32) * nb,
+                 bodies, np.zeros(n_envs + 1, dtype=np.int32), np.zeros(0, JOINT_DTYPE),
+                 dict(seed=seed, steps=500, n_objects=n_objects), lib)
+
+
 # ----------------------------------------------------------------------------- named workloads
 def by_name(name: str, n_envs: int, seed: int = 0, first_env: int = 0) -> Scene:
     if name == "drop_boxes":
@@ -499,6 +607,8 @@ def by_name(name: str, n_envs: int, seed: int = 0, first_env: int = 0) -> Scene:
         return hetero(n_envs, seed, pad_to=64, first_env=first_env)
     if name == "cartpole":
         return cartpole(n_envs, seed, first_env=first_env)
+    if name == "compound_tray":
+        return compound_tray(n_envs, seed, first_env=first_env)
     raise ValueError(name)
 
 
@@ -513,7 +623,9 @@ def single(bodies, joints=None, **params) -> Scene:
 def replicate(scene: Scene, n: int) -> Scene:
     """n copies of a one-env scene."""
     assert scene.n_envs == 1
-    return concat_envs(scene.name, scene.params.copy(), [scene.bodies] * n, [scene.joints] * n, dict(scene.meta))
+    out = concat_envs(scene.name, scene.params.copy(), [scene.bodies] * n, [scene.joints] * n, dict(scene.meta))
+    out.compounds = scene.compounds.copy()
+    return out
 
 
 body = _body

@@ -1,0 +1,258 @@
+"""Oracle pins for compound bodies (a body made of up to 4 primitive parts with poses in the body
+frame; the paper's objects are convex-decomposed meshes, Sec. III-B and App. B): mass
+properties, the broadphase box, the narrowphase of every pair of parts with its own manifold,
+resting poses and the per-part contact cache key.
+
+Pins: a one-part compound at the identity pose steps bit for bit like the primitive itself (so
+the compound path adds no arithmetic to a single part); the mass properties agree with a Monte
+Carlo integral over every part, including a part under a general rotation (a transposed rotation
+or a dropped parallel-axis term fails); the contact points of two compounds equal, point for
+point, those of every pair of parts placed as free primitives at world poses composed here with
+scipy (a wrong composition order or offset fails); a dumbbell comes to rest on its two end
+spheres with one manifold per sphere, and a bench on its two legs at the height its geometry
+fixes; the contact cache keys manifolds by part pair (two parts of one body touching the ground
+each keep their own impulses)."""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from oracle.oracle import Oracle, compound_mass_props, mass_props, narrow, reduce4
+from paper_2410_00425_amd import scenes as S
+
+G = 9.81
+FIELDS = ("pos", "quat", "linvel", "angvel")
+
+
+def with_compounds(sc, recs):
+    sc.compounds = np.array(recs, dtype=S.COMPOUND_DTYPE)
+    return sc
+
+
+def one_part(shape, dims):
+    return S.compound_record([(shape, dims, (0.0, 0.0, 0.0), (1.0, 0.0, 0.0, 0.0))])
+
+
+@pytest.mark.parametrize("shape,dims", [(S.SPHERE, (0.04,)), (S.CAPSULE, (0.03, 0.05)), (S.BOX, (0.05, 0.03, 0.02))])
+def test_one_part_compound_is_the_primitive(shape, dims):
+    q = Rotation.from_rotvec([0.3, -0.5, 0.2]).as_quat()
+    quat = (q[3], q[0], q[1], q[2])
+    other = S.body(S.BOX, (0.04, 0.04, 0.04), (0.03, 0.02, 0.25), mass=0.5, mu=0.6, angvel=(1.0, 0.0, 2.0))
+
+    def scene(compound):
+        sh = S.COMPOUND if compound else shape
+        d = (0.0,) if compound else dims
+        b = S.body(sh, d, (0.0, 0.0, 0.12), quat=quat, density=800.0, mu=0.7, angvel=(0.5, 2.0, 0.0))
+        sc = S.single([b, other], dt=0.005, pos_iters=8)
+        return with_compounds(sc, [one_part(shape, dims)]) if compound else sc
+
+    a, b = Oracle(scene(False), 32), Oracle(scene(True), 32)
+    for _ in range(6):
+        a.step(25)
+        b.step(25)
+        sa, sb = a.state(), b.state()
+        for k in FIELDS:
+            assert np.array_equal(sa[k], sb[k]), k
+    # the compound pairs are recorded as such
+    b.step(1, record=True)
+    r = b.record()
+    mine = r["pairs"][:, 1] == 0          # pairs of the compound (body 0): its partner and the plane
+    assert mine.sum() >= 1 and np.all(r["pairs"][mine, 5] == 12) and np.all(r["pairs"][mine, 4] >= 63)
+    assert np.all(r["pairs"][~mine, 5] < 12)
+
+
+def mc_inertia(rec, mass, n=400_000, seed=1):
+    """Principal moments about the body origin by Monte Carlo: each part sampled uniformly in its
+    own volume (rejection from its box), rotated and moved to its pose, weighted by its share of
+    the mass (parts weighted by volume, overlaps counted twice)."""
+    rng = np.random.default_rng(seed)
+    vols, parts = [], []
+    for k in range(int(rec["n_children"])):
+        sh, d = int(rec["shape"][k]), rec["dims"][k].astype(np.float64)
+        vols.append(mass_props(sh, d, 1.0)[0])
+        if sh == S.SPHERE:
+            half = np.array([d[0]] * 3)
+        elif sh == S.CAPSULE:
+            half = np.array([d[0], d[0], d[1] + d[0]])
+        else:
+            half = d.copy()
+        x = rng.uniform(-1, 1, (n, 3)) * half
+        if sh == S.SPHERE:
+            x = x[np.sum(x * x, 1) <= d[0] ** 2]
+        elif sh == S.CAPSULE:
+            z = np.clip(x[:, 2], -d[1], d[1])
+            x = x[x[:, 0] ** 2 + x[:, 1] ** 2 + (x[:, 2] - z) ** 2 <= d[0] ** 2]
+        pose = rec["pose"][k].astype(np.float64)
+        rot = Rotation.from_quat([pose[4], pose[5], pose[6], pose[3]])
+        parts.append(rot.apply(x) + pose[:3])
+    vt = sum(vols)
+    I = np.zeros((3, 3))
+    for v, x in zip(vols, parts):
+        m = mass * v / vt
+        r2 = np.sum(x * x, 1)
+        I += m * (np.diag([r2.mean()] * 3) - (x[:, :, None] * x[:, None, :]).mean(0))
+    return vt, I
+
+
+def tilted_pair():
+    """Two boxes under a general rotation, mirrored through the origin (centre of mass at the
+    origin; the products of inertia need not vanish: only the moments are compared)."""
+    q = Rotation.from_rotvec(0.9 * np.array([1.0, 2.0, 3.0]) / np.sqrt(14.0)).as_quat()
+    qw = (q[3], q[0], q[1], q[2])
+    return S.compound_record([(S.BOX, (0.05, 0.02, 0.01), (0.03, -0.01, 0.02), qw),
+                              (S.BOX, (0.05, 0.02, 0.01), (-0.03, 0.01, -0.02), qw)])
+
+
+@pytest.mark.parametrize("rec", [S.dumbbell(0.02, 0.03, 0.006), S.bench(0.04, 0.03, 0.005, 0.004, 0.015),
+                                 S.jack(0.035, 0.006), tilted_pair()], ids=["dumbbell", "bench", "jack", "tilted"])
+def test_compound_mass_properties(rec):
+    mass = 0.7
+    vol, I = compound_mass_props(rec, mass)
+    vt, Imc = mc_inertia(rec, mass)
+    assert abs(vol - vt) <= 1e-12 * vt
+    np.testing.assert_allclose(I, np.diag(Imc), rtol=1.5e-2)
+
+
+def test_library_templates_are_principal_and_centred():
+    for rec in S.compound_library(0):
+        _, Imc = mc_inertia(rec, 1.0, n=100_000)
+        off = np.abs(Imc - np.diag(np.diag(Imc))).max()
+        assert off < 2e-2 * np.diag(Imc).max()
+        # the volume-weighted centre of the parts is the origin
+        c = sum(mass_props(int(rec["shape"][k]), rec["dims"][k].astype(np.float64), 1.0)[0] * rec["pose"][k][:3]
+                for k in range(int(rec["n_children"])))
+        assert np.abs(c).max() < 1e-9
+
+
+def world_parts(rec, pos, quat):
+    """(shape, dims, pose) of every part in the world, composed with scipy."""
+    rot = Rotation.from_quat([quat[1], quat[2], quat[3], quat[0]])
+    out = []
+    for k in range(int(rec["n_children"])):
+        p = rec["pose"][k].astype(np.float64)
+        rk = rot * Rotation.from_quat([p[4], p[5], p[6], p[3]])
+        qk = rk.as_quat()
+        c = np.asarray(pos, np.float64) + rot.apply(p[:3])
+        out.append((int(rec["shape"][k]), rec["dims"][k].astype(np.float64),
+                    np.array([c[0], c[1], c[2], qk[3], qk[0], qk[1], qk[2]])))
+    return out
+
+
+def sorted_rows(a):
+    a = np.round(np.asarray(a, np.float64), 5)
+    return a[np.lexsort(a.T[::-1])] if len(a) else a.reshape(0, 6)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_compound_contacts_are_those_of_the_part_pairs(seed):
+    rng = np.random.default_rng(seed)
+    lib = S.compound_library(seed)
+    ra, rb = lib[rng.integers(len(lib))], lib[rng.integers(len(lib))]
+    if seed % 2 == 0:
+        ra = tilted_pair()     # parts under a general rotation (the library's are axis-aligned)
+    qa = Rotation.random(random_state=seed).as_quat()
+    qb = Rotation.random(random_state=seed + 100).as_quat()
+    # poses as the body records hold them (float32)
+    f32 = lambda x: np.asarray(x, np.float32).astype(np.float64)
+    qa, qb = f32((qa[3], qa[0], qa[1], qa[2])), f32((qb[3], qb[0], qb[1], qb[2]))
+    pa = np.array([0.0, 0.0, 0.5])
+    # B approaches A along a random direction until some part pair is within the contact offset
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    delta = 0.01
+    found = None
+    for dist in np.linspace(0.2, 0.0, 401):
+        pb = f32(pa + dist * u)
+        pts = []
+        for sa, da, posa in world_parts(ra, pa, qa):
+            for sb, db, posb in world_parts(rb, pb, qb):
+                o, _ = narrow(sa, da, posa, sb, db, posb, delta)
+                if len(o):
+                    if len(o) > 4:
+                        idx, _ = reduce4(o[:, :3], o[:, 6])
+                        o = o[sorted(idx)]
+                    pts.append(o[:, :6])
+        if pts:
+            found = (pb, pts)
+            break
+    assert found is not None
+    pb, pts = found
+    a = S.body(S.COMPOUND, (0.0,), tuple(pa), quat=tuple(qa), mass=1.0)
+    b = S.body(S.COMPOUND, (1.0,), tuple(pb), quat=tuple(qb), mass=1.0)
+    sc = with_compounds(S.single([a, b], dt=0.001, gravity=(0.0, 0.0, 0.0), plane_enabled=0), [ra, rb])
+    o = Oracle(sc, 64)
+    o.step(1, record=True)
+    r = o.record()
+    body_pairs = r["pairs"][r["pairs"][:, 2] == 1]
+    assert len(body_pairs) == 1 and body_pairs[0, 5] == 12
+    got = r["points"][r["point_ids"][:, 1] == 0, :6]
+    want = np.concatenate(pts)
+    assert body_pairs[0, 3] == len(want)
+    # the records' float32 quaternions are unit only to ~1e-7 (scipy normalises them, the step
+    # does not): a composition mistake moves points by centimetres
+    np.testing.assert_allclose(sorted_rows(got), sorted_rows(want), atol=1e-6)
+    # one manifold (solver block of kind 1) per part pair with points
+    assert np.sum(r["blocks"][:, 1] == 1) == len(pts)
+
+
+def dumbbell_scene(warm=0):
+    rec = S.dumbbell(0.02, 0.04, 0.006)
+    q = Rotation.from_rotvec([np.pi / 2 - 0.1, 0.0, 0.0]).as_quat()
+    b = S.body(S.COMPOUND, (0.0,), (0.0, 0.0, 0.08), quat=(q[3], q[0], q[1], q[2]), density=1000.0, mu=0.8)
+    return with_compounds(S.single([b], dt=0.005, pos_iters=8, warm_start=warm), [rec])
+
+
+def test_dumbbell_rests_on_its_end_spheres():
+    o = Oracle(dumbbell_scene(), 64)
+    o.step(400)
+    st = o.state()
+    assert abs(st["pos"][2, 0] - 0.02) < 1e-3
+    assert np.linalg.norm(st["linvel"][:, 0]) < 1e-3
+    q = st["quat"][:, 0]
+    axis = Rotation.from_quat([q[1], q[2], q[3], q[0]]).apply([0.0, 0.0, 1.0])
+    assert abs(axis[2]) < 1e-3     # lying: the bar is horizontal
+    o.step(1, record=True)
+    r = o.record()
+    assert len(r["pairs"]) == 1 and r["pairs"][0, 3] == 2
+    assert r["pairs"][0, 4] == 64 + 1     # first part pair with points: the first end sphere
+    assert np.sum(r["blocks"][:, 1] == 1) == 2
+    # the two normal impulses carry the weight over a substep
+    vol, _ = compound_mass_props(S.dumbbell(0.02, 0.04, 0.006), 1.0)
+    h = 0.005 / 8
+    w = 1000.0 * vol * G * h
+    assert abs(r["points"][:, 7].sum() - w) < 1e-2 * w and np.all(r["points"][:, 7] > 0.4 * w)
+
+
+def test_bench_rests_on_its_legs():
+    ha, hb, ht, leg, hl = 0.04, 0.03, 0.005, 0.004, 0.015
+    rec = S.bench(ha, hb, ht, leg, hl)
+    b = S.body(S.COMPOUND, (0.0,), (0.0, 0.0, 0.1), density=1000.0, mu=0.8)
+    o = Oracle(with_compounds(S.single([b], dt=0.005, pos_iters=8), [rec]), 64)
+    o.step(300)
+    st = o.state()
+    # the legs' lower faces at z = 0: the origin sits hl above the legs' centres
+    z_leg = float(rec["pose"][1][2])
+    assert abs(st["pos"][2, 0] - (hl - z_leg)) < 1e-3
+    o.step(1, record=True)
+    r = o.record()
+    assert r["pairs"][0, 3] == 8 and np.sum(r["blocks"][:, 1] == 1) == 2
+
+
+def test_cache_is_per_part_pair():
+    o = Oracle(dumbbell_scene(warm=1), 32)
+    o.step(300)
+    o.step(1, record=True)
+    r1 = o.record()
+    o.step(1, record=True)
+    r2 = o.record()
+    assert len(r1["points"]) == 2 and np.all(r1["points"][:, 7] > 0)
+    np.testing.assert_array_equal(r2["points"][:, 8], r1["points"][:, 7])
+
+
+def test_compound_tray_runs_within_capacity():
+    sc = S.compound_tray(16, seed=3)
+    o = Oracle(sc, 32)
+    o.step(200, n_threads=4)
+    st = o.state()
+    assert np.all(st["status"] == 0)
+    dyn = (sc.bodies["flags"] & 1) == 0
+    assert st["pos"][2, dyn].min() > 0.0
