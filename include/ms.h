@@ -42,7 +42,7 @@ typedef enum {
     MS_E_STATE = 6         /* call not valid in the object's current state */
 } ms_status;
 
-enum { MS_SPHERE = 0, MS_CAPSULE = 1, MS_BOX = 2 };
+enum { MS_SPHERE = 0, MS_CAPSULE = 1, MS_BOX = 2, MS_COMPOUND = 3 };
 enum { MS_BODY_STATIC = 1 };            /* zero inverse mass and inertia; never integrated */
 enum { MS_SOLVER_TGS = 0, MS_SOLVER_PGS = 1 };
 enum { MS_JOINT_REVOLUTE = 0, MS_JOINT_PRISMATIC = 1 };
@@ -60,11 +60,14 @@ enum {
 #define MS_MAX_BODIES_PER_ENV 64
 #define MS_MAX_JOINTS_PER_ENV 64
 #define MS_MAX_BLOCKS_PER_ENV 256   /* joints + manifold capacity of one env */
+#define MS_MAX_PARTS 4              /* primitive parts of one compound body */
 
 /* One rigid body.  Shape dims: sphere (r, -, -); capsule (r, half_len, -) with its axis along
  * body-local z and half_len = half the cylinder length; box (hx, hy, hz) half-extents.
  * mass > 0 gives the mass; otherwise mass = density * volume.  The centre of mass is the shape
- * centre and the principal axes are the shape axes.  88 bytes, no padding. */
+ * centre and the principal axes are the shape axes.  Compound (MS_COMPOUND): dims[0] holds the
+ * index of the body's entry in the scene's compound table (an integer value); its mass and
+ * inertia follow from its parts (see ms_compound_desc).  88 bytes, no padding. */
 typedef struct {
     int32_t shape;
     int32_t flags;
@@ -101,14 +104,35 @@ typedef struct {
     float upper;
 } ms_joint_desc;
 
+/* A compound body's shape: 1..MS_MAX_PARTS primitive parts (sphere, capsule or box with the
+ * body dims' meaning) at poses (px, py, pz, qw, qx, qy, qz) in the body frame: the convex pieces
+ * of a decomposed object (the paper's objects are convex-decomposed meshes, Sec. III-B and App.
+ * B, Environment Setup).  Contacts: every pair of parts of the two bodies (each part against the
+ * ground) runs the primitive narrowphase and keeps <= 4 points as its own manifold with its own
+ * friction patch, in part order (A's parts outer).  Mass: uniform density over the parts, shared
+ * by volume (overlaps count twice); inertia: each part's about its centre, rotated into the body
+ * frame and moved to the origin (parallel axes), summed.  The body frame must be the principal
+ * frame with the centre of mass at the origin: create rejects a compound whose centre of mass is
+ * off the origin by more than 1e-4 of its extent or whose products of inertia exceed 1e-3 of its
+ * largest moment.  Part quaternions must be unit to 1e-5.  180 bytes, no padding. */
+typedef struct {
+    int32_t n_children;
+    int32_t shape[MS_MAX_PARTS];
+    float dims[MS_MAX_PARTS][3];
+    float pose[MS_MAX_PARTS][7];
+} ms_compound_desc;
+
 /* A batch of envs in compressed form: env e owns bodies [env_body_off[e], env_body_off[e+1]) and
- * joints [env_joint_off[e], env_joint_off[e+1]).  Host memory, copied during create. */
+ * joints [env_joint_off[e], env_joint_off[e+1]); compound bodies index the compound table, shared
+ * by every env.  Host memory, copied during create. */
 typedef struct {
     int32_t n_envs;
     const int32_t* env_body_off;   /* [n_envs + 1] */
     const ms_body_desc* bodies;    /* [env_body_off[n_envs]] */
     const int32_t* env_joint_off;  /* [n_envs + 1] */
     const ms_joint_desc* joints;   /* [env_joint_off[n_envs]] */
+    int32_t n_compounds;                  /* entries of the compound table (0: none) */
+    const ms_compound_desc* compounds;    /* [n_compounds] (may be null when n_compounds is 0) */
 } ms_scene_desc;
 
 /* Step parameters.  One step advances dt; TGS runs pos_iters substeps of one iteration each,

@@ -68,8 +68,15 @@ struct BatchDev {
     int pad6;
     // per-phase wave-cycles, [16], summed over the launches (only in the per-phase clock build)
     unsigned long long* phase_clock;
+    // compound table (null when the batch has none): COMP_WORDS floats per compound, {parts (int
+    // bits), 0, 0, 0} then per part {shape (int bits), dims (3)}, {position (3), qw},
+    // {qx, qy, qz, 0}; a compound body's dim0 holds its table index
+    const float* comp;
+    int n_comp, pad7;
 };
 constexpr int CM_WORDS = 6, CP_WORDS = 4;
+constexpr int MAX_PARTS = 4, COMP_WORDS = 4 + 12 * MAX_PARTS;
+constexpr int SHAPE_COMPOUND = 3;
 
 // Work counters per env: steps, candidate pairs per shape kind (3 * min + max shape for body
 // pairs, 9 + shape for plane pairs), contact points, manifolds, colours.

@@ -89,18 +89,20 @@ struct LdsClass {
 };
 
 typedef void (*StepKernel)(const BatchDev*, const Tile*, int, const TileEnv*, int);
-// Kernel of a variant; opt selects the twin that carries the optional phases (contact forces,
-// contact cache).
-inline StepKernel kernel_of(int variant, bool opt) {
-    switch (variant) {
-        case 1: return opt ? ms_step_kernel_w2_opt : ms_step_kernel_w2;
-        case 2: return opt ? ms_step_kernel_one_opt : ms_step_kernel_one;
-        case 3: return opt ? ms_step_kernel_one_w2_opt : ms_step_kernel_one_w2;
-        default: return opt ? ms_step_kernel_opt : ms_step_kernel;
-    }
+// Kernel of a variant for a feature level: 0 the plain build, 1 the twin that carries the
+// optional phases (contact forces, contact cache), 3 the one that also handles compound bodies.
+inline StepKernel kernel_of(int variant, int feat) {
+    static const StepKernel k[3][4] = {
+        {ms_step_kernel, ms_step_kernel_w2, ms_step_kernel_one, ms_step_kernel_one_w2},
+        {ms_step_kernel_opt, ms_step_kernel_w2_opt, ms_step_kernel_one_opt, ms_step_kernel_one_w2_opt},
+        {ms_step_kernel_comp, ms_step_kernel_w2_comp, ms_step_kernel_one_comp, ms_step_kernel_one_w2_comp}};
+    const int f = feat >= 2 ? 2 : (feat > 0 ? 1 : 0);
+    return k[f][variant >= 0 && variant < 4 ? variant : 0];
 }
 typedef void (*BinsKernel)(const BatchDev*, const Tile*, const Bin*, int, const TileEnv*, int);
-inline BinsKernel bins_kernel(bool opt) { return opt ? ms_step_kernel_bins_opt : ms_step_kernel_bins; }
+inline BinsKernel bins_kernel(int feat) {
+    return feat >= 2 ? ms_step_kernel_bins_comp : (feat > 0 ? ms_step_kernel_bins_opt : ms_step_kernel_bins);
+}
 inline bool one_env_tile(const Tile& t) { return t.lanes == WAVE && t.count == 1; }
 
 // Cut tiles sorted by LDS need (largest first) into launch classes — a new class when a tile
@@ -149,7 +151,7 @@ void cut_classes(int n, TileRef tile_ref, bool split_ok, ClassVec& cls) {
 
 // Launch one class on stream s: the one-env part, then the general part.
 ms_status launch_class(const LdsClass& c, const BatchDev* dbd, const Tile* tiles, const TileEnv* tenv, int n_steps,
-                       int grid_cap, hipStream_t s, bool opt) {
+                       int grid_cap, hipStream_t s, int opt) {
     const size_t lds = size_t(c.lds_words) * 4;
     const int parts[2][3] = {{c.first_tile, c.n_one, c.variant},
                              {c.first_tile + c.n_one, c.n_tiles - c.n_one, c.variant_gen}};
@@ -182,9 +184,124 @@ struct Plan {
 // Workspace sections (byte offsets from the workspace base).
 struct WsLayout {
     size_t pos, quat, vel, angvel, ipos, iquat, ivel, iang, save, status, bpar, body_off, joint_off, jrec, targets, tiles,
-        bins, tenv, bd, stats, forces, bad_ids, phase_clock, cache_hdr, cache_man, cache_man_off, cache_pt, cache_pt_off, cache_save,
+        bins, tenv, bd, stats, forces, bad_ids, phase_clock, comp, cache_hdr, cache_man, cache_man_off, cache_pt, cache_pt_off, cache_save,
         cache_bytes, dbg_pairs, dbg_pair_off, dbg_pts, dbg_pt_off, dbg_man, dbg_man_off, dbg_counts, total;
 };
+
+// Volume and principal moments of a primitive about its centre, float32, in the step model's
+// order of operations (uniform density).
+float prim_volume(int shape, const float* d) {
+    const float fpi = 3.14159265358979323846f;
+    if (shape == MS_SPHERE) return 4.0f / 3.0f * fpi * d[0] * d[0] * d[0];
+    if (shape == MS_CAPSULE) { float L = 2.0f * d[1]; return fpi * d[0] * d[0] * L + 4.0f / 3.0f * fpi * d[0] * d[0] * d[0]; }
+    return 8.0f * d[0] * d[1] * d[2];
+}
+void prim_inertia(int shape, const float* d, float m, float I[3]) {
+    const float f0 = d[0], f1 = d[1], f2 = d[2];
+    if (shape == MS_SPHERE) { float i = 2.0f / 5.0f * m * f0 * f0; I[0] = I[1] = I[2] = i; }
+    else if (shape == MS_BOX) {
+        float a = 2.0f * f0, bb = 2.0f * f1, c = 2.0f * f2;
+        I[0] = m / 12.0f * (bb * bb + c * c); I[1] = m / 12.0f * (a * a + c * c); I[2] = m / 12.0f * (a * a + bb * bb);
+    } else {
+        const float fpi = 3.14159265358979323846f;
+        float r = f0, L = 2.0f * f1;
+        float vc = fpi * r * r * L, vs = 4.0f / 3.0f * fpi * r * r * r;
+        float rho = m / (vc + vs);
+        float mc = rho * vc, ms = rho * vs;
+        float izz = mc * r * r / 2.0f + ms * 2.0f * r * r / 5.0f;
+        float ixx = mc * (L * L / 12.0f + r * r / 4.0f) + ms * (2.0f * r * r / 5.0f + L * L / 4.0f + 3.0f * L * r / 8.0f);
+        I[0] = ixx; I[1] = ixx; I[2] = izz;
+    }
+}
+// Rotation matrix (row-major) of a quaternion (w, x, y, z), float32.
+template <class F> void quat_matrix(const F* q, F R[3][3]) {
+    const F w = q[0], x = q[1], y = q[2], z = q[3];
+    F xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+    R[0][0] = F(1) - F(2) * (yy + zz); R[0][1] = F(2) * (xy - wz);        R[0][2] = F(2) * (xz + wy);
+    R[1][0] = F(2) * (xy + wz);        R[1][1] = F(1) - F(2) * (xx + zz); R[1][2] = F(2) * (yz - wx);
+    R[2][0] = F(2) * (xz - wy);        R[2][1] = F(2) * (yz + wx);        R[2][2] = F(1) - F(2) * (xx + yy);
+}
+// Compound volume and principal moments (float32): the parts share the mass by volume; each
+// part's moments are rotated into the body frame and moved to the origin (parallel axes), summed
+// in part order; the diagonal is the body's principal moments.
+float compound_volume(const ms_compound_desc& c) {
+    float v = 0.0f;
+    for (int k = 0; k < c.n_children; ++k) v = v + prim_volume(c.shape[k], c.dims[k]);
+    return v;
+}
+void compound_inertia(const ms_compound_desc& c, float m, float I[3]) {
+    const float vt = compound_volume(c);
+    I[0] = I[1] = I[2] = 0.0f;
+    for (int k = 0; k < c.n_children; ++k) {
+        const float mk = m * (prim_volume(c.shape[k], c.dims[k]) / vt);
+        float Ik[3];
+        prim_inertia(c.shape[k], c.dims[k], mk, Ik);
+        float R[3][3];
+        quat_matrix(c.pose[k] + 3, R);
+        const float* cc = c.pose[k];
+        const float c2 = cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2];
+        for (int i = 0; i < 3; ++i) {
+            const float rot = R[i][0] * Ik[0] * R[i][0] + R[i][1] * Ik[1] * R[i][1] + R[i][2] * Ik[2] * R[i][2];
+            const float par = mk * (c2 - cc[i] * cc[i]);
+            I[i] = I[i] + (rot + par);
+        }
+    }
+}
+
+// A compound table entry: 1..4 parts of primitive shape with positive dims, finite poses and
+// unit quaternions, built in its principal frame with the centre of mass at the origin (checked
+// in float64: centre within 1e-4 of the extent, products of inertia within 1e-3 of the largest
+// moment).
+ms_status validate_compound(const ms_compound_desc& c, int k) {
+    if (c.n_children < 1 || c.n_children > MS_MAX_PARTS)
+        return fail(MS_E_INVALID_ARG, "compound %d: %d parts (1..%d supported)", k, c.n_children, MS_MAX_PARTS);
+    double vt = 0.0, com[3] = {0, 0, 0}, ext = 0.0;
+    for (int j = 0; j < c.n_children; ++j) {
+        const int sh = c.shape[j];
+        if (sh < MS_SPHERE || sh > MS_BOX) return fail(MS_E_INVALID_ARG, "compound %d part %d: bad shape %d", k, j, sh);
+        const int nd = sh == MS_SPHERE ? 1 : (sh == MS_CAPSULE ? 2 : 3);
+        for (int r = 0; r < nd; ++r)
+            if (!(c.dims[j][r] > 0.0f) || !std::isfinite(c.dims[j][r]))
+                return fail(MS_E_INVALID_ARG, "compound %d part %d: dims must be positive", k, j);
+        for (int r = 0; r < 7; ++r)
+            if (!std::isfinite(c.pose[j][r])) return fail(MS_E_INVALID_ARG, "compound %d part %d: non-finite pose", k, j);
+        const float* q = c.pose[j] + 3;
+        const double qn = double(q[0]) * q[0] + double(q[1]) * q[1] + double(q[2]) * q[2] + double(q[3]) * q[3];
+        if (std::fabs(qn - 1.0) > 2e-5) return fail(MS_E_INVALID_ARG, "compound %d part %d: quaternion not unit", k, j);
+        const double v = prim_volume(sh, c.dims[j]);
+        vt += v;
+        double bound = sh == MS_SPHERE ? c.dims[j][0]
+                     : sh == MS_CAPSULE ? double(c.dims[j][0]) + c.dims[j][1]
+                                        : std::sqrt(double(c.dims[j][0]) * c.dims[j][0] + double(c.dims[j][1]) * c.dims[j][1] +
+                                                    double(c.dims[j][2]) * c.dims[j][2]);
+        double cn = 0.0;
+        for (int r = 0; r < 3; ++r) { com[r] += v * c.pose[j][r]; cn += double(c.pose[j][r]) * c.pose[j][r]; }
+        ext = std::max(ext, std::sqrt(cn) + bound);
+    }
+    for (int r = 0; r < 3; ++r)
+        if (std::fabs(com[r] / vt) > 1e-4 * ext)
+            return fail(MS_E_INVALID_ARG, "compound %d: centre of mass not at the body origin", k);
+    // full inertia tensor (unit mass) in float64
+    double T[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int j = 0; j < c.n_children; ++j) {
+        const double mj = prim_volume(c.shape[j], c.dims[j]) / vt;
+        float Ik[3];
+        prim_inertia(c.shape[j], c.dims[j], float(mj), Ik);
+        double q[4] = {c.pose[j][3], c.pose[j][4], c.pose[j][5], c.pose[j][6]};
+        double R[3][3];
+        quat_matrix(q, R);
+        const double cc[3] = {c.pose[j][0], c.pose[j][1], c.pose[j][2]};
+        const double c2 = cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2];
+        for (int a = 0; a < 3; ++a)
+            for (int b2 = 0; b2 < 3; ++b2)
+                T[a][b2] += R[a][0] * Ik[0] * R[b2][0] + R[a][1] * Ik[1] * R[b2][1] + R[a][2] * Ik[2] * R[b2][2] +
+                            mj * ((a == b2 ? c2 : 0.0) - cc[a] * cc[b2]);
+    }
+    const double dmax = std::max(T[0][0], std::max(T[1][1], T[2][2]));
+    if (std::fabs(T[0][1]) > 1e-3 * dmax || std::fabs(T[0][2]) > 1e-3 * dmax || std::fabs(T[1][2]) > 1e-3 * dmax)
+        return fail(MS_E_INVALID_ARG, "compound %d: the body axes are not its principal axes", k);
+    return MS_OK;
+}
 
 ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     if (!p || !s) return fail(MS_E_INVALID_ARG, "null params or scene");
@@ -198,6 +315,10 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
     if (p->warm_start && !(std::isfinite(p->warm_radius) && p->warm_radius >= 0.0f))
         return fail(MS_E_INVALID_ARG, "warm_radius must be finite and >= 0");
     if (s->env_body_off[0] != 0 || s->env_joint_off[0] != 0) return fail(MS_E_INVALID_ARG, "offsets must start at 0");
+    if (s->n_compounds < 0 || (s->n_compounds > 0 && !s->compounds))
+        return fail(MS_E_INVALID_ARG, "bad compound table (%d entries)", s->n_compounds);
+    for (int k = 0; k < s->n_compounds; ++k)
+        if (ms_status st = validate_compound(s->compounds[k], k); st != MS_OK) return st;
     for (int e = 0; e < s->n_envs; ++e) {
         int nb = s->env_body_off[e + 1] - s->env_body_off[e];
         int nj = s->env_joint_off[e + 1] - s->env_joint_off[e];
@@ -218,8 +339,17 @@ ms_status validate(const ms_sim_params* p, const ms_scene_desc* s) {
         }
         for (int i = 0; i < nb; ++i) {
             const ms_body_desc& b = s->bodies[s->env_body_off[e] + i];
-            if (b.shape < MS_SPHERE || b.shape > MS_BOX) return fail(MS_E_INVALID_ARG, "env %d body %d: bad shape", e, i);
+            if (b.shape < MS_SPHERE || b.shape > MS_COMPOUND) return fail(MS_E_INVALID_ARG, "env %d body %d: bad shape", e, i);
             if ((b.flags & ~MS_BODY_STATIC) != 0) return fail(MS_E_INVALID_ARG, "env %d body %d: bad flags", e, i);
+            if (b.shape == MS_COMPOUND) {
+                const float ci = b.dims[0];
+                if (!(ci >= 0.0f) || !(ci < float(s->n_compounds)) || ci != float(int(ci)))
+                    return fail(MS_E_INVALID_ARG, "env %d body %d: compound index %g outside the table of %d", e, i,
+                                double(ci), s->n_compounds);
+                if (!(b.flags & MS_BODY_STATIC) && !(b.mass > 0.0f) && !(b.density > 0.0f))
+                    return fail(MS_E_INVALID_ARG, "env %d body %d: dynamic body needs mass or density", e, i);
+                continue;
+            }
             int nd = b.shape == MS_SPHERE ? 1 : (b.shape == MS_CAPSULE ? 2 : 3);
             for (int k = 0; k < nd; ++k)
                 if (!(b.dims[k] > 0.0f) || !std::isfinite(b.dims[k]))
@@ -376,6 +506,7 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     L.forces = take(3 * B * 4);
     L.bad_ids = take(4);
     L.phase_clock = take(16 * 8);
+    L.comp = take(size_t(std::max(s->n_compounds, 0)) * COMP_WORDS * 4);
     if (p->warm_start) {
         // contact cache: header [E][2], manifold records [sum mcap][6], point records [sum cap][4],
         // and a copy of all three for the tuner's save / restore
@@ -401,9 +532,19 @@ WsLayout layout_ws(const ms_sim_params* p, const ms_scene_desc* s, const Plan& p
     return L;
 }
 
-// Mass properties (uniform density; centre of mass at the shape centre).
-void mass_props(const ms_body_desc& b, float& invm, float inv_inertia[3]) {
+// Mass properties (uniform density; centre of mass at the shape centre, or at the origin of a
+// compound's body frame).
+void mass_props(const ms_body_desc& b, const ms_compound_desc* comps, float& invm, float inv_inertia[3]) {
     if (b.flags & MS_BODY_STATIC) { invm = 0.0f; inv_inertia[0] = inv_inertia[1] = inv_inertia[2] = 0.0f; return; }
+    if (b.shape == MS_COMPOUND) {
+        const ms_compound_desc& c = comps[int(b.dims[0])];
+        const float m = b.mass > 0.0f ? b.mass : b.density * compound_volume(c);
+        float I[3];
+        compound_inertia(c, m, I);
+        invm = 1.0f / m;
+        for (int k = 0; k < 3; ++k) inv_inertia[k] = 1.0f / I[k];
+        return;
+    }
     // float32 throughout, in the order of the step model's definition (uniform density).
     float m;
     if (b.mass > 0.0f) m = b.mass;
@@ -460,6 +601,9 @@ struct ms_batch {
     bool joints_ordered = true;
     // the step accumulates per-body contact forces (ms_set_contact_forces)
     bool forces_on = false;
+    // entries of the compound table (compound bodies run in the kernel twins with the optional
+    // phases, which hold the compound narrowphase)
+    int n_comp = 0;
     // fork / join streams for LDS classes after the first (default priority)
     hipStream_t side[MAX_CLASSES] = {};
     hipEvent_t ev_fork = nullptr;
@@ -473,8 +617,11 @@ struct ms_batch {
     }
 };
 
-// The batch runs the kernel twins with the optional phases (contact forces or contact cache on).
-static bool batch_opt(const ms_batch* b) { return b->forces_on || b->P.warm_start != 0; }
+// Feature level of the kernels a batch runs: 1 with the optional phases (contact forces or
+// contact cache on), 3 with compound bodies (a superset), else 0.
+static int batch_opt(const ms_batch* b) {
+    return b->n_comp > 0 ? 3 : ((b->forces_on || b->P.warm_start != 0) ? 1 : 0);
+}
 
 namespace {
 template <class T> T* at(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
@@ -513,6 +660,8 @@ void fill_batchdev(ms_batch* b) {
         d.warm_radius = p.warm_radius;
     }
     d.forces = b->forces_on ? at<float>(w, L.forces) : nullptr;
+    d.comp = b->n_comp > 0 ? at<float>(w, L.comp) : nullptr;
+    d.n_comp = b->n_comp;
     if (p.debug_export) {
         d.dbg_pairs = at<int>(w, L.dbg_pairs); d.dbg_pair_off = at<int>(w, L.dbg_pair_off);
         d.dbg_pts = at<float>(w, L.dbg_pts); d.dbg_pt_off = at<int>(w, L.dbg_pt_off);
@@ -630,6 +779,7 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
     b->J = scene->env_joint_off[b->E];
     b->body_off.assign(scene->env_body_off, scene->env_body_off + b->E + 1);
     b->joint_off.assign(scene->env_joint_off, scene->env_joint_off + b->E + 1);
+    b->n_comp = scene->n_compounds;
     plan_batch(params, scene, plan, b->plan);
     for (int e = 0; e < b->E && b->joints_ordered; ++e) {
         const int n = b->body_off[e + 1] - b->body_off[e];
@@ -675,7 +825,7 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
         for (int r = 0; r < 3; ++r) hs[7 * B + r * B + i] = d.linvel[r];
         for (int r = 0; r < 3; ++r) hs[10 * B + r * B + i] = d.angvel[r];
         float invm, iI[3];
-        mass_props(d, invm, iI);
+        mass_props(d, scene->compounds, invm, iI);
         int code = d.shape | (d.flags << 8);
         float codef;
         std::memcpy(&codef, &code, 4);
@@ -735,6 +885,19 @@ ms_status ms_create_batch(const ms_sim_params* params, const ms_scene_desc* scen
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e == hipSuccess) e = up(L.bpar, bp.data(), 3 * B * 16);
+    std::vector<float> ct(size_t(b->n_comp) * COMP_WORDS, 0.0f);
+    for (int k = 0; k < b->n_comp; ++k) {
+        const ms_compound_desc& c = scene->compounds[k];
+        float* r = &ct[size_t(k) * COMP_WORDS];
+        std::memcpy(&r[0], &c.n_children, 4);
+        for (int j = 0; j < c.n_children; ++j) {
+            float* q = r + 4 + 12 * j;
+            std::memcpy(&q[0], &c.shape[j], 4);
+            for (int t = 0; t < 3; ++t) q[1 + t] = c.dims[j][t];
+            for (int t = 0; t < 7; ++t) q[4 + t] = c.pose[j][t];
+        }
+    }
+    if (e == hipSuccess) e = up(L.comp, ct.data(), ct.size() * 4);
     if (e == hipSuccess) e = up(L.body_off, b->body_off.data(), (E + 1) * 4);
     if (e == hipSuccess) e = up(L.joint_off, b->joint_off.data(), (E + 1) * 4);
     if (e == hipSuccess) e = up(L.jrec, jr.data(), J * JREC * 4);
@@ -809,7 +972,7 @@ ms_status ms_step(ms_batch* b, const float* dev_targets, int32_t n_steps, void* 
     const Tile* tiles = at<Tile>(b->ws, b->lay.tiles);
     const TileEnv* tenv = at<TileEnv>(b->ws, b->lay.tenv);
     const int grid_cap = b->max_resident_groups;
-    const bool opt = batch_opt(b);
+    const int opt = batch_opt(b);
     if (cls.size() == 1) return launch_class(cls[0], b->dbd, tiles, tenv, int(n_steps), grid_cap, s, opt);
     if (!b->plan.bins.empty()) {   // every tile in one launch, a bin per workgroup
         const int nb = int(b->plan.bins.size());
@@ -1339,8 +1502,8 @@ ms_status ms_step_many(ms_batch* const* batches, const float* const* dev_targets
     for (int i = 0; i < n_batches; ++i)
         if (batches[i]->device != dev) return fail(MS_E_INVALID_ARG, "batch %d lives on device %d, not %d", i, batches[i]->device, dev);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    bool opt = false;
-    for (int i = 0; i < n_batches; ++i) opt = opt || batch_opt(batches[i]);
+    int opt = 0;
+    for (int i = 0; i < n_batches; ++i) opt |= batch_opt(batches[i]);
     Staging& st = g_stage;
     if (st.device != dev) {
         st.release();
@@ -1481,8 +1644,8 @@ ms_status ms_step_many_noalloc(ms_batch* const* batches, const float* const* dev
     for (int i = 0; i < n_batches; ++i)
         if (batches[i]->device != dev) return fail(MS_E_INVALID_ARG, "batch %d lives on device %d, not %d", i, batches[i]->device, dev);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    bool opt = false;
-    for (int i = 0; i < n_batches; ++i) opt = opt || batch_opt(batches[i]);
+    int opt = 0;
+    for (int i = 0; i < n_batches; ++i) opt |= batch_opt(batches[i]);
 
     std::lock_guard<std::mutex> lock(g_noalloc_mu);
     if (!g_noalloc_dev[dev]) {

@@ -77,6 +77,7 @@ struct Session {
     std::vector<int32_t> body_off, joint_off;
     std::vector<ms_body_desc> bodies;
     std::vector<ms_joint_desc> joints;
+    std::vector<ms_compound_desc> compounds;
     size_t ws_bytes = 0, bytes = 0, off = 0;
     int32_t n_envs = 0, n_joints = 0;
     ms_batch* b = nullptr;
@@ -197,7 +198,8 @@ void ms_server::admit_loop() {
         stats[6] = int64_t(alloc.peak);
         // build the batch outside the lock (its descriptors are not touched by other threads)
         ms_scene_desc sd{ss.n_envs, ss.body_off.data(), ss.bodies.data(), ss.joint_off.data(),
-                         ss.joints.empty() ? nullptr : ss.joints.data()};
+                         ss.joints.empty() ? nullptr : ss.joints.data(), int32_t(ss.compounds.size()),
+                         ss.compounds.empty() ? nullptr : ss.compounds.data()};
         char* base = arena + off;
         ms_batch* b = nullptr;
         lk.unlock();
@@ -435,6 +437,7 @@ ms_status ms_server_open(ms_server* s, const ms_sim_params* params, const ms_sce
     ss.n_joints = ss.joint_off.back();
     ss.bodies.assign(scene->bodies, scene->bodies + ss.body_off.back());
     if (ss.n_joints) ss.joints.assign(scene->joints, scene->joints + ss.n_joints);
+    if (scene->n_compounds > 0) ss.compounds.assign(scene->compounds, scene->compounds + scene->n_compounds);
     ss.ws_bytes = ws;
     ss.bytes = align_up(ws) + align_up(size_t(std::max(ss.n_joints, 1)) * 4);
     std::lock_guard<std::mutex> lk(s->mu);

@@ -817,6 +817,33 @@ __device__ __forceinline__ Shp shape_of(const EnvCtx& c, int i, V3 centre) {
     return s;
 }
 
+// ----------------------------------------------------------------------------- compound parts
+// A compound body holds its table index in dim0; its record (HBM, shared by every env of the
+// batch and read through the caches) lists its primitive parts with their body-frame poses.
+__device__ __forceinline__ bool is_compound(const EnvCtx& c, int i) {
+    return (iptr(c.L + c.lay.SH)[i] & 0xFF) == SHAPE_COMPOUND;
+}
+__device__ __forceinline__ const float* comp_rec(const EnvCtx& c, int i) {
+    return c.bd->comp + size_t(int(c.L[c.lay.DIM + i])) * COMP_WORDS;
+}
+__device__ __forceinline__ int n_parts(const EnvCtx& c, int i) {
+    return is_compound(c, i) ? gldi(reinterpret_cast<const int*>(comp_rec(c, i))) : 1;
+}
+// Part k of body i with the body's centre at `centre` (pair frame): the body itself, or a
+// compound's part at centre + R c_k with rotation R(q q_k), q the step-start orientation.
+__device__ __forceinline__ Shp part_of(const EnvCtx& c, int i, int k, V3 centre) {
+    if (!is_compound(c, i)) return shape_of(c, i, centre);
+    const float4* P = reinterpret_cast<const float4*>(comp_rec(c, i) + 4 + 12 * k);
+    const float4 r0 = gld4(P), r1 = gld4(P + 1), r2 = gld4(P + 2);
+    const Qt q = ldp4(c, i, P_Q0);
+    Shp s;
+    s.type = __float_as_int(r0.x);
+    s.d[0] = r0.y; s.d[1] = r0.z; s.d[2] = r0.w;
+    s.c = centre + mulv(rotm(q), v3(r1.x, r1.y, r1.z));
+    s.R = rotm(qmul(q, Qt{r1.w, r2.x, r2.y, r2.z}));
+    return s;
+}
+
 // ----------------------------------------------------------------------------- manifold block
 // Rows are records (array of structures): a manifold's 23 words and a point's 14 words are
 // contiguous, so a lane's row loads share one address and pair up into wide LDS reads.
@@ -1321,6 +1348,37 @@ __device__ __forceinline__ void joint_solve_pre(const EnvCtx& c, int j, const Jo
 }
 
 // ----------------------------------------------------------------------------- S1 AABB (exact)
+// Half size along world axis r of a primitive with rotation rows R (add, multiply, abs only).
+__device__ __forceinline__ float prim_half(int shape, float d0, float d1, float d2, float r0, float r1, float r2) {
+    if (shape == 2) {
+        float t0 = fabsf(r0) * d0;
+        float t1 = fabsf(r1) * d1;
+        float t2 = fabsf(r2) * d2;
+        return (t0 + t1) + t2;
+    }
+    if (shape == 0) return d0;
+    float t = fabsf(r2) * d1;
+    return t + d0;
+}
+// A compound's box: along each world axis the largest |R c_k| + the part's own half size.
+__device__ __forceinline__ void compound_half(const EnvCtx& c, int i, Qt q, const float R[3][3], float hm[3]) {
+    const float* rec = comp_rec(c, i);
+    const int np = gldi(reinterpret_cast<const int*>(rec));
+    hm[0] = 0.0f; hm[1] = 0.0f; hm[2] = 0.0f;
+    for (int k = 0; k < np; ++k) {
+        const float4* P = reinterpret_cast<const float4*>(rec + 4 + 12 * k);
+        const float4 r0 = gld4(P), r1 = gld4(P + 1), r2 = gld4(P + 2);
+        const M3 Rk = rotm(qmul(q, Qt{r1.w, r2.x, r2.y, r2.z}));
+        const int sh = __float_as_int(r0.x);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float o = R[r][0] * r1.x + R[r][1] * r1.y + R[r][2] * r1.z;
+            const float hv = fabsf(o) + prim_half(sh, r0.y, r0.z, r0.w, Rk.m[r][0], Rk.m[r][1], Rk.m[r][2]);
+            if (hv > hm[r]) hm[r] = hv;
+        }
+    }
+}
+template <bool COMP>
 __device__ __forceinline__ void body_aabb(const EnvCtx& c, int i) {
 #pragma clang fp contract(off)
     const Lay& l = c.lay;
@@ -1336,19 +1394,11 @@ __device__ __forceinline__ void body_aabb(const EnvCtx& c, int i) {
     int shape = iptr(c.L + l.SH)[i] & 0xFF;
     float d0 = c.L[l.DIM + i], d1 = c.L[l.DIM + n + i], d2 = c.L[l.DIM + 2 * n + i];
     float delta = c.bd->delta;
+    float hm[3] = {0.0f, 0.0f, 0.0f};
+    if (COMP && shape == SHAPE_COMPOUND) compound_half(c, i, q, R, hm);
+#pragma unroll
     for (int r = 0; r < 3; ++r) {
-        float hv;
-        if (shape == 2) {
-            float t0 = fabsf(R[r][0]) * d0;
-            float t1 = fabsf(R[r][1]) * d1;
-            float t2 = fabsf(R[r][2]) * d2;
-            hv = (t0 + t1) + t2;
-        } else if (shape == 0) {
-            hv = d0;
-        } else {
-            float t = fabsf(R[r][2]) * d1;
-            hv = t + d0;
-        }
+        float hv = (COMP && shape == SHAPE_COMPOUND) ? hm[r] : prim_half(shape, d0, d1, d2, R[r][0], R[r][1], R[r][2]);
         float half = hv + delta;
         float x = pose_rec(c, i)[P_X0 + r];
         c.L[l.AABB + r * n + i] = x - half;
@@ -2186,7 +2236,7 @@ __device__ __forceinline__ void np_candidate(const EnvCtx& c, int code, NOut& o,
 // S4 for one kept pair: a normal row per kept point (arms from the step-start centres, pre-step
 // normal velocity, effective mass) and the manifold's friction patch at the points' centroid.
 __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k, int a, int b, bool plane, V3 base,
-                                        V3 offB, int keep, int first, int m, bool dbg, int dpo, int dmo) {
+                                        V3 offB, int keep, int first, int m, int part, bool dbg, int dpo, int dmo) {
     const Lay& l = c.lay;
     const BatchDev& bd = *c.bd;
     int ia = plane ? -1 : a, ib = plane ? a : b;
@@ -2232,7 +2282,7 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
 #pragma unroll
     for (int K = 0; K < 4; ++K)
         if (K < keep) rsum += len3(o.pt[K].p - cc);
-    iptr(c.L + l.MAN + m * M_WORDS)[M_AB] = (ia < 0 ? 0xFF : ia) | (ib << 8);
+    iptr(c.L + l.MAN + m * M_WORDS)[M_AB] = (ia < 0 ? 0xFF : ia) | (ib << 8) | (part << 16);
     iptr(c.L + l.MAN + m * M_WORDS)[M_FC] = first | (keep << 16);
     mfr(c, M_RA, m) = rA.x; mfr(c, M_RA + 1, m) = rA.y; mfr(c, M_RA + 2, m) = rA.z;
     mfr(c, M_RB, m) = rB.x; mfr(c, M_RB + 1, m) = rB.y; mfr(c, M_RB + 2, m) = rB.z;
@@ -2250,6 +2300,113 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
         dm[0] = __int_as_float(k);
         dm[7] = __int_as_float(keep);
     }
+}
+
+// Whether any candidate of the chunk (lane's candidate `code`) involves a compound body; wave-
+// uniform (one ballot), so every lane of the wave takes the same narrowphase path.
+__device__ __forceinline__ bool compound_chunk_p(const EnvCtx& c, int code) {
+    bool cc = false;
+    if (code >= 0 && c.bd->comp != nullptr) {
+        const int a = code & 0xFF, b = code >> 8;
+        cc = is_compound(c, a) || (b != c.lay.n && is_compound(c, b));
+    }
+    return __ballot(cc) != 0;
+}
+
+// S3 + S4 for a chunk in which some candidate involves a compound body (lane per candidate, code
+// < 0: none).  Every pair of parts (A's parts outer; a ground pair pairs the plane with each part
+// of its body) runs the primitive narrowphase and keeps <= 4 points as a manifold of its own;
+// a primitive pair is the one pair of its two bodies.  Two passes: the first counts each
+// candidate's points and manifolds before the capacity rule, whose scan over the lanes places
+// every pair of parts in canonical order (candidate, then part pair); the second recomputes
+// each pair of parts and writes its rows.  A pair of parts with `pre` points and `mpre`
+// manifolds before it in the env keeps min(n, cap - pre) points if mpre < mcap, else none: the
+// sequential capacity rule (kept pairs are exactly the earlier pairs' full lists).
+__device__ __forceinline__ void compound_chunk(const EnvCtx& c, int code, int k, int& npts, int& nman, bool& overflow,
+                                               int li, int g, int G, bool dbg, int dpp, int dpo, int dmo) {
+    const Lay& l = c.lay;
+    const BatchDev& bd = *c.bd;
+    const int n = l.n;
+    int a = 0, b = 0, np = 0, nb = 1;
+    bool plane = false, comp = false;
+    V3 base = v3(0, 0, 0), offB = v3(0, 0, 0);
+    if (code >= 0) {
+        a = code & 0xFF;
+        b = code >> 8;
+        plane = b == n;
+        const V3 xa = ldp3(c, a, P_X0);
+        if (plane) {
+            base = v3(xa.x, xa.y, bd.plane_z);
+            offB = v3(0.0f, 0.0f, xa.z - bd.plane_z);
+            nb = n_parts(c, a);
+            np = nb;
+            comp = is_compound(c, a);
+        } else {
+            base = xa;
+            offB = ldp3(c, b, P_X0) - xa;
+            nb = n_parts(c, b);
+            np = n_parts(c, a) * nb;
+            comp = is_compound(c, a) || is_compound(c, b);
+        }
+    }
+    int* SC = iptr(c.L + l.SCAL);
+    int rawp = 0, rawm = 0, hit = -1, dec = 0, kept = 0, keptm = 0;
+    int P = 0, M = 0;
+    bool ovf = false;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll 1
+        for (int t = 0; t < np; ++t) {
+            const int i = t / nb, j = t - i * nb;
+            NOut o;
+            o.mask = 0;
+            o.decision = 0;
+            if (plane) {
+                const Shp sb = part_of(c, a, j, offB);
+                if (pass == 0) atomicAdd(&SC[16 + STAT_KIND0 + 9 + sb.type], 1);
+                np_plane(o, sb, bd.delta);
+            } else {
+                const Shp sa = part_of(c, a, i, v3(0, 0, 0));
+                const Shp sb = part_of(c, b, j, offB);
+                if (pass == 0) atomicAdd(&SC[16 + STAT_KIND0 + 3 * min(sa.type, sb.type) + max(sa.type, sb.type)], 1);
+                np_pair(o, sa, sb, bd.delta);
+            }
+            if (pass == 0) {
+                const int on = min(n_points(o), 4);   // the reduction keeps min(n, 4) points
+                rawp += on;
+                rawm += on > 0 ? 1 : 0;
+                if (on > 0 && hit < 0) hit = t;
+                if (t == 0) dec = o.decision;
+                continue;
+            }
+            reduce4(o);
+            compact4(o);
+            const int on = n_points(o);
+            if (on == 0) continue;
+            const int keep = M >= l.mcap ? 0 : min(max(l.cap - P, 0), on);
+            if (keep < on) ovf = true;
+            if (keep > 0) write_rows(c, o, k, a, b, plane, base, offB, keep, P, M, t, dbg, dpo, dmo);
+            P += on;
+            M += 1;
+            kept += keep;
+            keptm += keep > 0 ? 1 : 0;
+        }
+        if (pass == 0) {
+            int tot;
+            P = npts + group_scan_small<7>(rawp, li, g, G, tot);
+            M = nman + group_scan_small<5>(rawm, li, g, G, tot);
+        }
+    }
+    overflow |= group_bits(__ballot(ovf), g, G) != 0;
+    if (code >= 0 && dbg) {
+        int* dp = bd.dbg_pairs + 4 * size_t(dpp + k);
+        dp[0] = a; dp[1] = plane ? PLANE : b; dp[2] = kept; dp[3] = comp ? (hit < 0 ? 63 : 64 + hit) : dec;
+    }
+    int ktot, mtot;
+    group_scan_small<7>(kept, li, g, G, ktot);
+    group_scan_small<5>(keptm, li, g, G, mtot);
+    npts += ktot;
+    nman += mtot;
 }
 
 }  // namespace
@@ -2300,12 +2457,12 @@ __device__ __forceinline__ void accumulate_forces(const EnvCtx& c, int nn, int l
 }
 
 // ----------------------------------------------------------------------------- S4b contact cache
-// Pair key of manifold m, increasing in canonical order: (lower body, partner), the ground plane
-// after every partner of its body.
+// Key of manifold m, increasing in canonical order: (lower body, partner, pair of parts), the
+// ground plane after every partner of its body.
 __device__ __forceinline__ int man_key(const EnvCtx& c, int m) {
-    int a, b, first, cnt;
-    man_header(c, m, a, b, first, cnt);
-    return a >= 0 ? (a << 8) | b : (b << 8) | 0xFF;
+    const int ab = iptr(c.L + c.lay.MAN + m * M_WORDS)[M_AB];
+    const int a = ab & 0xFF, b = (ab >> 8) & 0xFF, part = (ab >> 16) & 0xF;
+    return ((a != 0xFF ? (a << 8) | b : (b << 8) | 0xFF) << 4) | part;
 }
 // Initial impulses from the last step's cache (lane per manifold): a manifold whose pair is
 // cached takes, for each point, the normal impulse of the nearest cached point of that pair
@@ -2377,7 +2534,7 @@ __device__ __forceinline__ void write_cache(const EnvCtx& c, int nman, int npts,
         const V3 t1 = mf3(c, M_T1, m);
         const V3 pt = mf(c, M_LT1, m) * t1 + mf(c, M_LT2, m) * cross3(mf3(c, M_NB, m), t1);
         int* rec = CM + m * CM_WORDS;
-        gsti(rec, a >= 0 ? (a << 8) | b : (b << 8) | 0xFF);
+        gsti(rec, man_key(c, m));
         gsti(rec + 1, first | (cnt << 16));
         gsti(rec + 2, __float_as_int(pt.x)); gsti(rec + 3, __float_as_int(pt.y)); gsti(rec + 4, __float_as_int(pt.z));
         gsti(rec + 5, __float_as_int(mf(c, M_LTW, m)));
@@ -2412,11 +2569,16 @@ enum { PH_LOAD, PH_POSE, PH_BROAD, PH_NARROW, PH_CACHE, PH_COLOUR, PH_LISTS, PH_
     } while (0)
 #endif
 
-// OPT: the build with the optional phases (contact-force readout, contact cache); the default
-// builds leave them out entirely, so that they cost the plain step no registers.
-template <bool ONE, bool OPT>
+// FEAT: the optional parts the build carries.  FEAT_OPT: the optional phases (contact-force
+// readout, contact cache); FEAT_COMP: compound bodies as well (their two-pass narrowphase and
+// boxes).  The default builds leave both out entirely, so that they cost the plain step no
+// registers, and the compound build is apart from the optional-phase one for the same reason.
+enum { FEAT_OPT = 1, FEAT_COMP = 2 };
+template <bool ONE, int FEAT>
 __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict__ batches, const Tile tile,
                                           const TileEnv* __restrict__ tenv, int n_steps, int lane) {
+    constexpr bool OPT = (FEAT & FEAT_OPT) != 0;
+    constexpr bool COMP = (FEAT & FEAT_COMP) != 0;
     {
 #ifdef MS_PHASE_CLOCK
         uint64_t ph_acc[N_PHASES] = {};
@@ -2530,7 +2692,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 float* Iwr = body_rec(c, i) + B_IW;
                 Iwr[0] = Iw[0][0]; Iwr[1] = Iw[1][1]; Iwr[2] = Iw[2][2];
                 Iwr[3] = Iw[0][1]; Iwr[4] = Iw[0][2]; Iwr[5] = Iw[1][2];
-                body_aabb(c, i);
+                body_aabb<COMP>(c, i);
                 iptr(c.L + l.CM)[2 * i] = 0;
                 iptr(c.L + l.CM)[2 * i + 1] = 0;
             }
@@ -2621,6 +2783,13 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 if (dbg) { dpp = bd.dbg_pair_off[c.env]; dpo = bd.dbg_pt_off[c.env]; dmo = bd.dbg_man_off[c.env]; }
                 for (int ch = 0; ch < nch; ++ch) {
                     int k = ch * G + li;
+                    if constexpr (COMP) {
+                        const int code = k < ncand ? int(CAND[k]) : -1;
+                        if (compound_chunk_p(c, code)) {
+                            compound_chunk(c, code, k, npts, nman, overflow, li, g, G, dbg, dpp, dpo, dmo);
+                            continue;
+                        }
+                    }
                     NOut o;
                     int a = 0, b = 0;
                     bool plane = false;
@@ -2643,7 +2812,7 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                         int* dp = bd.dbg_pairs + 4 * size_t(dpp + k);
                         dp[0] = a; dp[1] = plane ? PLANE : b; dp[2] = keep; dp[3] = o.decision;
                     }
-                    if (keep > 0) write_rows(c, o, k, a, b, plane, base, offB, keep, first, m_idx, dbg, dpo, dmo);
+                    if (keep > 0) write_rows(c, o, k, a, b, plane, base, offB, keep, first, m_idx, 0, dbg, dpo, dmo);
                     npts += ktot;
                     int mkept;
                     group_scan_small<1>(keep > 0 ? 1 : 0, li, g, G, mkept);
@@ -2830,19 +2999,19 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
 }
 
 // Workgroups of one wavefront walking the tile list.
-template <bool ONE, bool OPT>
+template <bool ONE, int FEAT>
 __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restrict__ batches,
                                            const Tile* __restrict__ tiles, int n_tiles,
                                            const TileEnv* __restrict__ tenv, int n_steps) {
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x)
-        step_tile<ONE, OPT>(lds, batches, tiles[t], tenv, n_steps, int(threadIdx.x));
+        step_tile<ONE, FEAT>(lds, batches, tiles[t], tenv, n_steps, int(threadIdx.x));
 }
 
 // One launch for every tile of a batch: workgroups of BIN_WAVES wavefronts, one bin each; wave w
 // runs tile w of its bin in the bin's LDS at that tile's offset (the scalar-env build for a tile
 // of one env on all 64 lanes, the general build otherwise).  Waves of a bin share nothing
 // but the allocation (every env lives in one wave), so they need no barrier.
-template <bool OPT>
+template <int FEAT>
 __device__ __forceinline__ void step_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles,
                                           const Bin* __restrict__ bins, int n_bins, const TileEnv* __restrict__ tenv,
                                           int n_steps) {
@@ -2854,41 +3023,51 @@ __device__ __forceinline__ void step_bins(const BatchDev* __restrict__ batches, 
     if (wave >= bin.count) return;
     const Tile tile = tiles[bin.tile[wave]];
     const int lane = int(threadIdx.x) & (WAVE - 1);
-    if (tile.lanes == WAVE && tile.count == 1) step_tile<true, OPT>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
-    else step_tile<false, OPT>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
+    if (tile.lanes == WAVE && tile.count == 1) step_tile<true, FEAT>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
+    else step_tile<false, FEAT>(lds + bin.off[wave], batches, tile, tenv, n_steps, lane);
 }
 
 // Builds of the same step: any tiling with unconstrained register allocation (small envs, where
 // the wave count is bounded by LDS anyway) or capped at 256 registers per lane (two waves per
 // SIMD); the same two for launches whose tiles all hold one env served by the whole wavefront;
 // and the bins launch.  The planner / tuner picks one per LDS class.  The *_opt twins carry the
-// optional phases (batches with contact forces or the contact cache on).
-#define MS_TILE_KERNEL(NAME, ONE, OPT, ATTR)                                                                   \
+// optional phases (batches with contact forces or the contact cache on), the *_comp ones those
+// and compound bodies.
+#define MS_TILE_KERNEL(NAME, ONE, FEAT, ATTR)                                                                   \
     extern "C" __global__ void __launch_bounds__(64) ATTR NAME(const BatchDev* __restrict__ batches,            \
                                                                const Tile* __restrict__ tiles, int n_tiles,    \
                                                                const TileEnv* __restrict__ tenv, int n_steps) { \
         extern __shared__ float lds[];                                                                         \
-        step_tiles<ONE, OPT>(lds, batches, tiles, n_tiles, tenv, n_steps);                                      \
+        step_tiles<ONE, FEAT>(lds, batches, tiles, n_tiles, tenv, n_steps);                                     \
     }
 #define MS_W2 __attribute__((amdgpu_waves_per_eu(2)))
-MS_TILE_KERNEL(ms_step_kernel, false, false, )
-MS_TILE_KERNEL(ms_step_kernel_w2, false, false, MS_W2)
-MS_TILE_KERNEL(ms_step_kernel_one, true, false, )
-MS_TILE_KERNEL(ms_step_kernel_one_w2, true, false, MS_W2)
-MS_TILE_KERNEL(ms_step_kernel_opt, false, true, )
-MS_TILE_KERNEL(ms_step_kernel_w2_opt, false, true, MS_W2)
-MS_TILE_KERNEL(ms_step_kernel_one_opt, true, true, )
-MS_TILE_KERNEL(ms_step_kernel_one_w2_opt, true, true, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel, false, 0, )
+MS_TILE_KERNEL(ms_step_kernel_w2, false, 0, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_one, true, 0, )
+MS_TILE_KERNEL(ms_step_kernel_one_w2, true, 0, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_opt, false, FEAT_OPT, )
+MS_TILE_KERNEL(ms_step_kernel_w2_opt, false, FEAT_OPT, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_one_opt, true, FEAT_OPT, )
+MS_TILE_KERNEL(ms_step_kernel_one_w2_opt, true, FEAT_OPT, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_comp, false, FEAT_OPT | FEAT_COMP, )
+MS_TILE_KERNEL(ms_step_kernel_w2_comp, false, FEAT_OPT | FEAT_COMP, MS_W2)
+MS_TILE_KERNEL(ms_step_kernel_one_comp, true, FEAT_OPT | FEAT_COMP, )
+MS_TILE_KERNEL(ms_step_kernel_one_w2_comp, true, FEAT_OPT | FEAT_COMP, MS_W2)
 
 extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) MS_W2
 ms_step_kernel_bins(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, const Bin* __restrict__ bins,
                     int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
-    step_bins<false>(batches, tiles, bins, n_bins, tenv, n_steps);
+    step_bins<0>(batches, tiles, bins, n_bins, tenv, n_steps);
 }
 extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) MS_W2
 ms_step_kernel_bins_opt(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles, const Bin* __restrict__ bins,
                         int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
-    step_bins<true>(batches, tiles, bins, n_bins, tenv, n_steps);
+    step_bins<FEAT_OPT>(batches, tiles, bins, n_bins, tenv, n_steps);
+}
+extern "C" __global__ void __launch_bounds__(WAVE * BIN_WAVES) MS_W2
+ms_step_kernel_bins_comp(const BatchDev* __restrict__ batches, const Tile* __restrict__ tiles,
+                         const Bin* __restrict__ bins, int n_bins, const TileEnv* __restrict__ tenv, int n_steps) {
+    step_bins<FEAT_OPT | FEAT_COMP>(batches, tiles, bins, n_bins, tenv, n_steps);
 }
 
 // ============================================================================= reset kernel

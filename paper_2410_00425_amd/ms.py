@@ -42,7 +42,8 @@ class MsError(RuntimeError):
 
 class ms_scene_desc(C.Structure):
     _fields_ = [("n_envs", C.c_int32), ("env_body_off", C.c_void_p), ("bodies", C.c_void_p),
-                ("env_joint_off", C.c_void_p), ("joints", C.c_void_p)]
+                ("env_joint_off", C.c_void_p), ("joints", C.c_void_p), ("n_compounds", C.c_int32),
+                ("compounds", C.c_void_p)]
 
 
 class ms_state_view(C.Structure):
@@ -123,8 +124,12 @@ def _scene_struct(scene):
     arrs = [np.ascontiguousarray(scene.body_off, np.int32), np.ascontiguousarray(scene.bodies),
             np.ascontiguousarray(scene.joint_off, np.int32), np.ascontiguousarray(scene.joints)]
     assert arrs[1].dtype == scenes.BODY_DTYPE and arrs[3].dtype == scenes.JOINT_DTYPE
+    comps = np.ascontiguousarray(getattr(scene, "compounds", np.zeros(0, scenes.COMPOUND_DTYPE)))
+    assert len(comps) == 0 or comps.dtype == scenes.COMPOUND_DTYPE
+    arrs.append(comps)
     sd = ms_scene_desc(scene.n_envs, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
-                       arrs[3].ctypes.data if len(arrs[3]) else None)
+                       arrs[3].ctypes.data if len(arrs[3]) else None, len(comps),
+                       comps.ctypes.data if len(comps) else None)
     return sd, arrs
 
 

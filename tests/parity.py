@@ -15,13 +15,24 @@ MARGIN = 1e-5
 REL = 1e-4
 
 
-def body_scale(bodies):
+def part_scale(shape, dims):
+    d = np.asarray(dims, np.float64)
+    return d.min() if shape == S.BOX else d[0]
+
+
+def body_scale(bodies, compounds=None):
+    """Smallest half-size of each body (of its smallest part for a compound)."""
     d = bodies["dims"].astype(np.float64)
-    return np.where(bodies["shape"] == S.BOX, d.min(axis=1), d[:, 0])
+    out = np.where(bodies["shape"] == S.BOX, d.min(axis=1), d[:, 0])
+    for i in np.nonzero(bodies["shape"] == S.COMPOUND)[0]:
+        rec = compounds[int(d[i, 0])]
+        out[i] = min(part_scale(int(rec["shape"][k]), rec["dims"][k][:3 if rec["shape"][k] == S.BOX else 1])
+                     for k in range(int(rec["n_children"])))
+    return out
 
 
-def env_ok(sa, sb, bodies, sl, rel=REL):
-    wf = 0.1 / body_scale(bodies[sl])
+def env_ok(sa, sb, bodies, sl, rel=REL, compounds=None):
+    wf = 0.1 / body_scale(bodies[sl], compounds)
     for k, fl in (("pos", 0.01), ("linvel", 0.1), ("angvel", wf), ("quat", 1.0)):
         x, y = np.asarray(sa[k][:, sl], np.float64), np.asarray(sb[k][:, sl], np.float64)
         if k == "quat":
@@ -35,7 +46,8 @@ def compare_states(scene, sa, sb, margins, envs=None, max_excused_frac=0.001, mi
     """Check the parity rule env by env; returns (bad envs, excused envs)."""
     bo = scene.body_off
     envs = range(scene.n_envs) if envs is None else envs
-    bad = [e for e in envs if not env_ok(sa, sb, scene.bodies, slice(bo[e], bo[e + 1]))]
+    comps = getattr(scene, "compounds", None)
+    bad = [e for e in envs if not env_ok(sa, sb, scene.bodies, slice(bo[e], bo[e + 1]), compounds=comps)]
     excused = [e for e in bad if margins[e] < MARGIN]
     return [e for e in bad if e not in excused], excused
 

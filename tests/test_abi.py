@@ -74,3 +74,54 @@ def test_empty_batch_and_size_limits_are_rejected():
     # exactly 64 bodies is accepted
     sixty_four = S.single([S.body(S.SPHERE, (0.01,), (0.03 * i, 0, 0.5), mass=1.0) for i in range(64)])
     assert ms.ms_query_batch_bytes(sixty_four) > 0
+
+
+def test_compound_table_validation():
+    """The compound table is checked by the host-only query: index in range and integral, 1..4
+    parts of primitive shape, unit part quaternions, centre of mass at the body origin and body
+    axes principal."""
+    from paper_2410_00425_amd import ms
+    sc = S.compound_tray(4, seed=0)
+    assert ms.ms_query_batch_bytes(sc) > 0
+
+    def rejected(mutate, code=ms.MS_E_INVALID_ARG):
+        bad = S.compound_tray(4, seed=0)
+        mutate(bad)
+        with pytest.raises(ms.MsError) as e:
+            ms.ms_query_batch_bytes(bad)
+        assert e.value.code == code
+
+    comp = np.nonzero(sc.bodies["shape"] == S.COMPOUND)[0][0]
+
+    def index(v):
+        def f(s):
+            s.bodies["dims"][comp, 0] = v
+        return f
+    rejected(index(float(len(sc.compounds))))
+    rejected(index(-1.0))
+    rejected(index(1.5))
+
+    def table(f):
+        def g(s):
+            s.compounds = s.compounds.copy()
+            f(s.compounds)
+        return g
+    rejected(table(lambda c: c["n_children"].__setitem__(0, 5)))
+    rejected(table(lambda c: c["n_children"].__setitem__(0, 0)))
+    rejected(table(lambda c: c["shape"].__setitem__((0, 0), 3)))
+    rejected(table(lambda c: c["pose"].__setitem__((0, 0, 3), 0.9)))       # quaternion not unit
+
+    def off_centre(c):
+        c["pose"][0, 0, 0] += 0.01                                          # centre of mass moves
+    rejected(table(off_centre))
+
+    def tilted(c):
+        # two boxes on a diagonal: centre at the origin, products of inertia nonzero
+        c[0] = S.compound_record([(S.BOX, (0.02, 0.01, 0.01), (0.03, 0.03, 0.0), (1.0, 0.0, 0.0, 0.0)),
+                                  (S.BOX, (0.02, 0.01, 0.01), (-0.03, -0.03, 0.0), (1.0, 0.0, 0.0, 0.0))])
+    rejected(table(tilted))
+    # a compound body in a scene without a table
+    nt = S.compound_tray(4, seed=0)
+    nt.compounds = nt.compounds[:0]
+    with pytest.raises(ms.MsError):
+        ms.ms_query_batch_bytes(nt)
