@@ -447,6 +447,10 @@ def main():
         _, _, res = run_workload(ms, S, "cartpole", 4096, 200, 20, 2, args.seed, settle_steps=args.settle,
                                  targets=S.cartpole_targets(args.seed, ids, 0))
         extra["cartpole"] = res
+        # compound bodies: the tray with about half of its 12 objects made of 2-3 primitive parts
+        _, _, res = run_workload(ms, S, "compound_tray", 4096, 100, 20, 1, args.seed, tune=True,
+                                 settle_steps=args.settle)
+        extra["compound_tray"] = res
         # the headline workload with the cross-step contact cache, and with the contact-force readout
         _, _, res = run_workload(ms, S, args.workload, args.envs, 100, 20, 1, args.seed, settle_steps=args.settle,
                                  warm_start=True)

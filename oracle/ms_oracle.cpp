@@ -1027,13 +1027,30 @@ template <class T> struct Stepper {
         }
         return C.n;
     }
+    // The midphase of compound pairs, in the pair frame: boxes of two parts grown by the contact
+    // offset overlap on every axis, or a part's grown box reaches the ground at z = 0 (add,
+    // subtract, multiply, abs and compare only, as in the broadphase).
+    static bool part_boxes_meet(const Shape<T>& A, const Shape<T>& B, T delta) {
+        for (int r = 0; r < 3; ++r) {
+            const T ha = part_half(A.type, A.d, A.R, r) + delta, hb = part_half(B.type, B.d, B.R, r) + delta;
+            const T ca = get(A.c, r), cb = get(B.c, r);
+            if (!(ca - ha <= cb + hb && cb - hb <= ca + ha)) return false;
+        }
+        return true;
+    }
+    static bool part_box_reaches_plane(const Shape<T>& B, T delta) {
+        return B.c.z - (part_half(B.type, B.d, B.R, 2) + delta) <= T(0);
+    }
+
     // Contact points of a pair with a compound body (a = -1: the ground plane; B's centre at cB):
-    // every pair of parts, A's parts outer, through the primitive narrowphase, each reduced to at
-    // most 4 points: one point set per pair of parts, each becoming its own manifold (its own
-    // friction patch: parts of one compound may touch a body from opposite sides).  Returns the
-    // number of part pairs; the decision code (in o[0]) is 64 + the index of the first part pair
-    // that produced points (63: none) and the margin the smallest over all; every part pair
-    // counts as a candidate of its primitive kind.
+    // every pair of parts, A's parts outer, whose boxes meet (the broadphase's rule at the level
+    // of parts: boxes grown by the contact offset overlap, or reach the ground), through the
+    // primitive narrowphase, each reduced to at most 4 points: one point set per pair of parts,
+    // each becoming its own manifold (its own friction patch: parts of one compound may touch a
+    // body from opposite sides).  Returns the number of part pairs; the decision code (in o[0])
+    // is 64 + the index of the first part pair that produced points (63: none) and the margin
+    // the smallest over the tested pairs; every tested pair counts as a candidate of its
+    // primitive kind.
     int compound_narrow(Out<T>* o, int a, int b, V3<T> cB, T delta, int64_t* cnt) const {
         Shape<T> pa[MAX_CHILDREN], pb[MAX_CHILDREN];
         const int na = a >= 0 ? parts(a, mk<T>(0, 0, 0), pa) : 1;
@@ -1043,6 +1060,7 @@ template <class T> struct Stepper {
         for (int i = 0; i < na; ++i)
             for (int j = 0; j < nb; ++j, ++idx) {
                 Out<T>& o2 = o[idx];
+                if (!(a < 0 ? part_box_reaches_plane(pb[j], delta) : part_boxes_meet(pa[i], pb[j], delta))) continue;
                 if (a < 0) {
                     narrow_plane(o2, T(0), pb[j], delta);
                     cnt[CNT_KIND0 + 9 + pb[j].type]++;

@@ -2302,6 +2302,26 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
     }
 }
 
+// The midphase of compound pairs, in the pair frame: the boxes of two parts grown by the contact
+// offset overlap on every axis, or a part's grown box reaches the ground at z = 0 (exact: the
+// same additions, products, abs and compares as the broadphase, so both sides test alike).
+__device__ __forceinline__ float part_half_axis(const Shp& s, int r) {
+    return prim_half(s.type, s.d[0], s.d[1], s.d[2], s.R.m[r][0], s.R.m[r][1], s.R.m[r][2]);
+}
+__device__ __forceinline__ bool part_boxes_meet(const Shp& A, const Shp& B, float delta) {
+    bool meet = true;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float ha = part_half_axis(A, r) + delta, hb = part_half_axis(B, r) + delta;
+        const float ca = comp(A.c, r), cb = comp(B.c, r);
+        meet = meet && (ca - ha <= cb + hb) && (cb - hb <= ca + ha);
+    }
+    return meet;
+}
+__device__ __forceinline__ bool part_box_reaches_plane(const Shp& B, float delta) {
+    return B.c.z - (part_half_axis(B, 2) + delta) <= 0.0f;
+}
+
 // Whether any candidate of the chunk (lane's candidate `code`) involves a compound body; wave-
 // uniform (one ballot), so every lane of the wave takes the same narrowphase path.
 __device__ __forceinline__ bool compound_chunk_p(const EnvCtx& c, int code) {
@@ -2313,100 +2333,161 @@ __device__ __forceinline__ bool compound_chunk_p(const EnvCtx& c, int code) {
     return __ballot(cc) != 0;
 }
 
+// The box of part k of body i (pair frame, body centre at `centre`): the part's centre and its
+// half size along each axis grown by the contact offset.
+__device__ __forceinline__ void part_box(const EnvCtx& c, int i, int k, V3 centre, float delta, V3& pc, V3& ph) {
+    const Shp s = part_of(c, i, k, centre);
+    pc = s.c;
+    ph = v3(part_half_axis(s, 0) + delta, part_half_axis(s, 1) + delta, part_half_axis(s, 2) + delta);
+}
+__device__ __forceinline__ bool boxes_meet(V3 ca, V3 ha, V3 cb, V3 hb) {
+    return (ca.x - ha.x <= cb.x + hb.x) && (cb.x - hb.x <= ca.x + ha.x) && (ca.y - ha.y <= cb.y + hb.y) &&
+           (cb.y - hb.y <= ca.y + ha.y) && (ca.z - ha.z <= cb.z + hb.z) && (cb.z - hb.z <= ca.z + ha.z);
+}
+
 // S3 + S4 for a chunk in which some candidate involves a compound body (lane per candidate, code
-// < 0: none).  Every pair of parts (A's parts outer; a ground pair pairs the plane with each part
-// of its body) runs the primitive narrowphase and keeps <= 4 points as a manifold of its own;
-// a primitive pair is the one pair of its two bodies.  Two passes: the first counts each
-// candidate's points and manifolds before the capacity rule, whose scan over the lanes places
-// every pair of parts in canonical order (candidate, then part pair); the second recomputes
-// each pair of parts and writes its rows.  A pair of parts with `pre` points and `mpre`
-// manifolds before it in the env keeps min(n, cap - pre) points if mpre < mcap, else none: the
-// sequential capacity rule (kept pairs are exactly the earlier pairs' full lists).
+// < 0: none).  The candidates expand into items, one per pair of parts (A's parts outer; a
+// ground pair pairs the plane with each part of its body) whose grown boxes meet, a primitive
+// pair being the one item of its candidate; the items, in this order, are the canonical order
+// of the chunk's manifolds.  Phase A: each lane tests its candidate's pairs of parts (a bit
+// mask), a scan over the lanes gives each candidate the offset of its first item.  Phase B:
+// rounds of G items, item r G + l on lane l, which finds its candidate by a binary search over
+// the lanes' offsets and its pair of parts as a set bit of the mask; then each item runs the
+// primitive narrowphase and keeps <= 4 points as a manifold of its own under the same capacity
+// rule and scans as a chunk of primitive candidates.
 __device__ __forceinline__ void compound_chunk(const EnvCtx& c, int code, int k, int& npts, int& nman, bool& overflow,
                                                int li, int g, int G, bool dbg, int dpp, int dpo, int dmo) {
     const Lay& l = c.lay;
     const BatchDev& bd = *c.bd;
     const int n = l.n;
-    int a = 0, b = 0, np = 0, nb = 1;
-    bool plane = false, comp = false;
-    V3 base = v3(0, 0, 0), offB = v3(0, 0, 0);
+    const float delta = bd.delta;
+    // ---- phase A: the item mask of this lane's candidate (bit t: pair of parts t; bit 16: the
+    // candidate involves a compound body)
+    int mask = 0;
     if (code >= 0) {
-        a = code & 0xFF;
-        b = code >> 8;
-        plane = b == n;
-        const V3 xa = ldp3(c, a, P_X0);
-        if (plane) {
-            base = v3(xa.x, xa.y, bd.plane_z);
-            offB = v3(0.0f, 0.0f, xa.z - bd.plane_z);
-            nb = n_parts(c, a);
-            np = nb;
-            comp = is_compound(c, a);
+        const int a = code & 0xFF, b = code >> 8;
+        const bool plane = b == n;
+        const int body = plane ? a : b;   // the side whose parts are listed second
+        const bool comp = is_compound(c, a) || (!plane && is_compound(c, b));
+        if (!comp) {
+            mask = 1;
         } else {
-            base = xa;
-            offB = ldp3(c, b, P_X0) - xa;
-            nb = n_parts(c, b);
-            np = n_parts(c, a) * nb;
-            comp = is_compound(c, a) || is_compound(c, b);
+            const V3 xa = ldp3(c, a, P_X0);
+            const V3 offB = plane ? v3(0.0f, 0.0f, xa.z - bd.plane_z) : ldp3(c, b, P_X0) - xa;
+            const int nb = n_parts(c, body);
+            const int na = plane ? 1 : n_parts(c, a);
+            V3 bc[MAX_PARTS], bh[MAX_PARTS];
+#pragma unroll
+            for (int j = 0; j < MAX_PARTS; ++j) {
+                bc[j] = v3(0, 0, 0);
+                bh[j] = v3(0, 0, 0);
+                if (j < nb) part_box(c, body, j, offB, delta, bc[j], bh[j]);
+            }
+            if (plane) {
+#pragma unroll
+                for (int j = 0; j < MAX_PARTS; ++j)
+                    if (j < nb && bc[j].z - bh[j].z <= 0.0f) mask |= 1 << j;
+            } else {
+#pragma unroll
+                for (int i = 0; i < MAX_PARTS; ++i) {
+                    if (i >= na) continue;
+                    V3 ac, ah;
+                    part_box(c, a, i, v3(0, 0, 0), delta, ac, ah);
+#pragma unroll
+                    for (int j = 0; j < MAX_PARTS; ++j)
+                        if (j < nb && boxes_meet(ac, ah, bc[j], bh[j])) mask |= 1 << (i * nb + j);
+                }
+            }
+            mask |= 1 << 16;
+        }
+        if (dbg) {
+            int* dp = bd.dbg_pairs + 4 * size_t(dpp + k);
+            dp[0] = a; dp[1] = plane ? PLANE : b; dp[2] = 0; dp[3] = comp ? 0x7FFFFFFF : 0;
         }
     }
-    int* SC = iptr(c.L + l.SCAL);
-    int rawp = 0, rawm = 0, hit = -1, dec = 0, kept = 0, keptm = 0;
-    int P = 0, M = 0;
-    bool ovf = false;
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll 1
-        for (int t = 0; t < np; ++t) {
-            const int i = t / nb, j = t - i * nb;
-            NOut o;
-            o.mask = 0;
-            o.decision = 0;
+    int T;
+    const int off = group_scan_small<5>(__popc(mask & 0xFFFF), li, g, G, T);
+    // ---- phase B: rounds of G items
+    const int rounds = wave_max((T + G - 1) / G);
+    const int lane0 = g * G;   // first lane of this lane's group
+    for (int r = 0; r < rounds; ++r) {
+        const int item = r * G + li;
+        // owner: the last lane of the group whose first item is <= item (lanes without items
+        // share their successor's offset, so the last such lane is the one holding the item)
+        int j = 0;
+        for (int step = G >> 1; step >= 1; step >>= 1) {
+            const int o = __shfl(off, lane0 + j + step);
+            if (o <= item) j += step;
+        }
+        const int ocode = __shfl(code, lane0 + j);
+        const int omask = __shfl(mask, lane0 + j);
+        const int ooff = __shfl(off, lane0 + j);
+        const int ok = __shfl(k, lane0 + j);
+        const bool valid = item < T;
+        NOut o;
+        o.mask = 0;
+        o.decision = 0;
+        int a = 0, b = 0, t = 0;
+        bool plane = false;
+        V3 base = v3(0, 0, 0), offB = v3(0, 0, 0);
+        if (valid) {
+            int m = omask & 0xFFFF;
+            for (int q = item - ooff; q > 0; --q) m &= m - 1;
+            t = __ffs(m) - 1;
+            a = ocode & 0xFF;
+            b = ocode >> 8;
+            plane = b == n;
+            const V3 xa = ldp3(c, a, P_X0);
             if (plane) {
-                const Shp sb = part_of(c, a, j, offB);
-                if (pass == 0) atomicAdd(&SC[16 + STAT_KIND0 + 9 + sb.type], 1);
-                np_plane(o, sb, bd.delta);
+                base = v3(xa.x, xa.y, bd.plane_z);
+                offB = v3(0.0f, 0.0f, xa.z - bd.plane_z);
+                const Shp sb = part_of(c, a, t, offB);
+                atomicAdd(&iptr(c.L + l.SCAL)[16 + STAT_KIND0 + 9 + sb.type], 1);
+                np_plane(o, sb, delta);
             } else {
-                const Shp sa = part_of(c, a, i, v3(0, 0, 0));
-                const Shp sb = part_of(c, b, j, offB);
-                if (pass == 0) atomicAdd(&SC[16 + STAT_KIND0 + 3 * min(sa.type, sb.type) + max(sa.type, sb.type)], 1);
-                np_pair(o, sa, sb, bd.delta);
-            }
-            if (pass == 0) {
-                const int on = min(n_points(o), 4);   // the reduction keeps min(n, 4) points
-                rawp += on;
-                rawm += on > 0 ? 1 : 0;
-                if (on > 0 && hit < 0) hit = t;
-                if (t == 0) dec = o.decision;
-                continue;
+                base = xa;
+                offB = ldp3(c, b, P_X0) - xa;
+                const int nb = n_parts(c, b);
+                const int ia = t / nb;
+                const Shp sa = part_of(c, a, ia, v3(0, 0, 0));
+                const Shp sb = part_of(c, b, t - ia * nb, offB);
+                atomicAdd(&iptr(c.L + l.SCAL)[16 + STAT_KIND0 + 3 * min(sa.type, sb.type) + max(sa.type, sb.type)], 1);
+                np_pair(o, sa, sb, delta);
             }
             reduce4(o);
             compact4(o);
-            const int on = n_points(o);
-            if (on == 0) continue;
-            const int keep = M >= l.mcap ? 0 : min(max(l.cap - P, 0), on);
-            if (keep < on) ovf = true;
-            if (keep > 0) write_rows(c, o, k, a, b, plane, base, offB, keep, P, M, t, dbg, dpo, dmo);
-            P += on;
-            M += 1;
-            kept += keep;
-            keptm += keep > 0 ? 1 : 0;
         }
-        if (pass == 0) {
-            int tot;
-            P = npts + group_scan_small<7>(rawp, li, g, G, tot);
-            M = nman + group_scan_small<5>(rawm, li, g, G, tot);
+        const int on = n_points(o);   // 0 for an invalid item
+        int tot;
+        const int pre = group_scan_small<3>(on, li, g, G, tot);
+        int keep = min(max(l.cap - (npts + pre), 0), on);
+        bool ovf = keep < on;
+        int mtot;
+        const int mpre = group_scan_small<1>(keep > 0 ? 1 : 0, li, g, G, mtot);
+        if (keep > 0 && nman + mpre >= l.mcap) { keep = 0; ovf = true; }
+        int ktot;
+        const int kpre = group_scan_small<3>(keep, li, g, G, ktot);
+        overflow |= group_bits(__ballot(ovf), g, G) != 0;
+        if (keep > 0) write_rows(c, o, ok, a, b, plane, base, offB, keep, npts + kpre, nman + mpre, t, dbg, dpo, dmo);
+        if (valid && dbg) {
+            int* dp = bd.dbg_pairs + 4 * size_t(dpp + ok);
+            if (keep > 0) atomicAdd(dp + 2, keep);
+            if (omask >> 16) {
+                if (on > 0) atomicMin(dp + 3, 64 + t);
+            } else {
+                dp[3] = o.decision;
+            }
         }
+        npts += ktot;
+        int mkept;
+        group_scan_small<1>(keep > 0 ? 1 : 0, li, g, G, mkept);
+        nman += mkept;
     }
-    overflow |= group_bits(__ballot(ovf), g, G) != 0;
-    if (code >= 0 && dbg) {
-        int* dp = bd.dbg_pairs + 4 * size_t(dpp + k);
-        dp[0] = a; dp[1] = plane ? PLANE : b; dp[2] = kept; dp[3] = comp ? (hit < 0 ? 63 : 64 + hit) : dec;
+    if (dbg && code >= 0 && (mask >> 16)) {
+        // a compound candidate without points: decision 63 (the debug export only)
+        __threadfence();
+        atomicCAS(bd.dbg_pairs + 4 * size_t(dpp + k) + 3, 0x7FFFFFFF, 63);
     }
-    int ktot, mtot;
-    group_scan_small<7>(kept, li, g, G, ktot);
-    group_scan_small<5>(keptm, li, g, G, mtot);
-    npts += ktot;
-    nman += mtot;
 }
 
 }  // namespace

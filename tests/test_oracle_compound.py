@@ -137,6 +137,24 @@ def world_parts(rec, pos, quat):
     return out
 
 
+def part_box(part, delta):
+    sh, d, pose = part
+    rot = Rotation.from_quat([pose[4], pose[5], pose[6], pose[3]]).as_matrix()
+    if sh == S.BOX:
+        half = np.abs(rot) @ d[:3]
+    elif sh == S.SPHERE:
+        half = np.full(3, d[0])
+    else:
+        half = np.abs(rot[:, 2]) * d[1] + d[0]
+    return pose[:3] - half - delta, pose[:3] + half + delta
+
+
+def boxes_meet(x, y, delta):
+    lx, hx = part_box(x, delta)
+    ly, hy = part_box(y, delta)
+    return bool(np.all(lx <= hy) and np.all(ly <= hx))
+
+
 def sorted_rows(a):
     a = np.round(np.asarray(a, np.float64), 5)
     return a[np.lexsort(a.T[::-1])] if len(a) else a.reshape(0, 6)
@@ -192,6 +210,12 @@ def test_compound_contacts_are_those_of_the_part_pairs(seed):
     np.testing.assert_allclose(sorted_rows(got), sorted_rows(want), atol=1e-6)
     # one manifold (solver block of kind 1) per part pair with points
     assert np.sum(r["blocks"][:, 1] == 1) == len(pts)
+    # the midphase: exactly the pairs of parts whose boxes grown by the contact offset overlap
+    # are tested (counted per shape kind)
+    c, _ = o.counters()
+    wa, wb = world_parts(ra, pa, qa), world_parts(rb, pb, qb)
+    assert c[0, 8:20].sum() == sum(boxes_meet(x, y, delta) for x in wa for y in wb)
+    assert c[0, 8:20].sum() < len(wa) * len(wb) or len(wa) * len(wb) == 1
 
 
 def dumbbell_scene(warm=0):
