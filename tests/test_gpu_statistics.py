@@ -6,14 +6,15 @@ Kolmogorov-Smirnov test (p > 0.01) and a difference of means within 3 standard e
 may overflow its contact or colour capacity, and the number of envs that stay bit-identical is
 reported and bounded below.  Workloads at their own lengths: one box per env (200 steps), the
 7-link arm with targets redrawn every 50 steps (1000 steps), the tray of 20 bodies (500 steps),
-the heterogeneous batch (500 steps); 512 envs each.  Plus a scene that overflows the 64
+the heterogeneous batch (500 steps), the tray of 12 objects about half of them compound bodies
+(500 steps); 512 envs each.  Plus a scene that overflows the 64
 parallel colours, against the oracle."""
 import numpy as np
 import pytest
 from scipy import stats
 from scipy.spatial.transform import Rotation
 
-from oracle.oracle import Oracle, mass_props
+from oracle.oracle import Oracle, compound_mass_props, mass_props
 from paper_2410_00425_amd import scenes as S
 
 from parity import compare_states
@@ -38,9 +39,15 @@ def mass_inertia(sc):
         if bd["flags"][i] & 1:
             continue
         dims = bd["dims"][i].astype(np.float64)
-        vol, _ = mass_props(int(bd["shape"][i]), dims, 1.0)
-        mi = float(bd["mass"][i]) if bd["mass"][i] > 0 else float(bd["density"][i]) * vol
-        _, inertia[i] = mass_props(int(bd["shape"][i]), dims, mi)
+        if bd["shape"][i] == S.COMPOUND:
+            rec = sc.compounds[int(dims[0])]
+            vol, _ = compound_mass_props(rec, 1.0)
+            mi = float(bd["mass"][i]) if bd["mass"][i] > 0 else float(bd["density"][i]) * vol
+            _, inertia[i] = compound_mass_props(rec, mi)
+        else:
+            vol, _ = mass_props(int(bd["shape"][i]), dims, 1.0)
+            mi = float(bd["mass"][i]) if bd["mass"][i] > 0 else float(bd["density"][i]) * vol
+            _, inertia[i] = mass_props(int(bd["shape"][i]), dims, mi)
         m[i] = mi
     return m, inertia
 
@@ -106,6 +113,7 @@ def run_both(name, steps, chunk=10, redraw_every=0, seed=5):
     ("arm_cube", 1000, 50, 0.5),
     ("tray", 500, 0, 0.25),
     ("hetero", 500, 0, 0.5),
+    ("compound_tray", 500, 0, 0.5),
 ])
 def test_full_length_statistics(name, steps, redraw, min_same):
     print(f"stats: {name} x {N_ENVS}, {steps} steps", flush=True)
@@ -123,7 +131,7 @@ def test_full_length_statistics(name, steps, redraw, min_same):
     assert same >= min_same * sc.n_envs, f"{same}/{sc.n_envs} bit-identical"
     dyn = (sc.bodies["flags"] & 1) == 0
     # final COM height by shape
-    for shape, label in ((S.SPHERE, "sphere"), (S.CAPSULE, "capsule"), (S.BOX, "box")):
+    for shape, label in ((S.SPHERE, "sphere"), (S.CAPSULE, "capsule"), (S.BOX, "box"), (S.COMPOUND, "compound")):
         sel = dyn & (sc.bodies["shape"] == shape)
         if sel.sum() > 1:
             same_distribution(g["pos"][2, sel], w["pos"][2, sel], f"{name} final z ({label})")
