@@ -2376,27 +2376,21 @@ __device__ __forceinline__ void compound_chunk(const EnvCtx& c, int code, int k,
             const V3 offB = plane ? v3(0.0f, 0.0f, xa.z - bd.plane_z) : ldp3(c, b, P_X0) - xa;
             const int nb = n_parts(c, body);
             const int na = plane ? 1 : n_parts(c, a);
-            V3 bc[MAX_PARTS], bh[MAX_PARTS];
-#pragma unroll
-            for (int j = 0; j < MAX_PARTS; ++j) {
-                bc[j] = v3(0, 0, 0);
-                bh[j] = v3(0, 0, 0);
-                if (j < nb) part_box(c, body, j, offB, delta, bc[j], bh[j]);
-            }
-            if (plane) {
-#pragma unroll
-                for (int j = 0; j < MAX_PARTS; ++j)
-                    if (j < nb && bc[j].z - bh[j].z <= 0.0f) mask |= 1 << j;
-            } else {
-#pragma unroll
-                for (int i = 0; i < MAX_PARTS; ++i) {
-                    if (i >= na) continue;
+            // one box of each side at a time (the parts' records stay in the caches), so that
+            // the test holds few registers
+            for (int t = 0; t < na * nb; ++t) {
+                const int i = t / nb, j = t - i * nb;
+                V3 bc, bh;
+                part_box(c, body, j, offB, delta, bc, bh);
+                bool meet;
+                if (plane) {
+                    meet = bc.z - bh.z <= 0.0f;
+                } else {
                     V3 ac, ah;
                     part_box(c, a, i, v3(0, 0, 0), delta, ac, ah);
-#pragma unroll
-                    for (int j = 0; j < MAX_PARTS; ++j)
-                        if (j < nb && boxes_meet(ac, ah, bc[j], bh[j])) mask |= 1 << (i * nb + j);
+                    meet = boxes_meet(ac, ah, bc, bh);
                 }
+                if (meet) mask |= 1 << t;
             }
             mask |= 1 << 16;
         }
@@ -2865,11 +2859,11 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
                 for (int ch = 0; ch < nch; ++ch) {
                     int k = ch * G + li;
                     if constexpr (COMP) {
+                        // the compound build has the one narrowphase path of part-pair items
+                        // (a chunk without compounds is one item per candidate)
                         const int code = k < ncand ? int(CAND[k]) : -1;
-                        if (compound_chunk_p(c, code)) {
-                            compound_chunk(c, code, k, npts, nman, overflow, li, g, G, dbg, dpp, dpo, dmo);
-                            continue;
-                        }
+                        compound_chunk(c, code, k, npts, nman, overflow, li, g, G, dbg, dpp, dpo, dmo);
+                        continue;
                     }
                     NOut o;
                     int a = 0, b = 0;

@@ -586,8 +586,9 @@ def compound_tray(n_envs: int = 4096, seed: int = 0, n_objects: int = 12, first_
     bodies = np.concatenate([objs, np.broadcast_to(tray_walls(), (n_envs, 4))], axis=1).reshape(-1)
     nb = n_objects + 4
     # a pair of compounds yields up to 9 manifolds (one per pair of parts): capacities above the
-    # defaults for 12 dynamic bodies (80 points, 40 manifolds)
-    params = make_params(dt=0.005, pos_iters=8, max_contacts_per_env=192, max_manifolds_per_env=64)
+    # defaults for 12 dynamic bodies (80 points, 40 manifolds), at the most that keeps an env
+    # within 20,480 bytes of LDS (8 envs per CU)
+    params = make_params(dt=0.005, pos_iters=8, max_contacts_per_env=164, max_manifolds_per_env=64)
     return Scene("compound_tray", params, np.arange(n_envs + 1, dtype=np.int32) * nb,
                  bodies, np.zeros(n_envs + 1, dtype=np.int32), np.zeros(0, JOINT_DTYPE),
                  dict(seed=seed, steps=500, n_objects=n_objects), lib)
