@@ -169,3 +169,51 @@ def test_compound_warm_start_and_forces_match_oracle():
     assert np.array_equal(f[:, ok], fo[:, ok])
     assert np.abs(f[2]).max() > 0.1
     b.close()
+
+
+def test_compound_batch_in_fused_and_served_steps():
+    """A compound batch fused with primitive batches (ms_step_many, its no-allocation form) and
+    served in a mix (ms_server) gives the same bits as stepped alone."""
+    print("compound: fused and served", flush=True)
+    import threading
+    m = ms()
+    scs = [S.compound_tray(48, seed=14), S.tray(32, seed=15), S.drop_boxes(40, seed=16)]
+
+    def alone(sc, steps):
+        b = m.Batch(sc)
+        b.step(steps)
+        st = b.state_numpy()
+        b.close()
+        return st
+
+    refs = [alone(sc, 6) for sc in scs]
+    for fn in (m.step_many, m.step_many_noalloc):
+        bs = [m.Batch(sc) for sc in scs]
+        for _ in range(3):
+            fn(bs, 2)
+        torch.cuda.synchronize()
+        for b, ref in zip(bs, refs):
+            st = b.state_numpy()
+            for k in FIELDS + ("status",):
+                assert np.array_equal(st[k], ref[k]), (fn.__name__, b.scene.name, k)
+            b.close()
+    srv = m.Server(128 << 20)
+    sids = [srv.open(sc) for sc in scs]
+
+    def drive(s):
+        for _ in range(3):
+            srv.wait(srv.submit(s, 2))
+
+    th = [threading.Thread(target=drive, args=(s,)) for s in sids]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    got = [srv.get_state(s) for s in sids]
+    for s in sids:
+        srv.close_session(s)
+    srv.drain()
+    srv.close()
+    for g, ref in zip(got, refs):
+        for k in FIELDS + ("status",):
+            assert np.array_equal(g[k], ref[k]), ("served", k)
