@@ -217,3 +217,58 @@ def test_compound_batch_in_fused_and_served_steps():
     for g, ref in zip(got, refs):
         for k in FIELDS + ("status",):
             assert np.array_equal(g[k], ref[k]), ("served", k)
+
+
+def test_articulated_compound_matches_oracle():
+    """Compound bodies on joints: a dumbbell pendulum swinging through two spheres, and the arm
+    with its cube replaced by a bench compound; bit for bit against the oracle."""
+    print("compound: on joints", flush=True)
+    import math
+    rec = S.dumbbell(0.03, 0.1, 0.01)
+    qy = (math.sqrt(0.5), -math.sqrt(0.5), 0.0, 0.0)
+    envs = []
+    for e in range(16):
+        th0 = 0.4 + 0.05 * e
+        d = 0.3
+        pos = (-d * math.sin(th0), 0.0, 1.0 - d * math.cos(th0))
+        quat = (math.cos(th0 / 2), 0.0, math.sin(th0 / 2), 0.0)
+        bodies = [S.body(S.COMPOUND, (0.0,), pos, quat=quat, mass=1.0),
+                  S.body(S.SPHERE, (0.04,), (0.05, 0.0, 0.62), mass=0.3),
+                  S.body(S.SPHERE, (0.03,), (0.12, 0.01, 0.66), mass=0.2)]
+        envs.append(np.concatenate(bodies))
+    joints = [S.joint(-1, 0, (0.0, 0.0, 1.0) + qy, (0.0, 0.0, 0.3) + qy, kd=0.01)] * 16
+    p = S.make_params(dt=0.005, pos_iters=8, plane_enabled=0)
+    sc = S.concat_envs("compound_pendulum", p, envs, joints, {})
+    sc.compounds = np.array([rec], dtype=S.COMPOUND_DTYPE)
+    # the arm, its cube a bench and its last link a dumbbell (the capsule link with a sphere at
+    # each end), both compounds
+    arm = S.arm_cube(8, seed=17)
+    cube = np.nonzero(arm.bodies["shape"] == S.BOX)[0]
+    recs = [S.bench(0.03, 0.02, 0.004, 0.004, 0.012)]
+    arm.bodies["shape"][cube] = S.COMPOUND
+    arm.bodies["dims"][cube] = 0.0
+    arm.bodies["mass"][cube] = 0.2
+    last = cube - 1
+    assert np.all(arm.bodies["shape"][last] == S.CAPSULE)
+    for e, i in enumerate(last):
+        r, hl = float(arm.bodies["dims"][i][0]), float(arm.bodies["dims"][i][1])
+        recs.append(S.dumbbell(1.2 * r, hl, r))
+        arm.bodies["shape"][i] = S.COMPOUND
+        arm.bodies["dims"][i] = (float(e + 1), 0.0, 0.0)
+    arm.compounds = np.array(recs, dtype=S.COMPOUND_DTYPE)
+    tg = S.arm_targets(17, np.arange(8), 1).reshape(-1)
+    for scene, targets in ((sc, None), (arm, tg)):
+        b = ms().Batch(scene)
+        o = Oracle(scene, 32)
+        t = None
+        if targets is not None:
+            o.set_targets(targets)
+            t = torch.from_numpy(targets).cuda()
+        for _ in range(4):
+            b.step(50, t)
+            o.step(50)
+        g, w = b.state_numpy(), o.state()
+        same = same_envs(scene, g, w)
+        assert same.all(), (scene.name, np.nonzero(~same)[0])
+        assert np.array_equal(g["status"], w["status"])
+        b.close()

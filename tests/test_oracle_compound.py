@@ -280,3 +280,43 @@ def test_compound_tray_runs_within_capacity():
     assert np.all(st["status"] == 0)
     dyn = (sc.bodies["flags"] & 1) == 0
     assert st["pos"][2, dyn].min() > 0.0
+
+
+def compound_pendulum(prec_dt=0.01, th0=0.05, d=0.3):
+    """A dumbbell (end spheres on its body z axis) hung d below a world revolute joint about the
+    body's y axis, released at th0."""
+    import math
+    rec = S.dumbbell(0.03, 0.1, 0.01)
+    qy = (math.sqrt(0.5), -math.sqrt(0.5), 0.0, 0.0)
+    piv = (0.0, 0.0, 1.0)
+    pos = (-d * math.sin(th0), 0.0, piv[2] - d * math.cos(th0))
+    quat = (math.cos(th0 / 2), 0.0, math.sin(th0 / 2), 0.0)
+    b = S.body(S.COMPOUND, (0.0,), pos, quat=quat, mass=1.0)
+    sc = S.single([b], [S.joint(-1, 0, piv + qy, (0.0, 0.0, d) + qy)], dt=prec_dt, pos_iters=4, plane_enabled=0)
+    return with_compounds(sc, [rec]), rec
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_compound_pendulum_period(prec):
+    # small-angle physical pendulum: T0 = 2 pi sqrt((I_yy / m + d^2) / (g d)) with the compound's
+    # moment about its y axis (finite-amplitude factor 1.00016 at 0.05 rad); the end spheres on
+    # the hanging axis make I_yy / m several times a solid sphere's, so a solver that used a wrong
+    # moment (a primitive's, the x one of a rotated frame) misses by far more than 0.5 %
+    import math
+    d = 0.3
+    sc, rec = compound_pendulum(d=d)
+    _, I = compound_mass_props(rec, 1.0)
+    o = Oracle(sc, prec)
+    xs = []
+    for _ in range(800):
+        o.step(1)
+        xs.append(o.state()["pos"][0, 0])
+    xs = np.array(xs)
+    down = np.nonzero((xs[:-1] > 0) & (xs[1:] <= 0))[0]
+    tc = [(k + xs[k] / (xs[k] - xs[k + 1])) * 0.01 for k in down]
+    T = (tc[4] - tc[0]) / 4
+    T0 = 2 * math.pi * math.sqrt((I[1] + d * d) / (G * d)) * 1.00016
+    assert T == pytest.approx(T0, rel=0.005)
+    # the moment matters: with I_yy replaced by a 0.03 m sphere's the period would differ by > 3 %
+    T_sphere = 2 * math.pi * math.sqrt((0.4 * 0.03 ** 2 + d * d) / (G * d))
+    assert abs(T_sphere / T0 - 1.0) > 0.03
