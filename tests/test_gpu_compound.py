@@ -272,3 +272,33 @@ def test_articulated_compound_matches_oracle():
         assert same.all(), (scene.name, np.nonzero(~same)[0])
         assert np.array_equal(g["status"], w["status"])
         b.close()
+
+
+def test_static_compounds_pgs_and_restitution():
+    """Static compound obstacles (benches as tables) under falling primitives and compounds, with
+    the PGS solver, velocity iterations and restitution; one step from oracle states and a run."""
+    print("compound: static compounds, PGS, restitution", flush=True)
+    sc = S.compound_tray(48, seed=18)
+    # the first object of every env becomes a static compound table
+    first = sc.body_off[:-1]
+    sc.bodies["shape"][first] = S.COMPOUND
+    sc.bodies["dims"][first] = (float(len(sc.compounds)), 0.0, 0.0)
+    sc.bodies["flags"][first] = 1
+    sc.bodies["pos"][first] = (0.0, 0.0, 0.03)
+    sc.bodies["quat"][first] = (1.0, 0.0, 0.0, 0.0)
+    sc.compounds = np.concatenate([sc.compounds, np.array([S.bench(0.1, 0.08, 0.008, 0.01, 0.02)],
+                                                          dtype=S.COMPOUND_DTYPE)])
+    sc.params["solver"] = S.PGS
+    sc.params["vel_iters"] = 2
+    sc.bodies["restitution"] = 0.3
+    one_step_parity(sc, oracle_state(sc, 100), max_excused=1)
+    b = ms().Batch(sc)
+    o = Oracle(sc, 32)
+    b.step(150)
+    o.step(150, n_threads=16)
+    g, w = b.state_numpy(), o.state()
+    same = same_envs(sc, g, w)
+    assert same.mean() >= 0.75, same.sum()
+    # the tables did not move
+    assert np.array_equal(g["pos"][:, first], sc.bodies["pos"][first].T)
+    b.close()
