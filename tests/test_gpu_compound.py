@@ -302,3 +302,43 @@ def test_static_compounds_pgs_and_restitution():
     # the tables did not move
     assert np.array_equal(g["pos"][:, first], sc.bodies["pos"][first].T)
     b.close()
+
+
+def four_part_scene(n_envs=32, seed=19):
+    """Pairs of 4-part compounds (two spheres on x, two capsules on y: 16 pairs of parts per
+    body pair, the most a candidate expands to) thrown at each other above the ground."""
+    rec = S.compound_record([(S.SPHERE, (0.025,), (0.05, 0.0, 0.0), (1.0, 0.0, 0.0, 0.0)),
+                             (S.SPHERE, (0.025,), (-0.05, 0.0, 0.0), (1.0, 0.0, 0.0, 0.0)),
+                             (S.CAPSULE, (0.015, 0.03), (0.0, 0.05, 0.0), (1.0, 0.0, 0.0, 0.0)),
+                             (S.CAPSULE, (0.015, 0.03), (0.0, -0.05, 0.0), (1.0, 0.0, 0.0, 0.0))])
+    rng = np.random.default_rng(seed)
+    envs = []
+    for e in range(n_envs):
+        q = rng.normal(size=(2, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        x = rng.uniform(0.09, 0.12)
+        bodies = [S.body(S.COMPOUND, (0.0,), (-x, 0.0, 0.2), quat=tuple(q[0]), density=800.0, linvel=(0.6, 0.0, 0.0),
+                         angvel=tuple(rng.normal(size=3))),
+                  S.body(S.COMPOUND, (0.0,), (x, 0.01, 0.21), quat=tuple(q[1]), density=800.0, linvel=(-0.6, 0.0, 0.0)),
+                  S.body(S.BOX, (0.05, 0.05, 0.01), (0.0, 0.0, 0.01), mass=1.0)]
+        envs.append(np.concatenate(bodies))
+    sc = S.concat_envs("four_part", S.make_params(dt=0.005, pos_iters=8, max_contacts_per_env=128,
+                                                   max_manifolds_per_env=48),
+                       envs, [np.zeros(0, S.JOINT_DTYPE)] * n_envs, {})
+    sc.compounds = np.array([rec], dtype=S.COMPOUND_DTYPE)
+    return sc
+
+
+def test_four_part_compounds_match_oracle():
+    print("compound: 4-part pairs", flush=True)
+    sc = four_part_scene()
+    for warm in (25, 40, 80):
+        one_step_parity(sc, oracle_state(sc, warm), max_excused=1)
+    b = ms().Batch(sc)
+    o = Oracle(sc, 32)
+    b.step(150)
+    o.step(150)
+    g, w = b.state_numpy(), o.state()
+    assert same_envs(sc, g, w).all()
+    assert np.all(w["status"] == 0)
+    b.close()
