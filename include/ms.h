@@ -307,11 +307,14 @@ ms_status ms_get_sizes(ms_batch* b, int32_t* n_envs, int32_t* n_bodies, int32_t*
  * `hip_stream`).  Per env, in canonical pair order, host_pairs receives int32 records
  * {env, a, b, kept_points, decision} for every candidate pair (b = 0xFFFF is the ground plane;
  * decision is the narrowphase branch: the separating axis for box pairs, the parallel branch for
- * capsule pairs, the inside face for sphere-box).  host_points receives float records
- * {px, py, pz, nx, ny, nz, s0, lambda_n} for every kept point (world frame, normal from A to B,
- * step-start separation, final normal impulse), and host_manifolds float records
- * {env, pair index within the env, colour, lambda_t1, lambda_t2, lambda_twist, mu, r_twist} per
- * manifold.  Buffers may be NULL (counts only); records beyond a *_cap are dropped. */
+ * capsule pairs, the inside face for sphere-box; for a pair with a compound body, kept_points
+ * sums its pairs of parts and decision is 64 + the first pair of parts with points, 63 if none).
+ * host_points receives float records {px, py, pz, nx, ny, nz, s0, lambda_n} for every kept point
+ * (world frame, normal from A to B, step-start separation, final normal impulse), and
+ * host_manifolds float records {env, pair index within the env, colour, lambda_t1, lambda_t2,
+ * lambda_twist, mu, r_twist} per manifold (a compound pair has one manifold per pair of parts
+ * with points, in part order).  Buffers may be NULL (counts only); records beyond a *_cap are
+ * dropped. */
 ms_status ms_get_contacts(ms_batch* b, int32_t* host_pairs, int32_t pairs_cap, float* host_points,
                           int32_t points_cap, float* host_manifolds, int32_t manifolds_cap,
                           int32_t* n_pairs, int32_t* n_points, int32_t* n_manifolds, void* hip_stream);
