@@ -160,6 +160,10 @@ __device__ __forceinline__ void st4(float* L, int off, int n, int i, Qt q) {
 // performed in program order, so lanes that exchange data through LDS between phases need only
 // a wavefront-scope fence, which keeps the compiler from moving memory operations across the
 // phase boundary and costs no wait on the hardware.
+__device__ __forceinline__ int opaque_lane(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -2302,39 +2306,15 @@ __device__ __forceinline__ void write_rows(const EnvCtx& c, const NOut& o, int k
     }
 }
 
-// The midphase of compound pairs, in the pair frame: the boxes of two parts grown by the contact
-// offset overlap on every axis, or a part's grown box reaches the ground at z = 0 (exact: the
-// same additions, products, abs and compares as the broadphase, so both sides test alike).
+// Half size of a part along axis r (add, multiply, abs only, as in the broadphase).
 __device__ __forceinline__ float part_half_axis(const Shp& s, int r) {
     return prim_half(s.type, s.d[0], s.d[1], s.d[2], s.R.m[r][0], s.R.m[r][1], s.R.m[r][2]);
 }
-__device__ __forceinline__ bool part_boxes_meet(const Shp& A, const Shp& B, float delta) {
-    bool meet = true;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const float ha = part_half_axis(A, r) + delta, hb = part_half_axis(B, r) + delta;
-        const float ca = comp(A.c, r), cb = comp(B.c, r);
-        meet = meet && (ca - ha <= cb + hb) && (cb - hb <= ca + ha);
-    }
-    return meet;
-}
-__device__ __forceinline__ bool part_box_reaches_plane(const Shp& B, float delta) {
-    return B.c.z - (part_half_axis(B, 2) + delta) <= 0.0f;
-}
 
-// Whether any candidate of the chunk (lane's candidate `code`) involves a compound body; wave-
-// uniform (one ballot), so every lane of the wave takes the same narrowphase path.
-__device__ __forceinline__ bool compound_chunk_p(const EnvCtx& c, int code) {
-    bool cc = false;
-    if (code >= 0 && c.bd->comp != nullptr) {
-        const int a = code & 0xFF, b = code >> 8;
-        cc = is_compound(c, a) || (b != c.lay.n && is_compound(c, b));
-    }
-    return __ballot(cc) != 0;
-}
-
-// The box of part k of body i (pair frame, body centre at `centre`): the part's centre and its
-// half size along each axis grown by the contact offset.
+// The midphase of compound pairs, in the pair frame: the box of part k of body i (body centre at
+// `centre`), its centre and its half size along each axis grown by the contact offset; two boxes
+// meet when they overlap on every axis, a box reaches the ground when its lowest z is <= 0
+// (the broadphase's rule one level down, with the same exact operations on both sides).
 __device__ __forceinline__ void part_box(const EnvCtx& c, int i, int k, V3 centre, float delta, V3& pc, V3& ph) {
     const Shp s = part_of(c, i, k, centre);
     pc = s.c;
@@ -2345,8 +2325,8 @@ __device__ __forceinline__ bool boxes_meet(V3 ca, V3 ha, V3 cb, V3 hb) {
            (cb.y - hb.y <= ca.y + ha.y) && (ca.z - ha.z <= cb.z + hb.z) && (cb.z - hb.z <= ca.z + ha.z);
 }
 
-// S3 + S4 for a chunk in which some candidate involves a compound body (lane per candidate, code
-// < 0: none).  The candidates expand into items, one per pair of parts (A's parts outer; a
+// S3 + S4 for a chunk of candidates in the compound build (lane per candidate, code < 0: none).
+// The candidates expand into items, one per pair of parts (A's parts outer; a
 // ground pair pairs the plane with each part of its body) whose grown boxes meet, a primitive
 // pair being the one item of its candidate; the items, in this order, are the canonical order
 // of the chunk's manifolds.  Phase A: each lane tests its candidate's pairs of parts (a bit
@@ -2736,7 +2716,11 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
         wave_sync();
         PHASE(PH_LOAD);
 
+        const int li_outer = li;
         for (int step = 0; step < n_steps; ++step) {
+            // the lane index, opaque to the optimiser at each step: lane-dependent addresses are
+            // formed where they are used instead of once per launch and held (spilled) across it
+            const int li = opaque_lane(li_outer);
             const bool frozen = !c.active || (SC[SC_STATUS] & 1);
             const int nn = frozen ? 0 : n;
             const int S = bd.S, K = bd.K;
@@ -3079,7 +3063,7 @@ __device__ __forceinline__ void step_tiles(float* lds, const BatchDev* __restric
                                            const Tile* __restrict__ tiles, int n_tiles,
                                            const TileEnv* __restrict__ tenv, int n_steps) {
     for (int t = blockIdx.x; t < n_tiles; t += gridDim.x)
-        step_tile<ONE, FEAT>(lds, batches, tiles[t], tenv, n_steps, int(threadIdx.x));
+        step_tile<ONE, FEAT>(lds, batches, tiles[t], tenv, n_steps, opaque_lane(int(threadIdx.x)));
 }
 
 // One launch for every tile of a batch: workgroups of BIN_WAVES wavefronts, one bin each; wave w
