@@ -342,3 +342,28 @@ def test_four_part_compounds_match_oracle():
     assert same_envs(sc, g, w).all()
     assert np.all(w["status"] == 0)
     b.close()
+
+
+def test_full_size_compound_tray_sampled_envs():
+    """4096 compound-tray envs in the benchmark's launch configuration (200 settling steps, the
+    autotuner, 5 more steps); 48 sampled envs run by the oracle alone over the same 205 steps
+    from the same generator state (an env does not depend on its batch), compared bit for bit."""
+    print("compound: full size, sampled envs", flush=True)
+    sc = S.compound_tray(4096, seed=0)
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(4096, 48, replace=False))
+    sub = sc.subset(sample)
+    b = ms().Batch(sc)
+    b.step(200)
+    b.tune(5)   # trial steps restore the state
+    b.step(5)
+    g = b.state_numpy()
+    o = Oracle(sub, 32)
+    o.step(205, n_threads=16)
+    w = o.state()
+    bo = sc.body_off
+    gs = {k: np.concatenate([g[k][:, bo[e]:bo[e + 1]] for e in sample], axis=1) for k in FIELDS}
+    same = same_envs(sub, gs, w)
+    assert same.mean() >= 0.9, same.sum()
+    assert np.all(g["status"][sample] == w["status"])
+    b.close()
