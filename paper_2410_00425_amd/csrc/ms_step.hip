@@ -2617,15 +2617,17 @@ enum { PH_LOAD, PH_POSE, PH_BROAD, PH_NARROW, PH_CACHE, PH_COLOUR, PH_LISTS, PH_
         const uint64_t t_ = __builtin_amdgcn_s_memtime();     \
         ph_acc[k] += t_ - ph_t;                               \
         ph_t = t_;                                            \
+        refresh_lay();                                        \
     } while (0)
 #else
-#define PHASE(k) \
-    do {         \
+#define PHASE(k)        \
+    do {                \
+        refresh_lay();  \
     } while (0)
 #endif
 
 // FEAT: the optional parts the build carries.  FEAT_OPT: the optional phases (contact-force
-// readout, contact cache); FEAT_COMP: compound bodies as well (their two-pass narrowphase and
+// readout, contact cache); FEAT_COMP: compound bodies as well (their part-pair narrowphase and
 // boxes).  The default builds leave both out entirely, so that they cost the plain step no
 // registers, and the compound build is apart from the optional-phase one for the same reason.
 enum { FEAT_OPT = 1, FEAT_COMP = 2 };
@@ -2648,6 +2650,14 @@ __device__ __forceinline__ void step_tile(float* lds, const BatchDev* __restrict
         c.env = te.env;
         c.L = lds + te.lds_off;
         c.lay = make_lay(te.n, te.nj, te.cap, te.mcap);
+        // In the general build the layout is per group (vector registers): it is re-derived
+        // from the env's four sizes at every phase boundary, opaque to the optimiser, so that
+        // its twenty-odd offsets are live within a phase instead of across the launch.
+        const int lay_n = te.n, lay_nj = te.nj, lay_cap = te.cap, lay_mcap = te.mcap;
+        auto refresh_lay = [&]() {
+            if constexpr (!ONE)
+                c.lay = make_lay(opaque_lane(lay_n), opaque_lane(lay_nj), opaque_lane(lay_cap), opaque_lane(lay_mcap));
+        };
         const BatchDev& bd = *c.bd;
         const Lay& l = c.lay;
         const int n = l.n;
