@@ -62,6 +62,7 @@ constexpr int BIN_BUDGET = 20480;   // default bin LDS budget in words: half a C
 // Per-env sizes used by the planner.
 struct EnvInfo {
     int n, nj, n_dyn, cap, mcap, words, lanes;
+    float cost;   // estimated work of a step (launch order only)
 };
 
 // Lanes per env: enough lanes for the env's parallel work, then widened until 64 / G envs of
@@ -414,6 +415,22 @@ void make_bins(Plan& out) {
     std::vector<int> used;
     out.bin_words = pack_bins(int(out.tiles.size()), [&](int t) -> const Tile& { return out.tiles[t]; }, out.bins, used,
                               out.bin_tiles, out.bin_budget);
+    // bins in order of their longest tile's estimated work (the waves of a bin run side by side),
+    // largest first, for the same reason as the tiles
+    std::vector<float> bcost(out.bins.size(), 0.0f);
+    for (size_t k = 0; k < out.bins.size(); ++k)
+        for (int w = 0; w < out.bins[k].count; ++w) {
+            const Tile& t = out.tiles[out.bins[k].tile[w]];
+            float c = 0.0f;
+            for (int e = 0; e < t.count; ++e) c += out.info[out.tenv[t.first + e].env].cost;
+            bcost[k] = std::max(bcost[k], c);
+        }
+    std::vector<int> idx(out.bins.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = int(k);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return bcost[x] > bcost[y]; });
+    std::vector<Bin> sorted(out.bins.size());
+    for (size_t k = 0; k < idx.size(); ++k) sorted[k] = out.bins[idx[k]];
+    out.bins.swap(sorted);
 }
 
 constexpr int TILE_BUDGET = 10240;  // tile LDS budget in words (40 KiB: four tiles per CU) unless one env needs more
@@ -447,9 +464,21 @@ void make_tiles(Plan& out, bool pack) {
         cur.count++;
     }
     if (cur.count > 0) out.tiles.push_back(cur);
-    // LDS classes: tiles sorted by LDS need (largest first, stable), then cut (cut_classes).
-    std::stable_sort(out.tiles.begin(), out.tiles.end(),
-                     [](const Tile& a, const Tile& b) { return a.lds_words > b.lds_words; });
+    // LDS classes: tiles sorted by LDS need (largest first), then cut (cut_classes).  Among
+    // tiles of one LDS size the estimated work decides, largest first: workgroups are handed
+    // out in order, so the longest tiles start first and the short ones fill the tail.
+    std::vector<float> tcost(out.tiles.size(), 0.0f);
+    for (size_t t = 0; t < out.tiles.size(); ++t)
+        for (int k = 0; k < out.tiles[t].count; ++k) tcost[t] += out.info[out.tenv[out.tiles[t].first + k].env].cost;
+    std::vector<int> idx(out.tiles.size());
+    for (size_t t = 0; t < idx.size(); ++t) idx[t] = int(t);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (out.tiles[a].lds_words != out.tiles[b].lds_words) return out.tiles[a].lds_words > out.tiles[b].lds_words;
+        return tcost[a] > tcost[b];
+    });
+    std::vector<Tile> sorted(out.tiles.size());
+    for (size_t t = 0; t < idx.size(); ++t) sorted[t] = out.tiles[idx[t]];
+    out.tiles.swap(sorted);
     cut_classes(int(out.tiles.size()), [&](int t) -> Tile& { return out.tiles[t]; }, pack, out.classes);
     for (const Tile& t : out.tiles) out.max_tile_words = std::max(out.max_tile_words, t.lds_words);
     make_bins(out);
@@ -471,6 +500,21 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
         I.mcap = p->max_manifolds_per_env > 0 ? p->max_manifolds_per_env : std::min(3 * I.n_dyn + 4, 192);
         I.words = env_lds_words(I.n, I.nj, I.cap, I.mcap);
         I.lanes = pick_lanes(I, forced, TILE_BUDGET);
+        // work estimate: narrowphase and solver cost grow with the bodies' shapes (a box more
+        // than a sphere, a compound by its parts) and with the joints
+        I.cost = 2.0f * float(I.nj);
+        for (int i = 0; i < I.n; ++i) {
+            const ms_body_desc& bd = s->bodies[s->env_body_off[e] + i];
+            auto shape_cost = [](int sh) { return sh == MS_BOX ? 3.0f : (sh == MS_CAPSULE ? 1.5f : 1.0f); };
+            float c = 0.0f;
+            if (bd.shape == MS_COMPOUND) {
+                const ms_compound_desc& cd = s->compounds[int(bd.dims[0])];
+                for (int k = 0; k < cd.n_children; ++k) c += 1.5f * shape_cost(cd.shape[k]);
+            } else {
+                c = shape_cost(bd.shape);
+            }
+            I.cost += (bd.flags & MS_BODY_STATIC) ? 0.5f * c : c;
+        }
     }
     make_tiles(out, pack);
     out.dbg_pair_off.assign(E + 1, 0);
