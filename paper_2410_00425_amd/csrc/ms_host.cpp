@@ -505,7 +505,7 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
         I.cost = 2.0f * float(I.nj);
         for (int i = 0; i < I.n; ++i) {
             const ms_body_desc& bd = s->bodies[s->env_body_off[e] + i];
-            auto shape_cost = [](int sh) { return sh == MS_BOX ? 3.0f : (sh == MS_CAPSULE ? 1.5f : 1.0f); };
+            auto shape_cost = [](int sh) { return sh == MS_BOX ? 6.0f : (sh == MS_CAPSULE ? 2.0f : 1.0f); };
             float c = 0.0f;
             if (bd.shape == MS_COMPOUND) {
                 const ms_compound_desc& cd = s->compounds[int(bd.dims[0])];
