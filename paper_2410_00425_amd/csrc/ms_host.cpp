@@ -502,7 +502,7 @@ void plan_batch(const ms_sim_params* p, const ms_scene_desc* s, const ms_plan* p
         I.lanes = pick_lanes(I, forced, TILE_BUDGET);
         // work estimate: narrowphase and solver cost grow with the bodies' shapes (a box more
         // than a sphere, a compound by its parts) and with the joints
-        I.cost = 2.0f * float(I.nj);
+        I.cost = 6.0f * float(I.nj);
         for (int i = 0; i < I.n; ++i) {
             const ms_body_desc& bd = s->bodies[s->env_body_off[e] + i];
             auto shape_cost = [](int sh) { return sh == MS_BOX ? 6.0f : (sh == MS_CAPSULE ? 2.0f : 1.0f); };
